@@ -1,0 +1,267 @@
+"""Oracle: a plain serial FP64 CPU implementation of the WENO5 / HLLC /
+immersed-boundary / SSP-RK3 path, used ONLY as test infrastructure.
+
+Only the test suite, the package smoke check and the benchmark's CPU-baseline
+leg may load it.  It shares no code with the GPU library; the C++ sources
+next to this file cite the part of the paper each function follows.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+_d = ctypes.c_double
+_i = ctypes.c_int
+_p = ctypes.c_void_p
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("ndim", _i), ("nx", _i), ("ny", _i),
+        ("x0", _d), ("x1", _d), ("y0", _d), ("y1", _d),
+        ("gamma", _d), ("cfl", _d), ("weno_eps", _d),
+        ("viscous", _i), ("mu", _d), ("prandtl", _d), ("nu_art", _d),
+        ("bc", _i * 4), ("inflow", _d * 4),
+    ]
+
+
+TRANSMISSIVE, REFLECTIVE, INFLOW, PERIODIC = 0, 1, 2, 3
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if _build.needs_build():
+            _build.build()
+        _lib = ctypes.CDLL(_build.LIB)
+        _lib.orc_cfl_dt.restype = _d
+        _lib.orc_weno5_left.restype = _d
+        _lib.orc_net_create.restype = _p
+        _lib.orc_net_create.argtypes = [_p, _p, _p, _d, _i]
+        _lib.orc_net_destroy.argtypes = [_p]
+        _lib.orc_net_forward.argtypes = [_p, _i, _p, _p]
+        _lib.orc_net_backward.argtypes = [_p, _i, _p, _p, _p, _p]
+    return _lib
+
+
+def config(ndim=2, nx=64, ny=64, x0=0.0, x1=1.0, y0=0.0, y1=1.0, gamma=1.4, cfl=0.5,
+           weno_eps=1e-6, viscous=0, mu=0.0, prandtl=0.72, nu_art=0.0,
+           bc=(0, 0, 0, 0), inflow=(1.0, 0.0, 0.0, 1.0)):
+    c = Config()
+    c.ndim, c.nx, c.ny = ndim, nx, (1 if ndim == 1 else ny)
+    c.x0, c.x1, c.y0, c.y1 = x0, x1, y0, y1
+    c.gamma, c.cfl, c.weno_eps = gamma, cfl, weno_eps
+    c.viscous, c.mu, c.prandtl, c.nu_art = viscous, mu, prandtl, nu_art
+    for k in range(4):
+        c.bc[k] = bc[k]
+        c.inflow[k] = inflow[k]
+    return c
+
+
+def _nvar(c):
+    return 3 if c.ndim == 1 else 4
+
+
+def _arr(x, shape=None):
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_p)
+
+
+def _shape(c):
+    return (_nvar(c), c.ny, c.nx)
+
+
+def prim_to_cons(c, W):
+    W = _arr(W, _shape(c))
+    U = np.empty_like(W)
+    assert lib().orc_prim_to_cons(ctypes.byref(c), _ptr(W), _ptr(U)) == 0
+    return U
+
+
+def cons_to_prim(c, U):
+    U = _arr(U, _shape(c))
+    W = np.empty_like(U)
+    assert lib().orc_cons_to_prim(ctypes.byref(c), _ptr(U), _ptr(W)) == 0
+    return W
+
+
+def _phi(c, phi):
+    return None if phi is None else _arr(phi, (c.ny, c.nx))
+
+
+def rhs(c, U, phi=None, wall=0, net=None):
+    """Return (dU/dt, U with IBM ghosts filled, positivity-fallback count)."""
+    U = _arr(U, _shape(c))
+    L = np.empty_like(U)
+    Uf = np.empty_like(U)
+    fb = ctypes.c_long(0)
+    phi = _phi(c, phi)
+    rc = lib().orc_rhs(ctypes.byref(c), _ptr(U), _ptr(L), _ptr(phi), _i(wall),
+                       _p(net.handle) if net else None, _ptr(Uf), ctypes.byref(fb))
+    assert rc == 0
+    return L, Uf, fb.value
+
+
+def rk3_step(c, U, dt, phi=None, wall=0, net=None):
+    U = _arr(U, _shape(c)).copy()
+    fb = ctypes.c_long(0)
+    phi = _phi(c, phi)
+    rc = lib().orc_rk3_step(ctypes.byref(c), _ptr(U), _d(dt), _ptr(phi), _i(wall),
+                            _p(net.handle) if net else None, ctypes.byref(fb))
+    assert rc == 0
+    return U, fb.value
+
+
+def cfl_dt(c, U, phi=None, wall=0):
+    U = _arr(U, _shape(c))
+    phi = _phi(c, phi)
+    return lib().orc_cfl_dt(ctypes.byref(c), _ptr(U), _ptr(phi), _i(wall))
+
+
+def run(c, U, t_end, t0=0.0, max_steps=10 ** 9, phi=None, wall=0, net=None):
+    """Advance to t_end with CFL steps. Returns (U, t, steps, fallback count)."""
+    U = _arr(U, _shape(c)).copy()
+    t = _d(0.0)
+    steps = _i(0)
+    fb = ctypes.c_long(0)
+    phi = _phi(c, phi)
+    rc = lib().orc_run(ctypes.byref(c), _ptr(U), _d(t0), _d(t_end), _i(int(min(max_steps, 2 ** 31 - 1))),
+                       _ptr(phi), _i(wall), _p(net.handle) if net else None,
+                       ctypes.byref(t), ctypes.byref(steps), ctypes.byref(fb))
+    assert rc == 0
+    return U, t.value, steps.value, fb.value
+
+
+def weno5_left(f5, eps=1e-6):
+    f5 = _arr(f5, (5,))
+    return lib().orc_weno5_left(_ptr(f5), _d(eps))
+
+
+def hllc_x(WL, WR, gamma=1.4):
+    WL, WR = _arr(WL, (4,)), _arr(WR, (4,))
+    F = np.empty(4)
+    lib().orc_hllc_x(_ptr(WL), _ptr(WR), _d(gamma), _ptr(F))
+    return F
+
+
+def riemann_star(left, right, gamma=1.4):
+    out = np.empty(4)
+    it = _i(0)
+    lib().orc_riemann_star(*[_d(v) for v in (*left, *right, gamma)], _ptr(out), ctypes.byref(it))
+    return dict(p=out[0], u=out[1], rhoL=out[2], rhoR=out[3], iterations=it.value)
+
+
+def riemann_sample(left, right, x, t, xd=0.5, gamma=1.4):
+    x = _arr(x)
+    r, u, p = np.empty_like(x), np.empty_like(x), np.empty_like(x)
+    lib().orc_riemann_sample(*[_d(v) for v in (*left, *right, gamma, xd, t)], _i(x.size),
+                             _ptr(x), _ptr(r), _ptr(u), _ptr(p))
+    return r, u, p
+
+
+def rh_post_shock(mach, gamma=1.4, rho1=1.4, p1=1.0):
+    out = np.empty(3)
+    lib().orc_rh_post_shock(_d(mach), _d(gamma), _d(rho1), _d(p1), _ptr(out))
+    return out
+
+
+def ibm_classify(c, phi):
+    phi = _phi(c, phi)
+    cls = np.empty((c.ny, c.nx), dtype=np.uint8)
+    n = lib().orc_ibm_classify(ctypes.byref(c), _ptr(phi), cls.ctypes.data_as(_p))
+    assert n >= 0
+    return cls, n
+
+
+def ibm_ghosts(c, phi):
+    phi = _phi(c, phi)
+    cap = c.nx * c.ny
+    ij = np.empty((cap, 2), dtype=np.int32)
+    nrm = np.empty((cap, 2))
+    src = np.empty((cap, 4), dtype=np.int32)
+    w = np.empty((cap, 4))
+    n = lib().orc_ibm_ghosts(ctypes.byref(c), _ptr(phi), _i(cap), ij.ctypes.data_as(_p), _ptr(nrm),
+                             src.ctypes.data_as(_p), _ptr(w))
+    return dict(ij=ij[:n], normal=nrm[:n], src=src[:n], w=w[:n])
+
+
+def ibm_fill(c, U, phi, wall=0):
+    U = _arr(U, _shape(c)).copy()
+    assert lib().orc_ibm_fill(ctypes.byref(c), _ptr(U), _ptr(_phi(c, phi)), _i(wall)) == 0
+    return U
+
+
+def rhs_jvp(c, U, Udot, gdot=0.0, indot=(0, 0, 0, 0), phi=None, wall=0):
+    U, Udot = _arr(U, _shape(c)), _arr(Udot, _shape(c))
+    L, Ld = np.empty_like(U), np.empty_like(U)
+    ind = _arr(indot, (4,))
+    rc = lib().orc_rhs_jvp(ctypes.byref(c), _ptr(U), _ptr(Udot), _d(gdot), _ptr(ind), _ptr(_phi(c, phi)),
+                           _i(wall), _ptr(L), _ptr(Ld))
+    assert rc == 0
+    return L, Ld
+
+
+def rk3_step_jvp(c, U, Udot, dt, gdot=0.0, indot=(0, 0, 0, 0), phi=None, wall=0):
+    U, Udot = _arr(U, _shape(c)).copy(), _arr(Udot, _shape(c)).copy()
+    ind = _arr(indot, (4,))
+    rc = lib().orc_rk3_step_jvp(ctypes.byref(c), _ptr(U), _ptr(Udot), _d(dt), _d(gdot), _ptr(ind),
+                                _ptr(_phi(c, phi)), _i(wall))
+    assert rc == 0
+    return U, Udot
+
+
+def shock_tangent(c, phi, mach, xs, nsteps, dt, target_rho, wall=0, rho1=1.4, p1=1.0):
+    """J = mean_fluid (rho - target)^2 after nsteps; returns (J, dJ/dM, dJ/dgamma, U)."""
+    J = _d(0.0)
+    dJ = np.empty(2)
+    U = np.empty((4, c.ny, c.nx))
+    tgt = _arr(target_rho, (c.ny, c.nx))
+    rc = lib().orc_shock_tangent(ctypes.byref(c), _ptr(_phi(c, phi)), _i(wall), _d(mach), _d(xs),
+                                 _d(rho1), _d(p1), _i(nsteps), _d(dt), _ptr(tgt), ctypes.byref(J),
+                                 _ptr(dJ), _ptr(U))
+    assert rc == 0
+    return J.value, dJ[0], dJ[1], U
+
+
+NET_PARAMS = 10180
+
+
+class Net:
+    """The learned face-flux correction, evaluated in double precision with
+    optional bfloat16 rounding of every matrix-product operand."""
+
+    def __init__(self, params, mean, inv_std, out_scale, emulate_bf16=True):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == NET_PARAMS
+        self._keep = (p, _arr(mean, (4,)), _arr(inv_std, (4,)))
+        self.handle = lib().orc_net_create(_ptr(p), _ptr(self._keep[1]), _ptr(self._keep[2]),
+                                           _d(out_scale), _i(1 if emulate_bf16 else 0))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.orc_net_destroy(_p(self.handle))
+            self.handle = None
+
+    def forward(self, st):
+        st = _arr(st).reshape(-1, 6, 4)
+        dF = np.empty((st.shape[0], 4))
+        lib().orc_net_forward(_p(self.handle), _i(st.shape[0]), _ptr(st), _ptr(dF))
+        return dF
+
+    def backward(self, st, dFbar):
+        st = _arr(st).reshape(-1, 6, 4)
+        dFbar = _arr(dFbar).reshape(-1, 4)
+        g = np.zeros(NET_PARAMS)
+        dst = np.empty_like(st)
+        lib().orc_net_backward(_p(self.handle), _i(st.shape[0]), _ptr(st), _ptr(dFbar), _ptr(g), _ptr(dst))
+        return g, dst
