@@ -1,0 +1,197 @@
+/*
+ * shk.h -- C ABI of the MI355X (gfx950) WENO5 / HLLC / immersed-boundary /
+ * SSP-RK3 library (libshk.so).
+ *
+ * The library evaluates the right-hand side of the compressible Euler (and,
+ * optionally, Navier-Stokes) equations on a uniform Cartesian grid and
+ * advances it with the three-stage strong-stability-preserving Runge-Kutta
+ * scheme.  The method is the one of section 2 of arXiv 2601.04400:
+ *   - state U = (rho, rho u, rho v, E), flux tensor and ideal-gas equation of
+ *     state: eq. (euler) and the equation of state after it;
+ *   - fifth-order WENO reconstruction of the primitive variables (rho,u,v,p),
+ *     component by component, per dimension (Jiang-Shu weights);
+ *   - HLLC flux of section 2 (Davis wave speeds, contact speed, star states;
+ *     the star energy is the Rankine-Hugoniot-consistent
+ *     E + (s*-u)(rho s* + p/(s-u)));
+ *   - conservative flux-difference update of section 2 (with the optional
+ *     Laplacian artificial viscosity nu lap U), advanced by Shu-Osher SSP-RK3;
+ *   - ghost-cell immersed boundary (section 2, Mittal & Iaccarino) on a
+ *     signed-distance level set.
+ *
+ * Conventions
+ *   Ownership.  Every buffer (state, right-hand side, level set, workspace,
+ *     time-step scalars) is allocated and owned by the caller.  The library
+ *     never allocates device memory; it carves the caller's workspace.
+ *   Pointers.  Unless stated otherwise every array argument is a DEVICE
+ *     pointer; descriptors, handles and *_host outputs are host pointers.
+ *   Layout.  A state is [nbatch][nvar][ny][nx], x fastest, with nvar = 3 in 1D
+ *     (rho, rho u, E) and 4 in 2D (rho, rho u, rho v, E).  Element type is
+ *     double for SHK_F64 and float for SHK_F32 and SHK_MIXED.  No ghost
+ *     layers are stored: boundary values are produced on the fly.
+ *   Asynchrony.  All work is enqueued on the grid's HIP stream; no call
+ *     synchronises except shk_init_grid, shk_set_ib_levelset, shk_get_time
+ *     and shk_poll_faults, which say so.
+ *   Errors.  Every call returns a status; argument errors are detected before
+ *     anything is enqueued.  shk_last_error gives a message.  Numerical
+ *     faults during a run are latched in a device fault word
+ *     (shk_poll_faults).
+ *   Threads.  A handle must not be used by two host threads at once.
+ */
+#ifndef SHK_H
+#define SHK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct shk_grid shk_grid;
+
+typedef enum {
+  SHK_OK = 0,
+  SHK_EINVAL = 1,       /* bad argument (null pointer, size, enum value)       */
+  SHK_ESTATE = 2,       /* call not valid in the handle's current state         */
+  SHK_EHIP = 3,         /* a HIP runtime call failed                            */
+  SHK_EFAULT = 4,       /* a numerical fault was latched (see shk_poll_faults)  */
+  SHK_EUNSUPPORTED = 5, /* option combination not implemented                   */
+  SHK_ESPACE = 6        /* workspace smaller than shk_workspace_bytes()         */
+} shk_status;
+
+typedef enum { SHK_F64 = 0, SHK_F32 = 1, SHK_MIXED = 2 } shk_precision;
+/* SHK_MIXED: float storage, double arithmetic everywhere in the kernels.      */
+
+typedef enum {
+  SHK_BC_TRANSMISSIVE = 0, /* zero-order extrapolation of the nearest cell     */
+  SHK_BC_REFLECTIVE = 1,   /* mirror, normal momentum negated                  */
+  SHK_BC_INFLOW = 2,       /* fixed state inflow_prim                          */
+  SHK_BC_PERIODIC = 3
+} shk_bc;
+
+/* Fault word bits (shk_poll_faults). */
+#define SHK_FAULT_NONFINITE  0x1u  /* a non-finite value was written           */
+#define SHK_FAULT_FALLBACK   0x2u  /* positivity fallback used at some face    */
+#define SHK_FAULT_NONPHYS    0x4u  /* a cell with rho <= 0 or p <= 0 was read  */
+#define SHK_FAULT_NET        0x8u  /* flux-net output rejected (fallback used) */
+
+typedef struct {
+  int ndim;            /* 1 or 2; ndim 1 requires ny == 1                     */
+  int nx, ny;          /* interior cells                                      */
+  int nbatch;          /* independent grids sharing geometry and parameters   */
+  double x0, x1, y0, y1; /* domain; cell centres at x0 + (i+1/2) dx           */
+  int prec;            /* shk_precision                                       */
+  double gamma;        /* ratio of specific heats (> 1)                       */
+  double cfl;          /* Courant number of the automatic step                */
+  double weno_eps;     /* WENO epsilon (1e-6 if <= 0)                         */
+  int viscous;         /* 1: Navier-Stokes viscous and heat fluxes (2D only)  */
+  double mu, prandtl;  /* constant dynamic viscosity; Prandtl number          */
+  double nu_art;       /* Laplacian artificial viscosity nu (0 = off)         */
+  int bc[4];           /* shk_bc for x-lo, x-hi, y-lo, y-hi                   */
+  double inflow_prim[4]; /* (rho, u, v, p) used by SHK_BC_INFLOW              */
+  int ibm;             /* 1: reserve immersed-boundary tables in the workspace */
+  int adjoint;         /* 1: reserve adjoint buffers in the workspace          */
+} shk_grid_desc;
+
+/* Bytes of device workspace a grid with this descriptor needs (0 on a bad
+ * descriptor).  The caller allocates it (256-byte aligned) and keeps it
+ * alive until shk_destroy. */
+size_t shk_workspace_bytes(const shk_grid_desc* desc);
+
+/* Validate desc, carve workspace, initialise the device scalars (t = 0,
+ * t_end = +inf) on hip_stream (a hipStream_t; NULL = default stream) and
+ * return a handle in *out.  Synchronises the stream once.  Errors: SHK_EINVAL
+ * (bad desc or null pointer), SHK_ESPACE (ws_bytes too small), SHK_EHIP. */
+shk_status shk_init_grid(const shk_grid_desc* desc, void* workspace, size_t ws_bytes,
+                         void* hip_stream, shk_grid** out);
+
+/* Release the handle (not the caller's memory).  NULL is accepted. */
+void shk_destroy(shk_grid* g);
+
+/* Change the stream subsequent calls enqueue on. */
+shk_status shk_set_stream(shk_grid* g, void* hip_stream);
+
+/* Convert primitive planes W -> conservative planes U (same layout as a
+ * state; in 1D W holds (rho, u, p)), E = p/(gamma-1) + rho (u^2+v^2)/2.
+ * W and U are device arrays of the grid's element type; they may not alias. */
+shk_status shk_prim_to_cons(shk_grid* g, const void* W, void* U);
+
+/* Immersed boundary on the signed-distance level set phi (device, double,
+ * [ny][nx], phi < 0 inside the solid; shared by all batch members).
+ * Classifies cells (fluid phi >= 0, solid, ghost = solid within 3 cells of a
+ * fluid cell along x or y), and builds the per-ghost image-point table
+ * (mirror point at twice the wall distance along grad phi, fluid-only
+ * bilinear weights).  wall: 0 slip (normal velocity reflected), 1 no-slip
+ * adiabatic (velocity reversed); rho and p are copied from the image point.
+ * From then on ghost cells are refilled before every right-hand side and the
+ * right-hand side is zero at solid and ghost cells.  Requires desc.ibm = 1
+ * and ndim = 2.  Synchronises the stream once (to size the ghost list).
+ * phi = NULL removes the immersed boundary. */
+shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall);
+
+/* Number of ghost cells of the current immersed boundary (host output). */
+shk_status shk_ib_ghost_count(const shk_grid* g, int* n_host);
+
+/* Copy the cell classes (0 fluid, 1 solid, 2 ghost) into cls (device,
+ * uint8 [ny][nx]). */
+shk_status shk_ib_classes(shk_grid* g, uint8_t* cls);
+
+/* Right-hand side dUdt = L(U) of the semi-discrete scheme (section 2
+ * conservative update without the time step).  With an immersed boundary
+ * the ghost cells of U are refilled IN PLACE first (U is then in/out).
+ * U and dUdt must not alias. */
+shk_status shk_rhs(shk_grid* g, void* U, void* dUdt);
+
+/* One SSP-RK3 step of U in place:
+ *   U1 = U + dt L(U); U2 = 3/4 U + 1/4 U1 + dt/4 L(U1);
+ *   U <- 1/3 U + 2/3 U2 + 2 dt/3 L(U2).
+ * dt_in: device array of nbatch doubles with a fixed step, or NULL for the
+ * automatic step dt = cfl / max_fluid[(|u|+a)/dx + (|v|+a)/dy] (plus the
+ * explicit viscous limit), computed from U on the device and shortened so
+ * that the device time lands exactly on t_end (after which steps are
+ * no-ops).  dt_out: device array of nbatch doubles receiving the step used,
+ * or NULL. */
+shk_status shk_rk3_step(shk_grid* g, void* U, const double* dt_in, double* dt_out);
+
+/* Set the device time of every batch member to t0, the stop time to t_end
+ * and the automatic-step counter to 0 (enqueued). */
+shk_status shk_set_time(shk_grid* g, double t0, double t_end);
+
+/* Read the device time, end flag and number of automatic steps taken since
+ * shk_set_time of batch member b (host outputs, each may be NULL;
+ * synchronises). */
+shk_status shk_get_time(shk_grid* g, int b, double* t_host, int* done_host, int* steps_host);
+
+/* Read and clear the fault word and the positivity-fallback face count
+ * (synchronises). */
+shk_status shk_poll_faults(shk_grid* g, uint32_t* flags_host, uint64_t* fallback_faces_host);
+
+/* Kernel timing for performance reports.  With enable = 1 every later
+ * shk_rk3_step brackets each of its kernels with HIP events on the grid's
+ * stream (a small gap between launches results); enable = 0 stops and
+ * discards the records.  shk_profile_read synchronises and returns, per kernel
+ * class, the summed duration in milliseconds and the launch count:
+ * index 0 time-step reduction, 1 stage 1, 2 stage 2, 3 stage 3, 4 ghost fill.
+ * ms_host and count_host are host arrays of 5 entries. */
+shk_status shk_profile(shk_grid* g, int enable);
+shk_status shk_profile_read(shk_grid* g, double* ms_host, int* count_host);
+
+/* Message of the last failed call on this handle ("" if none). */
+const char* shk_last_error(const shk_grid* g);
+
+/* Name of a status code. */
+const char* shk_status_string(int status);
+
+/* Post-shock state (rho2, u2, p2) behind a normal shock of Mach number
+ * mach moving into gas at rest (rho1, p1) (normal-shock relations; the
+ * paper's shock-cylinder inflow state is the Mach-5 case), and its
+ * derivatives with respect to mach and gamma.  Host arrays; d_dmach and
+ * d_dgamma may be NULL. */
+shk_status shk_normal_shock_state(double mach, double gamma, double rho1, double p1, double* out3_host,
+                                  double* d_dmach3_host, double* d_dgamma3_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHK_H */

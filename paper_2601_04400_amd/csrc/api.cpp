@@ -1,0 +1,431 @@
+// Host side of the C ABI declared in include/shk.h: argument validation,
+// workspace carving and kernel sequencing on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/shk.h"
+#include "grid.hpp"
+
+using namespace shk;
+
+// Host arithmetic here (inflow state, normal-shock relations) is evaluated as
+// written, without contraction into fused multiply-adds.
+#pragma clang fp contract(off)
+
+struct WsLayout {
+  size_t scalars, globals, dtbuf, u1, u2, cls, row_count, row_off, g_cell, g_src, g_w, g_nrm;
+  size_t adj[8];
+  size_t total;
+};
+
+struct shk_grid {
+  shk_grid_desc d;
+  GridArgs a;
+  hipStream_t st;
+  char* ws;
+  size_t ws_bytes;
+  WsLayout L;
+  size_t esize;
+  GhostTable gt;
+  bool ibm_on;
+  std::string err;
+  // kernel timing (shk_profile)
+  bool prof = false;
+  struct Rec { int cls; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  ~shk_grid() {
+    for (auto& r : recs) { pool.push_back(r.a); pool.push_back(r.b); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+inline size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool desc_ok(const shk_grid_desc* d, std::string* why) {
+  auto bad = [&](const char* m) { if (why) *why = m; return false; };
+  if (!d) return bad("null descriptor");
+  if (d->ndim != 1 && d->ndim != 2) return bad("ndim must be 1 or 2");
+  if (d->nx < 1 || d->ny < 1 || d->nbatch < 1) return bad("nx, ny, nbatch must be >= 1");
+  if (d->ndim == 1 && d->ny != 1) return bad("ndim 1 requires ny == 1");
+  if (d->nx > (1 << 26) || d->ny > (1 << 26)) return bad("grid too large");
+  if ((long long)d->nx * d->ny * d->nbatch * 4 > (1LL << 40)) return bad("grid too large");
+  if (d->prec < 0 || d->prec > 2) return bad("prec must be SHK_F64, SHK_F32 or SHK_MIXED");
+  if (!(d->gamma > 1.0) || !std::isfinite(d->gamma)) return bad("gamma must be > 1");
+  if (!(d->x1 > d->x0)) return bad("x1 must exceed x0");
+  if (d->ndim == 2 && !(d->y1 > d->y0)) return bad("y1 must exceed y0");
+  if (!(d->cfl > 0.0)) return bad("cfl must be > 0");
+  for (int k = 0; k < 4; ++k)
+    if (d->bc[k] < 0 || d->bc[k] > 3) return bad("unknown boundary condition");
+  if ((d->bc[0] == SHK_BC_PERIODIC) != (d->bc[1] == SHK_BC_PERIODIC)) return bad("periodic x needs both sides");
+  if (d->ndim == 2 && (d->bc[2] == SHK_BC_PERIODIC) != (d->bc[3] == SHK_BC_PERIODIC))
+    return bad("periodic y needs both sides");
+  if (d->viscous && d->ndim != 2) return bad("viscous terms need ndim 2");
+  if (d->viscous && (!(d->mu >= 0.0) || !(d->prandtl > 0.0))) return bad("viscous needs mu >= 0, prandtl > 0");
+  if (d->ibm && d->ndim != 2) return bad("immersed boundary needs ndim 2");
+  if (d->nu_art < 0.0) return bad("nu_art must be >= 0");
+  return true;
+}
+
+size_t elem_size(const shk_grid_desc* d) { return d->prec == SHK_F64 ? 8 : 4; }
+
+WsLayout layout(const shk_grid_desc* d) {
+  WsLayout L{};
+  const size_t ncell = size_t(d->nx) * d->ny;
+  const int nvar = d->ndim == 1 ? 3 : 4;
+  const size_t state = size_t(d->nbatch) * nvar * ncell * elem_size(d);
+  size_t o = 0;
+  L.scalars = o; o += al(sizeof(StepScalars) * d->nbatch);
+  L.globals = o; o += al(sizeof(Globals));
+  L.dtbuf = o; o += al(sizeof(double) * d->nbatch);
+  L.u1 = o; o += al(state);
+  L.u2 = o; o += al(state);
+  if (d->ibm) {
+    const size_t cap = ncell;
+    L.cls = o; o += al(ncell);
+    L.row_count = o; o += al(sizeof(int) * (d->ny + 1));
+    L.row_off = o; o += al(sizeof(int) * (d->ny + 1));
+    L.g_cell = o; o += al(sizeof(int) * cap);
+    L.g_src = o; o += al(sizeof(int) * 4 * cap);
+    L.g_w = o; o += al(sizeof(double) * 4 * cap);
+    L.g_nrm = o; o += al(sizeof(double) * 2 * cap);
+  }
+  L.total = o;
+  return L;
+}
+
+shk_status fail(shk_grid* g, shk_status s, const std::string& m) {
+  if (g) g->err = m;
+  return s;
+}
+
+shk_status hip_check(shk_grid* g, hipError_t e, const char* where) {
+  if (e == hipSuccess) return SHK_OK;
+  return fail(g, SHK_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+hipEvent_t take_event(shk_grid* g) {
+  if (!g->pool.empty()) { hipEvent_t e = g->pool.back(); g->pool.pop_back(); return e; }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Run f() between two events recorded on the grid's stream when profiling.
+template <class F>
+hipError_t timed(shk_grid* g, int cls, F&& f) {
+  if (!g->prof) return f();
+  hipEvent_t a = take_event(g), b = take_event(g);
+  if (!a || !b) return f();
+  (void)hipEventRecord(a, g->st);
+  hipError_t e = f();
+  (void)hipEventRecord(b, g->st);
+  g->recs.push_back({cls, a, b});
+  return e;
+}
+
+template <class S>
+shk_status stage_seq(shk_grid* g, S* U, const double* dtp) {
+  const GridArgs& a = g->a;
+  S* U1 = reinterpret_cast<S*>(g->ws + g->L.u1);
+  S* U2 = reinterpret_cast<S*>(g->ws + g->L.u2);
+  auto stage = [&](int mode, const S* Us, const S* Un, S* Uo) -> hipError_t {
+    return timed(g, mode, [&]() {
+      if (g->d.prec == SHK_MIXED)
+        return launch_stage_mixed(a, mode, reinterpret_cast<const float*>(Us), reinterpret_cast<const float*>(Un),
+                                  reinterpret_cast<float*>(Uo), dtp, g->st);
+      return launch_stage<S>(a, mode, Us, Un, Uo, dtp, g->st);
+    });
+  };
+  auto fill = [&](S* X) -> hipError_t {
+    if (!g->ibm_on) return hipSuccess;
+    return timed(g, 4, [&]() { return launch_ibm_fill<S>(a, g->gt, X, g->st); });
+  };
+  hipError_t e;
+  if ((e = fill(U)) != hipSuccess) return hip_check(g, e, "ibm fill");
+  if ((e = stage(MODE_STAGE1, U, U, U1)) != hipSuccess) return hip_check(g, e, "stage 1");
+  if ((e = fill(U1)) != hipSuccess) return hip_check(g, e, "ibm fill");
+  if ((e = stage(MODE_STAGE2, U1, U, U2)) != hipSuccess) return hip_check(g, e, "stage 2");
+  if ((e = fill(U2)) != hipSuccess) return hip_check(g, e, "ibm fill");
+  if ((e = stage(MODE_STAGE3, U2, U, U)) != hipSuccess) return hip_check(g, e, "stage 3");
+  return SHK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t shk_workspace_bytes(const shk_grid_desc* desc) {
+  if (!desc_ok(desc, nullptr)) return 0;
+  return layout(desc).total;
+}
+
+shk_status shk_init_grid(const shk_grid_desc* desc, void* workspace, size_t ws_bytes, void* hip_stream,
+                         shk_grid** out) {
+  std::string why;
+  if (!out) return SHK_EINVAL;
+  *out = nullptr;
+  if (!desc_ok(desc, &why)) return SHK_EINVAL;
+  if (!workspace) return SHK_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return SHK_EINVAL;
+  WsLayout L = layout(desc);
+  if (ws_bytes < L.total) return SHK_ESPACE;
+  shk_grid* g = new (std::nothrow) shk_grid();
+  if (!g) return SHK_EINVAL;
+  g->d = *desc;
+  if (!(g->d.weno_eps > 0.0)) g->d.weno_eps = 1e-6;
+  g->st = reinterpret_cast<hipStream_t>(hip_stream);
+  g->ws = static_cast<char*>(workspace);
+  g->ws_bytes = ws_bytes;
+  g->L = L;
+  g->esize = elem_size(desc);
+  g->ibm_on = false;
+  g->gt = GhostTable{0, nullptr, nullptr, nullptr, nullptr, 0};
+  GridArgs& a = g->a;
+  std::memset(&a, 0, sizeof(a));
+  const shk_grid_desc& d = g->d;
+  a.ndim = d.ndim; a.nx = d.nx; a.ny = d.ny; a.nbatch = d.nbatch; a.nvar = d.ndim == 1 ? 3 : 4;
+  a.ncell = (long long)d.nx * d.ny;
+  a.x0 = d.x0; a.y0 = d.ndim == 2 ? d.y0 : 0.0;
+  a.dx = (d.x1 - d.x0) / d.nx;
+  a.dy = d.ndim == 2 ? (d.y1 - d.y0) / d.ny : 1.0;
+  a.inv_dx = 1.0 / a.dx; a.inv_dy = 1.0 / a.dy;
+  a.gamma = d.gamma; a.eps = d.weno_eps; a.cfl = d.cfl;
+  a.viscous = d.viscous; a.mu = d.mu; a.prandtl = d.prandtl > 0 ? d.prandtl : 1.0;
+  a.kappa = d.viscous ? d.mu * d.gamma / ((d.gamma - 1.0) * a.prandtl) : 0.0;
+  a.nu_art = d.nu_art;
+  for (int k = 0; k < 4; ++k) a.bc[k] = d.bc[k];
+  {
+    const double* w = d.inflow_prim;
+    const double v = d.ndim == 2 ? w[2] : 0.0;
+    a.inflow_cons[0] = w[0];
+    a.inflow_cons[1] = w[0] * w[1];
+    a.inflow_cons[2] = w[0] * v;
+    a.inflow_cons[3] = w[3] / (d.gamma - 1.0) + 0.5 * w[0] * (w[1] * w[1] + v * v);
+  }
+  a.cls = nullptr;
+  a.sc = reinterpret_cast<StepScalars*>(g->ws + L.scalars);
+  a.glob = reinterpret_cast<Globals*>(g->ws + L.globals);
+  a.dtbuf = reinterpret_cast<double*>(g->ws + L.dtbuf);
+  hipError_t e = launch_init_scalars(a, 0.0, std::numeric_limits<double>::infinity(), g->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+  if (e != hipSuccess) {
+    delete g;
+    return SHK_EHIP;
+  }
+  *out = g;
+  return SHK_OK;
+}
+
+void shk_destroy(shk_grid* g) { delete g; }
+
+shk_status shk_set_stream(shk_grid* g, void* hip_stream) {
+  if (!g) return SHK_EINVAL;
+  g->st = reinterpret_cast<hipStream_t>(hip_stream);
+  return SHK_OK;
+}
+
+shk_status shk_prim_to_cons(shk_grid* g, const void* W, void* U) {
+  if (!g) return SHK_EINVAL;
+  if (!W || !U || W == U) return fail(g, SHK_EINVAL, "prim_to_cons: null or aliased arrays");
+  hipError_t e = g->esize == 8
+                     ? launch_prim_to_cons<double>(g->a, static_cast<const double*>(W), static_cast<double*>(U), g->st)
+                     : launch_prim_to_cons<float>(g->a, static_cast<const float*>(W), static_cast<float*>(U), g->st);
+  return hip_check(g, e, "prim_to_cons");
+}
+
+shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
+  if (!g) return SHK_EINVAL;
+  if (!phi) {
+    g->ibm_on = false;
+    g->a.cls = nullptr;
+    g->gt.n = 0;
+    return SHK_OK;
+  }
+  if (!g->d.ibm) return fail(g, SHK_ESTATE, "set_ib_levelset: grid created without desc.ibm = 1");
+  if (wall != 0 && wall != 1) return fail(g, SHK_EINVAL, "set_ib_levelset: wall must be 0 (slip) or 1 (no-slip)");
+  GridArgs& a = g->a;
+  uint8_t* cls = reinterpret_cast<uint8_t*>(g->ws + g->L.cls);
+  int* rc = reinterpret_cast<int*>(g->ws + g->L.row_count);
+  int* ro = reinterpret_cast<int*>(g->ws + g->L.row_off);
+  GhostTable gt;
+  gt.cell = reinterpret_cast<int*>(g->ws + g->L.g_cell);
+  gt.src = reinterpret_cast<int*>(g->ws + g->L.g_src);
+  gt.w = reinterpret_cast<double*>(g->ws + g->L.g_w);
+  gt.nrm = reinterpret_cast<double*>(g->ws + g->L.g_nrm);
+  gt.wall = wall;
+  gt.n = 0;
+  hipError_t e = hipMemsetAsync(rc, 0, sizeof(int) * (a.ny + 1), g->st);
+  if (e == hipSuccess) e = launch_ibm_classify(a, phi, cls, rc, g->st);
+  if (e == hipSuccess) e = launch_ibm_table(a, phi, cls, rc, ro, gt, g->st);
+  int n = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&n, ro + a.ny, sizeof(int), hipMemcpyDeviceToHost, g->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+  if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset");
+  gt.n = n;
+  g->gt = gt;
+  a.cls = cls;
+  g->ibm_on = true;
+  return SHK_OK;
+}
+
+shk_status shk_ib_ghost_count(const shk_grid* g, int* n_host) {
+  if (!g || !n_host) return SHK_EINVAL;
+  *n_host = g->ibm_on ? g->gt.n : 0;
+  return SHK_OK;
+}
+
+shk_status shk_ib_classes(shk_grid* g, uint8_t* cls) {
+  if (!g || !cls) return SHK_EINVAL;
+  if (!g->ibm_on) return fail(g, SHK_ESTATE, "ib_classes: no immersed boundary set");
+  return hip_check(g, hipMemcpyAsync(cls, g->a.cls, size_t(g->a.ncell), hipMemcpyDeviceToDevice, g->st),
+                   "ib_classes");
+}
+
+shk_status shk_rhs(shk_grid* g, void* U, void* dUdt) {
+  if (!g) return SHK_EINVAL;
+  if (!U || !dUdt || U == dUdt) return fail(g, SHK_EINVAL, "rhs: null or aliased arrays");
+  hipError_t e = hipSuccess;
+  if (g->esize == 8) {
+    if (g->ibm_on) e = launch_ibm_fill<double>(g->a, g->gt, static_cast<double*>(U), g->st);
+    if (e == hipSuccess)
+      e = launch_stage<double>(g->a, MODE_RHS, static_cast<double*>(U), static_cast<double*>(U),
+                               static_cast<double*>(dUdt), nullptr, g->st);
+  } else {
+    if (g->ibm_on) e = launch_ibm_fill<float>(g->a, g->gt, static_cast<float*>(U), g->st);
+    if (e == hipSuccess) {
+      if (g->d.prec == SHK_MIXED)
+        e = launch_stage_mixed(g->a, MODE_RHS, static_cast<float*>(U), static_cast<float*>(U),
+                               static_cast<float*>(dUdt), nullptr, g->st);
+      else
+        e = launch_stage<float>(g->a, MODE_RHS, static_cast<float*>(U), static_cast<float*>(U),
+                                static_cast<float*>(dUdt), nullptr, g->st);
+    }
+  }
+  return hip_check(g, e, "rhs");
+}
+
+shk_status shk_rk3_step(shk_grid* g, void* U, const double* dt_in, double* dt_out) {
+  if (!g) return SHK_EINVAL;
+  if (!U) return fail(g, SHK_EINVAL, "rk3_step: null state");
+  const double* dtp = dt_in;
+  if (!dt_in) {
+    hipError_t e = timed(g, 0, [&]() {
+      return g->esize == 8 ? launch_cfl<double>(g->a, static_cast<const double*>(U), dt_out, g->st)
+                           : launch_cfl<float>(g->a, static_cast<const float*>(U), dt_out, g->st);
+    });
+    if (e != hipSuccess) return hip_check(g, e, "cfl");
+    dtp = g->a.dtbuf;
+  }
+  if (g->esize == 8) return stage_seq<double>(g, static_cast<double*>(U), dtp);
+  return stage_seq<float>(g, static_cast<float*>(U), dtp);
+}
+
+shk_status shk_set_time(shk_grid* g, double t0, double t_end) {
+  if (!g) return SHK_EINVAL;
+  if (!(t_end >= t0)) return fail(g, SHK_EINVAL, "set_time: t_end < t0");
+  return hip_check(g, launch_init_scalars(g->a, t0, t_end, g->st), "set_time");
+}
+
+shk_status shk_get_time(shk_grid* g, int b, double* t_host, int* done_host, int* steps_host) {
+  if (!g || b < 0 || b >= g->d.nbatch) return SHK_EINVAL;
+  StepScalars s;
+  hipError_t e = hipMemcpyAsync(&s, g->a.sc + b, sizeof(s), hipMemcpyDeviceToHost, g->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+  if (e != hipSuccess) return hip_check(g, e, "get_time");
+  if (t_host) *t_host = s.t;
+  if (done_host) *done_host = s.done;
+  if (steps_host) *steps_host = s.nsteps;
+  return SHK_OK;
+}
+
+shk_status shk_poll_faults(shk_grid* g, uint32_t* flags_host, uint64_t* fallback_faces_host) {
+  if (!g) return SHK_EINVAL;
+  Globals gl;
+  hipError_t e = hipMemcpyAsync(&gl, g->a.glob, sizeof(gl), hipMemcpyDeviceToHost, g->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+  Globals z{};
+  if (e == hipSuccess) e = hipMemcpyAsync(g->a.glob, &z, sizeof(z), hipMemcpyHostToDevice, g->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+  if (e != hipSuccess) return hip_check(g, e, "poll_faults");
+  if (flags_host) *flags_host = gl.fault;
+  if (fallback_faces_host) *fallback_faces_host = gl.fallbacks;
+  return SHK_OK;
+}
+
+shk_status shk_profile(shk_grid* g, int enable) {
+  if (!g) return SHK_EINVAL;
+  if (!g->recs.empty()) {
+    hipError_t e = hipStreamSynchronize(g->st);
+    for (auto& r : g->recs) { g->pool.push_back(r.a); g->pool.push_back(r.b); }
+    g->recs.clear();
+    if (e != hipSuccess) return hip_check(g, e, "profile");
+  }
+  g->prof = enable != 0;
+  return SHK_OK;
+}
+
+shk_status shk_profile_read(shk_grid* g, double* ms_host, int* count_host) {
+  if (!g || !ms_host || !count_host) return SHK_EINVAL;
+  for (int k = 0; k < 5; ++k) { ms_host[k] = 0.0; count_host[k] = 0; }
+  hipError_t e = hipStreamSynchronize(g->st);
+  if (e != hipSuccess) return hip_check(g, e, "profile_read");
+  for (auto& r : g->recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess && r.cls >= 0 && r.cls < 5) {
+      ms_host[r.cls] += ms;
+      count_host[r.cls] += 1;
+    }
+  }
+  return SHK_OK;
+}
+
+const char* shk_last_error(const shk_grid* g) { return g ? g->err.c_str() : "null handle"; }
+
+const char* shk_status_string(int s) {
+  switch (s) {
+    case SHK_OK: return "SHK_OK";
+    case SHK_EINVAL: return "SHK_EINVAL";
+    case SHK_ESTATE: return "SHK_ESTATE";
+    case SHK_EHIP: return "SHK_EHIP";
+    case SHK_EFAULT: return "SHK_EFAULT";
+    case SHK_EUNSUPPORTED: return "SHK_EUNSUPPORTED";
+    case SHK_ESPACE: return "SHK_ESPACE";
+    default: return "unknown status";
+  }
+}
+
+shk_status shk_normal_shock_state(double M, double g, double r1, double p1, double* out3, double* dM3,
+                                  double* dg3) {
+  if (!out3 || !(g > 1.0) || !(r1 > 0.0) || !(p1 > 0.0) || !(M >= 1.0)) return SHK_EINVAL;
+  const double a1 = std::sqrt(g * p1 / r1);
+  const double M2 = M * M;
+  const double den = (g - 1.0) * M2 + 2.0;
+  const double r2 = r1 * (g + 1.0) * M2 / den;
+  const double p2 = p1 * (1.0 + 2.0 * g / (g + 1.0) * (M2 - 1.0));
+  const double u2 = M * a1 * (1.0 - r1 / r2);
+  out3[0] = r2; out3[1] = u2; out3[2] = p2;
+  // d/dM
+  const double dr2_dM = r1 * (g + 1.0) * (2.0 * M * den - M2 * 2.0 * (g - 1.0) * M) / (den * den);
+  const double dp2_dM = p1 * 2.0 * g / (g + 1.0) * 2.0 * M;
+  const double du2_dM = a1 * (1.0 - r1 / r2) + M * a1 * (r1 / (r2 * r2)) * dr2_dM;
+  // d/dgamma
+  const double da1_dg = 0.5 * std::sqrt(p1 / (r1 * g));
+  const double dr2_dg = r1 * (M2 * den - (g + 1.0) * M2 * M2) / (den * den);
+  const double dp2_dg = p1 * 2.0 * (M2 - 1.0) / ((g + 1.0) * (g + 1.0));
+  const double du2_dg = M * da1_dg * (1.0 - r1 / r2) + M * a1 * (r1 / (r2 * r2)) * dr2_dg;
+  if (dM3) { dM3[0] = dr2_dM; dM3[1] = du2_dM; dM3[2] = dp2_dM; }
+  if (dg3) { dg3[0] = dr2_dg; dg3[1] = du2_dg; dg3[2] = dp2_dg; }
+  return SHK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Device building blocks of the face flux: primitive conversion, WENO5-JS
+// reconstruction and the HLLC Riemann flux, written for gfx950.
+//
+// All functions are templated on the arithmetic type C (double or float) and
+// work in the face-normal frame: component 1 is the normal velocity and
+// component 2 the tangential one, so the same code serves x- and y-faces.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace shk {
+
+template <class C>
+struct Prim {
+  C r, un, ut, p;
+};
+
+// Ideal-gas primitives from conservative variables (section 2 equation of
+// state).  mn/mt are the normal/tangential momenta.
+template <class C>
+__device__ __forceinline__ Prim<C> to_prim(C rho, C mn, C mt, C E, C gm1) {
+  Prim<C> w;
+  C ir = C(1) / rho;
+  w.r = rho;
+  w.un = mn * ir;
+  w.ut = mt * ir;
+  w.p = gm1 * (E - C(0.5) * rho * (w.un * w.un + w.ut * w.ut));
+  return w;
+}
+
+// WENO5-JS left-biased value at the face between c and d of the five cells
+// a b c d e (Jiang-Shu indicators, ideal weights 1/10, 6/10, 3/10, eps).
+// The nonlinear weights d_k/(eps+beta_k)^2 are normalised by multiplying
+// through with the product of the three squared denominators, which leaves
+// a single division per reconstruction.
+template <class C>
+__device__ __forceinline__ C weno5(C a, C b, C c, C d, C e, C eps) {
+  const C k13 = C(13) / C(12);
+  C s0 = a - C(2) * b + c, t0 = a - C(4) * b + C(3) * c;
+  C s1 = b - C(2) * c + d, t1 = b - d;
+  C s2 = c - C(2) * d + e, t2 = C(3) * c - C(4) * d + e;
+  C g0 = eps + (k13 * s0 * s0 + C(0.25) * t0 * t0);
+  C g1 = eps + (k13 * s1 * s1 + C(0.25) * t1 * t1);
+  C g2 = eps + (k13 * s2 * s2 + C(0.25) * t2 * t2);
+  g0 = g0 * g0;
+  g1 = g1 * g1;
+  g2 = g2 * g2;
+  C w0 = C(0.1) * (g1 * g2);
+  C w1 = C(0.6) * (g0 * g2);
+  C w2 = C(0.3) * (g0 * g1);
+  C q0 = C(2) * a - C(7) * b + C(11) * c;
+  C q1 = C(5) * c - b + C(2) * d;
+  C q2 = C(2) * c + C(5) * d - e;
+  return (w0 * q0 + w1 * q1 + w2 * q2) / (C(6) * (w0 + w1 + w2));
+}
+
+// HLLC flux (section 2) in the face-normal frame, components
+// (mass, normal momentum, tangential momentum, energy).
+//   wave speeds (Davis): sL = min(uL-aL, uR-aR), sR = max(uL+aL, uR+aR)
+//   contact: s* = (pR - pL + rL uL (sL-uL) - rR uR (sR-uR)) / (rL (sL-uL) - rR (sR-uR))
+//   star state on side k: (sk-uk)/(sk-s*) [r, r s*, r ut, E + (s*-uk)(r s* + p/(sk-uk))]
+// The sign(s*) blend picks the left bracket FL + min(0,sL)(U*L-UL) for
+// s* > 0, the right bracket FR + max(0,sR)(U*R-UR) for s* < 0 and their mean
+// at s* = 0.
+template <class C>
+struct Flux4 {
+  C f0, f1, f2, f3;
+};
+
+template <class C>
+__device__ __forceinline__ Flux4<C> hllc_side(const Prim<C>& w, C E, C s, C ss, bool supersonic) {
+  // physical flux of this side
+  C mn = w.r * w.un;
+  Flux4<C> F;
+  F.f0 = mn;
+  F.f1 = mn * w.un + w.p;
+  F.f2 = mn * w.ut;
+  F.f3 = w.un * (E + w.p);
+  if (supersonic) return F;
+  C su = s - w.un;
+  C chi = su / (s - ss);
+  C rs = chi * w.r;
+  C d0 = rs - w.r;
+  C d1 = rs * ss - mn;
+  C d2 = rs * w.ut - w.r * w.ut;
+  C d3 = chi * (E + (ss - w.un) * (w.r * ss + w.p / su)) - E;
+  F.f0 = F.f0 + s * d0;
+  F.f1 = F.f1 + s * d1;
+  F.f2 = F.f2 + s * d2;
+  F.f3 = F.f3 + s * d3;
+  return F;
+}
+
+template <class C>
+__device__ __forceinline__ Flux4<C> hllc(const Prim<C>& L, const Prim<C>& R, C gamma, C igm1) {
+  C aL = sqrt(gamma * L.p / L.r);
+  C aR = sqrt(gamma * R.p / R.r);
+  C sL = fmin(L.un - aL, R.un - aR);
+  C sR = fmax(L.un + aL, R.un + aR);
+  C dL = sL - L.un, dR = sR - R.un;
+  C ss = (R.p - L.p + L.r * L.un * dL - R.r * R.un * dR) / (L.r * dL - R.r * dR);
+  C EL = L.p * igm1 + C(0.5) * L.r * (L.un * L.un + L.ut * L.ut);
+  C ER = R.p * igm1 + C(0.5) * R.r * (R.un * R.un + R.ut * R.ut);
+  if (ss > C(0)) return hllc_side(L, EL, sL, ss, sL >= C(0));
+  if (ss < C(0)) return hllc_side(R, ER, sR, ss, sR <= C(0));
+  Flux4<C> A = hllc_side(L, EL, sL, ss, sL >= C(0));
+  Flux4<C> B = hllc_side(R, ER, sR, ss, sR <= C(0));
+  return Flux4<C>{C(0.5) * (A.f0 + B.f0), C(0.5) * (A.f1 + B.f1), C(0.5) * (A.f2 + B.f2),
+                  C(0.5) * (A.f3 + B.f3)};
+}
+
+}  // namespace shk

@@ -1,0 +1,79 @@
+// Internal (non-ABI) description of a grid shared by the host API and the
+// kernels: sizes, physics constants, boundary rules and workspace pointers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace shk {
+
+enum : int { BC_TRANS = 0, BC_REFL = 1, BC_INFLOW = 2, BC_PERIODIC = 3 };
+enum : uint8_t { CELL_FLUID = 0, CELL_SOLID = 1, CELL_GHOST = 2 };
+constexpr int HALO = 3;
+
+// Per-batch-member device scalars of the time loop.
+struct alignas(64) StepScalars {
+  double dt;                    // step used by the stages (0 => no-op)
+  double t;                     // device time
+  double t_end;                 // stop time
+  unsigned long long smax_bits; // max wave-speed sum (bit pattern of a double >= 0)
+  unsigned long long rmin_bits; // min density (bit pattern of a double > 0)
+  int done;                     // t_end reached
+  unsigned int blocks_done;     // last-block detection of the reduction
+  int nsteps;                   // automatic steps taken with dt > 0
+};
+
+struct Globals {
+  unsigned int fault;           // SHK_FAULT_* bits
+  unsigned int pad;
+  unsigned long long fallbacks; // positivity-fallback faces
+};
+
+// Everything a kernel needs to know about the grid (passed by value).
+struct GridArgs {
+  int ndim, nx, ny, nbatch, nvar;
+  long long ncell;      // nx * ny
+  double x0, y0, dx, dy, inv_dx, inv_dy;
+  double gamma, eps, cfl;
+  int viscous;
+  double mu, kappa, prandtl;   // kappa = mu gamma / ((gamma-1) Pr), gas constant 1
+  double nu_art;
+  int bc[4];
+  double inflow_cons[4];       // conservative inflow state (rho, rho u, rho v, E)
+  const uint8_t* cls;          // cell classes [ny][nx] or nullptr (no IBM)
+  StepScalars* sc;             // [nbatch]
+  double* dtbuf;               // [nbatch] step of the automatic time stepping
+  Globals* glob;
+};
+
+// Ghost-cell table of the immersed boundary (structure of arrays).
+struct GhostTable {
+  int n;
+  int* cell;        // flat index of the ghost
+  int* src;         // [n][4] flat indices of the interpolation cells (-1 unused)
+  double* w;        // [n][4] weights
+  double* nrm;      // [n][2] unit normal
+  int wall;         // 0 slip, 1 no-slip adiabatic
+};
+
+// Host-side launchers (stage.hip, ibm.hip).
+template <class S>
+hipError_t launch_prim_to_cons(const GridArgs& a, const S* W, S* U, hipStream_t st);
+template <class S>
+hipError_t launch_cfl(const GridArgs& a, const S* U, double* dt_out, hipStream_t st);
+template <class S>
+hipError_t launch_stage(const GridArgs& a, int mode, const S* Us, const S* Un, S* Uout,
+                        const double* dtp, hipStream_t st);
+hipError_t launch_init_scalars(const GridArgs& a, double t0, double t_end, hipStream_t st);
+template <class S>
+hipError_t launch_ibm_fill(const GridArgs& a, const GhostTable& gt, S* U, hipStream_t st);
+hipError_t launch_ibm_classify(const GridArgs& a, const double* phi, uint8_t* cls, int* row_count,
+                               hipStream_t st);
+hipError_t launch_ibm_table(const GridArgs& a, const double* phi, const uint8_t* cls, const int* row_count,
+                            int* row_off, GhostTable gt, hipStream_t st);
+hipError_t launch_stage_mixed(const GridArgs& a, int mode, const float* Us, const float* Un, float* Uout,
+                              const double* dtp, hipStream_t st);
+
+// stage modes
+enum : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2, MODE_STAGE3 = 3 };
+
+}  // namespace shk

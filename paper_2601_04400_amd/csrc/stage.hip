@@ -1,0 +1,494 @@
+// Fused right-hand-side / SSP-RK3 stage kernel, CFL reduction and
+// primitive-to-conservative conversion for gfx950.
+//
+// One workgroup owns a TX x TY tile of cells.  It stages the tile plus a
+// 3-cell halo of primitive variables in LDS (boundary rules applied while
+// loading), computes every x- and y-face flux of the tile once (WENO5-JS on
+// (rho, u, v, p), HLLC, optional viscous flux) into LDS, and finishes with the
+// flux difference and the Runge-Kutta combination, writing each cell once.
+// HBM traffic per stage is one read of the stage state (halo re-reads hit
+// L2), one read of U^n for stages 2 and 3, and one write.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "flux.hpp"
+#include "grid.hpp"
+
+namespace shk {
+
+// ----------------------------------------------------------- boundary rules
+// Map a possibly out-of-range index along one axis to its source cell.
+// flag: 0 copy, 1 copy and negate the momentum normal to this axis,
+// 2 replace the whole state by the inflow state.
+__device__ __forceinline__ int bc_source(int g, int n, int bc_lo, int bc_hi, int& flag) {
+  if (g >= 0 && g < n) return g;
+  const bool lo = g < 0;
+  const int bc = lo ? bc_lo : bc_hi;
+  const int depth = lo ? -g : g - (n - 1);  // 1 for the first ghost layer
+  int s;
+  switch (bc) {
+    case BC_REFL: s = lo ? depth - 1 : n - depth; flag = flag | 1; break;
+    case BC_INFLOW: s = lo ? 0 : n - 1; flag = 2; break;
+    case BC_PERIODIC: s = ((g % n) + n) % n; break;
+    default: s = lo ? 0 : n - 1; break;  // transmissive
+  }
+  return s < 0 ? 0 : (s >= n ? n - 1 : s);
+}
+
+// Conservative state (rho, m_x, m_y, E) of cell (gi, gj), which may lie in
+// the ghost layers; x rules are applied first, then y rules (a y inflow
+// overrides everything, as for a y-ghost layer filled after the x-ghosts).
+template <class S, class C, int NDIM>
+__device__ __forceinline__ void load_cons(const GridArgs& a, const S* __restrict__ U, int gi, int gj,
+                                          C q[4]) {
+  int fx = 0, fy = 0;
+  const int si = bc_source(gi, a.nx, a.bc[0], a.bc[1], fx);
+  int sj = 0;
+  if (NDIM == 2) sj = bc_source(gj, a.ny, a.bc[2], a.bc[3], fy);
+  if (fy == 2 || fx == 2) {
+    for (int v = 0; v < 4; ++v) q[v] = C(a.inflow_cons[v]);
+    if (NDIM == 1) q[2] = C(0);
+  } else {
+    const long long c = (long long)sj * a.nx + si;
+    if (NDIM == 2) {
+      q[0] = C(U[c]);
+      q[1] = C(U[a.ncell + c]);
+      q[2] = C(U[2 * a.ncell + c]);
+      q[3] = C(U[3 * a.ncell + c]);
+    } else {
+      q[0] = C(U[c]);
+      q[1] = C(U[a.ncell + c]);
+      q[2] = C(0);
+      q[3] = C(U[2 * a.ncell + c]);
+    }
+    if (fx & 1) q[1] = -q[1];
+  }
+  if (fy & 1) q[2] = -q[2];
+}
+
+template <class C>
+__device__ __forceinline__ bool finite_val(C x) {
+  return isfinite(x);
+}
+
+// ------------------------------------------------------------ stage kernel
+template <class S, class C, int NDIM, int TX, int TY, bool VISC, int MODE>
+__global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restrict__ Us,
+                                                    const S* __restrict__ Un, S* __restrict__ Uout,
+                                                    const double* __restrict__ dtp) {
+  constexpr int NT = 256;
+  constexpr int H = HALO;
+  constexpr int PX = TX + 2 * H;
+  constexpr int PY = NDIM == 2 ? TY + 2 * H : 1;
+  constexpr int NFX = (TX + 1) * TY;
+  constexpr int NFY = NDIM == 2 ? TX * (TY + 1) : 0;
+  constexpr int FYR = NDIM == 2 ? TY + 1 : 1;
+  static_assert(NDIM == 2 || TY == 1, "1D tiles are one row");
+
+  __shared__ C w[4][PY * PX];
+  __shared__ C fxs[4][TY * (TX + 1)];
+  __shared__ C fys[4][FYR * TX];
+  __shared__ unsigned int blk_fallback, blk_fault;
+
+  const int b = blockIdx.z;
+  double dt = 0.0;
+  if (MODE != MODE_RHS) {
+    dt = dtp[b];
+    if (dt == 0.0) return;  // end time reached: the step is a no-op
+  }
+  if (threadIdx.x == 0) { blk_fallback = 0; blk_fault = 0; }
+  const int i0 = blockIdx.x * TX;
+  const int j0 = blockIdx.y * TY;
+  const long long boff = (long long)b * a.nvar * a.ncell;
+  const S* __restrict__ Ub = Us + boff;
+  const C gm1 = C(a.gamma - 1.0);
+
+  // 1. halo tile of primitives
+  for (int k = threadIdx.x; k < PY * PX; k += NT) {
+    const int lx = k % PX, ly = k / PX;
+    const bool inx = lx >= H && lx < TX + H;
+    const bool iny = NDIM == 1 || (ly >= H && ly < TY + H);
+    if (!VISC && !inx && !iny) continue;  // corner block: read only by viscous stencils
+    const int gi = i0 + lx - H;
+    const int gj = NDIM == 2 ? j0 + ly - H : 0;
+    C q[4];
+    load_cons<S, C, NDIM>(a, Ub, gi, gj, q);
+    Prim<C> p = to_prim(q[0], q[1], q[2], q[3], gm1);
+    w[0][k] = p.r;
+    w[1][k] = p.un;
+    w[2][k] = p.ut;
+    w[3][k] = p.p;
+  }
+  __syncthreads();
+
+  // 2. face fluxes
+  const C eps = C(a.eps);
+  const C gam = C(a.gamma);
+  const C igm1 = C(1.0 / (a.gamma - 1.0));
+  unsigned int my_fallback = 0;
+  for (int k = threadIdx.x; k < NFX + NFY; k += NT) {
+    const bool isx = k < NFX;
+    int s0, st, cn, ct, oidx;
+    bool owned;  // this tile is the one that reports the face (fallback count)
+    if (isx) {
+      const int fi = k % (TX + 1), y = k / (TX + 1);
+      s0 = (NDIM == 2 ? (y + H) * PX : 0) + fi;
+      st = 1; cn = 1; ct = 2;
+      oidx = y * (TX + 1) + fi;
+      const int gf = i0 + fi;
+      owned = j0 + y < a.ny && gf <= a.nx && (fi < TX || gf == a.nx);
+    } else {
+      const int kk = k - NFX;
+      const int x = kk % TX, fj = kk / TX;
+      s0 = fj * PX + x + H;
+      st = PX; cn = 2; ct = 1;
+      oidx = fj * TX + x;
+      const int gf = j0 + fj;
+      owned = i0 + x < a.nx && gf <= a.ny && (fj < TY || gf == a.ny);
+    }
+    Prim<C> L, R;
+    {
+      const C* f = w[0] + s0;
+      C v0 = f[0], v1 = f[st], v2 = f[2 * st], v3 = f[3 * st], v4 = f[4 * st], v5 = f[5 * st];
+      L.r = weno5(v0, v1, v2, v3, v4, eps);
+      R.r = weno5(v5, v4, v3, v2, v1, eps);
+    }
+    {
+      const C* f = w[cn] + s0;
+      C v0 = f[0], v1 = f[st], v2 = f[2 * st], v3 = f[3 * st], v4 = f[4 * st], v5 = f[5 * st];
+      L.un = weno5(v0, v1, v2, v3, v4, eps);
+      R.un = weno5(v5, v4, v3, v2, v1, eps);
+    }
+    {
+      const C* f = w[ct] + s0;
+      C v0 = f[0], v1 = f[st], v2 = f[2 * st], v3 = f[3 * st], v4 = f[4 * st], v5 = f[5 * st];
+      L.ut = weno5(v0, v1, v2, v3, v4, eps);
+      R.ut = weno5(v5, v4, v3, v2, v1, eps);
+    }
+    {
+      const C* f = w[3] + s0;
+      C v0 = f[0], v1 = f[st], v2 = f[2 * st], v3 = f[3 * st], v4 = f[4 * st], v5 = f[5 * st];
+      L.p = weno5(v0, v1, v2, v3, v4, eps);
+      R.p = weno5(v5, v4, v3, v2, v1, eps);
+    }
+    if (!(L.r > C(0)) || !(L.p > C(0)) || !(R.r > C(0)) || !(R.p > C(0))) {
+      // positivity fallback: first-order states from the two adjacent cells
+      const int ia = s0 + 2 * st, ib = s0 + 3 * st;
+      L = Prim<C>{w[0][ia], w[cn][ia], w[ct][ia], w[3][ia]};
+      R = Prim<C>{w[0][ib], w[cn][ib], w[ct][ib], w[3][ib]};
+      if (owned) ++my_fallback;
+    }
+    Flux4<C> F = hllc(L, R, gam, igm1);
+    if (VISC) {
+      const int ia = s0 + 2 * st, ib = s0 + 3 * st;
+      const int tt = isx ? PX : 1;  // tangential LDS stride
+      const C dn = C(isx ? a.dx : a.dy), dtn = C(isx ? a.dy : a.dx);
+      const C mu = C(a.mu), kap = C(a.kappa);
+      const C un_n = (w[cn][ib] - w[cn][ia]) / dn;
+      const C ut_n = (w[ct][ib] - w[ct][ia]) / dn;
+      const C T_n = (w[3][ib] / w[0][ib] - w[3][ia] / w[0][ia]) / dn;
+      const C un_t = (w[cn][ia + tt] - w[cn][ia - tt] + w[cn][ib + tt] - w[cn][ib - tt]) / (C(4) * dtn);
+      const C ut_t = (w[ct][ia + tt] - w[ct][ia - tt] + w[ct][ib + tt] - w[ct][ib - tt]) / (C(4) * dtn);
+      const C tnn = mu * (C(4.0 / 3.0) * un_n - C(2.0 / 3.0) * ut_t);
+      const C tnt = mu * (un_t + ut_n);
+      const C qn = -kap * T_n;
+      const C ubn = C(0.5) * (w[cn][ia] + w[cn][ib]);
+      const C ubt = C(0.5) * (w[ct][ia] + w[ct][ib]);
+      F.f1 = F.f1 - tnn;
+      F.f2 = F.f2 - tnt;
+      F.f3 = F.f3 - (ubn * tnn + ubt * tnt - qn);
+    }
+    if (isx) {
+      fxs[0][oidx] = F.f0; fxs[1][oidx] = F.f1; fxs[2][oidx] = F.f2; fxs[3][oidx] = F.f3;
+    } else {
+      fys[0][oidx] = F.f0; fys[1][oidx] = F.f2; fys[2][oidx] = F.f1; fys[3][oidx] = F.f3;
+    }
+  }
+  if (my_fallback) atomicAdd(&blk_fallback, my_fallback);
+  __syncthreads();
+
+  // 3. flux difference and Runge-Kutta combination
+  const C idx = C(a.inv_dx), idy = C(a.inv_dy);
+  const S* __restrict__ Unb = Un + boff;
+  S* __restrict__ Ob = Uout + boff;
+  bool bad = false;
+  for (int k = threadIdx.x; k < TX * TY; k += NT) {
+    const int x = k % TX, y = k / TX;
+    const int gi = i0 + x, gj = j0 + y;
+    if (gi >= a.nx || gj >= a.ny) continue;
+    const long long cell = (long long)gj * a.nx + gi;
+    C Lv[4];
+    for (int v = 0; v < 4; ++v) {
+      C r = -(fxs[v][y * (TX + 1) + x + 1] - fxs[v][y * (TX + 1) + x]) * idx;
+      if (NDIM == 2) r = r - (fys[v][(y + 1) * TX + x] - fys[v][y * TX + x]) * idy;
+      Lv[v] = r;
+    }
+    if (a.nu_art != 0.0) {
+      C c0[4], xm[4], xp[4];
+      load_cons<S, C, NDIM>(a, Ub, gi, gj, c0);
+      load_cons<S, C, NDIM>(a, Ub, gi - 1, gj, xm);
+      load_cons<S, C, NDIM>(a, Ub, gi + 1, gj, xp);
+      const C nu = C(a.nu_art);
+      for (int v = 0; v < 4; ++v) {
+        C lap = (xp[v] - C(2) * c0[v] + xm[v]) * (idx * idx);
+        if (NDIM == 2) {
+          C ym[4], yp[4];
+          load_cons<S, C, NDIM>(a, Ub, gi, gj - 1, ym);
+          load_cons<S, C, NDIM>(a, Ub, gi, gj + 1, yp);
+          lap = lap + (yp[v] - C(2) * c0[v] + ym[v]) * (idy * idy);
+        }
+        Lv[v] = Lv[v] + nu * lap;
+      }
+    }
+    if (a.cls != nullptr && a.cls[cell] != CELL_FLUID) {
+      for (int v = 0; v < 4; ++v) Lv[v] = C(0);
+    }
+    for (int e = 0; e < a.nvar; ++e) {
+      const int v = (NDIM == 1 && e == 2) ? 3 : e;
+      const long long o = (long long)e * a.ncell + cell;
+      C out;
+      if (MODE == MODE_RHS) {
+        out = Lv[v];
+      } else if (MODE == MODE_STAGE1) {
+        out = C(Ub[o]) + C(dt) * Lv[v];
+      } else if (MODE == MODE_STAGE2) {
+        out = C(0.75) * C(Unb[o]) + C(0.25) * C(Ub[o]) + C(0.25 * dt) * Lv[v];
+      } else {
+        out = C(1.0 / 3.0) * C(Unb[o]) + C(2.0 / 3.0) * C(Ub[o]) + C((2.0 / 3.0) * dt) * Lv[v];
+      }
+      bad = bad || !finite_val(out);
+      Ob[o] = S(out);
+    }
+  }
+  if (bad) atomicOr(&blk_fault, 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (blk_fallback) {
+      atomicAdd(&a.glob->fallbacks, (unsigned long long)blk_fallback);
+      atomicOr(&a.glob->fault, 2u);
+    }
+    if (blk_fault) atomicOr(&a.glob->fault, blk_fault);
+  }
+}
+
+// ------------------------------------------------------------ CFL kernel
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Max over fluid cells of (|u|+a)/dx + (|v|+a)/dy and min density, reduced
+// exactly (max/min are order-free; the double bit patterns of non-negative
+// values order like unsigned integers), then the last block turns it into
+// the step: dt = cfl / max, the explicit viscous limit, and the shortening
+// that lands on t_end.  Arithmetic follows the written order without
+// contraction so the step is reproducible bit for bit.
+template <class S>
+__global__ void __launch_bounds__(256) cfl_kernel(GridArgs a, const S* __restrict__ U,
+                                                  double* __restrict__ dt_out) {
+#pragma clang fp contract(off)
+  __shared__ double red_s[4], red_r[4];
+  __shared__ bool is_last;
+  const int b = blockIdx.y;
+  const S* Ub = U + (long long)b * a.nvar * a.ncell;
+  double smax = 0.0, rmin = INFINITY;
+  const double g = a.gamma;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell;
+       c += (long long)gridDim.x * blockDim.x) {
+    if (a.cls != nullptr && a.cls[c] != CELL_FLUID) continue;
+    double r = double(Ub[c]);
+    double u = double(Ub[a.ncell + c]) / r;
+    double v = a.ndim == 2 ? double(Ub[2 * a.ncell + c]) / r : 0.0;
+    double E = double(Ub[(a.nvar - 1) * a.ncell + c]);
+    double p = (g - 1.0) * (E - 0.5 * r * (u * u + v * v));
+    double cs = sqrt(g * p / r);
+    double s = (fabs(u) + cs) / a.dx;
+    if (a.ndim == 2) s = s + (fabs(v) + cs) / a.dy;
+    smax = fmax(smax, s);
+    rmin = fmin(rmin, r);
+  }
+  smax = wave_max(smax);
+  rmin = wave_min(rmin);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) { red_s[wid] = smax; red_r[wid] = rmin; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = red_s[0], r = red_r[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) { s = fmax(s, red_s[k]); r = fmin(r, red_r[k]); }
+    StepScalars* sc = a.sc + b;
+    atomicMax(&sc->smax_bits, (unsigned long long)__double_as_longlong(s));
+    atomicMin(&sc->rmin_bits, (unsigned long long)__double_as_longlong(r));
+    __threadfence();
+    unsigned int prev = atomicAdd(&sc->blocks_done, 1u);
+    is_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (is_last && threadIdx.x == 0) {
+    __threadfence();
+    StepScalars* sc = a.sc + b;
+    const double sm = __longlong_as_double((long long)atomicAdd(&sc->smax_bits, 0ull));
+    const double rm = __longlong_as_double((long long)atomicAdd(&sc->rmin_bits, 0ull));
+    double dt = a.cfl / sm;
+    if (a.viscous && a.mu > 0.0) {
+      const double h = a.ndim == 2 ? fmin(a.dx, a.dy) : a.dx;
+      const double dv = 0.25 * h * h * rm / (a.mu * fmax(4.0 / 3.0, a.gamma / a.prandtl));
+      dt = fmin(dt, dv);
+    }
+    const double t = sc->t;
+    if (sc->done) {
+      dt = 0.0;
+    } else if (t + dt >= sc->t_end) {
+      dt = sc->t_end - t;
+      sc->t = sc->t_end;
+      sc->done = 1;
+    } else {
+      sc->t = t + dt;
+    }
+    sc->dt = dt;
+    if (dt > 0.0) sc->nsteps = sc->nsteps + 1;
+    a.dtbuf[b] = dt;
+    if (dt_out) dt_out[b] = dt;
+    atomicExch(&sc->smax_bits, 0ull);
+    atomicExch(&sc->rmin_bits, (unsigned long long)__double_as_longlong(INFINITY));
+    atomicExch(&sc->blocks_done, 0u);
+  }
+}
+
+__global__ void init_scalars_kernel(GridArgs a, double t0, double t_end) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < a.nbatch) {
+    StepScalars* sc = a.sc + b;
+    sc->dt = 0.0;
+    sc->t = t0;
+    sc->t_end = t_end;
+    sc->smax_bits = 0ull;
+    sc->rmin_bits = (unsigned long long)__double_as_longlong(INFINITY);
+    sc->done = t0 >= t_end ? 1 : 0;
+    sc->blocks_done = 0u;
+    sc->nsteps = 0;
+    a.dtbuf[b] = 0.0;
+  }
+  if (b == 0) {
+    a.glob->fault = 0u;
+    a.glob->fallbacks = 0ull;
+  }
+}
+
+// E = p/(gamma-1) + rho (u^2+v^2)/2 as written (no contraction), so that a
+// state built here is bit-identical to one built by any IEEE evaluation of
+// the same expression.
+template <class S>
+__global__ void __launch_bounds__(256) prim_to_cons_kernel(GridArgs a, const S* __restrict__ W,
+                                                           S* __restrict__ U) {
+#pragma clang fp contract(off)
+  const long long n = a.ncell;
+  const long long total = n * a.nbatch;
+  const double igm = a.gamma - 1.0;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+       k += (long long)gridDim.x * blockDim.x) {
+    const long long b = k / n, c = k - b * n;
+    const S* Wb = W + b * a.nvar * n;
+    S* Ub = U + b * a.nvar * n;
+    double r = double(Wb[c]), u = double(Wb[n + c]);
+    double v = a.ndim == 2 ? double(Wb[2 * n + c]) : 0.0;
+    double p = double(Wb[(a.nvar - 1) * n + c]);
+    double E = p / igm + 0.5 * r * (u * u + v * v);
+    Ub[c] = S(r);
+    Ub[n + c] = S(r * u);
+    if (a.ndim == 2) Ub[2 * n + c] = S(r * v);
+    Ub[(a.nvar - 1) * n + c] = S(E);
+  }
+}
+
+// --------------------------------------------------------------- launchers
+static inline unsigned int blocks_for(long long n, int per) {
+  long long b = (n + per - 1) / per;
+  if (b > 65535LL * 16) b = 65535LL * 16;
+  return (unsigned int)(b < 1 ? 1 : b);
+}
+
+template <class S>
+hipError_t launch_prim_to_cons(const GridArgs& a, const S* W, S* U, hipStream_t st) {
+  hipLaunchKernelGGL(prim_to_cons_kernel<S>, dim3(blocks_for(a.ncell * a.nbatch, 256)), dim3(256), 0, st,
+                     a, W, U);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_cfl(const GridArgs& a, const S* U, double* dt_out, hipStream_t st) {
+  // enough blocks to cover the chip, each thread then strides
+  unsigned int nb = blocks_for(a.ncell, 256 * 4);
+  if (nb > 2048) nb = 2048;
+  hipLaunchKernelGGL(cfl_kernel<S>, dim3(nb, a.nbatch), dim3(256), 0, st, a, U, dt_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_scalars(const GridArgs& a, double t0, double t_end, hipStream_t st) {
+  hipLaunchKernelGGL(init_scalars_kernel, dim3((a.nbatch + 63) / 64), dim3(64), 0, st, a, t0, t_end);
+  return hipGetLastError();
+}
+
+// 2D tile shape (cells); chosen for 256 threads and a halo overhead near 2x.
+constexpr int TX2 = 32, TY2 = 8;
+constexpr int TX1 = 256;
+
+template <class S, class C, int MODE>
+static hipError_t launch_mode(const GridArgs& a, const S* Us, const S* Un, S* Uo, const double* dtp,
+                              hipStream_t st) {
+  if (a.ndim == 1) {
+    dim3 grid((a.nx + TX1 - 1) / TX1, 1, a.nbatch);
+    hipLaunchKernelGGL((stage_kernel<S, C, 1, TX1, 1, false, MODE>), grid, dim3(256), 0, st, a, Us, Un, Uo,
+                       dtp);
+  } else {
+    dim3 grid((a.nx + TX2 - 1) / TX2, (a.ny + TY2 - 1) / TY2, a.nbatch);
+    if (a.viscous)
+      hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, true, MODE>), grid, dim3(256), 0, st, a, Us, Un,
+                         Uo, dtp);
+    else
+      hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, false, MODE>), grid, dim3(256), 0, st, a, Us, Un,
+                         Uo, dtp);
+  }
+  return hipGetLastError();
+}
+
+template <class S, class C>
+static hipError_t launch_stage_c(const GridArgs& a, int mode, const S* Us, const S* Un, S* Uo,
+                                 const double* dtp, hipStream_t st) {
+  switch (mode) {
+    case MODE_RHS: return launch_mode<S, C, MODE_RHS>(a, Us, Un, Uo, dtp, st);
+    case MODE_STAGE1: return launch_mode<S, C, MODE_STAGE1>(a, Us, Un, Uo, dtp, st);
+    case MODE_STAGE2: return launch_mode<S, C, MODE_STAGE2>(a, Us, Un, Uo, dtp, st);
+    default: return launch_mode<S, C, MODE_STAGE3>(a, Us, Un, Uo, dtp, st);
+  }
+}
+
+// double storage: double arithmetic.  float storage: float arithmetic unless
+// mixed (then double arithmetic).
+hipError_t launch_stage_mixed(const GridArgs& a, int mode, const float* Us, const float* Un, float* Uo,
+                              const double* dtp, hipStream_t st) {
+  return launch_stage_c<float, double>(a, mode, Us, Un, Uo, dtp, st);
+}
+
+template <>
+hipError_t launch_stage<double>(const GridArgs& a, int mode, const double* Us, const double* Un, double* Uo,
+                                const double* dtp, hipStream_t st) {
+  return launch_stage_c<double, double>(a, mode, Us, Un, Uo, dtp, st);
+}
+template <>
+hipError_t launch_stage<float>(const GridArgs& a, int mode, const float* Us, const float* Un, float* Uo,
+                               const double* dtp, hipStream_t st) {
+  return launch_stage_c<float, float>(a, mode, Us, Un, Uo, dtp, st);
+}
+
+template hipError_t launch_prim_to_cons<double>(const GridArgs&, const double*, double*, hipStream_t);
+template hipError_t launch_prim_to_cons<float>(const GridArgs&, const float*, float*, hipStream_t);
+template hipError_t launch_cfl<double>(const GridArgs&, const double*, double*, hipStream_t);
+template hipError_t launch_cfl<float>(const GridArgs&, const float*, double*, hipStream_t);
+
+}  // namespace shk

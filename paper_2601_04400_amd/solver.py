@@ -1,0 +1,176 @@
+"""Python face of libshk: a Grid owns a torch-allocated workspace and calls
+the C ABI with raw device pointers on torch's current HIP stream.  Argument
+marshalling only -- every step of the computation runs in the HIP kernels.
+"""
+import ctypes
+
+import torch
+
+from ._lib import GridDesc, check, lib
+
+F64, F32, MIXED = 0, 1, 2
+TRANSMISSIVE, REFLECTIVE, INFLOW, PERIODIC = 0, 1, 2, 3
+_PREC = {"f64": F64, "f32": F32, "mixed": MIXED, F64: F64, F32: F32, MIXED: MIXED}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Grid:
+    """A uniform grid with its physics, boundary rules and workspace."""
+
+    def __init__(self, nx, ny=1, ndim=2, nbatch=1, domain=(0.0, 1.0, 0.0, 1.0), prec="f64", gamma=1.4,
+                 cfl=0.5, weno_eps=1e-6, viscous=False, mu=0.0, prandtl=0.72, nu_art=0.0,
+                 bc=(TRANSMISSIVE,) * 4, inflow=(1.0, 0.0, 0.0, 1.0), ibm=False, adjoint=False,
+                 device="cuda"):
+        d = GridDesc()
+        d.ndim, d.nx, d.ny, d.nbatch = ndim, nx, (1 if ndim == 1 else ny), nbatch
+        d.x0, d.x1 = domain[0], domain[1]
+        d.y0, d.y1 = (domain[2], domain[3]) if ndim == 2 else (0.0, 1.0)
+        d.prec = _PREC[prec]
+        d.gamma, d.cfl, d.weno_eps = gamma, cfl, weno_eps
+        d.viscous, d.mu, d.prandtl, d.nu_art = int(viscous), mu, prandtl, nu_art
+        for k in range(4):
+            d.bc[k] = bc[k]
+            d.inflow_prim[k] = inflow[k]
+        d.ibm, d.adjoint = int(ibm), int(adjoint)
+        self.desc = d
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if d.prec == F64 else torch.float32
+        self.nvar = 3 if ndim == 1 else 4
+        self.shape = (nbatch, self.nvar, d.ny, nx)
+        nbytes = lib().shk_workspace_bytes(ctypes.byref(d))
+        if nbytes == 0:
+            raise ValueError("invalid grid description")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws = self.workspace[off:off + nbytes]
+        h = ctypes.c_void_p()
+        check(lib().shk_init_grid(ctypes.byref(d), _ptr(self._ws), nbytes, _stream(), ctypes.byref(h)),
+              None, "init_grid")
+        self.handle = h
+        self.phi = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib().shk_destroy(h)
+            self.handle = None
+
+    # -- helpers
+    def _sync_stream(self):
+        check(lib().shk_set_stream(self.handle, _stream()), self.handle, "set_stream")
+
+    def _check_state(self, U):
+        if not (U.is_cuda and U.dtype == self.dtype and U.is_contiguous() and U.numel() == self._numel()):
+            raise ValueError(f"state must be a contiguous {self.dtype} CUDA tensor with {self._numel()} elements")
+
+    def _numel(self):
+        b, v, ny, nx = self.shape
+        return b * v * ny * nx
+
+    def empty_state(self):
+        return torch.empty(self.shape, dtype=self.dtype, device=self.device)
+
+    # -- ABI calls
+    def prim_to_cons(self, W):
+        W = W.to(device=self.device, dtype=self.dtype).contiguous().reshape(self.shape)
+        U = self.empty_state()
+        self._sync_stream()
+        check(lib().shk_prim_to_cons(self.handle, _ptr(W), _ptr(U)), self.handle, "prim_to_cons")
+        return U
+
+    def set_levelset(self, phi, wall=0):
+        if phi is None:
+            check(lib().shk_set_ib_levelset(self.handle, None, 0), self.handle, "set_ib_levelset")
+            self.phi = None
+            return 0
+        phi = phi.to(device=self.device, dtype=torch.float64).contiguous()
+        if phi.numel() != self.desc.nx * self.desc.ny:
+            raise ValueError("level set must have ny*nx entries")
+        self.phi = phi  # the table is built from it; keep it alive
+        self._sync_stream()
+        check(lib().shk_set_ib_levelset(self.handle, _ptr(phi), int(wall)), self.handle, "set_ib_levelset")
+        n = ctypes.c_int()
+        check(lib().shk_ib_ghost_count(self.handle, ctypes.byref(n)), self.handle, "ib_ghost_count")
+        return n.value
+
+    def classes(self):
+        c = torch.empty((self.desc.ny, self.desc.nx), dtype=torch.uint8, device=self.device)
+        self._sync_stream()
+        check(lib().shk_ib_classes(self.handle, _ptr(c)), self.handle, "ib_classes")
+        return c
+
+    def rhs(self, U, out=None):
+        self._check_state(U)
+        out = self.empty_state() if out is None else out
+        self._sync_stream()
+        check(lib().shk_rhs(self.handle, _ptr(U), _ptr(out)), self.handle, "rhs")
+        return out
+
+    def step(self, U, dt=None, dt_out=None):
+        """One SSP-RK3 step in place; dt: None (automatic CFL step), a float
+        or a CUDA float64 tensor of nbatch entries."""
+        self._check_state(U)
+        if dt is not None and not torch.is_tensor(dt):
+            dt = torch.full((self.shape[0],), float(dt), dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        check(lib().shk_rk3_step(self.handle, _ptr(U), _ptr(dt), _ptr(dt_out)), self.handle, "rk3_step")
+        return U
+
+    def set_time(self, t0, t_end):
+        self._sync_stream()
+        check(lib().shk_set_time(self.handle, float(t0), float(t_end)), self.handle, "set_time")
+
+    def get_time(self, b=0):
+        t, done, steps = ctypes.c_double(), ctypes.c_int(), ctypes.c_int()
+        self._sync_stream()
+        check(lib().shk_get_time(self.handle, b, ctypes.byref(t), ctypes.byref(done), ctypes.byref(steps)),
+              self.handle, "get_time")
+        return t.value, bool(done.value), steps.value
+
+    def advance(self, U, t_end, t0=0.0, max_steps=10 ** 7, chunk=64):
+        """Automatic-step RK3 from t0 until every batch member reaches t_end
+        (steps after the end are no-ops on the device).  Returns the device
+        (t, steps) of batch member 0."""
+        self.set_time(t0, t_end)
+        issued = 0
+        while issued < max_steps:
+            n = min(chunk, max_steps - issued)
+            for _ in range(n):
+                self.step(U)
+            issued += n
+            done = all(self.get_time(b)[1] for b in range(self.shape[0]))
+            if done:
+                break
+        t, _, steps = self.get_time(0)
+        return t, steps
+
+    def profile(self, enable=True):
+        check(lib().shk_profile(self.handle, int(enable)), self.handle, "profile")
+
+    def profile_read(self):
+        """{kernel class: (total ms, launches)} for cfl, stage1..3, ghost_fill."""
+        ms, cnt = (ctypes.c_double * 5)(), (ctypes.c_int * 5)()
+        check(lib().shk_profile_read(self.handle, ms, cnt), self.handle, "profile_read")
+        names = ("cfl", "stage1", "stage2", "stage3", "ghost_fill")
+        return {n: (ms[k], cnt[k]) for k, n in enumerate(names)}
+
+    def poll_faults(self):
+        f, n = ctypes.c_uint32(), ctypes.c_uint64()
+        self._sync_stream()
+        check(lib().shk_poll_faults(self.handle, ctypes.byref(f), ctypes.byref(n)), self.handle, "poll_faults")
+        return f.value, n.value
+
+
+def normal_shock_state(mach, gamma=1.4, rho1=1.4, p1=1.0):
+    """(rho2, u2, p2) behind a Mach-`mach` shock into gas at rest, with the
+    derivatives with respect to mach and gamma (host computation in libshk)."""
+    out, dM, dg = (ctypes.c_double * 3)(), (ctypes.c_double * 3)(), (ctypes.c_double * 3)()
+    check(lib().shk_normal_shock_state(mach, gamma, rho1, p1, out, dM, dg), None, "normal_shock_state")
+    return list(out), list(dM), list(dg)
