@@ -44,14 +44,13 @@ def cpu_info():
     return model, os.cpu_count()
 
 
-def cpu_baseline(n, budget_s):
+def cpu_baseline(nx, ny, budget_s):
     """The oracle (serial FP64 C++), timed on a bounded number of RK3 steps of
     the same problem from the same initial state."""
-    import numpy as np
     import oracle
     from paper_2601_04400_amd import inputs
-    c = oracle.config(nx=n, ny=n)
-    U = oracle.prim_to_cons(c, inputs.riemann2d_prim(n, n))
+    c = oracle.config(nx=nx, ny=ny)
+    U = oracle.prim_to_cons(c, inputs.riemann2d_prim(nx, ny))
     t0 = time.perf_counter()
     U1, _, s1, _ = oracle.run(c, U, 1e30, max_steps=1)
     one = time.perf_counter() - t0
@@ -60,8 +59,8 @@ def cpu_baseline(n, budget_s):
     _, _, s, _ = oracle.run(c, U, 1e30, max_steps=steps)
     el = time.perf_counter() - t0
     model, ncpu = cpu_info()
-    return {"value": n * n * s / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{s} automatic RK3 steps of the {n}x{n} four-quadrant problem from t=0 "
+    return {"value": nx * ny * s / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{s} automatic RK3 steps of the {nx}x{ny} four-quadrant problem from t=0 "
                       f"({el:.1f} s, serial FP64 oracle, 1 thread of {ncpu} on '{model}')"}
 
 
@@ -70,7 +69,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--n", type=int, default=512, help="cells per side")
+    ap.add_argument("--nx", type=int, default=512, help="cells along x")
+    ap.add_argument("--ny", type=int, default=512, help="cells along y")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
+                    help="instead: time a plain device copy of MB megabytes (counter calibration)")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "mixed"])
     ap.add_argument("--graph", action="store_true", help="replay the timed steps from a HIP graph")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
@@ -86,10 +88,27 @@ def main():
     import torch
     from paper_2601_04400_amd import Grid, inputs
 
-    n, K, W = args.n, args.steps, args.warmup
-    g = Grid(n, n, prec=args.prec)
-    U = g.prim_to_cons(torch.from_numpy(inputs.riemann2d_prim(n, n)))
-    g.set_time(0.0, 1e30)
+    if args.copy_probe:
+        nbytes = args.copy_probe * 2 ** 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes,
+                          "copies": args.steps, "GB_per_s": 2 * nbytes * args.steps / el / 1e9}), flush=True)
+        return
+
+    nx, ny, K, W = args.nx, args.ny, args.steps, args.warmup
+    n2 = nx * ny
+    g = Grid(nx, ny, prec=args.prec)
+    U = g.prim_to_cons(torch.from_numpy(inputs.riemann2d_prim(nx, ny)))
+    g.set_time(0.0, 1e30)  # no end time inside the run: every step is a full step
     for _ in range(W):
         g.step(U)
     torch.cuda.synchronize()
@@ -118,7 +137,7 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms_per_step = el * 1e3 / K
-    value = n * n * K / el
+    value = n2 * K / el
 
     # pass B: the same K steps with HIP events around every kernel
     g.profile(True)
@@ -131,9 +150,9 @@ def main():
     esize = 8 if args.prec == "f64" else 4
     stage_ms = sum(prof[k][0] for k in ("stage1", "stage2", "stage3")) / K
     launches = sum(prof[k][1] for k in ("stage1", "stage2", "stage3"))
-    bytes_step = WORDS_PER_CELL_STEP * esize * n * n
+    bytes_step = WORDS_PER_CELL_STEP * esize * n2
     gbs = bytes_step / (stage_ms * 1e-3) / 1e9
-    tflops = 3 * FLOPS_PER_CELL_STAGE * n * n / (stage_ms * 1e-3) / 1e12
+    tflops = 3 * FLOPS_PER_CELL_STAGE * n2 / (stage_ms * 1e-3) / 1e12
     fpeak = FP64_PEAK_TFLOPS if args.prec in ("f64", "mixed") else FP32_PEAK_TFLOPS
     hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
@@ -150,16 +169,16 @@ def main():
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.prec, "data": "synthetic",
-        "config": {"workload": f"2D Euler four-quadrant Riemann problem {n}x{n} on [0,1]^2, gamma 1.4, "
+        "config": {"workload": f"2D Euler four-quadrant Riemann problem {nx}x{ny} on [0,1]^2, gamma 1.4, "
                                "seeded +-5% quadrant states, transmissive, WENO5-JS+HLLC, SSP-RK3, CFL 0.5",
-                   "nx": n, "ny": n, "prec": args.prec, "graph": bool(args.graph)},
+                   "nx": nx, "ny": ny, "prec": args.prec, "graph": bool(args.graph)},
         "hbm_frac_of_peak": round(bytes_step * K / el / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roof,
         "kernel_ms": {k: round(v[0] / max(v[1], 1), 5) for k, v in prof.items() if v[1]},
         "faults": {"flags": flags, "fallback_faces": fb},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(nx, ny, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

@@ -20,7 +20,7 @@ using namespace shk;
 #pragma clang fp contract(off)
 
 struct WsLayout {
-  size_t scalars, globals, dtbuf, u1, u2, cls, row_count, row_off, g_cell, g_src, g_w, g_nrm;
+  size_t scalars, globals, dtbuf, xslots, u1, u2, cls, row_count, row_off, g_cell, g_src, g_w, g_nrm;
   size_t adj[8];
   size_t total;
 };
@@ -87,6 +87,7 @@ WsLayout layout(const shk_grid_desc* d) {
   L.scalars = o; o += al(sizeof(StepScalars) * d->nbatch);
   L.globals = o; o += al(sizeof(Globals));
   L.dtbuf = o; o += al(sizeof(double) * d->nbatch);
+  L.xslots = o; o += al(sizeof(unsigned long long) * 2 * XSLOTS * d->nbatch);
   L.u1 = o; o += al(state);
   L.u2 = o; o += al(state);
   if (d->ibm) {
@@ -134,23 +135,46 @@ hipError_t timed(shk_grid* g, int cls, F&& f) {
 }
 
 template <class S>
-shk_status stage_seq(shk_grid* g, S* U, const double* dtp) {
-  const GridArgs& a = g->a;
+hipError_t stage_launch(shk_grid* g, const GridArgs& a, int mode, const S* Us, const S* Un, S* Uo,
+                        const double* dtp, const S* Lin) {
+  if (g->d.prec == SHK_MIXED)
+    return launch_stage_mixed(a, mode, reinterpret_cast<const float*>(Us), reinterpret_cast<const float*>(Un),
+                              reinterpret_cast<float*>(Uo), dtp, reinterpret_cast<const float*>(Lin), g->st);
+  return launch_stage<S>(a, mode, Us, Un, Uo, dtp, Lin, g->st);
+}
+
+// One SSP-RK3 step.  With a fixed step or an immersed boundary the stages
+// are the plain three (after a separate reduction for the automatic step);
+// otherwise the automatic step is fused into the stages (S1L, S2F, S3F).
+template <class S>
+shk_status stage_seq(shk_grid* g, S* U, const double* dt_in, double* dt_out) {
+  GridArgs a = g->a;
+  a.dt_out = dt_out;
   S* U1 = reinterpret_cast<S*>(g->ws + g->L.u1);
   S* U2 = reinterpret_cast<S*>(g->ws + g->L.u2);
+  hipError_t e;
+  if (!dt_in && !g->ibm_on) {
+    if ((e = timed(g, 1, [&]() { return stage_launch<S>(g, a, MODE_S1L, U, U, U1, nullptr, nullptr); })) != hipSuccess)
+      return hip_check(g, e, "stage 1");
+    if ((e = timed(g, 2, [&]() { return stage_launch<S>(g, a, MODE_S2F, U, U, U2, nullptr, U1); })) != hipSuccess)
+      return hip_check(g, e, "stage 2");
+    if ((e = timed(g, 3, [&]() { return stage_launch<S>(g, a, MODE_S3F, U2, U, U, nullptr, nullptr); })) != hipSuccess)
+      return hip_check(g, e, "stage 3");
+    return SHK_OK;
+  }
+  const double* dtp = dt_in;
+  if (!dt_in) {
+    e = timed(g, 0, [&]() { return launch_cfl<S>(a, U, dt_out, g->st); });
+    if (e != hipSuccess) return hip_check(g, e, "cfl");
+    dtp = a.dtbuf;
+  }
   auto stage = [&](int mode, const S* Us, const S* Un, S* Uo) -> hipError_t {
-    return timed(g, mode, [&]() {
-      if (g->d.prec == SHK_MIXED)
-        return launch_stage_mixed(a, mode, reinterpret_cast<const float*>(Us), reinterpret_cast<const float*>(Un),
-                                  reinterpret_cast<float*>(Uo), dtp, g->st);
-      return launch_stage<S>(a, mode, Us, Un, Uo, dtp, g->st);
-    });
+    return timed(g, mode, [&]() { return stage_launch<S>(g, a, mode, Us, Un, Uo, dtp, nullptr); });
   };
   auto fill = [&](S* X) -> hipError_t {
     if (!g->ibm_on) return hipSuccess;
     return timed(g, 4, [&]() { return launch_ibm_fill<S>(a, g->gt, X, g->st); });
   };
-  hipError_t e;
   if ((e = fill(U)) != hipSuccess) return hip_check(g, e, "ibm fill");
   if ((e = stage(MODE_STAGE1, U, U, U1)) != hipSuccess) return hip_check(g, e, "stage 1");
   if ((e = fill(U1)) != hipSuccess) return hip_check(g, e, "ibm fill");
@@ -216,6 +240,7 @@ shk_status shk_init_grid(const shk_grid_desc* desc, void* workspace, size_t ws_b
   a.sc = reinterpret_cast<StepScalars*>(g->ws + L.scalars);
   a.glob = reinterpret_cast<Globals*>(g->ws + L.globals);
   a.dtbuf = reinterpret_cast<double*>(g->ws + L.dtbuf);
+  a.xslots = reinterpret_cast<unsigned long long*>(g->ws + L.xslots);
   hipError_t e = launch_init_scalars(a, 0.0, std::numeric_limits<double>::infinity(), g->st);
   if (e == hipSuccess) e = hipStreamSynchronize(g->st);
   if (e != hipSuccess) {
@@ -299,16 +324,16 @@ shk_status shk_rhs(shk_grid* g, void* U, void* dUdt) {
     if (g->ibm_on) e = launch_ibm_fill<double>(g->a, g->gt, static_cast<double*>(U), g->st);
     if (e == hipSuccess)
       e = launch_stage<double>(g->a, MODE_RHS, static_cast<double*>(U), static_cast<double*>(U),
-                               static_cast<double*>(dUdt), nullptr, g->st);
+                               static_cast<double*>(dUdt), nullptr, nullptr, g->st);
   } else {
     if (g->ibm_on) e = launch_ibm_fill<float>(g->a, g->gt, static_cast<float*>(U), g->st);
     if (e == hipSuccess) {
       if (g->d.prec == SHK_MIXED)
         e = launch_stage_mixed(g->a, MODE_RHS, static_cast<float*>(U), static_cast<float*>(U),
-                               static_cast<float*>(dUdt), nullptr, g->st);
+                               static_cast<float*>(dUdt), nullptr, nullptr, g->st);
       else
         e = launch_stage<float>(g->a, MODE_RHS, static_cast<float*>(U), static_cast<float*>(U),
-                                static_cast<float*>(dUdt), nullptr, g->st);
+                                static_cast<float*>(dUdt), nullptr, nullptr, g->st);
     }
   }
   return hip_check(g, e, "rhs");
@@ -317,17 +342,8 @@ shk_status shk_rhs(shk_grid* g, void* U, void* dUdt) {
 shk_status shk_rk3_step(shk_grid* g, void* U, const double* dt_in, double* dt_out) {
   if (!g) return SHK_EINVAL;
   if (!U) return fail(g, SHK_EINVAL, "rk3_step: null state");
-  const double* dtp = dt_in;
-  if (!dt_in) {
-    hipError_t e = timed(g, 0, [&]() {
-      return g->esize == 8 ? launch_cfl<double>(g->a, static_cast<const double*>(U), dt_out, g->st)
-                           : launch_cfl<float>(g->a, static_cast<const float*>(U), dt_out, g->st);
-    });
-    if (e != hipSuccess) return hip_check(g, e, "cfl");
-    dtp = g->a.dtbuf;
-  }
-  if (g->esize == 8) return stage_seq<double>(g, static_cast<double*>(U), dtp);
-  return stage_seq<float>(g, static_cast<float*>(U), dtp);
+  if (g->esize == 8) return stage_seq<double>(g, static_cast<double*>(U), dt_in, dt_out);
+  return stage_seq<float>(g, static_cast<float*>(U), dt_in, dt_out);
 }
 
 shk_status shk_set_time(shk_grid* g, double t0, double t_end) {

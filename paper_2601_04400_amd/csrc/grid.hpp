@@ -9,6 +9,7 @@ namespace shk {
 enum : int { BC_TRANS = 0, BC_REFL = 1, BC_INFLOW = 2, BC_PERIODIC = 3 };
 enum : uint8_t { CELL_FLUID = 0, CELL_SOLID = 1, CELL_GHOST = 2 };
 constexpr int HALO = 3;
+constexpr int XSLOTS = 64;  // atomic targets the blocks of one reduction spread over
 
 // Per-batch-member device scalars of the time loop.
 struct alignas(64) StepScalars {
@@ -42,6 +43,8 @@ struct GridArgs {
   const uint8_t* cls;          // cell classes [ny][nx] or nullptr (no IBM)
   StepScalars* sc;             // [nbatch]
   double* dtbuf;               // [nbatch] step of the automatic time stepping
+  double* dt_out;              // optional caller copy of the step (per call)
+  unsigned long long* xslots;  // [nbatch][2][XSLOTS] spread extrema of the fused step
   Globals* glob;
 };
 
@@ -62,7 +65,7 @@ template <class S>
 hipError_t launch_cfl(const GridArgs& a, const S* U, double* dt_out, hipStream_t st);
 template <class S>
 hipError_t launch_stage(const GridArgs& a, int mode, const S* Us, const S* Un, S* Uout,
-                        const double* dtp, hipStream_t st);
+                        const double* dtp, const S* Lin, hipStream_t st);
 hipError_t launch_init_scalars(const GridArgs& a, double t0, double t_end, hipStream_t st);
 template <class S>
 hipError_t launch_ibm_fill(const GridArgs& a, const GhostTable& gt, S* U, hipStream_t st);
@@ -71,9 +74,10 @@ hipError_t launch_ibm_classify(const GridArgs& a, const double* phi, uint8_t* cl
 hipError_t launch_ibm_table(const GridArgs& a, const double* phi, const uint8_t* cls, const int* row_count,
                             int* row_off, GhostTable gt, hipStream_t st);
 hipError_t launch_stage_mixed(const GridArgs& a, int mode, const float* Us, const float* Un, float* Uout,
-                              const double* dtp, hipStream_t st);
+                              const double* dtp, const float* Lin, hipStream_t st);
 
 // stage modes
-enum : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2, MODE_STAGE3 = 3 };
+enum : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2, MODE_STAGE3 = 3,
+             MODE_S1L = 4, MODE_S2F = 5, MODE_S3F = 6 };
 
 }  // namespace shk

@@ -40,9 +40,9 @@ __device__ __forceinline__ int bc_source(int g, int n, int bc_lo, int bc_hi, int
 // Conservative state (rho, m_x, m_y, E) of cell (gi, gj), which may lie in
 // the ghost layers; x rules are applied first, then y rules (a y inflow
 // overrides everything, as for a y-ghost layer filled after the x-ghosts).
-template <class S, class C, int NDIM>
-__device__ __forceinline__ void load_cons(const GridArgs& a, const S* __restrict__ U, int gi, int gj,
-                                          C q[4]) {
+// get(e, c) returns plane e of interior cell c.
+template <class C, int NDIM, class Get>
+__device__ __forceinline__ void load_cons_f(const GridArgs& a, int gi, int gj, Get&& get, C q[4]) {
   int fx = 0, fy = 0;
   const int si = bc_source(gi, a.nx, a.bc[0], a.bc[1], fx);
   int sj = 0;
@@ -52,20 +52,85 @@ __device__ __forceinline__ void load_cons(const GridArgs& a, const S* __restrict
     if (NDIM == 1) q[2] = C(0);
   } else {
     const long long c = (long long)sj * a.nx + si;
+    q[0] = get(0, c);
+    q[1] = get(1, c);
     if (NDIM == 2) {
-      q[0] = C(U[c]);
-      q[1] = C(U[a.ncell + c]);
-      q[2] = C(U[2 * a.ncell + c]);
-      q[3] = C(U[3 * a.ncell + c]);
+      q[2] = get(2, c);
+      q[3] = get(3, c);
     } else {
-      q[0] = C(U[c]);
-      q[1] = C(U[a.ncell + c]);
       q[2] = C(0);
-      q[3] = C(U[2 * a.ncell + c]);
+      q[3] = get(2, c);
     }
     if (fx & 1) q[1] = -q[1];
   }
   if (fy & 1) q[2] = -q[2];
+}
+
+template <class S, class C, int NDIM>
+__device__ __forceinline__ void load_cons(const GridArgs& a, const S* __restrict__ U, int gi, int gj,
+                                          C q[4]) {
+  load_cons_f<C, NDIM>(a, gi, gj, [&](int e, long long c) { return C(U[e * a.ncell + c]); }, q);
+}
+
+// Automatic step from the reduced maxima of a batch member (dt = cfl / max
+// wave-speed sum, explicit viscous limit, shortened to land on t_end; 0 once
+// t_end was reached).  *last tells whether this step reaches t_end.  Evaluated
+// as written, without contraction, so every caller gets the same bits.
+__device__ __forceinline__ double step_dt(const GridArgs& a, const StepScalars* sc, double sm,
+                                                    double rm, bool* last) {
+#pragma clang fp contract(off)
+  *last = false;
+  if (sc->done) return 0.0;
+  double dt = a.cfl / sm;
+  if (a.viscous && a.mu > 0.0) {
+    const double h = a.ndim == 2 ? fmin(a.dx, a.dy) : a.dx;
+    const double dv = 0.25 * h * h * rm / (a.mu * fmax(4.0 / 3.0, a.gamma / a.prandtl));
+    dt = fmin(dt, dv);
+  }
+  if (sc->t + dt >= sc->t_end) {
+    dt = sc->t_end - sc->t;
+    *last = true;
+  }
+  return dt;
+}
+
+__device__ __forceinline__ double bits_to_double(unsigned long long u) { return __longlong_as_double((long long)u); }
+
+// Wave-speed sum (|u|+a)/dx + (|v|+a)/dy of one cell (1D: x term), in double
+// and in written order.
+template <class S>
+__device__ __forceinline__ double wave_speed_sum(const GridArgs& a, const S* __restrict__ U, long long c,
+                                                            double* rho) {
+#pragma clang fp contract(off)
+  const double g = a.gamma;
+  const double r = double(U[c]);
+  const double u = double(U[a.ncell + c]) / r;
+  const double v = a.ndim == 2 ? double(U[2 * a.ncell + c]) / r : 0.0;
+  const double E = double(U[(a.nvar - 1) * a.ncell + c]);
+  const double p = (g - 1.0) * (E - 0.5 * r * (u * u + v * v));
+  const double cs = sqrt(g * p / r);
+  double s = (fabs(u) + cs) / a.dx;
+  if (a.ndim == 2) s = s + (fabs(v) + cs) / a.dy;
+  *rho = r;
+  return s;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Extrema of the fused step, spread over XSLOTS atomic targets per batch
+// member to avoid contention; every wave that calls this reduces all slots.
+__device__ __forceinline__ void read_extrema(const GridArgs& a, int b, double* sm, double* rm) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long* xs = a.xslots + (long long)b * 2 * XSLOTS;
+  *sm = wave_max(bits_to_double(xs[lane]));
+  *rm = wave_min(bits_to_double(xs[XSLOTS + lane]));
 }
 
 template <class C>
@@ -74,10 +139,19 @@ __device__ __forceinline__ bool finite_val(C x) {
 }
 
 // ------------------------------------------------------------ stage kernel
+// Modes: MODE_RHS writes L(U); MODE_STAGE1..3 are the three Shu-Osher stages
+// with the step read from dtp[b].  The fused automatic-step sequence is
+//   MODE_S1L: L0 = L(U^n) (written to Uout) and the block maxima of the
+//             wave-speed sum and minima of the density of U^n;
+//   MODE_S2F: dt from those extrema; U1 = U^n + dt L0 is formed while the
+//             tile is loaded (never stored); writes U2;
+//   MODE_S3F: stage 3 with the step of S2F; one block advances the device
+//             time and clears the extrema for the next step.
 template <class S, class C, int NDIM, int TX, int TY, bool VISC, int MODE>
 __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restrict__ Us,
                                                     const S* __restrict__ Un, S* __restrict__ Uout,
-                                                    const double* __restrict__ dtp) {
+                                                    const double* __restrict__ dtp,
+                                                    const S* __restrict__ Lin) {
   constexpr int NT = 256;
   constexpr int H = HALO;
   constexpr int PX = TX + 2 * H;
@@ -91,19 +165,66 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
   __shared__ C fxs[4][TY * (TX + 1)];
   __shared__ C fys[4][FYR * TX];
   __shared__ unsigned int blk_fallback, blk_fault;
+  __shared__ double red_s[NT / 64], red_r[NT / 64];
 
   const int b = blockIdx.z;
+  StepScalars* sc = a.sc + b;
+  const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
   double dt = 0.0;
-  if (MODE != MODE_RHS) {
+  if (MODE == MODE_STAGE1 || MODE == MODE_STAGE2 || MODE == MODE_STAGE3) {
     dt = dtp[b];
     if (dt == 0.0) return;  // end time reached: the step is a no-op
+  } else if (MODE == MODE_S1L) {
+    if (sc->done) return;
+  } else if (MODE == MODE_S2F) {
+    bool last;
+    double sm, rm;
+    read_extrema(a, b, &sm, &rm);
+    dt = step_dt(a, sc, sm, rm, &last);
+    if (lead) {
+      a.dtbuf[b] = dt;
+      if (a.dt_out) a.dt_out[b] = dt;
+    }
+    if (dt == 0.0) return;
+  } else if (MODE == MODE_S3F) {
+    dt = a.dtbuf[b];
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+      // block 0 advances the device time and clears the extrema
+      double sm, rm;
+      read_extrema(a, b, &sm, &rm);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        bool last;
+        const double d2 = step_dt(a, sc, sm, rm, &last);
+        if (d2 > 0.0) {
+          sc->t = last ? sc->t_end : sc->t + d2;
+          sc->nsteps = sc->nsteps + 1;
+          if (last) sc->done = 1;
+        }
+        sc->dt = d2;
+      }
+      if (threadIdx.x < XSLOTS) {
+        unsigned long long* xs = a.xslots + (long long)b * 2 * XSLOTS;
+        xs[threadIdx.x] = 0ull;
+        xs[XSLOTS + threadIdx.x] = (unsigned long long)__double_as_longlong(INFINITY);
+      }
+    }
+    if (dt == 0.0) return;
   }
   if (threadIdx.x == 0) { blk_fallback = 0; blk_fault = 0; }
   const int i0 = blockIdx.x * TX;
   const int j0 = blockIdx.y * TY;
   const long long boff = (long long)b * a.nvar * a.ncell;
   const S* __restrict__ Ub = Us + boff;
+  const S* __restrict__ Lb = MODE == MODE_S2F ? Lin + boff : nullptr;
   const C gm1 = C(a.gamma - 1.0);
+  const C cdt = C(dt);
+  // stage-1 state formed on the fly (fused sequence), rounded to storage and
+  // evaluated like the stored stage-1 state of the three-stage path
+  auto u1_at = [&](int e, long long c) {
+#pragma clang fp contract(off)
+    return C(S(C(Ub[e * a.ncell + c]) + cdt * C(Lb[e * a.ncell + c])));
+  };
 
   // 1. halo tile of primitives
   for (int k = threadIdx.x; k < PY * PX; k += NT) {
@@ -114,7 +235,10 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     const int gi = i0 + lx - H;
     const int gj = NDIM == 2 ? j0 + ly - H : 0;
     C q[4];
-    load_cons<S, C, NDIM>(a, Ub, gi, gj, q);
+    if (MODE == MODE_S2F)
+      load_cons_f<C, NDIM>(a, gi, gj, u1_at, q);
+    else
+      load_cons<S, C, NDIM>(a, Ub, gi, gj, q);
     Prim<C> p = to_prim(q[0], q[1], q[2], q[3], gm1);
     w[0][k] = p.r;
     w[1][k] = p.un;
@@ -214,7 +338,12 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
   const S* __restrict__ Unb = Un + boff;
   S* __restrict__ Ob = Uout + boff;
   bool bad = false;
+  double smax = 0.0, rmin = INFINITY;
   for (int k = threadIdx.x; k < TX * TY; k += NT) {
+    // Flux difference and stage combination are evaluated as written (no
+    // fused multiply-add), so the fused and the three-stage sequences agree
+    // bit for bit and the association is the oracle's.
+#pragma clang fp contract(off)
     const int x = k % TX, y = k / TX;
     const int gi = i0 + x, gj = j0 + y;
     if (gi >= a.nx || gj >= a.ny) continue;
@@ -227,34 +356,52 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     }
     if (a.nu_art != 0.0) {
       C c0[4], xm[4], xp[4];
-      load_cons<S, C, NDIM>(a, Ub, gi, gj, c0);
-      load_cons<S, C, NDIM>(a, Ub, gi - 1, gj, xm);
-      load_cons<S, C, NDIM>(a, Ub, gi + 1, gj, xp);
+      if (MODE == MODE_S2F) {
+        load_cons_f<C, NDIM>(a, gi, gj, u1_at, c0);
+        load_cons_f<C, NDIM>(a, gi - 1, gj, u1_at, xm);
+        load_cons_f<C, NDIM>(a, gi + 1, gj, u1_at, xp);
+      } else {
+        load_cons<S, C, NDIM>(a, Ub, gi, gj, c0);
+        load_cons<S, C, NDIM>(a, Ub, gi - 1, gj, xm);
+        load_cons<S, C, NDIM>(a, Ub, gi + 1, gj, xp);
+      }
       const C nu = C(a.nu_art);
-      for (int v = 0; v < 4; ++v) {
-        C lap = (xp[v] - C(2) * c0[v] + xm[v]) * (idx * idx);
-        if (NDIM == 2) {
-          C ym[4], yp[4];
+      C ym[4], yp[4];
+      if (NDIM == 2) {
+        if (MODE == MODE_S2F) {
+          load_cons_f<C, NDIM>(a, gi, gj - 1, u1_at, ym);
+          load_cons_f<C, NDIM>(a, gi, gj + 1, u1_at, yp);
+        } else {
           load_cons<S, C, NDIM>(a, Ub, gi, gj - 1, ym);
           load_cons<S, C, NDIM>(a, Ub, gi, gj + 1, yp);
-          lap = lap + (yp[v] - C(2) * c0[v] + ym[v]) * (idy * idy);
         }
+      }
+      for (int v = 0; v < 4; ++v) {
+        C lap = (xp[v] - C(2) * c0[v] + xm[v]) * (idx * idx);
+        if (NDIM == 2) lap = lap + (yp[v] - C(2) * c0[v] + ym[v]) * (idy * idy);
         Lv[v] = Lv[v] + nu * lap;
       }
     }
     if (a.cls != nullptr && a.cls[cell] != CELL_FLUID) {
       for (int v = 0; v < 4; ++v) Lv[v] = C(0);
     }
+    if (MODE == MODE_S1L && (a.cls == nullptr || a.cls[cell] == CELL_FLUID)) {
+      double r;
+      smax = fmax(smax, wave_speed_sum(a, Ub, cell, &r));
+      rmin = fmin(rmin, r);
+    }
     for (int e = 0; e < a.nvar; ++e) {
       const int v = (NDIM == 1 && e == 2) ? 3 : e;
       const long long o = (long long)e * a.ncell + cell;
       C out;
-      if (MODE == MODE_RHS) {
+      if (MODE == MODE_RHS || MODE == MODE_S1L) {
         out = Lv[v];
       } else if (MODE == MODE_STAGE1) {
-        out = C(Ub[o]) + C(dt) * Lv[v];
+        out = C(Ub[o]) + cdt * Lv[v];
       } else if (MODE == MODE_STAGE2) {
         out = C(0.75) * C(Unb[o]) + C(0.25) * C(Ub[o]) + C(0.25 * dt) * Lv[v];
+      } else if (MODE == MODE_S2F) {
+        out = C(0.75) * C(Ub[o]) + C(0.25) * u1_at(e, cell) + C(0.25 * dt) * Lv[v];
       } else {
         out = C(1.0 / 3.0) * C(Unb[o]) + C(2.0 / 3.0) * C(Ub[o]) + C((2.0 / 3.0) * dt) * Lv[v];
       }
@@ -262,9 +409,22 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
       Ob[o] = S(out);
     }
   }
+  if (MODE == MODE_S1L) {
+    smax = wave_max(smax);
+    rmin = wave_min(rmin);
+    if ((threadIdx.x & 63) == 0) { red_s[threadIdx.x >> 6] = smax; red_r[threadIdx.x >> 6] = rmin; }
+  }
   if (bad) atomicOr(&blk_fault, 1u);
   __syncthreads();
   if (threadIdx.x == 0) {
+    if (MODE == MODE_S1L) {
+      double s2 = red_s[0], r2 = red_r[0];
+      for (int k = 1; k < NT / 64; ++k) { s2 = fmax(s2, red_s[k]); r2 = fmin(r2, red_r[k]); }
+      unsigned long long* xs = a.xslots + (long long)b * 2 * XSLOTS;
+      const int slot = (blockIdx.x + blockIdx.y * gridDim.x) & (XSLOTS - 1);
+      atomicMax(&xs[slot], (unsigned long long)__double_as_longlong(s2));
+      atomicMin(&xs[XSLOTS + slot], (unsigned long long)__double_as_longlong(r2));
+    }
     if (blk_fallback) {
       atomicAdd(&a.glob->fallbacks, (unsigned long long)blk_fallback);
       atomicOr(&a.glob->fault, 2u);
@@ -274,14 +434,6 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
 }
 
 // ------------------------------------------------------------ CFL kernel
-__device__ __forceinline__ double wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-  return v;
-}
 
 // Max over fluid cells of (|u|+a)/dx + (|v|+a)/dy and min density, reduced
 // exactly (max/min are order-free; the double bit patterns of non-negative
@@ -292,25 +444,16 @@ __device__ __forceinline__ double wave_min(double v) {
 template <class S>
 __global__ void __launch_bounds__(256) cfl_kernel(GridArgs a, const S* __restrict__ U,
                                                   double* __restrict__ dt_out) {
-#pragma clang fp contract(off)
   __shared__ double red_s[4], red_r[4];
   __shared__ bool is_last;
   const int b = blockIdx.y;
   const S* Ub = U + (long long)b * a.nvar * a.ncell;
   double smax = 0.0, rmin = INFINITY;
-  const double g = a.gamma;
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell;
        c += (long long)gridDim.x * blockDim.x) {
     if (a.cls != nullptr && a.cls[c] != CELL_FLUID) continue;
-    double r = double(Ub[c]);
-    double u = double(Ub[a.ncell + c]) / r;
-    double v = a.ndim == 2 ? double(Ub[2 * a.ncell + c]) / r : 0.0;
-    double E = double(Ub[(a.nvar - 1) * a.ncell + c]);
-    double p = (g - 1.0) * (E - 0.5 * r * (u * u + v * v));
-    double cs = sqrt(g * p / r);
-    double s = (fabs(u) + cs) / a.dx;
-    if (a.ndim == 2) s = s + (fabs(v) + cs) / a.dy;
-    smax = fmax(smax, s);
+    double r;
+    smax = fmax(smax, wave_speed_sum(a, Ub, c, &r));
     rmin = fmin(rmin, r);
   }
   smax = wave_max(smax);
@@ -318,10 +461,10 @@ __global__ void __launch_bounds__(256) cfl_kernel(GridArgs a, const S* __restric
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) { red_s[wid] = smax; red_r[wid] = rmin; }
   __syncthreads();
+  StepScalars* sc = a.sc + b;
   if (threadIdx.x == 0) {
     double s = red_s[0], r = red_r[0];
     for (int k = 1; k < (int)(blockDim.x >> 6); ++k) { s = fmax(s, red_s[k]); r = fmin(r, red_r[k]); }
-    StepScalars* sc = a.sc + b;
     atomicMax(&sc->smax_bits, (unsigned long long)__double_as_longlong(s));
     atomicMin(&sc->rmin_bits, (unsigned long long)__double_as_longlong(r));
     __threadfence();
@@ -331,27 +474,16 @@ __global__ void __launch_bounds__(256) cfl_kernel(GridArgs a, const S* __restric
   __syncthreads();
   if (is_last && threadIdx.x == 0) {
     __threadfence();
-    StepScalars* sc = a.sc + b;
-    const double sm = __longlong_as_double((long long)atomicAdd(&sc->smax_bits, 0ull));
-    const double rm = __longlong_as_double((long long)atomicAdd(&sc->rmin_bits, 0ull));
-    double dt = a.cfl / sm;
-    if (a.viscous && a.mu > 0.0) {
-      const double h = a.ndim == 2 ? fmin(a.dx, a.dy) : a.dx;
-      const double dv = 0.25 * h * h * rm / (a.mu * fmax(4.0 / 3.0, a.gamma / a.prandtl));
-      dt = fmin(dt, dv);
-    }
-    const double t = sc->t;
-    if (sc->done) {
-      dt = 0.0;
-    } else if (t + dt >= sc->t_end) {
-      dt = sc->t_end - t;
-      sc->t = sc->t_end;
-      sc->done = 1;
-    } else {
-      sc->t = t + dt;
+    const double sm = bits_to_double(atomicAdd(&sc->smax_bits, 0ull));
+    const double rm = bits_to_double(atomicAdd(&sc->rmin_bits, 0ull));
+    bool last;
+    const double dt = step_dt(a, sc, sm, rm, &last);
+    if (dt > 0.0) {
+      sc->t = last ? sc->t_end : sc->t + dt;
+      sc->nsteps = sc->nsteps + 1;
+      if (last) sc->done = 1;
     }
     sc->dt = dt;
-    if (dt > 0.0) sc->nsteps = sc->nsteps + 1;
     a.dtbuf[b] = dt;
     if (dt_out) dt_out[b] = dt;
     atomicExch(&sc->smax_bits, 0ull);
@@ -373,6 +505,11 @@ __global__ void init_scalars_kernel(GridArgs a, double t0, double t_end) {
     sc->blocks_done = 0u;
     sc->nsteps = 0;
     a.dtbuf[b] = 0.0;
+    unsigned long long* xs = a.xslots + (long long)b * 2 * XSLOTS;
+    for (int k = 0; k < XSLOTS; ++k) {
+      xs[k] = 0ull;
+      xs[XSLOTS + k] = (unsigned long long)__double_as_longlong(INFINITY);
+    }
   }
   if (b == 0) {
     a.glob->fault = 0u;
@@ -440,50 +577,54 @@ constexpr int TX1 = 256;
 
 template <class S, class C, int MODE>
 static hipError_t launch_mode(const GridArgs& a, const S* Us, const S* Un, S* Uo, const double* dtp,
-                              hipStream_t st) {
+                              const S* Lin, hipStream_t st) {
   if (a.ndim == 1) {
     dim3 grid((a.nx + TX1 - 1) / TX1, 1, a.nbatch);
     hipLaunchKernelGGL((stage_kernel<S, C, 1, TX1, 1, false, MODE>), grid, dim3(256), 0, st, a, Us, Un, Uo,
-                       dtp);
+                       dtp, Lin);
   } else {
     dim3 grid((a.nx + TX2 - 1) / TX2, (a.ny + TY2 - 1) / TY2, a.nbatch);
     if (a.viscous)
       hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, true, MODE>), grid, dim3(256), 0, st, a, Us, Un,
-                         Uo, dtp);
+                         Uo, dtp, Lin);
     else
       hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, false, MODE>), grid, dim3(256), 0, st, a, Us, Un,
-                         Uo, dtp);
+                         Uo, dtp, Lin);
   }
   return hipGetLastError();
 }
 
 template <class S, class C>
 static hipError_t launch_stage_c(const GridArgs& a, int mode, const S* Us, const S* Un, S* Uo,
-                                 const double* dtp, hipStream_t st) {
+                                 const double* dtp, const S* Lin, hipStream_t st) {
   switch (mode) {
-    case MODE_RHS: return launch_mode<S, C, MODE_RHS>(a, Us, Un, Uo, dtp, st);
-    case MODE_STAGE1: return launch_mode<S, C, MODE_STAGE1>(a, Us, Un, Uo, dtp, st);
-    case MODE_STAGE2: return launch_mode<S, C, MODE_STAGE2>(a, Us, Un, Uo, dtp, st);
-    default: return launch_mode<S, C, MODE_STAGE3>(a, Us, Un, Uo, dtp, st);
+    case MODE_RHS: return launch_mode<S, C, MODE_RHS>(a, Us, Un, Uo, dtp, Lin, st);
+    case MODE_STAGE1: return launch_mode<S, C, MODE_STAGE1>(a, Us, Un, Uo, dtp, Lin, st);
+    case MODE_STAGE2: return launch_mode<S, C, MODE_STAGE2>(a, Us, Un, Uo, dtp, Lin, st);
+    case MODE_STAGE3: return launch_mode<S, C, MODE_STAGE3>(a, Us, Un, Uo, dtp, Lin, st);
+    case MODE_S1L: return launch_mode<S, C, MODE_S1L>(a, Us, Un, Uo, dtp, Lin, st);
+    case MODE_S2F: return launch_mode<S, C, MODE_S2F>(a, Us, Un, Uo, dtp, Lin, st);
+    case MODE_S3F: return launch_mode<S, C, MODE_S3F>(a, Us, Un, Uo, dtp, Lin, st);
+    default: return hipErrorInvalidValue;
   }
 }
 
 // double storage: double arithmetic.  float storage: float arithmetic unless
 // mixed (then double arithmetic).
 hipError_t launch_stage_mixed(const GridArgs& a, int mode, const float* Us, const float* Un, float* Uo,
-                              const double* dtp, hipStream_t st) {
-  return launch_stage_c<float, double>(a, mode, Us, Un, Uo, dtp, st);
+                              const double* dtp, const float* Lin, hipStream_t st) {
+  return launch_stage_c<float, double>(a, mode, Us, Un, Uo, dtp, Lin, st);
 }
 
 template <>
 hipError_t launch_stage<double>(const GridArgs& a, int mode, const double* Us, const double* Un, double* Uo,
-                                const double* dtp, hipStream_t st) {
-  return launch_stage_c<double, double>(a, mode, Us, Un, Uo, dtp, st);
+                                const double* dtp, const double* Lin, hipStream_t st) {
+  return launch_stage_c<double, double>(a, mode, Us, Un, Uo, dtp, Lin, st);
 }
 template <>
 hipError_t launch_stage<float>(const GridArgs& a, int mode, const float* Us, const float* Un, float* Uo,
-                               const double* dtp, hipStream_t st) {
-  return launch_stage_c<float, float>(a, mode, Us, Un, Uo, dtp, st);
+                               const double* dtp, const float* Lin, hipStream_t st) {
+  return launch_stage_c<float, float>(a, mode, Us, Un, Uo, dtp, Lin, st);
 }
 
 template hipError_t launch_prim_to_cons<double>(const GridArgs&, const double*, double*, hipStream_t);

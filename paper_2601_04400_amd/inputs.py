@@ -130,3 +130,21 @@ def riemann_batch_states(seeds, rho=(0.1, 1.5), p=(0.1, 1.5), vel=(-1.0, 1.0)):
         S[:, 3] = g.uniform(*p, size=4)
         out.append(S)
     return out
+
+
+def shock_cylinder(nx, ny, post, domain=(0.0, 2.0, 0.0, 1.0), centre=(0.3, 0.5), radius=0.1, xs=0.1,
+                   pre=(1.4, 0.0, 0.0, 1.0)):
+    """Planar normal shock at x = xs moving into gas at rest `pre` towards a
+    circular cylinder.  `post` is the post-shock primitive state (rho, u, v, p)
+    supplied by the caller.  Returns the primitive field, the level set and
+    the boundary rules: inflow (post-shock) on the left, transmissive on the
+    right, reflective walls at the bottom and top (section 3 setup)."""
+    W = shock_prim(nx, ny, domain, xs, post, pre)
+    phi = circle_phi(nx, ny, domain, centre, radius)
+    return dict(W=W, phi=phi, domain=domain, bc=(2, 0, 1, 1), inflow=tuple(post))
+
+
+def cylinder_viscosity(mach, reynolds=1000.0, diameter=0.2, rho1=1.4, a1=1.0):
+    """Dynamic viscosity giving Reynolds number `reynolds` on the cylinder
+    diameter with the pre-shock density and the shock speed M a1."""
+    return rho1 * mach * a1 * diameter / reynolds

@@ -1,0 +1,104 @@
+"""GPU parity of the immersed boundary and the viscous terms against the
+oracle: cell classes and ghost lists bit-exact, right-hand sides to 1e-13,
+trajectories to 1e-11 (per conserved field)."""
+import numpy as np
+import pytest
+
+from paper_2601_04400_amd import inputs
+from gpu_util import assert_fields, make_pair
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def to_np(U):
+    torch.cuda.synchronize()
+    return U.detach().to("cpu", torch.float64).numpy()
+
+
+def setup(orc, nx, ny, mach=3.0, viscous=False, prec="f64", domain=(0.0, 2.0, 0.0, 1.0)):
+    post_o = orc.rh_post_shock(mach)
+    post = (post_o[0], post_o[1], 0.0, post_o[2])
+    sc = inputs.shock_cylinder(nx, ny, post, domain=domain)
+    mu = inputs.cylinder_viscosity(mach) if viscous else 0.0
+    c, g = make_pair(orc, nx, ny, domain=domain, bc=sc["bc"], inflow=sc["inflow"], viscous=viscous,
+                     mu=mu, prec=prec, ibm=True)
+    return c, g, sc
+
+
+def test_classes_and_ghost_count_bitwise(orc):
+    for nx, ny in ((96, 48), (1024, 512), (77, 53)):
+        c, g, sc = setup(orc, nx, ny)
+        ng = g.set_levelset(torch.from_numpy(sc["phi"]), wall=0)
+        cls_o, ng_o = orc.ibm_classify(c, sc["phi"])
+        np.testing.assert_array_equal(g.classes().cpu().numpy(), cls_o)
+        assert ng == ng_o > 0
+
+
+@pytest.mark.parametrize("viscous,wall", [(False, 0), (True, 1), (False, 1), (True, 0)])
+def test_rhs_with_ibm(orc, viscous, wall):
+    nx, ny = 160, 80
+    c, g, sc = setup(orc, nx, ny, viscous=viscous)
+    # a rough state so every ghost interpolation and wall rule matters
+    W = inputs.random_prim(nx, ny, seed=5)
+    Uo = orc.prim_to_cons(c, W)
+    Lo, Ufo, _ = orc.rhs(c, Uo, phi=sc["phi"], wall=wall)
+    g.set_levelset(torch.from_numpy(sc["phi"]), wall=wall)
+    Ug = torch.from_numpy(Uo).to(g.device).reshape(g.shape).contiguous()
+    Lg = to_np(g.rhs(Ug))[0]
+    assert_fields(to_np(Ug)[0], Ufo, 1e-14, "ghost-filled state")
+    assert_fields(Lg, Lo, 1e-13, f"ibm rhs viscous={viscous} wall={wall}")
+
+
+def test_shock_cylinder_ns_trajectory_small(orc):
+    """Mach-3 shock on the cylinder, Navier-Stokes, no-slip adiabatic wall, at
+    160x80, 40 automatic steps (the shock reaches the cylinder)."""
+    nx, ny = 160, 80
+    c, g, sc = setup(orc, nx, ny, viscous=True)
+    Uo = orc.prim_to_cons(c, sc["W"])
+    Ue, te, steps_o, fbo = orc.run(c, Uo, 1.0, max_steps=40, phi=sc["phi"], wall=1)
+    g.set_levelset(torch.from_numpy(sc["phi"]), wall=1)
+    Ug = g.prim_to_cons(torch.from_numpy(sc["W"]))
+    g.set_time(0.0, 1.0)
+    for _ in range(40):
+        g.step(Ug)
+    t, done, steps = g.get_time()
+    assert steps == steps_o == 40 and abs(t - te) <= 1e-14 * te
+    assert_fields(to_np(Ug)[0], Ue, 1e-11, "NS shock-cylinder trajectory")
+    assert g.poll_faults() == (0, 0) and fbo == 0
+
+
+def test_shock_cylinder_ns_full_size_step(orc):
+    """1024x512 (the Navier-Stokes cylinder size): one right-hand side and one
+    automatic step from the initial condition."""
+    nx, ny = 1024, 512
+    c, g, sc = setup(orc, nx, ny, viscous=True)
+    Uo = orc.prim_to_cons(c, sc["W"])
+    g.set_levelset(torch.from_numpy(sc["phi"]), wall=1)
+    Ug = g.prim_to_cons(torch.from_numpy(sc["W"]))
+    Lo, _, _ = orc.rhs(c, Uo, phi=sc["phi"], wall=1)
+    U0 = Ug.clone()
+    assert_fields(to_np(g.rhs(U0))[0], Lo, 1e-13, "1024x512 rhs")
+    dto = orc.cfl_dt(c, Uo, phi=sc["phi"])
+    U1o, _ = orc.rk3_step(c, Uo, dto, phi=sc["phi"], wall=1)
+    dts = torch.zeros(1, dtype=torch.float64, device=g.device)
+    g.set_time(0.0, 1.0)
+    g.step(Ug, dt_out=dts)
+    assert float(dts.cpu()[0]) == dto
+    assert_fields(to_np(Ug)[0], U1o, 1e-13, "1024x512 step")
+
+
+def test_quiescent_cylinder_stays_at_rest_gpu(orc):
+    nx, ny = 96, 96
+    dom = (0.0, 1.0, 0.0, 1.0)
+    phi = inputs.circle_phi(nx, ny, dom, (0.45, 0.52), 0.2)
+    c, g = make_pair(orc, nx, ny, domain=dom, bc=(1, 1, 1, 1), viscous=True, mu=1e-3, ibm=True)
+    W = np.zeros((4, ny, nx)); W[0] = 1.0; W[3] = 1.0
+    g.set_levelset(torch.from_numpy(phi), wall=1)
+    U = g.prim_to_cons(torch.from_numpy(W))
+    g.set_time(0.0, 1.0)
+    for _ in range(10):
+        g.step(U)
+    u = to_np(U)[0]
+    fl = phi >= 0
+    assert np.max(np.abs(u[1][fl])) < 1e-14 and np.max(np.abs(u[2][fl])) < 1e-14
