@@ -64,6 +64,44 @@ def cpu_baseline(nx, ny, budget_s):
                       f"({el:.1f} s, serial FP64 oracle, 1 thread of {ncpu} on '{model}')"}
 
 
+def adjoint_ratio(n=256, steps=200, every=20):
+    """Adjoint:forward cost on the inviscid shock-cylinder sensitivity problem
+    (256^2, 200 fixed steps, checkpoints every 20): wall time of the backward
+    pass (segment replays included) over the forward pass."""
+    import torch
+    from paper_2601_04400_amd import Grid, inputs, normal_shock_state
+    from paper_2601_04400_amd.adjoint import rollout
+    dom = (0.0, 1.0, 0.0, 1.0)
+    phi = inputs.circle_phi(n, n, dom, (0.3, 0.5), 0.1)
+    post, _, _ = normal_shock_state(3.0)
+    inflow = (post[0], post[1], 0.0, post[2])
+    g = Grid(n, n, domain=dom, bc=(2, 0, 1, 1), inflow=inflow, ibm=True, adjoint=True)
+    g.set_levelset(torch.from_numpy(phi), wall=0)
+    U0 = g.prim_to_cons(torch.from_numpy(inputs.shock_prim(n, n, dom, 0.1, inflow, (1.4, 0, 0, 1))))
+    d = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g.set_time(0.0, 1.0)
+    g.step(U0.clone(), dt_out=d)
+    dt = 0.6 * float(d.cpu()[0])
+    params = torch.tensor([[1.4, *inflow]], dtype=torch.float64, device="cuda", requires_grad=True)
+    res = {}
+    for rep in range(2):  # second repetition is the measurement
+        U0.grad = None
+        U0.requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U = rollout(g, U0, params, steps, dt, every)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        U.backward(torch.ones_like(U))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res = {"forward_ms": round((t1 - t0) * 1e3, 3), "backward_ms": round((t2 - t1) * 1e3, 3),
+               "ratio": round((t2 - t1) / (t1 - t0), 3)}
+    res["workload"] = (f"inviscid Mach-3 shock on a cylinder, {n}x{n}, {steps} fixed RK3 steps, "
+                       f"checkpoint every {every}, slip immersed boundary; backward includes segment replays")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +115,7 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay the timed steps from a HIP graph")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint:forward cost measurement")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -177,6 +216,8 @@ def main():
         "kernel_ms": {k: round(v[0] / max(v[1], 1), 5) for k, v in prof.items() if v[1]},
         "faults": {"flags": flags, "fallback_faces": fb},
     }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_ratio()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nx, ny, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -153,6 +153,29 @@ shk_status shk_rhs(shk_grid* g, void* U, void* dUdt);
  * or NULL. */
 shk_status shk_rk3_step(shk_grid* g, void* U, const double* dt_in, double* dt_out);
 
+/* Discrete adjoint of shk_rhs (reverse mode).  The chain rule through the
+ * unrolled solver (section 2, gradient of the unrolled loss through the
+ * solver step S) is built from these vector-Jacobian products.  U: state at
+ * which shk_rhs was evaluated (device, double; it is not modified, the
+ * ghost refill is recomputed on a copy).  dUdt_bar: adjoint of the
+ * right-hand side.  U_bar += (d rhs / d U)^T dUdt_bar, the map including the
+ * immersed-boundary refill and the boundary rules.  param_bar (device,
+ * [nbatch][5]) += derivatives with respect to (gamma, inflow rho, u, v, p).
+ * Every branch is the one the forward evaluation takes; the WENO weights are
+ * differentiated.  Reproducible bit for bit (no atomics in the sums).
+ * Requires desc.adjoint = 1, prec SHK_F64, ndim 2, inviscid, nu_art = 0
+ * (else SHK_ESTATE / SHK_EUNSUPPORTED). */
+shk_status shk_rhs_adjoint(shk_grid* g, const void* U, const void* dUdt_bar, void* U_bar, double* param_bar);
+
+/* Discrete adjoint of one fixed-step SSP-RK3 step.  U_n: the state the step
+ * started from (device, double, not modified); dt: device array of nbatch
+ * steps (treated as constants); U_bar: on entry the adjoint of the state
+ * after the step, on return the adjoint of U_n; param_bar (device,
+ * [nbatch][5]) += parameter derivatives as for shk_rhs_adjoint.  The stage
+ * states are recomputed from U_n in the workspace.  Same requirements as
+ * shk_rhs_adjoint. */
+shk_status shk_rk3_step_adjoint(shk_grid* g, const void* U_n, const double* dt, void* U_bar, double* param_bar);
+
 /* Set the device time of every batch member to t0, the stop time to t_end
  * and the automatic-step counter to 0 (enqueued). */
 shk_status shk_set_time(shk_grid* g, double t0, double t_end);

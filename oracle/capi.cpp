@@ -4,6 +4,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
 
 #include "exact_riemann.hpp"
@@ -218,6 +219,27 @@ int orc_rhs_jvp(const Config* c, const double* U, const double* Udot, double gdo
   return 0;
 }
 
+// Full Jacobian of the RHS by forward mode, one input direction at a time
+// (small grids only): J[out][in] over the external state layout, followed by
+// the columns for gamma and the four inflow primitives (ncols = n + 5).
+int orc_rhs_jacobian(const Config* c, const double* U, const double* phi, int wall, double* J) {
+  if (!config_ok(c)) return 1;
+  const size_t n = size_t(nvar_ext(*c)) * c->nx * c->ny;
+  std::vector<double> Ud(n, 0.0), L(n), Ld(n);
+  const size_t ncol = n + 5;
+  for (size_t col = 0; col < ncol; ++col) {
+    std::fill(Ud.begin(), Ud.end(), 0.0);
+    double gd = 0.0, ind[4] = {0, 0, 0, 0};
+    if (col < n) Ud[col] = 1.0;
+    else if (col == n) gd = 1.0;
+    else ind[col - n - 1] = 1.0;
+    int rc = orc_rhs_jvp(c, U, Ud.data(), gd, ind, phi, wall, L.data(), Ld.data());
+    if (rc) return rc;
+    for (size_t r = 0; r < n; ++r) J[r * ncol + col] = Ld[r];
+  }
+  return 0;
+}
+
 // Tangent of one RK3 step with fixed dt; U and Udot are advanced in place.
 int orc_rk3_step_jvp(const Config* c, double* U, double* Udot, double dt, double gdot,
                      const double* indot, const double* phi, int wall) {
@@ -236,6 +258,28 @@ int orc_rk3_step_jvp(const Config* c, double* U, double* Udot, double dt, double
   rk3_step(*c, P, ib, f, D(dt), nullptr, nullptr);
   store_state(*c, f, Ud.data());
   for (size_t k = 0; k < ne * n; ++k) { U[k] = Ud[k].v; Udot[k] = Ud[k].d[0]; }
+  return 0;
+}
+
+// Full Jacobian of one fixed-dt RK3 step (small grids), same column layout
+// as orc_rhs_jacobian.
+int orc_rk3_step_jacobian(const Config* c, const double* U, double dt, const double* phi, int wall,
+                          double* J) {
+  if (!config_ok(c)) return 1;
+  const size_t n = size_t(nvar_ext(*c)) * c->nx * c->ny;
+  std::vector<double> Uc(n), Ud(n);
+  const size_t ncol = n + 5;
+  for (size_t col = 0; col < ncol; ++col) {
+    std::copy(U, U + n, Uc.begin());
+    std::fill(Ud.begin(), Ud.end(), 0.0);
+    double gd = 0.0, ind[4] = {0, 0, 0, 0};
+    if (col < n) Ud[col] = 1.0;
+    else if (col == n) gd = 1.0;
+    else ind[col - n - 1] = 1.0;
+    int rc = orc_rk3_step_jvp(c, Uc.data(), Ud.data(), dt, gd, ind, phi, wall);
+    if (rc) return rc;
+    for (size_t r = 0; r < n; ++r) J[r * ncol + col] = Ud[r];
+  }
   return 0;
 }
 

@@ -35,6 +35,8 @@ _SIGS = {
     "shk_ib_classes": (_i, [_p, _p]),
     "shk_rhs": (_i, [_p, _p, _p]),
     "shk_rk3_step": (_i, [_p, _p, _p, _p]),
+    "shk_rhs_adjoint": (_i, [_p, _p, _p, _p, _p]),
+    "shk_rk3_step_adjoint": (_i, [_p, _p, _p, _p, _p]),
     "shk_set_time": (_i, [_p, _d, _d]),
     "shk_get_time": (_i, [_p, _i, _p, _p, _p]),
     "shk_poll_faults": (_i, [_p, _p, _p]),

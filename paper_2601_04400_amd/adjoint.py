@@ -1,0 +1,49 @@
+"""Differentiable rollout of the RK3 solver: torch.autograd.Function whose
+backward runs the hand-written discrete adjoint kernels with checkpointing.
+
+Section 2 trains through m unrolled solver steps and infers physical
+parameters by reverse-mode differentiation; here the forward pass keeps a
+copy of the state every `every` steps, and the backward pass replays each
+segment from its checkpoint (recomputing the step-start states) and runs
+shk_rk3_step_adjoint in reverse.  Memory: nsteps/every + every states.
+"""
+import torch
+
+
+class _Rollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U0, params, grid, nsteps, dt, every):
+        U = U0.detach().clone()
+        ckpts = [U.clone()]
+        for s in range(nsteps):
+            grid.step(U, dt)
+            if (s + 1) % every == 0 and s + 1 < nsteps:
+                ckpts.append(U.clone())
+        ctx.grid, ctx.nsteps, ctx.dt, ctx.every = grid, nsteps, dt, every
+        ctx.ckpts = ckpts
+        return U
+
+    @staticmethod
+    def backward(ctx, U_bar):
+        g, dt, every, nsteps = ctx.grid, ctx.dt, ctx.every, ctx.nsteps
+        Ub = U_bar.detach().to(dtype=torch.float64).contiguous().clone()
+        pb = g.param_bar()
+        for c in range(len(ctx.ckpts) - 1, -1, -1):
+            first = c * every
+            count = min(every, nsteps - first)
+            U = ctx.ckpts[c].clone()
+            starts = [U.clone()]
+            for _ in range(count - 1):
+                g.step(U, dt)
+                starts.append(U.clone())
+            for k in range(count - 1, -1, -1):
+                g.step_adjoint(starts[k], dt, Ub, pb)
+        return Ub, pb, None, None, None, None
+
+
+def rollout(grid, U0, params, nsteps, dt, every=20):
+    """U after `nsteps` fixed-dt RK3 steps from U0, differentiable with
+    respect to U0 and `params` = tensor [nbatch, 5] of (gamma, inflow rho, u,
+    v, p).  `params` carries no values into the solver: it must equal the
+    grid's own description and only receives the gradient."""
+    return _Rollout.apply(U0, params, grid, nsteps, dt, every)

@@ -1,0 +1,698 @@
+// Discrete adjoint (reverse mode) of the right-hand side and of the SSP-RK3
+// step, FP64, for gfx950.
+//
+// The chain rule through the unrolled solver (section 2, the gradient of the
+// unrolled loss through the solver steps) needs vector-Jacobian products of
+// one right-hand side, L_bar -> U_bar = (dL/dU)^T L_bar, plus the partial
+// derivatives with respect to gamma and the inflow state.  They are written
+// out by hand here, with every branch (Davis min/max, sign of s*, supersonic
+// sides, positivity fallback, boundary rules, cell classes) fixed to the one
+// the forward evaluation takes, and the WENO weights differentiated.
+//
+// Layout of one workgroup: a TX x TY tile of cells.  Every face whose
+// stencil can reach the tile (directly or through a boundary ghost layer)
+// is recomputed in the forward direction and reversed; the six stencil
+// contributions of a face are added to LDS accumulators in six passes
+// separated by barriers, so that within a pass no two faces touch the same
+// entry.  The summation order is therefore fixed and the result is
+// reproducible bit for bit, without atomics.
+#include <hip/hip_runtime.h>
+
+#include "flux.hpp"
+#include "grid.hpp"
+
+namespace shk {
+
+namespace {
+
+// Boundary source (same rules as the forward loads).
+__device__ __forceinline__ int adj_bc_source(int g, int n, int bc_lo, int bc_hi, int& flag) {
+  if (g >= 0 && g < n) return g;
+  const bool lo = g < 0;
+  const int bc = lo ? bc_lo : bc_hi;
+  const int depth = lo ? -g : g - (n - 1);
+  int s;
+  switch (bc) {
+    case BC_REFL: s = lo ? depth - 1 : n - depth; flag = flag | 1; break;
+    case BC_INFLOW: s = lo ? 0 : n - 1; flag = 2; break;
+    case BC_PERIODIC: s = ((g % n) + n) % n; break;
+    default: s = lo ? 0 : n - 1; break;
+  }
+  return s < 0 ? 0 : (s >= n ? n - 1 : s);
+}
+
+__device__ __forceinline__ void adj_load_cons(const GridArgs& a, const double* __restrict__ U, int gi, int gj,
+                                              double q[4]) {
+  int fx = 0, fy = 0;
+  const int si = adj_bc_source(gi, a.nx, a.bc[0], a.bc[1], fx);
+  const int sj = adj_bc_source(gj, a.ny, a.bc[2], a.bc[3], fy);
+  if (fy == 2 || fx == 2) {
+    for (int v = 0; v < 4; ++v) q[v] = a.inflow_cons[v];
+  } else {
+    const long long c = (long long)sj * a.nx + si;
+    q[0] = U[c];
+    q[1] = U[a.ncell + c];
+    q[2] = U[2 * a.ncell + c];
+    q[3] = U[3 * a.ncell + c];
+    if (fx & 1) q[1] = -q[1];
+  }
+  if (fy & 1) q[2] = -q[2];
+}
+
+// Reverse of one WENO5-JS reconstruction f(a,b,c,d,e) (the forward value is
+// recomputed): d f / d beta_k = -2 omega_k (q_k - f) / (eps + beta_k).
+__device__ __forceinline__ void weno5_vjp(double a, double b, double c, double d, double e, double eps,
+                                          double fb, double& ga, double& gb, double& gc, double& gd,
+                                          double& ge) {
+  const double k13 = 13.0 / 12.0;
+  const double s0 = a - 2.0 * b + c, t0 = a - 4.0 * b + 3.0 * c;
+  const double s1 = b - 2.0 * c + d, t1 = b - d;
+  const double s2 = c - 2.0 * d + e, t2 = 3.0 * c - 4.0 * d + e;
+  const double g0 = eps + (k13 * s0 * s0 + 0.25 * t0 * t0);
+  const double g1 = eps + (k13 * s1 * s1 + 0.25 * t1 * t1);
+  const double g2 = eps + (k13 * s2 * s2 + 0.25 * t2 * t2);
+  const double h0 = g0 * g0, h1 = g1 * g1, h2 = g2 * g2;
+  const double w0 = 0.1 * (h1 * h2), w1 = 0.6 * (h0 * h2), w2 = 0.3 * (h0 * h1);
+  const double is = 1.0 / (w0 + w1 + w2);
+  const double o0 = w0 * is, o1 = w1 * is, o2 = w2 * is;
+  const double q0 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
+  const double q1 = (5.0 * c - b + 2.0 * d) * (1.0 / 6.0);
+  const double q2 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
+  const double f = o0 * q0 + o1 * q1 + o2 * q2;
+  const double qb0 = fb * o0, qb1 = fb * o1, qb2 = fb * o2;
+  const double bb0 = -2.0 * fb * o0 * (q0 - f) / g0;
+  const double bb1 = -2.0 * fb * o1 * (q1 - f) / g1;
+  const double bb2 = -2.0 * fb * o2 * (q2 - f) / g2;
+  const double sb0 = bb0 * (2.0 * k13) * s0, tb0 = bb0 * 0.5 * t0;
+  const double sb1 = bb1 * (2.0 * k13) * s1, tb1 = bb1 * 0.5 * t1;
+  const double sb2 = bb2 * (2.0 * k13) * s2, tb2 = bb2 * 0.5 * t2;
+  ga += qb0 * (2.0 / 6.0) + sb0 + tb0;
+  gb += qb0 * (-7.0 / 6.0) + qb1 * (-1.0 / 6.0) - 2.0 * sb0 - 4.0 * tb0 + sb1 + tb1;
+  gc += qb0 * (11.0 / 6.0) + qb1 * (5.0 / 6.0) + qb2 * (2.0 / 6.0) + sb0 + 3.0 * tb0 - 2.0 * sb1 + sb2 +
+        3.0 * tb2;
+  gd += qb1 * (2.0 / 6.0) + qb2 * (5.0 / 6.0) + sb1 - tb1 - 2.0 * sb2 - 4.0 * tb2;
+  ge += qb2 * (-1.0 / 6.0) + sb2 + tb2;
+}
+
+struct PB {
+  double r, un, ut, p;
+};
+
+// Reverse of one HLLC bracket (side state w with energy E, wave speed s,
+// contact speed ss).  Fb is the upstream gradient times the bracket weight.
+__device__ __forceinline__ void hllc_side_vjp(const Prim<double>& w, double E, double s, double ss, bool sup,
+                                              const double Fb[4], PB& wb, double& Eb, double& sb,
+                                              double& ssb) {
+  const double mn = w.r * w.un;
+  double mnb = 0.0;
+  if (!sup) {
+    const double su = s - w.un;
+    const double den = s - ss;
+    const double chi = su / den;
+    const double rs = chi * w.r;
+    const double d0 = rs - w.r, d1 = rs * ss - mn, d2 = rs * w.ut - w.r * w.ut;
+    const double C = w.r * ss + w.p / su;
+    const double B = E + (ss - w.un) * C;
+    const double d3 = chi * B - E;
+    sb += Fb[0] * d0 + Fb[1] * d1 + Fb[2] * d2 + Fb[3] * d3;
+    const double db0 = s * Fb[0], db1 = s * Fb[1], db2 = s * Fb[2], db3 = s * Fb[3];
+    const double rsb = db0 + db1 * ss + db2 * w.ut;
+    wb.r -= db0;
+    ssb += db1 * rs;
+    mnb -= db1;
+    wb.ut += db2 * (rs - w.r);
+    wb.r -= db2 * w.ut;
+    double chib = db3 * B;
+    const double Bb = db3 * chi;
+    Eb -= db3;
+    Eb += Bb;
+    ssb += Bb * C;
+    wb.un -= Bb * C;
+    const double Cb = Bb * (ss - w.un);
+    wb.r += Cb * ss;
+    ssb += Cb * w.r;
+    wb.p += Cb / su;
+    double sub = -Cb * w.p / (su * su);
+    chib += rsb * w.r;
+    wb.r += rsb * chi;
+    sub += chib / den;
+    const double denb = -chib * chi / den;
+    sb += denb;
+    ssb -= denb;
+    sb += sub;
+    wb.un -= sub;
+  }
+  // physical flux (mn, mn un + p, mn ut, un (E + p))
+  mnb += Fb[0] + Fb[1] * w.un + Fb[2] * w.ut;
+  wb.un += Fb[1] * mn + Fb[3] * (E + w.p);
+  wb.p += Fb[1] + Fb[3] * w.un;
+  wb.ut += Fb[2] * mn;
+  Eb += Fb[3] * w.un;
+  wb.r += mnb * w.un;
+  wb.un += mnb * w.r;
+}
+
+// Reverse of the HLLC flux in the face-normal frame.
+__device__ __forceinline__ void hllc_vjp(const Prim<double>& L, const Prim<double>& R, double gamma,
+                                         const double Fb[4], PB& Lb, PB& Rb, double& gb) {
+  const double gm1 = gamma - 1.0, igm1 = 1.0 / gm1;
+  const double zL = gamma * L.p / L.r, zR = gamma * R.p / R.r;
+  const double aL = sqrt(zL), aR = sqrt(zR);
+  const bool minL = (L.un - aL) <= (R.un - aR);
+  const bool maxL = (L.un + aL) >= (R.un + aR);
+  const double sL = minL ? L.un - aL : R.un - aR;
+  const double sR = maxL ? L.un + aL : R.un + aR;
+  const double dL = sL - L.un, dR = sR - R.un;
+  const double num = R.p - L.p + L.r * L.un * dL - R.r * R.un * dR;
+  const double den = L.r * dL - R.r * dR;
+  const double ss = num / den;
+  const double EL = L.p * igm1 + 0.5 * L.r * (L.un * L.un + L.ut * L.ut);
+  const double ER = R.p * igm1 + 0.5 * R.r * (R.un * R.un + R.ut * R.ut);
+  double ELb = 0.0, ERb = 0.0, sLb = 0.0, sRb = 0.0, ssb = 0.0;
+  Lb = PB{0.0, 0.0, 0.0, 0.0};
+  Rb = PB{0.0, 0.0, 0.0, 0.0};
+  if (ss > 0.0) {
+    hllc_side_vjp(L, EL, sL, ss, sL >= 0.0, Fb, Lb, ELb, sLb, ssb);
+  } else if (ss < 0.0) {
+    hllc_side_vjp(R, ER, sR, ss, sR <= 0.0, Fb, Rb, ERb, sRb, ssb);
+  } else {
+    const double Fh[4] = {0.5 * Fb[0], 0.5 * Fb[1], 0.5 * Fb[2], 0.5 * Fb[3]};
+    hllc_side_vjp(L, EL, sL, ss, sL >= 0.0, Fh, Lb, ELb, sLb, ssb);
+    hllc_side_vjp(R, ER, sR, ss, sR <= 0.0, Fh, Rb, ERb, sRb, ssb);
+  }
+  // energies E = p/(gamma-1) + rho (un^2 + ut^2)/2
+  Lb.p += ELb * igm1;
+  gb -= ELb * L.p * igm1 * igm1;
+  Lb.r += ELb * 0.5 * (L.un * L.un + L.ut * L.ut);
+  Lb.un += ELb * L.r * L.un;
+  Lb.ut += ELb * L.r * L.ut;
+  Rb.p += ERb * igm1;
+  gb -= ERb * R.p * igm1 * igm1;
+  Rb.r += ERb * 0.5 * (R.un * R.un + R.ut * R.ut);
+  Rb.un += ERb * R.r * R.un;
+  Rb.ut += ERb * R.r * R.ut;
+  // contact speed
+  const double numb = ssb / den;
+  const double denb = -ssb * ss / den;
+  Rb.p += numb;
+  Lb.p -= numb;
+  Lb.r += numb * L.un * dL;
+  Lb.un += numb * L.r * dL;
+  double dLb = numb * L.r * L.un;
+  Rb.r -= numb * R.un * dR;
+  Rb.un -= numb * R.r * dR;
+  double dRb = -numb * R.r * R.un;
+  Lb.r += denb * dL;
+  dLb += denb * L.r;
+  Rb.r -= denb * dR;
+  dRb -= denb * R.r;
+  sLb += dLb;
+  Lb.un -= dLb;
+  sRb += dRb;
+  Rb.un -= dRb;
+  // Davis wave speeds
+  double aLb = 0.0, aRb = 0.0;
+  if (minL) { Lb.un += sLb; aLb -= sLb; } else { Rb.un += sLb; aRb -= sLb; }
+  if (maxL) { Lb.un += sRb; aLb += sRb; } else { Rb.un += sRb; aRb += sRb; }
+  // sound speeds a = sqrt(gamma p / rho)
+  const double zLb = aLb / (2.0 * aL), zRb = aRb / (2.0 * aR);
+  gb += zLb * L.p / L.r + zRb * R.p / R.r;
+  Lb.p += zLb * gamma / L.r;
+  Lb.r -= zLb * zL / L.r;
+  Rb.p += zRb * gamma / R.r;
+  Rb.r -= zRb * zR / R.r;
+}
+
+// Forward recompute and reverse of one face: stencil values v[comp][6] in the
+// face frame, upstream flux gradient Fb -> stencil gradients sl[6][4].
+__device__ __forceinline__ void face_vjp(const double v[4][6], double eps, double gamma, const double Fb[4],
+                                         double sl[6][4], double& gb) {
+  Prim<double> L, R;
+  L.r = weno5(v[0][0], v[0][1], v[0][2], v[0][3], v[0][4], eps);
+  R.r = weno5(v[0][5], v[0][4], v[0][3], v[0][2], v[0][1], eps);
+  L.un = weno5(v[1][0], v[1][1], v[1][2], v[1][3], v[1][4], eps);
+  R.un = weno5(v[1][5], v[1][4], v[1][3], v[1][2], v[1][1], eps);
+  L.ut = weno5(v[2][0], v[2][1], v[2][2], v[2][3], v[2][4], eps);
+  R.ut = weno5(v[2][5], v[2][4], v[2][3], v[2][2], v[2][1], eps);
+  L.p = weno5(v[3][0], v[3][1], v[3][2], v[3][3], v[3][4], eps);
+  R.p = weno5(v[3][5], v[3][4], v[3][3], v[3][2], v[3][1], eps);
+  const bool fallback = !(L.r > 0.0) || !(L.p > 0.0) || !(R.r > 0.0) || !(R.p > 0.0);
+  if (fallback) {
+    L = Prim<double>{v[0][2], v[1][2], v[2][2], v[3][2]};
+    R = Prim<double>{v[0][3], v[1][3], v[2][3], v[3][3]};
+  }
+  PB Lb, Rb;
+  hllc_vjp(L, R, gamma, Fb, Lb, Rb, gb);
+  const double lb[4] = {Lb.r, Lb.un, Lb.ut, Lb.p};
+  const double rb[4] = {Rb.r, Rb.un, Rb.ut, Rb.p};
+  for (int c = 0; c < 4; ++c)
+    for (int s = 0; s < 6; ++s) sl[s][c] = 0.0;
+  if (fallback) {
+    for (int c = 0; c < 4; ++c) {
+      sl[2][c] = lb[c];
+      sl[3][c] = rb[c];
+    }
+    return;
+  }
+  for (int c = 0; c < 4; ++c) {
+    weno5_vjp(v[c][0], v[c][1], v[c][2], v[c][3], v[c][4], eps, lb[c], sl[0][c], sl[1][c], sl[2][c], sl[3][c],
+              sl[4][c]);
+    weno5_vjp(v[c][5], v[c][4], v[c][3], v[c][2], v[c][1], eps, rb[c], sl[5][c], sl[4][c], sl[3][c], sl[2][c],
+              sl[1][c]);
+  }
+}
+
+__device__ __forceinline__ double lam_at(const GridArgs& a, const double* __restrict__ lam, int v, int gi, int gj) {
+  // adjoint of the right-hand side at a cell; zero outside the domain and at
+  // non-fluid cells (where the right-hand side is set to zero)
+  const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
+  if (gi < 0 || gi >= a.nx) {
+    if (!px) return 0.0;
+    gi = ((gi % a.nx) + a.nx) % a.nx;
+  }
+  if (gj < 0 || gj >= a.ny) {
+    if (!py) return 0.0;
+    gj = ((gj % a.ny) + a.ny) % a.ny;
+  }
+  const long long c = (long long)gj * a.nx + gi;
+  if (a.cls != nullptr && a.cls[c] != CELL_FLUID) return 0.0;
+  return lam[v * a.ncell + c];
+}
+
+}  // namespace
+
+// out = J^T (clam_f dt lam) + c1 X1 + c2 X2 for every cell of the tile, where J
+// is the Jacobian of the right-hand side at the stage state Us.  part receives
+// this block's partial derivatives (gamma, rho_in, u_in, v_in, p_in).
+template <int TX, int TY>
+__global__ void __launch_bounds__(256) rhs_adjoint_kernel(GridArgs a, const double* __restrict__ Us,
+                                                          const double* __restrict__ lam, double clam_f,
+                                                          const double* __restrict__ dtp,
+                                                          const double* __restrict__ X1, double c1,
+                                                          const double* __restrict__ X2, double c2,
+                                                          double* __restrict__ out, double* __restrict__ part) {
+  constexpr int NT = 256;
+  constexpr int M = 5;
+  constexpr int PX = TX + 2 * M, PY = TY + 2 * M;
+  constexpr int NFX = (TX + 5) * TY, NFY = TX * (TY + 5);
+  __shared__ double w[4][PY * PX];
+  __shared__ double ax[4][TY * PX];
+  __shared__ double ay[4][PY * TX];
+  __shared__ double red[5][NT / 64];
+
+  const int b = blockIdx.z;
+  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  const long long boff = (long long)b * 4 * a.ncell;
+  const double* __restrict__ Ub = Us + boff;
+  const double* __restrict__ Lb = lam + boff;
+  const double clam = clam_f * (dtp ? dtp[b] : 1.0);
+  const double gamma = a.gamma, gm1 = gamma - 1.0;
+  const bool perx = a.bc[0] == BC_PERIODIC, pery = a.bc[2] == BC_PERIODIC;
+
+  for (int k = threadIdx.x; k < PY * PX; k += NT) {
+    const int lx = k % PX, ly = k / PX;
+    const bool inx = lx >= M && lx < TX + M;
+    const bool iny = ly >= M && ly < TY + M;
+    if (!inx && !iny) continue;
+    double q[4];
+    adj_load_cons(a, Ub, i0 - M + lx, j0 - M + ly, q);
+    const Prim<double> p = to_prim(q[0], q[1], q[2], q[3], gm1);
+    w[0][k] = p.r;
+    w[1][k] = p.un;
+    w[2][k] = p.ut;
+    w[3][k] = p.p;
+  }
+  for (int k = threadIdx.x; k < TY * PX; k += NT)
+    for (int c = 0; c < 4; ++c) ax[c][k] = 0.0;
+  for (int k = threadIdx.x; k < PY * TX; k += NT)
+    for (int c = 0; c < 4; ++c) ay[c][k] = 0.0;
+  __syncthreads();
+
+  double gacc = 0.0;
+  for (int base = 0; base < NFX + NFY; base += NT) {
+    const int k = base + threadIdx.x;
+    bool act = false, isx = true, own = false;
+    int row = 0, pos0 = 0;
+    double sl[6][4];
+    if (k < NFX + NFY) {
+      isx = k < NFX;
+      int s0, st, cn, ct;
+      double Fb[4];
+      bool valid;
+      if (isx) {
+        const int fl = 3 + k % (TX + 5), y = k / (TX + 5);
+        const int gf = i0 - M + fl;  // left face of cell gf
+        const int gj = j0 + y;
+        valid = gj < a.ny && (perx || (gf >= 0 && gf <= a.nx));
+        // faces near the tile edges are recomputed by two tiles; the one with
+        // the face in [i0, i1) (or the right domain face) reports its gamma part
+        own = (gf >= i0 && gf < min(i0 + TX, a.nx)) || (!perx && gf == a.nx && i0 + TX >= a.nx);
+        s0 = (y + M) * PX + fl - 3;
+        st = 1; cn = 1; ct = 2;
+        row = y; pos0 = fl - 3;
+        if (valid) {
+          const double sc = clam * a.inv_dx;
+          Fb[0] = sc * (lam_at(a, Lb, 0, gf, gj) - lam_at(a, Lb, 0, gf - 1, gj));
+          Fb[1] = sc * (lam_at(a, Lb, 1, gf, gj) - lam_at(a, Lb, 1, gf - 1, gj));
+          Fb[2] = sc * (lam_at(a, Lb, 2, gf, gj) - lam_at(a, Lb, 2, gf - 1, gj));
+          Fb[3] = sc * (lam_at(a, Lb, 3, gf, gj) - lam_at(a, Lb, 3, gf - 1, gj));
+        }
+      } else {
+        const int kk = k - NFX;
+        const int x = kk % TX, gl = 3 + kk / TX;
+        const int gf = j0 - M + gl;
+        const int gi = i0 + x;
+        valid = gi < a.nx && (pery || (gf >= 0 && gf <= a.ny));
+        own = (gf >= j0 && gf < min(j0 + TY, a.ny)) || (!pery && gf == a.ny && j0 + TY >= a.ny);
+        s0 = (gl - 3) * PX + x + M;
+        st = PX; cn = 2; ct = 1;
+        row = x; pos0 = gl - 3;
+        if (valid) {
+          const double sc = clam * a.inv_dy;
+          Fb[0] = sc * (lam_at(a, Lb, 0, gi, gf) - lam_at(a, Lb, 0, gi, gf - 1));
+          Fb[1] = sc * (lam_at(a, Lb, 2, gi, gf) - lam_at(a, Lb, 2, gi, gf - 1));
+          Fb[2] = sc * (lam_at(a, Lb, 1, gi, gf) - lam_at(a, Lb, 1, gi, gf - 1));
+          Fb[3] = sc * (lam_at(a, Lb, 3, gi, gf) - lam_at(a, Lb, 3, gi, gf - 1));
+        }
+      }
+      if (valid && (Fb[0] != 0.0 || Fb[1] != 0.0 || Fb[2] != 0.0 || Fb[3] != 0.0)) {
+        double v[4][6];
+        for (int s = 0; s < 6; ++s) {
+          v[0][s] = w[0][s0 + s * st];
+          v[1][s] = w[cn][s0 + s * st];
+          v[2][s] = w[ct][s0 + s * st];
+          v[3][s] = w[3][s0 + s * st];
+        }
+        double gface = 0.0;
+        face_vjp(v, a.eps, gamma, Fb, sl, gface);
+        if (own) gacc += gface;
+        act = true;
+      }
+    }
+    for (int s = 0; s < 6; ++s) {
+      if (act) {
+        if (isx) {
+          const int p = row * PX + pos0 + s;
+          ax[0][p] += sl[s][0];
+          ax[1][p] += sl[s][1];
+          ax[2][p] += sl[s][2];
+          ax[3][p] += sl[s][3];
+        } else {
+          const int p = (pos0 + s) * TX + row;
+          ay[0][p] += sl[s][0];
+          ay[1][p] += sl[s][2];  // face frame (rho, v, u, p) -> (rho, u, v, p)
+          ay[2][p] += sl[s][1];
+          ay[3][p] += sl[s][3];
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // fold boundary ghost layers, then the primitive-variable adjoint per cell
+  double inb[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < TX * TY; k += NT) {
+    const int x = k % TX, y = k / TX;
+    const int gi = i0 + x, gj = j0 + y;
+    if (gi >= a.nx || gj >= a.ny) continue;
+    double Wb[4];
+    for (int c = 0; c < 4; ++c) Wb[c] = ax[c][y * PX + x + M] + ay[c][(y + M) * TX + x];
+    if (!perx) {
+      for (int g = 1; g <= 3; ++g) {
+        // left ghost -g
+        const int lxl = -g - i0 + M;
+        if (lxl >= 0) {
+          const int p = y * PX + lxl;
+          if (a.bc[0] == BC_TRANS && gi == 0) {
+            for (int c = 0; c < 4; ++c) Wb[c] += ax[c][p];
+          } else if (a.bc[0] == BC_REFL && gi == g - 1) {
+            Wb[0] += ax[0][p]; Wb[1] -= ax[1][p]; Wb[2] += ax[2][p]; Wb[3] += ax[3][p];
+          } else if (a.bc[0] == BC_INFLOW && gi == 0) {
+            for (int c = 0; c < 4; ++c) inb[c] += ax[c][p];
+          }
+        }
+        // right ghost nx-1+g
+        const int lxr = a.nx - 1 + g - i0 + M;
+        if (lxr < PX) {
+          const int p = y * PX + lxr;
+          if (a.bc[1] == BC_TRANS && gi == a.nx - 1) {
+            for (int c = 0; c < 4; ++c) Wb[c] += ax[c][p];
+          } else if (a.bc[1] == BC_REFL && gi == a.nx - g) {
+            Wb[0] += ax[0][p]; Wb[1] -= ax[1][p]; Wb[2] += ax[2][p]; Wb[3] += ax[3][p];
+          } else if (a.bc[1] == BC_INFLOW && gi == a.nx - 1) {
+            for (int c = 0; c < 4; ++c) inb[c] += ax[c][p];
+          }
+        }
+      }
+    }
+    if (!pery) {
+      for (int g = 1; g <= 3; ++g) {
+        const int lyl = -g - j0 + M;
+        if (lyl >= 0) {
+          const int p = lyl * TX + x;
+          if (a.bc[2] == BC_TRANS && gj == 0) {
+            for (int c = 0; c < 4; ++c) Wb[c] += ay[c][p];
+          } else if (a.bc[2] == BC_REFL && gj == g - 1) {
+            Wb[0] += ay[0][p]; Wb[1] += ay[1][p]; Wb[2] -= ay[2][p]; Wb[3] += ay[3][p];
+          } else if (a.bc[2] == BC_INFLOW && gj == 0) {
+            for (int c = 0; c < 4; ++c) inb[c] += ay[c][p];
+          }
+        }
+        const int lyr = a.ny - 1 + g - j0 + M;
+        if (lyr < PY) {
+          const int p = lyr * TX + x;
+          if (a.bc[3] == BC_TRANS && gj == a.ny - 1) {
+            for (int c = 0; c < 4; ++c) Wb[c] += ay[c][p];
+          } else if (a.bc[3] == BC_REFL && gj == a.ny - g) {
+            Wb[0] += ay[0][p]; Wb[1] += ay[1][p]; Wb[2] -= ay[2][p]; Wb[3] += ay[3][p];
+          } else if (a.bc[3] == BC_INFLOW && gj == a.ny - 1) {
+            for (int c = 0; c < 4; ++c) inb[c] += ay[c][p];
+          }
+        }
+      }
+    }
+    // W = (rho, m_x/rho, m_y/rho, (gamma-1)(E - (m_x^2 + m_y^2)/(2 rho)))
+    const long long cell = (long long)gj * a.nx + gi;
+    const double r = Ub[cell];
+    const double u = Ub[a.ncell + cell] / r, vv = Ub[2 * a.ncell + cell] / r;
+    const double E = Ub[3 * a.ncell + cell];
+    const double ke = 0.5 * (u * u + vv * vv);
+    double Uo[4];
+    Uo[0] = Wb[0] - Wb[1] * u / r - Wb[2] * vv / r + Wb[3] * gm1 * ke;
+    Uo[1] = Wb[1] / r - Wb[3] * gm1 * u;
+    Uo[2] = Wb[2] / r - Wb[3] * gm1 * vv;
+    Uo[3] = Wb[3] * gm1;
+    gacc += Wb[3] * (E - r * ke);
+    for (int c = 0; c < 4; ++c) {
+      const long long o = boff + c * a.ncell + cell;
+      double val = Uo[c];
+      if (X1) val += c1 * X1[o];
+      if (X2) val += c2 * X2[o];
+      out[o] = val;
+    }
+  }
+
+  // block partial derivatives, reduced in a fixed order
+  double vals[5] = {gacc, inb[0], inb[1], inb[2], inb[3]};
+  for (int q = 0; q < 5; ++q) {
+    double v = vals[q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    double s = 0.0;
+    for (int k = 0; k < NT / 64; ++k) s += red[threadIdx.x][k];
+    const long long blk = ((long long)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    part[blk * 5 + threadIdx.x] = s;
+  }
+}
+
+// ------------------------------------------------- immersed boundary transpose
+// Entries (ghost, corner) of the refill, one per valid interpolation source,
+// sorted by source cell and then by entry index: rank of an entry = number of
+// entries ordered before it (deterministic; the list is a few thousand long).
+__global__ void __launch_bounds__(256) ibm_entries_rank_kernel(GhostTable gt, int* __restrict__ keys,
+                                                               int* __restrict__ vals, int* __restrict__ nvalid) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n4 = 4 * gt.n;
+  if (e >= n4) return;
+  const int ke = gt.src[e];
+  if (ke < 0) return;
+  int rank = 0;
+  for (int f = 0; f < n4; ++f) {
+    const int kf = gt.src[f];
+    if (kf < 0) continue;
+    rank += (kf < ke || (kf == ke && f < e)) ? 1 : 0;
+  }
+  keys[rank] = ke;
+  vals[rank] = e;
+  atomicAdd(nvalid, 1);
+}
+
+// X (adjoint w.r.t. the filled state) -> adjoint w.r.t. the state before the
+// refill: each source cell gathers the shares of the ghosts that read it.
+// One thread per run of equal keys (the first entry of the run).
+__global__ void __launch_bounds__(256) ibm_fill_adjoint_kernel(GridArgs a, GhostTable gt, const int* __restrict__ keys,
+                                                               const int* __restrict__ vals, int nent,
+                                                               const double* __restrict__ Us, double* __restrict__ X,
+                                                               double* __restrict__ part) {
+  __shared__ double red[4];
+  const int b = blockIdx.y;
+  const long long n = a.ncell;
+  const double* __restrict__ Ub = Us + (long long)b * 4 * n;
+  double* __restrict__ Xb = X + (long long)b * 4 * n;
+  const double gamma = a.gamma, gm1 = gamma - 1.0;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double gacc = 0.0;
+  if (i < nent && (i == 0 || keys[i] != keys[i - 1])) {
+    const int src = keys[i];
+    double Wsb[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = i; j < nent && keys[j] == src; ++j) {
+      const int e = vals[j];
+      const int k = e >> 2, m = e & 3;
+      // forward of ghost k: image-point primitives, then the wall rule
+      double Wi[4] = {0.0, 0.0, 0.0, 0.0};
+      int first = -1;
+      for (int mm = 0; mm < 4; ++mm) {
+        const int sm = gt.src[4 * k + mm];
+        if (sm < 0) continue;
+        if (first < 0) first = mm;
+        const double wm = gt.w[4 * k + mm];
+        const double r = Ub[sm];
+        const double u = Ub[n + sm] / r, v = Ub[2 * n + sm] / r;
+        const double p = gm1 * (Ub[3 * n + sm] - 0.5 * r * (u * u + v * v));
+        Wi[0] += wm * r; Wi[1] += wm * u; Wi[2] += wm * v; Wi[3] += wm * p;
+      }
+      const double nxv = gt.nrm[2 * k], nyv = gt.nrm[2 * k + 1];
+      double ug, vg;
+      if (gt.wall == 0) {
+        const double un = Wi[1] * nxv + Wi[2] * nyv;
+        ug = Wi[1] - 2.0 * un * nxv;
+        vg = Wi[2] - 2.0 * un * nyv;
+      } else {
+        ug = -Wi[1];
+        vg = -Wi[2];
+      }
+      // reverse of U_g = (rho, rho ug, rho vg, p/(gamma-1) + rho (ug^2+vg^2)/2)
+      const int gc = gt.cell[k];
+      const double X0 = Xb[gc], X1 = Xb[n + gc], X2 = Xb[2 * n + gc], X3 = Xb[3 * n + gc];
+      const double rb = X0 + X1 * ug + X2 * vg + X3 * 0.5 * (ug * ug + vg * vg);
+      const double ugb = X1 * Wi[0] + X3 * Wi[0] * ug;
+      const double vgb = X2 * Wi[0] + X3 * Wi[0] * vg;
+      const double pb = X3 / gm1;
+      if (m == first) gacc -= X3 * Wi[3] / (gm1 * gm1);
+      double Wub, Wvb;
+      if (gt.wall == 0) {
+        const double unb = -2.0 * (ugb * nxv + vgb * nyv);
+        Wub = ugb + unb * nxv;
+        Wvb = vgb + unb * nyv;
+      } else {
+        Wub = -ugb;
+        Wvb = -vgb;
+      }
+      const double wm = gt.w[4 * k + m];
+      Wsb[0] += wm * rb; Wsb[1] += wm * Wub; Wsb[2] += wm * Wvb; Wsb[3] += wm * pb;
+    }
+    const double r = Ub[src];
+    const double u = Ub[n + src] / r, v = Ub[2 * n + src] / r;
+    const double E = Ub[3 * n + src];
+    const double ke = 0.5 * (u * u + v * v);
+    Xb[src] += Wsb[0] - Wsb[1] * u / r - Wsb[2] * v / r + Wsb[3] * gm1 * ke;
+    Xb[n + src] += Wsb[1] / r - Wsb[3] * gm1 * u;
+    Xb[2 * n + src] += Wsb[2] / r - Wsb[3] * gm1 * v;
+    Xb[3 * n + src] += Wsb[3] * gm1;
+    gacc += Wsb[3] * (E - r * ke);
+  }
+  double v = gacc;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const long long blk = (long long)b * gridDim.x + blockIdx.x;
+    part[blk * 5] = red[0] + red[1] + red[2] + red[3];
+    for (int q = 1; q < 5; ++q) part[blk * 5 + q] = 0.0;
+  }
+}
+
+// The refill overwrites the ghost cells, so their pre-refill adjoint is zero.
+__global__ void __launch_bounds__(256) ibm_zero_ghosts_kernel(GridArgs a, GhostTable gt, double* __restrict__ X) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= gt.n) return;
+  double* Xb = X + (long long)blockIdx.y * 4 * a.ncell;
+  const int c = gt.cell[k];
+  for (int v = 0; v < 4; ++v) Xb[v * a.ncell + c] = 0.0;
+}
+
+// param_bar[b][q] += sum over the blocks of member b of part (fixed order).
+__global__ void __launch_bounds__(64) partials_finalize_kernel(const double* __restrict__ part, int nblk_per_b,
+                                                               int nbatch, double* __restrict__ param_bar) {
+  const int t = threadIdx.x;
+  if (t >= 5 * nbatch) return;
+  const int b = t / 5, q = t % 5;
+  double s = 0.0;
+  for (int k = 0; k < nblk_per_b; ++k) s += part[((long long)b * nblk_per_b + k) * 5 + q];
+  param_bar[b * 5 + q] += s;
+}
+
+// y = alpha x (+ y if accumulate), elementwise over n entries.
+__global__ void __launch_bounds__(256) axpy_kernel(long long n, double alpha, const double* __restrict__ x,
+                                                   double* __restrict__ y, int accumulate) {
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+    y[k] = accumulate ? y[k] + alpha * x[k] : alpha * x[k];
+}
+
+// ------------------------------------------------------------------ launchers
+constexpr int ATX = 32, ATY = 8;
+
+int adjoint_blocks(const GridArgs& a) { return ((a.nx + ATX - 1) / ATX) * ((a.ny + ATY - 1) / ATY); }
+
+hipError_t launch_rhs_adjoint(const GridArgs& a, const double* Us, const double* lam, double clam_f,
+                              const double* dtp, const double* X1, double c1, const double* X2, double c2,
+                              double* out, double* part, double* param_bar, hipStream_t st) {
+  dim3 grid((a.nx + ATX - 1) / ATX, (a.ny + ATY - 1) / ATY, a.nbatch);
+  hipLaunchKernelGGL((rhs_adjoint_kernel<ATX, ATY>), grid, dim3(256), 0, st, a, Us, lam, clam_f, dtp, X1, c1, X2,
+                     c2, out, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !param_bar) return e;
+  hipLaunchKernelGGL(partials_finalize_kernel, dim3(1), dim3(64 * ((5 * a.nbatch + 63) / 64)), 0, st, part,
+                     (int)(grid.x * grid.y), a.nbatch, param_bar);
+  return hipGetLastError();
+}
+
+hipError_t launch_ibm_entries(const GhostTable& gt, int* keys, int* vals, int* nvalid, hipStream_t st) {
+  if (gt.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(ibm_entries_rank_kernel, dim3((4 * gt.n + 255) / 256), dim3(256), 0, st, gt, keys, vals,
+                     nvalid);
+  return hipGetLastError();
+}
+
+hipError_t launch_ibm_fill_adjoint(const GridArgs& a, const GhostTable& gt, const int* keys, const int* vals,
+                                   int nent, const double* Us, double* X, double* part, double* param_bar,
+                                   hipStream_t st) {
+  if (gt.n == 0) return hipSuccess;
+  const unsigned int nb = (unsigned int)((nent + 255) / 256);
+  if (nent > 0) {
+    hipLaunchKernelGGL(ibm_fill_adjoint_kernel, dim3(nb, a.nbatch), dim3(256), 0, st, a, gt, keys, vals, nent, Us,
+                       X, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (param_bar) {
+      hipLaunchKernelGGL(partials_finalize_kernel, dim3(1), dim3(64 * ((5 * a.nbatch + 63) / 64)), 0, st, part,
+                         (int)nb, a.nbatch, param_bar);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  hipLaunchKernelGGL(ibm_zero_ghosts_kernel, dim3((gt.n + 255) / 256, a.nbatch), dim3(256), 0, st, a, gt, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(long long n, double alpha, const double* x, double* y, int accumulate, hipStream_t st) {
+  long long nb = (n + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(axpy_kernel, dim3((unsigned int)nb), dim3(256), 0, st, n, alpha, x, y, accumulate);
+  return hipGetLastError();
+}
+
+}  // namespace shk

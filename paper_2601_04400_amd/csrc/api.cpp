@@ -21,7 +21,7 @@ using namespace shk;
 
 struct WsLayout {
   size_t scalars, globals, dtbuf, xslots, u1, u2, cls, row_count, row_off, g_cell, g_src, g_w, g_nrm;
-  size_t adj[8];
+  size_t adjA, adjB, adjC, adjP, adjQ, adjPart, entKeys, entVals, entCount;
   size_t total;
 };
 
@@ -35,6 +35,7 @@ struct shk_grid {
   size_t esize;
   GhostTable gt;
   bool ibm_on;
+  int nent = 0;  // valid (ghost, source) entries of the refill transpose
   std::string err;
   // kernel timing (shk_profile)
   bool prof = false;
@@ -99,6 +100,22 @@ WsLayout layout(const shk_grid_desc* d) {
     L.g_src = o; o += al(sizeof(int) * 4 * cap);
     L.g_w = o; o += al(sizeof(double) * 4 * cap);
     L.g_nrm = o; o += al(sizeof(double) * 2 * cap);
+  }
+  if (d->adjoint) {
+    const size_t st64 = al(size_t(d->nbatch) * 4 * ncell * sizeof(double));
+    L.adjA = o; o += st64;
+    L.adjB = o; o += st64;
+    L.adjC = o; o += st64;
+    L.adjP = o; o += st64;
+    L.adjQ = o; o += st64;
+    const size_t nblk = size_t((d->nx + 31) / 32) * ((d->ny + 7) / 8);
+    const size_t nent_blk = d->ibm ? (4 * ncell + 255) / 256 : 0;
+    L.adjPart = o; o += al(sizeof(double) * 5 * d->nbatch * (nblk > nent_blk ? nblk : nent_blk));
+    if (d->ibm) {
+      L.entKeys = o; o += al(sizeof(int) * 4 * ncell);
+      L.entVals = o; o += al(sizeof(int) * 4 * ncell);
+      L.entCount = o; o += al(sizeof(int));
+    }
   }
   L.total = o;
   return L;
@@ -300,6 +317,19 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
   g->gt = gt;
   a.cls = cls;
   g->ibm_on = true;
+  g->nent = 0;
+  if (g->d.adjoint && n > 0) {
+    int* keys = reinterpret_cast<int*>(g->ws + g->L.entKeys);
+    int* vals = reinterpret_cast<int*>(g->ws + g->L.entVals);
+    int* cnt = reinterpret_cast<int*>(g->ws + g->L.entCount);
+    int nv = 0;
+    e = hipMemsetAsync(cnt, 0, sizeof(int), g->st);
+    if (e == hipSuccess) e = launch_ibm_entries(gt, keys, vals, cnt, g->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&nv, cnt, sizeof(int), hipMemcpyDeviceToHost, g->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+    if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset (adjoint entries)");
+    g->nent = nv;
+  }
   return SHK_OK;
 }
 
@@ -344,6 +374,86 @@ shk_status shk_rk3_step(shk_grid* g, void* U, const double* dt_in, double* dt_ou
   if (!U) return fail(g, SHK_EINVAL, "rk3_step: null state");
   if (g->esize == 8) return stage_seq<double>(g, static_cast<double*>(U), dt_in, dt_out);
   return stage_seq<float>(g, static_cast<float*>(U), dt_in, dt_out);
+}
+
+static shk_status adjoint_ok(shk_grid* g) {
+  if (!g->d.adjoint) return fail(g, SHK_ESTATE, "adjoint: grid created without desc.adjoint = 1");
+  if (g->d.prec != SHK_F64 || g->d.ndim != 2 || g->d.viscous || g->d.nu_art != 0.0)
+    return fail(g, SHK_EUNSUPPORTED, "adjoint: implemented for 2D inviscid FP64 without artificial viscosity");
+  return SHK_OK;
+}
+
+// Ghost refill of a double state (no-op without immersed boundary).
+static hipError_t fill64(shk_grid* g, double* X) {
+  return g->ibm_on ? launch_ibm_fill<double>(g->a, g->gt, X, g->st) : hipSuccess;
+}
+
+// Transpose of the refill on an adjoint array X (w.r.t. the filled state Us).
+static hipError_t fillT(shk_grid* g, const double* Us, double* X, double* param_bar) {
+  if (!g->ibm_on) return hipSuccess;
+  const int* keys = reinterpret_cast<const int*>(g->ws + g->L.entKeys);
+  const int* vals = reinterpret_cast<const int*>(g->ws + g->L.entVals);
+  double* part = reinterpret_cast<double*>(g->ws + g->L.adjPart);
+  return launch_ibm_fill_adjoint(g->a, g->gt, keys, vals, g->nent, Us, X, part, param_bar, g->st);
+}
+
+shk_status shk_rhs_adjoint(shk_grid* g, const void* U, const void* dUdt_bar, void* U_bar, double* param_bar) {
+  if (!g) return SHK_EINVAL;
+  shk_status s = adjoint_ok(g);
+  if (s != SHK_OK) return s;
+  if (!U || !dUdt_bar || !U_bar) return fail(g, SHK_EINVAL, "rhs_adjoint: null array");
+  const GridArgs& a = g->a;
+  const size_t bytes = size_t(a.nbatch) * 4 * a.ncell * sizeof(double);
+  double* A = reinterpret_cast<double*>(g->ws + g->L.adjA);
+  double* P = reinterpret_cast<double*>(g->ws + g->L.adjP);
+  double* part = reinterpret_cast<double*>(g->ws + g->L.adjPart);
+  hipError_t e = hipMemcpyAsync(A, U, bytes, hipMemcpyDeviceToDevice, g->st);
+  if (e == hipSuccess) e = fill64(g, A);
+  if (e == hipSuccess)
+    e = launch_rhs_adjoint(a, A, static_cast<const double*>(dUdt_bar), 1.0, nullptr, nullptr, 0.0, nullptr, 0.0, P,
+                           part, param_bar, g->st);
+  if (e == hipSuccess) e = fillT(g, A, P, param_bar);
+  if (e == hipSuccess) e = launch_axpy((long long)a.nbatch * 4 * a.ncell, 1.0, P, static_cast<double*>(U_bar), 1, g->st);
+  return hip_check(g, e, "rhs_adjoint");
+}
+
+shk_status shk_rk3_step_adjoint(shk_grid* g, const void* U_n, const double* dt, void* U_bar, double* param_bar) {
+  if (!g) return SHK_EINVAL;
+  shk_status s = adjoint_ok(g);
+  if (s != SHK_OK) return s;
+  if (!U_n || !dt || !U_bar) return fail(g, SHK_EINVAL, "rk3_step_adjoint: null array");
+  const GridArgs& a = g->a;
+  const long long n = (long long)a.nbatch * 4 * a.ncell;
+  const size_t bytes = size_t(n) * sizeof(double);
+  double* A = reinterpret_cast<double*>(g->ws + g->L.adjA);  // U^n filled
+  double* B = reinterpret_cast<double*>(g->ws + g->L.adjB);  // U1 filled
+  double* C = reinterpret_cast<double*>(g->ws + g->L.adjC);  // U2 filled
+  double* P = reinterpret_cast<double*>(g->ws + g->L.adjP);
+  double* Q = reinterpret_cast<double*>(g->ws + g->L.adjQ);
+  double* part = reinterpret_cast<double*>(g->ws + g->L.adjPart);
+  double* Ub = static_cast<double*>(U_bar);
+  hipError_t e = hipMemcpyAsync(A, U_n, bytes, hipMemcpyDeviceToDevice, g->st);
+  // forward recompute of the stage states
+  if (e == hipSuccess) e = fill64(g, A);
+  if (e == hipSuccess) e = launch_stage<double>(a, MODE_STAGE1, A, A, B, dt, nullptr, g->st);
+  if (e == hipSuccess) e = fill64(g, B);
+  if (e == hipSuccess) e = launch_stage<double>(a, MODE_STAGE2, B, A, C, dt, nullptr, g->st);
+  if (e == hipSuccess) e = fill64(g, C);
+  // stage 3: U = 1/3 U^n + 2/3 U2 + 2/3 dt L(U2)
+  if (e == hipSuccess)
+    e = launch_rhs_adjoint(a, C, Ub, 2.0 / 3.0, dt, Ub, 2.0 / 3.0, nullptr, 0.0, P, part, param_bar, g->st);
+  if (e == hipSuccess) e = launch_axpy(n, 1.0 / 3.0, Ub, Q, 0, g->st);
+  if (e == hipSuccess) e = fillT(g, C, P, param_bar);  // P = adjoint of U2
+  // stage 2: U2 = 3/4 U^n + 1/4 U1 + dt/4 L(U1)
+  if (e == hipSuccess)
+    e = launch_rhs_adjoint(a, B, P, 0.25, dt, P, 0.25, nullptr, 0.0, Ub, part, param_bar, g->st);
+  if (e == hipSuccess) e = launch_axpy(n, 0.75, P, Q, 1, g->st);
+  if (e == hipSuccess) e = fillT(g, B, Ub, param_bar);  // Ub = adjoint of U1
+  // stage 1: U1 = U^n + dt L(U^n)
+  if (e == hipSuccess) e = launch_rhs_adjoint(a, A, Ub, 1.0, dt, Q, 1.0, Ub, 1.0, P, part, param_bar, g->st);
+  if (e == hipSuccess) e = fillT(g, A, P, param_bar);
+  if (e == hipSuccess) e = hipMemcpyAsync(Ub, P, bytes, hipMemcpyDeviceToDevice, g->st);
+  return hip_check(g, e, "rk3_step_adjoint");
 }
 
 shk_status shk_set_time(shk_grid* g, double t0, double t_end) {

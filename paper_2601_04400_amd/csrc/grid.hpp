@@ -76,6 +76,17 @@ hipError_t launch_ibm_table(const GridArgs& a, const double* phi, const uint8_t*
 hipError_t launch_stage_mixed(const GridArgs& a, int mode, const float* Us, const float* Un, float* Uout,
                               const double* dtp, const float* Lin, hipStream_t st);
 
+// adjoint (adjoint.hip)
+int adjoint_blocks(const GridArgs& a);
+hipError_t launch_rhs_adjoint(const GridArgs& a, const double* Us, const double* lam, double clam_f,
+                              const double* dtp, const double* X1, double c1, const double* X2, double c2,
+                              double* out, double* part, double* param_bar, hipStream_t st);
+hipError_t launch_ibm_entries(const GhostTable& gt, int* keys, int* vals, int* nvalid, hipStream_t st);
+hipError_t launch_ibm_fill_adjoint(const GridArgs& a, const GhostTable& gt, const int* keys, const int* vals,
+                                   int nent, const double* Us, double* X, double* part, double* param_bar,
+                                   hipStream_t st);
+hipError_t launch_axpy(long long n, double alpha, const double* x, double* y, int accumulate, hipStream_t st);
+
 // stage modes
 enum : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2, MODE_STAGE3 = 3,
              MODE_S1L = 4, MODE_S2F = 5, MODE_S3F = 6 };

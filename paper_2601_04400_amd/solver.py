@@ -123,6 +123,30 @@ class Grid:
         check(lib().shk_rk3_step(self.handle, _ptr(U), _ptr(dt), _ptr(dt_out)), self.handle, "rk3_step")
         return U
 
+    def param_bar(self):
+        """Zeroed accumulator for (gamma, inflow rho, u, v, p) derivatives."""
+        return torch.zeros((self.shape[0], 5), dtype=torch.float64, device=self.device)
+
+    def rhs_adjoint(self, U, dUdt_bar, U_bar, param_bar=None):
+        """U_bar += (d rhs/dU)^T dUdt_bar; param_bar += parameter derivatives."""
+        for t in (U, dUdt_bar, U_bar):
+            self._check_state(t)
+        self._sync_stream()
+        check(lib().shk_rhs_adjoint(self.handle, _ptr(U), _ptr(dUdt_bar), _ptr(U_bar), _ptr(param_bar)),
+              self.handle, "rhs_adjoint")
+        return U_bar
+
+    def step_adjoint(self, U_n, dt, U_bar, param_bar=None):
+        """U_bar (adjoint after the step) -> adjoint of U_n, in place."""
+        self._check_state(U_n)
+        self._check_state(U_bar)
+        if not torch.is_tensor(dt):
+            dt = torch.full((self.shape[0],), float(dt), dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        check(lib().shk_rk3_step_adjoint(self.handle, _ptr(U_n), _ptr(dt), _ptr(U_bar), _ptr(param_bar)),
+              self.handle, "rk3_step_adjoint")
+        return U_bar
+
     def set_time(self, t0, t_end):
         self._sync_stream()
         check(lib().shk_set_time(self.handle, float(t0), float(t_end)), self.handle, "set_time")
