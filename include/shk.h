@@ -91,6 +91,7 @@ typedef struct {
   double inflow_prim[4]; /* (rho, u, v, p) used by SHK_BC_INFLOW              */
   int ibm;             /* 1: reserve immersed-boundary tables in the workspace */
   int adjoint;         /* 1: reserve adjoint buffers in the workspace          */
+  int flux_net;        /* 1: reserve learned-flux buffers (ndim 2, SHK_F64)   */
 } shk_grid_desc;
 
 /* Bytes of device workspace a grid with this descriptor needs (0 on a bad
@@ -175,6 +176,66 @@ shk_status shk_rhs_adjoint(shk_grid* g, const void* U, const void* dUdt_bar, voi
  * states are recomputed from U_n in the workspace.  Same requirements as
  * shk_rhs_adjoint. */
 shk_status shk_rk3_step_adjoint(shk_grid* g, const void* U_n, const double* dt, void* U_bar, double* param_bar);
+
+/* ---- Learned flux correction (section 2 neural flux, per-face MLP form) ----
+ * F = F_HLLC + dF with dF = s_out tanh(MLP(x)), x = the 6-cell stencil of
+ * (rho, u_n, u_t, p) in the face-normal frame normalised as (w - mean) *
+ * inv_std; hidden layers 64-64-64 with ReLU; the same parameters for x- and
+ * y-faces (u_n/u_t rotated).  Weights are bfloat16 and every matrix product
+ * runs on the matrix cores with FP32 accumulation.
+ * Parameter vector theta (FP32, 10180 entries, gradients and Adam use it):
+ * W0[64][24], b0[64], W1[64][64], b1[64], W2[64][64], b2[64], W3[4][64], b3[4].
+ * Device form used by the kernels (shk_flux_net_pack writes it): bf16
+ * W0[64][32] (inputs zero-padded), W1[64][64], W2[64][64], W3[16][64]
+ * (outputs zero-padded) = 11264 values, and FP32 biases b0[64], b1[64],
+ * b2[64], b3[16] = 208 values. */
+
+/* Enable (enable = 1) or disable the correction.  w_bf16 (device, 11264
+ * bf16 bit patterns) and bias (device, 208 floats) stay owned by the caller
+ * and must outlive their use; norm_host = host {mean[4], inv_std[4]};
+ * out_scale = s_out.  While enabled, shk_rhs and shk_rk3_step evaluate the
+ * network for every face of each stage state before the stage kernel (the
+ * automatic step then uses the separate reduction), and the adjoint entry
+ * points include its reverse pass.  A non-finite network output falls back to
+ * the uncorrected flux at that face and sets SHK_FAULT_NET.  Requires
+ * desc.flux_net = 1 (SHK_ESTATE otherwise). */
+shk_status shk_set_flux_net(shk_grid* g, const uint16_t* w_bf16, const float* bias, const double* norm_host,
+                            float out_scale, int enable);
+
+/* Accumulate the parameter gradient (device, 10180 floats, theta order) of
+ * every later adjoint call into grad (+=); NULL stops accumulating. */
+shk_status shk_set_flux_net_grad(shk_grid* g, float* grad);
+
+/* Network output for every face of state U (device double): dF (device,
+ * [nbatch][nface][4] floats, face frame), faces ordered x-faces
+ * (j*(nx+1)+i, i = 0..nx) then y-faces ((nx+1)*ny + j*nx + i, j = 0..ny). */
+shk_status shk_flux_net_eval(shk_grid* g, const void* U, float* dF);
+
+/* Reverse of the network alone: face-flux gradients formed from the
+ * right-hand-side adjoint lam as in the flux difference (F_bar = (lam_right -
+ * lam_left)/h, face frame); writes dX (device, [nbatch][nface][6][4] floats,
+ * gradient w.r.t. the stencil primitives) and adds the parameter gradient to
+ * grad (device, 10180 floats, may be NULL).  Requires desc.adjoint = 1. */
+shk_status shk_flux_net_vjp(shk_grid* g, const void* U, const void* lam, float* dX, float* grad);
+
+/* Device form (bf16 weights, FP32 biases) from theta; all device arrays. */
+shk_status shk_flux_net_pack(const float* theta, uint16_t* w_bf16, float* bias, void* hip_stream);
+
+/* One Adam step on n parameters (device arrays; step counts from 1). */
+shk_status shk_adam(float* theta, const float* grad, float* m, float* v, int n, float lr, float beta1, float beta2,
+                    float eps, int step, void* hip_stream);
+
+/* Block average by factor x factor (the restriction d(U) of section 2):
+ * fine [nbatch][nvar][ny_f][nx_f] -> coarse [nbatch][nvar][ny_f/factor][nx_f/factor],
+ * device doubles; nx_f, ny_f must be multiples of factor. */
+shk_status shk_restrict(const double* fine, double* coarse, int nx_f, int ny_f, int factor, int nvar, int nbatch,
+                        void* hip_stream);
+
+/* Unrolled-loss term of section 2 per batch member: loss[b] += ||U_b - T_b||^2
+ * / per_batch, and G_b += scale * 2 (U_b - T_b) / per_batch if G is not NULL.
+ * part: device scratch of nbatch * 256 doubles.  Fixed summation order. */
+shk_status shk_mse(const double* U, const double* T, double* G, double scale, long long per_batch, int nbatch,
+                   double* part, double* loss, void* hip_stream);
 
 /* Set the device time of every batch member to t0, the stop time to t_end
  * and the automatic-step counter to 0 (enqueued). */

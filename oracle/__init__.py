@@ -201,42 +201,46 @@ def ibm_fill(c, U, phi, wall=0):
     return U
 
 
-def rhs_jvp(c, U, Udot, gdot=0.0, indot=(0, 0, 0, 0), phi=None, wall=0):
+def rhs_jvp(c, U, Udot, gdot=0.0, indot=(0, 0, 0, 0), phi=None, wall=0, net=None):
     U, Udot = _arr(U, _shape(c)), _arr(Udot, _shape(c))
     L, Ld = np.empty_like(U), np.empty_like(U)
     ind = _arr(indot, (4,))
     rc = lib().orc_rhs_jvp(ctypes.byref(c), _ptr(U), _ptr(Udot), _d(gdot), _ptr(ind), _ptr(_phi(c, phi)),
-                           _i(wall), _ptr(L), _ptr(Ld))
+                           _i(wall), _ptr(L), _ptr(Ld), _net(net))
     assert rc == 0
     return L, Ld
 
 
-def rhs_jacobian(c, U, phi=None, wall=0):
+def _net(net):
+    return _p(net.handle) if net is not None else None
+
+
+def rhs_jacobian(c, U, phi=None, wall=0, net=None):
     """Dense Jacobian of the RHS (small grids): columns = state entries, then
     gamma and the inflow primitives (rho, u, v, p)."""
     U = _arr(U, _shape(c))
     n = U.size
     J = np.empty((n, n + 5))
-    assert lib().orc_rhs_jacobian(ctypes.byref(c), _ptr(U), _ptr(_phi(c, phi)), _i(wall), _ptr(J)) == 0
+    assert lib().orc_rhs_jacobian(ctypes.byref(c), _ptr(U), _ptr(_phi(c, phi)), _i(wall), _ptr(J), _net(net)) == 0
     return J
 
 
-def rk3_step_jacobian(c, U, dt, phi=None, wall=0):
+def rk3_step_jacobian(c, U, dt, phi=None, wall=0, net=None):
     """Dense Jacobian of one fixed-dt RK3 step (small grids), columns as in
     rhs_jacobian."""
     U = _arr(U, _shape(c))
     n = U.size
     J = np.empty((n, n + 5))
     assert lib().orc_rk3_step_jacobian(ctypes.byref(c), _ptr(U), _d(dt), _ptr(_phi(c, phi)), _i(wall),
-                                       _ptr(J)) == 0
+                                       _ptr(J), _net(net)) == 0
     return J
 
 
-def rk3_step_jvp(c, U, Udot, dt, gdot=0.0, indot=(0, 0, 0, 0), phi=None, wall=0):
+def rk3_step_jvp(c, U, Udot, dt, gdot=0.0, indot=(0, 0, 0, 0), phi=None, wall=0, net=None):
     U, Udot = _arr(U, _shape(c)).copy(), _arr(Udot, _shape(c)).copy()
     ind = _arr(indot, (4,))
     rc = lib().orc_rk3_step_jvp(ctypes.byref(c), _ptr(U), _ptr(Udot), _d(dt), _d(gdot), _ptr(ind),
-                                _ptr(_phi(c, phi)), _i(wall))
+                                _ptr(_phi(c, phi)), _i(wall), _net(net))
     assert rc == 0
     return U, Udot
 

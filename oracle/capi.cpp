@@ -199,7 +199,7 @@ int orc_ibm_fill(const Config* c, double* U, const double* phi, int wall) {
 // Jacobian-vector product of the RHS: direction (Udot, gdot, indot[4]) over
 // (state, gamma, inflow primitive state).
 int orc_rhs_jvp(const Config* c, const double* U, const double* Udot, double gdot, const double* indot,
-                const double* phi, int wall, double* L, double* Ldot) {
+                const double* phi, int wall, double* L, double* Ldot, const void* net) {
   if (!config_ok(c)) return 1;
   using D = Dual<1>;
   Ibm ib = build_ibm(*c, phi, wall);
@@ -212,7 +212,7 @@ int orc_rhs_jvp(const Config* c, const double* U, const double* Udot, double gdo
   for (size_t k = 0; k < ne * n; ++k) { Ud[k] = D(U[k]); Ud[k].d[0] = Udot[k]; }
   Field<D> f(c->nx, c->ny), Lf(c->nx, c->ny);
   load_state(*c, Ud.data(), f);
-  run_rhs(*c, P, ib, f, Lf, nullptr, nullptr);
+  run_rhs(*c, P, ib, f, Lf, as_net(net), nullptr);
   std::vector<D> out(ne * n);
   store_state(*c, Lf, out.data());
   for (size_t k = 0; k < ne * n; ++k) { L[k] = out[k].v; Ldot[k] = out[k].d[0]; }
@@ -222,7 +222,7 @@ int orc_rhs_jvp(const Config* c, const double* U, const double* Udot, double gdo
 // Full Jacobian of the RHS by forward mode, one input direction at a time
 // (small grids only): J[out][in] over the external state layout, followed by
 // the columns for gamma and the four inflow primitives (ncols = n + 5).
-int orc_rhs_jacobian(const Config* c, const double* U, const double* phi, int wall, double* J) {
+int orc_rhs_jacobian(const Config* c, const double* U, const double* phi, int wall, double* J, const void* net) {
   if (!config_ok(c)) return 1;
   const size_t n = size_t(nvar_ext(*c)) * c->nx * c->ny;
   std::vector<double> Ud(n, 0.0), L(n), Ld(n);
@@ -233,7 +233,7 @@ int orc_rhs_jacobian(const Config* c, const double* U, const double* phi, int wa
     if (col < n) Ud[col] = 1.0;
     else if (col == n) gd = 1.0;
     else ind[col - n - 1] = 1.0;
-    int rc = orc_rhs_jvp(c, U, Ud.data(), gd, ind, phi, wall, L.data(), Ld.data());
+    int rc = orc_rhs_jvp(c, U, Ud.data(), gd, ind, phi, wall, L.data(), Ld.data(), net);
     if (rc) return rc;
     for (size_t r = 0; r < n; ++r) J[r * ncol + col] = Ld[r];
   }
@@ -242,7 +242,7 @@ int orc_rhs_jacobian(const Config* c, const double* U, const double* phi, int wa
 
 // Tangent of one RK3 step with fixed dt; U and Udot are advanced in place.
 int orc_rk3_step_jvp(const Config* c, double* U, double* Udot, double dt, double gdot,
-                     const double* indot, const double* phi, int wall) {
+                     const double* indot, const double* phi, int wall, const void* net) {
   if (!config_ok(c)) return 1;
   using D = Dual<1>;
   Ibm ib = build_ibm(*c, phi, wall);
@@ -255,7 +255,7 @@ int orc_rk3_step_jvp(const Config* c, double* U, double* Udot, double dt, double
   for (size_t k = 0; k < ne * n; ++k) { Ud[k] = D(U[k]); Ud[k].d[0] = Udot[k]; }
   Field<D> f(c->nx, c->ny);
   load_state(*c, Ud.data(), f);
-  rk3_step(*c, P, ib, f, D(dt), nullptr, nullptr);
+  rk3_step(*c, P, ib, f, D(dt), as_net(net), nullptr);
   store_state(*c, f, Ud.data());
   for (size_t k = 0; k < ne * n; ++k) { U[k] = Ud[k].v; Udot[k] = Ud[k].d[0]; }
   return 0;
@@ -264,7 +264,7 @@ int orc_rk3_step_jvp(const Config* c, double* U, double* Udot, double dt, double
 // Full Jacobian of one fixed-dt RK3 step (small grids), same column layout
 // as orc_rhs_jacobian.
 int orc_rk3_step_jacobian(const Config* c, const double* U, double dt, const double* phi, int wall,
-                          double* J) {
+                          double* J, const void* net) {
   if (!config_ok(c)) return 1;
   const size_t n = size_t(nvar_ext(*c)) * c->nx * c->ny;
   std::vector<double> Uc(n), Ud(n);
@@ -276,7 +276,7 @@ int orc_rk3_step_jacobian(const Config* c, const double* U, double dt, const dou
     if (col < n) Ud[col] = 1.0;
     else if (col == n) gd = 1.0;
     else ind[col - n - 1] = 1.0;
-    int rc = orc_rk3_step_jvp(c, Uc.data(), Ud.data(), dt, gd, ind, phi, wall);
+    int rc = orc_rk3_step_jvp(c, Uc.data(), Ud.data(), dt, gd, ind, phi, wall, net);
     if (rc) return rc;
     for (size_t r = 0; r < n; ++r) J[r * ncol + col] = Ud[r];
   }

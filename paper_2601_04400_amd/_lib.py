@@ -19,7 +19,7 @@ class GridDesc(ctypes.Structure):
         ("x0", _d), ("x1", _d), ("y0", _d), ("y1", _d),
         ("prec", _i), ("gamma", _d), ("cfl", _d), ("weno_eps", _d),
         ("viscous", _i), ("mu", _d), ("prandtl", _d), ("nu_art", _d),
-        ("bc", _i * 4), ("inflow_prim", _d * 4), ("ibm", _i), ("adjoint", _i),
+        ("bc", _i * 4), ("inflow_prim", _d * 4), ("ibm", _i), ("adjoint", _i), ("flux_net", _i),
     ]
 
 
@@ -37,6 +37,14 @@ _SIGS = {
     "shk_rk3_step": (_i, [_p, _p, _p, _p]),
     "shk_rhs_adjoint": (_i, [_p, _p, _p, _p, _p]),
     "shk_rk3_step_adjoint": (_i, [_p, _p, _p, _p, _p]),
+    "shk_set_flux_net": (_i, [_p, _p, _p, _p, ctypes.c_float, _i]),
+    "shk_set_flux_net_grad": (_i, [_p, _p]),
+    "shk_flux_net_eval": (_i, [_p, _p, _p]),
+    "shk_flux_net_vjp": (_i, [_p, _p, _p, _p, _p]),
+    "shk_flux_net_pack": (_i, [_p, _p, _p, _p]),
+    "shk_adam": (_i, [_p, _p, _p, _p, _i, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _i, _p]),
+    "shk_restrict": (_i, [_p, _p, _i, _i, _i, _i, _i, _p]),
+    "shk_mse": (_i, [_p, _p, _p, _d, ctypes.c_longlong, _i, _p, _p, _p]),
     "shk_set_time": (_i, [_p, _d, _d]),
     "shk_get_time": (_i, [_p, _i, _p, _p, _p]),
     "shk_poll_faults": (_i, [_p, _p, _p]),

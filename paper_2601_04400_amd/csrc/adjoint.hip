@@ -386,6 +386,23 @@ __global__ void __launch_bounds__(256) rhs_adjoint_kernel(GridArgs a, const doub
         double gface = 0.0;
         face_vjp(v, a.eps, gamma, Fb, sl, gface);
         if (own) gacc += gface;
+        if (a.dXnet != nullptr) {
+          // stencil gradient of the learned correction at this face
+          long long gfi;
+          if (isx) {
+            const int gf = i0 - M + 3 + k % (TX + 5), gj = j0 + k / (TX + 5);
+            const int gw = (gf >= 0 && gf <= a.nx) ? gf : ((gf % a.nx) + a.nx) % a.nx;
+            gfi = (long long)gj * (a.nx + 1) + gw;
+          } else {
+            const int kk = k - NFX;
+            const int gi = i0 + kk % TX, gf = j0 - M + 3 + kk / TX;
+            const int gw = (gf >= 0 && gf <= a.ny) ? gf : ((gf % a.ny) + a.ny) % a.ny;
+            gfi = (long long)(a.nx + 1) * a.ny + (long long)gw * a.nx + gi;
+          }
+          const float* d = a.dXnet + ((long long)b * a.nface + gfi) * 24;
+          for (int s2 = 0; s2 < 6; ++s2)
+            for (int c2 = 0; c2 < 4; ++c2) sl[s2][c2] += double(d[s2 * 4 + c2]);
+        }
         act = true;
       }
     }

@@ -12,6 +12,7 @@
 
 #include "../../include/shk.h"
 #include "grid.hpp"
+#include "mlp.hpp"
 
 using namespace shk;
 
@@ -22,6 +23,7 @@ using namespace shk;
 struct WsLayout {
   size_t scalars, globals, dtbuf, xslots, u1, u2, cls, row_count, row_off, g_cell, g_src, g_w, g_nrm;
   size_t adjA, adjB, adjC, adjP, adjQ, adjPart, entKeys, entVals, entCount;
+  size_t netF, netX, netPart;
   size_t total;
 };
 
@@ -36,6 +38,9 @@ struct shk_grid {
   GhostTable gt;
   bool ibm_on;
   int nent = 0;  // valid (ghost, source) entries of the refill transpose
+  NetArgs net{};
+  bool net_on = false;
+  float* net_grad = nullptr;
   std::string err;
   // kernel timing (shk_profile)
   bool prof = false;
@@ -73,6 +78,7 @@ bool desc_ok(const shk_grid_desc* d, std::string* why) {
   if (d->viscous && d->ndim != 2) return bad("viscous terms need ndim 2");
   if (d->viscous && (!(d->mu >= 0.0) || !(d->prandtl > 0.0))) return bad("viscous needs mu >= 0, prandtl > 0");
   if (d->ibm && d->ndim != 2) return bad("immersed boundary needs ndim 2");
+  if (d->flux_net && (d->ndim != 2 || d->prec != SHK_F64)) return bad("flux net needs ndim 2 and SHK_F64");
   if (d->nu_art < 0.0) return bad("nu_art must be >= 0");
   return true;
 }
@@ -117,6 +123,16 @@ WsLayout layout(const shk_grid_desc* d) {
       L.entCount = o; o += al(sizeof(int));
     }
   }
+  if (d->flux_net) {
+    const size_t nface = size_t(d->nx + 1) * d->ny + size_t(d->nx) * (d->ny + 1);
+    L.netF = o; o += al(sizeof(float) * 4 * nface * d->nbatch);
+    if (d->adjoint) {
+      L.netX = o; o += al(sizeof(float) * 24 * nface * d->nbatch);
+      size_t nb = (nface + 255) / 256;
+      if (nb > 1024) nb = 1024;
+      L.netPart = o; o += al(sizeof(float) * NET_NP * nb * d->nbatch);
+    }
+  }
   L.total = o;
   return L;
 }
@@ -151,6 +167,16 @@ hipError_t timed(shk_grid* g, int cls, F&& f) {
   return e;
 }
 
+// With the learned correction on, evaluate it for every face of the stage
+// state Us (face-batched MFMA pass) and let the stage kernel add it.
+template <class S>
+hipError_t net_prepare(shk_grid* g, GridArgs& a, const S* Us) {
+  if (!g->net_on) return hipSuccess;
+  float* dF = reinterpret_cast<float*>(g->ws + g->L.netF);
+  a.dF = dF;
+  return launch_net_forward(a, g->net, reinterpret_cast<const double*>(Us), dF, g->st);
+}
+
 template <class S>
 hipError_t stage_launch(shk_grid* g, const GridArgs& a, int mode, const S* Us, const S* Un, S* Uo,
                         const double* dtp, const S* Lin) {
@@ -170,7 +196,7 @@ shk_status stage_seq(shk_grid* g, S* U, const double* dt_in, double* dt_out) {
   S* U1 = reinterpret_cast<S*>(g->ws + g->L.u1);
   S* U2 = reinterpret_cast<S*>(g->ws + g->L.u2);
   hipError_t e;
-  if (!dt_in && !g->ibm_on) {
+  if (!dt_in && !g->ibm_on && !g->net_on) {
     if ((e = timed(g, 1, [&]() { return stage_launch<S>(g, a, MODE_S1L, U, U, U1, nullptr, nullptr); })) != hipSuccess)
       return hip_check(g, e, "stage 1");
     if ((e = timed(g, 2, [&]() { return stage_launch<S>(g, a, MODE_S2F, U, U, U2, nullptr, U1); })) != hipSuccess)
@@ -186,6 +212,8 @@ shk_status stage_seq(shk_grid* g, S* U, const double* dt_in, double* dt_out) {
     dtp = a.dtbuf;
   }
   auto stage = [&](int mode, const S* Us, const S* Un, S* Uo) -> hipError_t {
+    hipError_t en = net_prepare<S>(g, a, Us);
+    if (en != hipSuccess) return en;
     return timed(g, mode, [&]() { return stage_launch<S>(g, a, mode, Us, Un, Uo, dtp, nullptr); });
   };
   auto fill = [&](S* X) -> hipError_t {
@@ -257,6 +285,7 @@ shk_status shk_init_grid(const shk_grid_desc* desc, void* workspace, size_t ws_b
   a.sc = reinterpret_cast<StepScalars*>(g->ws + L.scalars);
   a.glob = reinterpret_cast<Globals*>(g->ws + L.globals);
   a.dtbuf = reinterpret_cast<double*>(g->ws + L.dtbuf);
+  a.nface = (long long)(d.nx + 1) * d.ny + (long long)d.nx * (d.ny + 1);
   a.xslots = reinterpret_cast<unsigned long long*>(g->ws + L.xslots);
   hipError_t e = launch_init_scalars(a, 0.0, std::numeric_limits<double>::infinity(), g->st);
   if (e == hipSuccess) e = hipStreamSynchronize(g->st);
@@ -351,9 +380,11 @@ shk_status shk_rhs(shk_grid* g, void* U, void* dUdt) {
   if (!U || !dUdt || U == dUdt) return fail(g, SHK_EINVAL, "rhs: null or aliased arrays");
   hipError_t e = hipSuccess;
   if (g->esize == 8) {
-    if (g->ibm_on) e = launch_ibm_fill<double>(g->a, g->gt, static_cast<double*>(U), g->st);
+    GridArgs a = g->a;
+    if (g->ibm_on) e = launch_ibm_fill<double>(a, g->gt, static_cast<double*>(U), g->st);
+    if (e == hipSuccess) e = net_prepare<double>(g, a, static_cast<double*>(U));
     if (e == hipSuccess)
-      e = launch_stage<double>(g->a, MODE_RHS, static_cast<double*>(U), static_cast<double*>(U),
+      e = launch_stage<double>(a, MODE_RHS, static_cast<double*>(U), static_cast<double*>(U),
                                static_cast<double*>(dUdt), nullptr, nullptr, g->st);
   } else {
     if (g->ibm_on) e = launch_ibm_fill<float>(g->a, g->gt, static_cast<float*>(U), g->st);
@@ -374,6 +405,22 @@ shk_status shk_rk3_step(shk_grid* g, void* U, const double* dt_in, double* dt_ou
   if (!U) return fail(g, SHK_EINVAL, "rk3_step: null state");
   if (g->esize == 8) return stage_seq<double>(g, static_cast<double*>(U), dt_in, dt_out);
   return stage_seq<float>(g, static_cast<float*>(U), dt_in, dt_out);
+}
+
+// rhs-adjoint launch with the learned correction's reverse pass first (its
+// stencil gradient is then added by the adjoint kernel face by face).
+static hipError_t rhs_adj(shk_grid* g, const double* Us, const double* lam, double clam_f, const double* dtp,
+                          const double* X1, double c1, const double* X2, double c2, double* out, double* param_bar) {
+  GridArgs a = g->a;
+  double* part = reinterpret_cast<double*>(g->ws + g->L.adjPart);
+  if (g->net_on) {
+    float* dX = reinterpret_cast<float*>(g->ws + g->L.netX);
+    float* np = reinterpret_cast<float*>(g->ws + g->L.netPart);
+    hipError_t e = launch_net_backward(a, g->net, Us, lam, clam_f, dtp, dX, np, g->net_grad, g->st);
+    if (e != hipSuccess) return e;
+    a.dXnet = dX;
+  }
+  return launch_rhs_adjoint(a, Us, lam, clam_f, dtp, X1, c1, X2, c2, out, part, param_bar, g->st);
 }
 
 static shk_status adjoint_ok(shk_grid* g) {
@@ -409,9 +456,9 @@ shk_status shk_rhs_adjoint(shk_grid* g, const void* U, const void* dUdt_bar, voi
   double* part = reinterpret_cast<double*>(g->ws + g->L.adjPart);
   hipError_t e = hipMemcpyAsync(A, U, bytes, hipMemcpyDeviceToDevice, g->st);
   if (e == hipSuccess) e = fill64(g, A);
+  (void)part;
   if (e == hipSuccess)
-    e = launch_rhs_adjoint(a, A, static_cast<const double*>(dUdt_bar), 1.0, nullptr, nullptr, 0.0, nullptr, 0.0, P,
-                           part, param_bar, g->st);
+    e = rhs_adj(g, A, static_cast<const double*>(dUdt_bar), 1.0, nullptr, nullptr, 0.0, nullptr, 0.0, P, param_bar);
   if (e == hipSuccess) e = fillT(g, A, P, param_bar);
   if (e == hipSuccess) e = launch_axpy((long long)a.nbatch * 4 * a.ncell, 1.0, P, static_cast<double*>(U_bar), 1, g->st);
   return hip_check(g, e, "rhs_adjoint");
@@ -430,30 +477,102 @@ shk_status shk_rk3_step_adjoint(shk_grid* g, const void* U_n, const double* dt, 
   double* C = reinterpret_cast<double*>(g->ws + g->L.adjC);  // U2 filled
   double* P = reinterpret_cast<double*>(g->ws + g->L.adjP);
   double* Q = reinterpret_cast<double*>(g->ws + g->L.adjQ);
-  double* part = reinterpret_cast<double*>(g->ws + g->L.adjPart);
   double* Ub = static_cast<double*>(U_bar);
   hipError_t e = hipMemcpyAsync(A, U_n, bytes, hipMemcpyDeviceToDevice, g->st);
   // forward recompute of the stage states
   if (e == hipSuccess) e = fill64(g, A);
-  if (e == hipSuccess) e = launch_stage<double>(a, MODE_STAGE1, A, A, B, dt, nullptr, g->st);
+  GridArgs an = a;
+  if (e == hipSuccess) e = net_prepare<double>(g, an, A);
+  if (e == hipSuccess) e = launch_stage<double>(an, MODE_STAGE1, A, A, B, dt, nullptr, g->st);
   if (e == hipSuccess) e = fill64(g, B);
-  if (e == hipSuccess) e = launch_stage<double>(a, MODE_STAGE2, B, A, C, dt, nullptr, g->st);
+  if (e == hipSuccess) e = net_prepare<double>(g, an, B);
+  if (e == hipSuccess) e = launch_stage<double>(an, MODE_STAGE2, B, A, C, dt, nullptr, g->st);
   if (e == hipSuccess) e = fill64(g, C);
   // stage 3: U = 1/3 U^n + 2/3 U2 + 2/3 dt L(U2)
-  if (e == hipSuccess)
-    e = launch_rhs_adjoint(a, C, Ub, 2.0 / 3.0, dt, Ub, 2.0 / 3.0, nullptr, 0.0, P, part, param_bar, g->st);
+  if (e == hipSuccess) e = rhs_adj(g, C, Ub, 2.0 / 3.0, dt, Ub, 2.0 / 3.0, nullptr, 0.0, P, param_bar);
   if (e == hipSuccess) e = launch_axpy(n, 1.0 / 3.0, Ub, Q, 0, g->st);
   if (e == hipSuccess) e = fillT(g, C, P, param_bar);  // P = adjoint of U2
   // stage 2: U2 = 3/4 U^n + 1/4 U1 + dt/4 L(U1)
-  if (e == hipSuccess)
-    e = launch_rhs_adjoint(a, B, P, 0.25, dt, P, 0.25, nullptr, 0.0, Ub, part, param_bar, g->st);
+  if (e == hipSuccess) e = rhs_adj(g, B, P, 0.25, dt, P, 0.25, nullptr, 0.0, Ub, param_bar);
   if (e == hipSuccess) e = launch_axpy(n, 0.75, P, Q, 1, g->st);
   if (e == hipSuccess) e = fillT(g, B, Ub, param_bar);  // Ub = adjoint of U1
   // stage 1: U1 = U^n + dt L(U^n)
-  if (e == hipSuccess) e = launch_rhs_adjoint(a, A, Ub, 1.0, dt, Q, 1.0, Ub, 1.0, P, part, param_bar, g->st);
+  if (e == hipSuccess) e = rhs_adj(g, A, Ub, 1.0, dt, Q, 1.0, Ub, 1.0, P, param_bar);
   if (e == hipSuccess) e = fillT(g, A, P, param_bar);
   if (e == hipSuccess) e = hipMemcpyAsync(Ub, P, bytes, hipMemcpyDeviceToDevice, g->st);
   return hip_check(g, e, "rk3_step_adjoint");
+}
+
+shk_status shk_set_flux_net(shk_grid* g, const uint16_t* w_bf16, const float* bias, const double* norm_host,
+                            float out_scale, int enable) {
+  if (!g) return SHK_EINVAL;
+  if (!enable) {
+    g->net_on = false;
+    return SHK_OK;
+  }
+  if (!g->d.flux_net) return fail(g, SHK_ESTATE, "set_flux_net: grid created without desc.flux_net = 1");
+  if (!w_bf16 || !bias || !norm_host) return fail(g, SHK_EINVAL, "set_flux_net: null array");
+  NetArgs n{};
+  n.w = reinterpret_cast<const unsigned short*>(w_bf16);
+  n.bias = bias;
+  for (int k = 0; k < 4; ++k) {
+    n.mean[k] = norm_host[k];
+    n.inv_std[k] = norm_host[4 + k];
+  }
+  n.out_scale = out_scale;
+  g->net = n;
+  g->net_on = true;
+  return SHK_OK;
+}
+
+shk_status shk_set_flux_net_grad(shk_grid* g, float* grad) {
+  if (!g) return SHK_EINVAL;
+  g->net_grad = grad;
+  return SHK_OK;
+}
+
+shk_status shk_flux_net_eval(shk_grid* g, const void* U, float* dF) {
+  if (!g || !U || !dF) return SHK_EINVAL;
+  if (!g->net_on) return fail(g, SHK_ESTATE, "flux_net_eval: no flux net set");
+  return hip_check(g, launch_net_forward(g->a, g->net, static_cast<const double*>(U), dF, g->st), "flux_net_eval");
+}
+
+shk_status shk_flux_net_vjp(shk_grid* g, const void* U, const void* lam, float* dX, float* grad) {
+  if (!g || !U || !lam || !dX) return SHK_EINVAL;
+  if (!g->net_on) return fail(g, SHK_ESTATE, "flux_net_vjp: no flux net set");
+  if (!g->d.adjoint) return fail(g, SHK_ESTATE, "flux_net_vjp: grid created without desc.adjoint = 1");
+  float* np = reinterpret_cast<float*>(g->ws + g->L.netPart);
+  return hip_check(g,
+                   launch_net_backward(g->a, g->net, static_cast<const double*>(U), static_cast<const double*>(lam),
+                                       1.0, nullptr, dX, np, grad, g->st),
+                   "flux_net_vjp");
+}
+
+shk_status shk_flux_net_pack(const float* theta, uint16_t* w_bf16, float* bias, void* hip_stream) {
+  if (!theta || !w_bf16 || !bias) return SHK_EINVAL;
+  return launch_net_pack(theta, reinterpret_cast<unsigned short*>(w_bf16), bias,
+                         reinterpret_cast<hipStream_t>(hip_stream)) == hipSuccess ? SHK_OK : SHK_EHIP;
+}
+
+shk_status shk_adam(float* theta, const float* grad, float* m, float* v, int n, float lr, float beta1, float beta2,
+                    float eps, int step, void* hip_stream) {
+  if (!theta || !grad || !m || !v || n <= 0 || step < 1) return SHK_EINVAL;
+  return launch_adam(theta, grad, m, v, n, lr, beta1, beta2, eps, step, reinterpret_cast<hipStream_t>(hip_stream)) ==
+                 hipSuccess ? SHK_OK : SHK_EHIP;
+}
+
+shk_status shk_restrict(const double* fine, double* coarse, int nx_f, int ny_f, int factor, int nvar, int nbatch,
+                        void* hip_stream) {
+  if (!fine || !coarse || factor < 1 || nx_f % factor || ny_f % factor || nvar < 1 || nbatch < 1) return SHK_EINVAL;
+  return launch_restrict(fine, coarse, nx_f, ny_f, factor, nvar, nbatch, reinterpret_cast<hipStream_t>(hip_stream)) ==
+                 hipSuccess ? SHK_OK : SHK_EHIP;
+}
+
+shk_status shk_mse(const double* U, const double* T, double* G, double scale, long long per_batch, int nbatch,
+                   double* part, double* loss, void* hip_stream) {
+  if (!U || !T || !part || !loss || per_batch < 1 || nbatch < 1 || nbatch > 4096) return SHK_EINVAL;
+  return launch_mse(U, T, G, scale, per_batch, nbatch, part, loss, reinterpret_cast<hipStream_t>(hip_stream)) ==
+                 hipSuccess ? SHK_OK : SHK_EHIP;
 }
 
 shk_status shk_set_time(shk_grid* g, double t0, double t_end) {

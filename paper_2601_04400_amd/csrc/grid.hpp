@@ -45,6 +45,9 @@ struct GridArgs {
   double* dtbuf;               // [nbatch] step of the automatic time stepping
   double* dt_out;              // optional caller copy of the step (per call)
   unsigned long long* xslots;  // [nbatch][2][XSLOTS] spread extrema of the fused step
+  const float* dF;             // learned flux correction per face [nbatch][nface][4] or nullptr
+  const float* dXnet;          // its stencil gradient per face [nbatch][nface][24] or nullptr
+  long long nface;             // x-faces (nx+1)*ny then y-faces nx*(ny+1)
   Globals* glob;
 };
 

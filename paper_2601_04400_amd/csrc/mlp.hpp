@@ -1,0 +1,39 @@
+// Learned face-flux correction: parameter layout shared by the host API and
+// the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "grid.hpp"
+
+namespace shk {
+
+// Packed parameter vector theta (FP32, the order of gradients and Adam):
+// W0[64][24], b0[64], W1[64][64], b1[64], W2[64][64], b2[64], W3[4][64], b3[4].
+constexpr int NET_G_W0 = 0, NET_G_B0 = 1536, NET_G_W1 = 1600, NET_G_B1 = 5696, NET_G_W2 = 5760,
+              NET_G_B2 = 9856, NET_G_W3 = 9920, NET_G_B3 = 10176, NET_NP = 10180;
+// Device (MFMA) layout: bf16 W0[64][32] (inputs padded), W1[64][64], W2[64][64],
+// W3[16][64] (outputs padded); FP32 biases b0[64], b1[64], b2[64], b3[16].
+constexpr int NET_OFF_W0 = 0, NET_OFF_W1 = 2048, NET_OFF_W2 = 6144, NET_OFF_W3 = 10240, NET_NW = 11264;
+constexpr int NET_OFF_B0 = 0, NET_OFF_B1 = 64, NET_OFF_B2 = 128, NET_OFF_B3 = 192, NET_NB = 208;
+
+struct NetArgs {
+  const unsigned short* w;  // [NET_NW] bf16 bits
+  const float* bias;        // [NET_NB]
+  double mean[4], inv_std[4];
+  float out_scale;
+};
+
+long long net_face_count(const GridArgs& a);
+unsigned int net_backward_blocks(const GridArgs& a);
+hipError_t launch_net_forward(const GridArgs& a, const NetArgs& n, const double* U, float* dF, hipStream_t st);
+hipError_t launch_net_backward(const GridArgs& a, const NetArgs& n, const double* U, const double* lam, double clam_f,
+                               const double* dtp, float* dX, float* part, float* grad, hipStream_t st);
+hipError_t launch_net_pack(const float* theta, unsigned short* w, float* bias, hipStream_t st);
+hipError_t launch_adam(float* theta, const float* grad, float* m, float* v, int n, float lr, float b1, float b2,
+                       float eps, int step, hipStream_t st);
+hipError_t launch_restrict(const double* fine, double* coarse, int nxf, int nyf, int factor, int nvar, int nbatch,
+                           hipStream_t st);
+hipError_t launch_mse(const double* U, const double* T, double* G, double scale, long long per_b, int nbatch,
+                      double* part, double* loss, hipStream_t st);
+
+}  // namespace shk

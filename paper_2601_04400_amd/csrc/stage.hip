@@ -324,6 +324,25 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
       F.f2 = F.f2 - tnt;
       F.f3 = F.f3 - (ubn * tnn + ubt * tnt - qn);
     }
+    if (a.dF != nullptr) {
+      // learned correction of this face (face frame), from the face-batched pass
+      long long gfi = -1;
+      if (isx) {
+        const int fi = k % (TX + 1), y = k / (TX + 1);
+        if (i0 + fi <= a.nx && j0 + y < a.ny) gfi = (long long)(j0 + y) * (a.nx + 1) + i0 + fi;
+      } else {
+        const int kk = k - NFX, x = kk % TX, fj = kk / TX;
+        if (i0 + x < a.nx && j0 + fj <= a.ny)
+          gfi = (long long)(a.nx + 1) * a.ny + (long long)(j0 + fj) * a.nx + i0 + x;
+      }
+      if (gfi >= 0) {
+        const float* d = a.dF + ((long long)b * a.nface + gfi) * 4;
+        F.f0 = F.f0 + C(d[0]);
+        F.f1 = F.f1 + C(d[1]);
+        F.f2 = F.f2 + C(d[2]);
+        F.f3 = F.f3 + C(d[3]);
+      }
+    }
     if (isx) {
       fxs[0][oidx] = F.f0; fxs[1][oidx] = F.f1; fxs[2][oidx] = F.f2; fxs[3][oidx] = F.f3;
     } else {

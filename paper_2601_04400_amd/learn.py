@@ -1,0 +1,264 @@
+"""Learned flux correction: parameters, training on solver-generated data,
+and evaluation against the uncorrected solver.
+
+Section 2 trains the neural flux on low-resolution runs against block-
+averaged high-resolution data with an unrolled m-step mean-squared loss and
+Adam, the gradients flowing back through the solver steps.  Here every piece
+runs in the library's kernels: fine runs and the 4x4 restriction generate the
+data, the coarse solver with the correction is unrolled m steps, the loss
+terms seed the adjoint, shk_rk3_step_adjoint (with the network's reverse
+pass) accumulates the parameter gradient, and shk_adam updates the FP32
+master parameters, which shk_flux_net_pack turns into the bf16 device form.
+The Python code only sequences calls and owns memory.
+"""
+import ctypes
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import inputs
+from ._lib import check, lib
+from .solver import Grid
+
+NP = 10180
+NW, NB = 11264, 208
+# Fixed input normalisation from the sampling ranges of the training initial
+# states (rho, p ~ U[0.1, 1.5]; u, v ~ U[-1, 1]) and the output scale.
+DEFAULT_MEAN = (0.8, 0.0, 0.0, 0.8)
+DEFAULT_STD = (0.4, 0.58, 0.58, 0.4)
+DEFAULT_OUT_SCALE = 0.1
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def init_theta(seed=0, zero_output=False):
+    """He-style random initial parameters in theta order (FP32, host)."""
+    g = np.random.default_rng(seed)
+    parts = []
+    for nout, nin in ((64, 24), (64, 64), (64, 64), (4, 64)):
+        W = g.normal(size=(nout, nin)) * math.sqrt(2.0 / nin)
+        if nout == 4:
+            W = W * (0.0 if zero_output else 0.1)
+        parts += [W.ravel(), np.zeros(nout)]
+    theta = np.concatenate(parts).astype(np.float32)
+    assert theta.size == NP
+    return theta
+
+
+class FluxNet:
+    """FP32 master parameters with Adam state and the bf16 device form."""
+
+    def __init__(self, theta, mean=DEFAULT_MEAN, inv_std=None, out_scale=DEFAULT_OUT_SCALE, device="cuda"):
+        self.theta = torch.as_tensor(np.asarray(theta, dtype=np.float32)).to(device).contiguous()
+        assert self.theta.numel() == NP
+        self.mean = tuple(float(x) for x in mean)
+        self.inv_std = tuple(float(x) for x in (inv_std or [1.0 / s for s in DEFAULT_STD]))
+        self.out_scale = float(out_scale)
+        self.w = torch.empty(NW, dtype=torch.int16, device=device)
+        self.bias = torch.empty(NB, dtype=torch.float32, device=device)
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
+        self.grad = torch.zeros_like(self.theta)
+        self.step_count = 0
+        self.pack()
+
+    def pack(self):
+        check(lib().shk_flux_net_pack(_p(self.theta), _p(self.w), _p(self.bias), _stream()), None, "flux_net_pack")
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_count += 1
+        check(lib().shk_adam(_p(self.theta), _p(self.grad), _p(self.m), _p(self.v), NP, lr, beta1, beta2, eps,
+                             self.step_count, _stream()), None, "adam")
+        self.pack()
+
+
+def restrict(fine, factor):
+    """Block average (device doubles [nb][nv][ny][nx]) by factor."""
+    nb, nv, ny, nx = fine.shape
+    out = torch.empty((nb, nv, ny // factor, nx // factor), dtype=torch.float64, device=fine.device)
+    check(lib().shk_restrict(_p(fine), _p(out), nx, ny, factor, nv, nb, _stream()), None, "restrict")
+    return out
+
+
+def mse_accumulate(U, T, G, scale, loss, part):
+    """loss[b] += ||U_b - T_b||^2 / N; G_b += scale * dloss/dU_b."""
+    nb = U.shape[0]
+    per = U[0].numel()
+    check(lib().shk_mse(_p(U), _p(T), _p(G), float(scale), per, nb, _p(part), _p(loss), _stream()), None, "mse")
+
+
+def riemann_batch(seeds, n, device="cuda"):
+    """Primitive fields of random four-quadrant problems (one per seed)."""
+    W = np.stack([inputs.riemann2d_prim(n, n, states=S) for S in inputs.riemann_batch_states(seeds)])
+    return torch.from_numpy(W).to(device)
+
+
+class Dataset:
+    """Coarse (restricted) snapshots of fine runs: snaps[k] = d(U_fine(k dt_c))."""
+
+    def __init__(self, seeds, nc=128, factor=4, nsnap=24, cfl_frac=0.5, device="cuda", keep_fine_ic=False):
+        nf = nc * factor
+        nb = len(seeds)
+        W = riemann_batch(seeds, nf, device)
+        gf = Grid(nf, nf, nbatch=nb, device=device)
+        Uf = gf.prim_to_cons(W)
+        self.fine_ic = Uf.clone() if keep_fine_ic else None
+        self.factor = factor
+        gc = Grid(nc, nc, nbatch=nb, device=device)
+        U0c = restrict(Uf, factor)
+        # coarse step: a fraction of the CFL step of the initial coarse state
+        d = torch.zeros(nb, dtype=torch.float64, device=device)
+        gc.set_time(0.0, 1e30)
+        gc.step(U0c.clone(), dt_out=d)
+        self.dt_c = (cfl_frac * d).contiguous()
+        dt_f = (self.dt_c / factor).contiguous()
+        snaps = [U0c]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsnap):
+            for _ in range(factor):
+                gf.step(Uf, dt_f)
+            snaps.append(restrict(Uf, factor))
+        torch.cuda.synchronize()
+        self.fine_ms_per_coarse_step = (time.perf_counter() - t0) * 1e3 / max(nsnap, 1)
+        self.snaps = torch.stack(snaps)  # [nsnap+1][nb][4][nc][nc]
+        self.nc, self.nb, self.nsnap = nc, nb, nsnap
+        torch.cuda.synchronize()
+
+
+def train(net, data, iters=400, m=4, lr=1e-3, lr_late=1e-4, switch=None, log_every=50, log=None):
+    """Unrolled m-step training: loss = 1/m sum_s ||U^{n+s} - T^{n+s}||^2
+    (mean over entries, summed over the batch), gradient by the adjoint."""
+    nc, nb = data.nc, data.nb
+    g = Grid(nc, nc, nbatch=nb, adjoint=True, flux_net=True, device=data.snaps.device)
+    g.set_flux_net(net)
+    g.set_flux_net_grad(net.grad)
+    part = torch.empty(nb * 256, dtype=torch.float64, device=data.snaps.device)
+    history = []
+    switch = switch if switch is not None else int(0.875 * iters)
+    for it in range(iters):
+        k = it % (data.nsnap - m + 1)
+        U = data.snaps[k].clone()
+        states = [U.clone()]
+        for s in range(m):
+            g.step(U, data.dt_c)
+            states.append(U.clone())
+        loss = torch.zeros(nb, dtype=torch.float64, device=U.device)
+        net.grad.zero_()
+        Ub = torch.zeros_like(U)
+        for s in range(m, 0, -1):
+            mse_accumulate(states[s], data.snaps[k + s], Ub, 1.0 / m, loss, part)
+            g.step_adjoint(states[s - 1], data.dt_c, Ub, None)
+        net.adam(lr if it < switch else lr_late)
+        L = float(loss.sum()) / m if (log is not None and (it % log_every == 0 or it == iters - 1)) else None
+        if L is not None:
+            history.append((it, k, L))
+            log(f"iter {it} start {k} loss {L:.6e}")
+    g.set_flux_net_grad(None)
+    return history
+
+
+def dataset_loss(net, data, m=4):
+    """Unrolled m-step loss summed over every start index of the data set."""
+    nc, nb = data.nc, data.nb
+    g = Grid(nc, nc, nbatch=nb, flux_net=True, device=data.snaps.device)
+    g.set_flux_net(net)
+    part = torch.empty(nb * 256, dtype=torch.float64, device=data.snaps.device)
+    loss = torch.zeros(nb, dtype=torch.float64, device=data.snaps.device)
+    for k in range(data.nsnap - m + 1):
+        U = data.snaps[k].clone()
+        for s in range(1, m + 1):
+            g.step(U, data.dt_c)
+            mse_accumulate(U, data.snaps[k + s], None, 1.0, loss, part)
+    return float(loss.sum()) / m
+
+
+def evaluate(net, seeds, nc=128, factor=4, nsteps=24, cfl_frac=0.5, device="cuda"):
+    """Held-out error of the coarse solver with and without the correction
+    against the restricted fine solution after nsteps coarse steps, plus the
+    time per coarse step of each, and of the fine solver."""
+    data = Dataset(seeds, nc=nc, factor=factor, nsnap=nsteps, cfl_frac=cfl_frac, device=device,
+                   keep_fine_ic=True)
+    target = data.snaps[-1]
+    out = {f"plain_{nc * factor}": {"l1_error": 0.0, "ms_per_step": data.fine_ms_per_coarse_step,
+                                    "note": "the reference itself (restricted fine solution)"}}
+    if factor >= 4:
+        # intermediate resolution: half the fine spacing, restricted to the coarse grid
+        nm = nc * 2
+        gm = Grid(nm, nm, nbatch=len(seeds), device=device)
+        Um = restrict(data.fine_ic, factor // 2)
+        dtm = (data.dt_c / 2).contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2 * nsteps):
+            gm.step(Um, dtm)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"plain_{nm}"] = {"l1_error": float((restrict(Um, 2) - target).abs().mean()),
+                              "ms_per_step": el * 1e3 / nsteps}
+    for name, use in (("plain", False), ("learned", True)):
+        g = Grid(nc, nc, nbatch=len(seeds), flux_net=True, device=device)
+        g.set_flux_net(net if use else None)
+        U = data.snaps[0].clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            g.step(U, data.dt_c)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        err = float((U - target).abs().mean())
+        out[name if name != "plain" else "plain"] = {"l1_error": err, "ms_per_step": el * 1e3 / nsteps}
+    out[f"learned_{nc}"] = out.pop("learned")
+    out[f"plain_{nc}"] = out.pop("plain")
+    out["learned"] = out[f"learned_{nc}"]
+    out["plain"] = out[f"plain_{nc}"]
+    return out
+
+
+def main():
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="train and evaluate the learned flux correction")
+    ap.add_argument("--train-seeds", type=int, default=64)
+    ap.add_argument("--heldout", type=int, default=16)
+    ap.add_argument("--nc", type=int, default=128)
+    ap.add_argument("--factor", type=int, default=4)
+    ap.add_argument("--nsnap", type=int, default=24)
+    ap.add_argument("--m", type=int, default=4)
+    ap.add_argument("--iters", type=int, default=800)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-late", type=float, default=1e-4)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    t0 = time.perf_counter()
+    data = Dataset(list(range(a.train_seeds)), nc=a.nc, factor=a.factor, nsnap=a.nsnap)
+    print(f"data: {a.train_seeds} problems, {a.nsnap} coarse snapshots, {time.perf_counter() - t0:.1f} s", flush=True)
+    net = FluxNet(init_theta(0, zero_output=True))
+    before = dataset_loss(net, data, m=a.m)
+    t1 = time.perf_counter()
+    hist = train(net, data, iters=a.iters, m=a.m, lr=a.lr, lr_late=a.lr_late, log_every=50,
+                 log=lambda s: print(s, flush=True))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    after = dataset_loss(net, data, m=a.m)
+    ev = evaluate(net, list(range(1000, 1000 + a.heldout)), nc=a.nc, factor=a.factor, nsteps=a.nsnap)
+    res = {"train_problems": a.train_seeds, "heldout_problems": a.heldout, "coarse": a.nc,
+           "fine": a.nc * a.factor, "unroll_m": a.m, "iters": a.iters, "train_seconds": round(train_s, 2),
+           "train_ms_per_iter": round(train_s * 1e3 / a.iters, 3), "training_loss_before": before,
+           "training_loss_after": after, "heldout": ev, "history": hist}
+    print(json.dumps(res), flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

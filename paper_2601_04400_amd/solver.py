@@ -27,7 +27,7 @@ class Grid:
     def __init__(self, nx, ny=1, ndim=2, nbatch=1, domain=(0.0, 1.0, 0.0, 1.0), prec="f64", gamma=1.4,
                  cfl=0.5, weno_eps=1e-6, viscous=False, mu=0.0, prandtl=0.72, nu_art=0.0,
                  bc=(TRANSMISSIVE,) * 4, inflow=(1.0, 0.0, 0.0, 1.0), ibm=False, adjoint=False,
-                 device="cuda"):
+                 flux_net=False, device="cuda"):
         d = GridDesc()
         d.ndim, d.nx, d.ny, d.nbatch = ndim, nx, (1 if ndim == 1 else ny), nbatch
         d.x0, d.x1 = domain[0], domain[1]
@@ -38,7 +38,7 @@ class Grid:
         for k in range(4):
             d.bc[k] = bc[k]
             d.inflow_prim[k] = inflow[k]
-        d.ibm, d.adjoint = int(ibm), int(adjoint)
+        d.ibm, d.adjoint, d.flux_net = int(ibm), int(adjoint), int(flux_net)
         self.desc = d
         self.device = torch.device(device)
         self.dtype = torch.float64 if d.prec == F64 else torch.float32
@@ -55,6 +55,8 @@ class Grid:
               None, "init_grid")
         self.handle = h
         self.phi = None
+        self.net = None
+        self.nface = (nx + 1) * d.ny + nx * (d.ny + 1)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -122,6 +124,37 @@ class Grid:
         self._sync_stream()
         check(lib().shk_rk3_step(self.handle, _ptr(U), _ptr(dt), _ptr(dt_out)), self.handle, "rk3_step")
         return U
+
+    # -- learned flux correction
+    def set_flux_net(self, net):
+        """Attach a learn.FluxNet (its device buffers must stay alive) or None."""
+        if net is None:
+            check(lib().shk_set_flux_net(self.handle, None, None, None, 0.0, 0), self.handle, "set_flux_net")
+            self.net = None
+            return
+        norm = (ctypes.c_double * 8)(*net.mean, *net.inv_std)
+        check(lib().shk_set_flux_net(self.handle, _ptr(net.w), _ptr(net.bias), norm, float(net.out_scale), 1),
+              self.handle, "set_flux_net")
+        self.net = net
+
+    def set_flux_net_grad(self, grad):
+        check(lib().shk_set_flux_net_grad(self.handle, _ptr(grad)), self.handle, "set_flux_net_grad")
+
+    def flux_net_eval(self, U):
+        self._check_state(U)
+        dF = torch.empty((self.shape[0], self.nface, 4), dtype=torch.float32, device=self.device)
+        self._sync_stream()
+        check(lib().shk_flux_net_eval(self.handle, _ptr(U), _ptr(dF)), self.handle, "flux_net_eval")
+        return dF
+
+    def flux_net_vjp(self, U, lam, grad=None):
+        self._check_state(U)
+        self._check_state(lam)
+        dX = torch.empty((self.shape[0], self.nface, 6, 4), dtype=torch.float32, device=self.device)
+        self._sync_stream()
+        check(lib().shk_flux_net_vjp(self.handle, _ptr(U), _ptr(lam), _ptr(dX), _ptr(grad)), self.handle,
+              "flux_net_vjp")
+        return dX
 
     def param_bar(self):
         """Zeroed accumulator for (gamma, inflow rho, u, v, p) derivatives."""

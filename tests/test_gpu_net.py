@@ -1,0 +1,164 @@
+"""GPU learned flux correction (BF16 MFMA, FP32 accumulation) against the
+oracle's double-precision network with every matrix-product operand rounded
+to bfloat16.
+
+Tolerance: 4e-3 of the largest reference value (one bfloat16 unit in the last
+place is 2^-8 = 3.9e-3).  Both sides round the same operands to bfloat16; they
+differ in the accumulation (FP32 vs FP64, K <= 64), which now and then moves
+an activation across a bfloat16 rounding boundary.
+"""
+import numpy as np
+import pytest
+
+from paper_2601_04400_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def to_np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def stencils_periodic(orc, c, U):
+    """Face-frame stencils of every face (x-faces then y-faces) of a periodic
+    grid, from the oracle's primitive variables."""
+    W = orc.cons_to_prim(c, U)  # [4][ny][nx]
+    ny, nx = W.shape[1:]
+    st = []
+    for j in range(ny):
+        for f in range(nx + 1):
+            cells = [(f - 3 + s) % nx for s in range(6)]
+            st.append([[W[0, j, i], W[1, j, i], W[2, j, i], W[3, j, i]] for i in cells])
+    for f in range(ny + 1):
+        for i in range(nx):
+            cells = [(f - 3 + s) % ny for s in range(6)]
+            st.append([[W[0, jj, i], W[2, jj, i], W[1, jj, i], W[3, jj, i]] for jj in cells])
+    return np.array(st)
+
+
+def face_bar_periodic(lam, dx, dy):
+    """Face-flux adjoint (face frame) from a right-hand-side adjoint."""
+    ny, nx = lam.shape[1:]
+    out = []
+    for j in range(ny):
+        for f in range(nx + 1):
+            r, l = f % nx, (f - 1) % nx
+            d = (lam[:, j, r] - lam[:, j, l]) / dx
+            out.append([d[0], d[1], d[2], d[3]])
+    for f in range(ny + 1):
+        for i in range(nx):
+            r, l = f % ny, (f - 1) % ny
+            d = (lam[:, r, i] - lam[:, l, i]) / dy
+            out.append([d[0], d[2], d[1], d[3]])
+    return np.array(out)
+
+
+def make_net(orc, seed, scale_out=1.0):
+    import paper_2601_04400_amd.learn as L
+    theta = L.init_theta(seed)
+    theta[9920:10176] *= 10.0 * scale_out  # a lively output layer for the comparison
+    inv = [1.0 / s for s in L.DEFAULT_STD]
+    gpu = L.FluxNet(theta, L.DEFAULT_MEAN, inv, 0.1)
+    ref = orc.Net(theta, L.DEFAULT_MEAN, inv, 0.1, emulate_bf16=True)
+    return gpu, ref, theta
+
+
+def test_net_forward_vs_oracle(orc):
+    nx, ny = 37, 21
+    from paper_2601_04400_amd import Grid
+    c = orc.config(nx=nx, ny=ny, bc=(3, 3, 3, 3))
+    g = Grid(nx, ny, bc=(3, 3, 3, 3), flux_net=True)
+    net, ref, _ = make_net(orc, 3)
+    g.set_flux_net(net)
+    U = orc.prim_to_cons(c, inputs.smooth_prim(nx, ny, seed=5, amp=0.3))
+    dF = to_np(g.flux_net_eval(torch.from_numpy(U).cuda().reshape(g.shape)))[0]
+    want = ref.forward(stencils_periodic(orc, c, U))
+    assert dF.shape == want.shape
+    scale = np.max(np.abs(want))
+    assert scale > 1e-3
+    assert np.max(np.abs(dF - want)) <= 4e-3 * scale
+
+
+def test_net_reverse_vs_oracle(orc):
+    nx, ny = 37, 21
+    from paper_2601_04400_amd import Grid
+    c = orc.config(nx=nx, ny=ny, bc=(3, 3, 3, 3))
+    g = Grid(nx, ny, bc=(3, 3, 3, 3), flux_net=True, adjoint=True)
+    net, ref, _ = make_net(orc, 4)
+    g.set_flux_net(net)
+    U = orc.prim_to_cons(c, inputs.smooth_prim(nx, ny, seed=6, amp=0.3))
+    lam = np.random.default_rng(2).normal(size=U.shape)
+    grad = torch.zeros(10180, dtype=torch.float32, device="cuda")
+    dX = to_np(g.flux_net_vjp(torch.from_numpy(U).cuda().reshape(g.shape),
+                              torch.from_numpy(lam).cuda().reshape(g.shape), grad))[0]
+    st = stencils_periodic(orc, c, U)
+    Fb = face_bar_periodic(lam, 1.0 / nx, 1.0 / ny)
+    gref, dref = ref.backward(st, Fb)
+    gg = to_np(grad).astype(np.float64)
+    assert np.max(np.abs(dX - dref)) <= 4e-3 * np.max(np.abs(dref))
+    # parameter gradient per layer block
+    for lo, hi in ((0, 1536), (1536, 1600), (1600, 5696), (5696, 5760), (5760, 9856), (9856, 9920),
+                   (9920, 10176), (10176, 10180)):
+        s = np.max(np.abs(gref[lo:hi]))
+        assert np.max(np.abs(gg[lo:hi] - gref[lo:hi])) <= 4e-3 * s + 1e-12, (lo, hi)
+
+
+def test_zero_output_layer_gives_plain_solver(orc):
+    import paper_2601_04400_amd.learn as L
+    from paper_2601_04400_amd import Grid
+    n = 48
+    W = inputs.riemann2d_prim(n, n)
+    net = L.FluxNet(L.init_theta(1, zero_output=True))
+    ga = Grid(n, n, flux_net=True)
+    ga.set_flux_net(net)
+    gb = Grid(n, n)
+    Ua = ga.prim_to_cons(torch.from_numpy(W))
+    Ub = gb.prim_to_cons(torch.from_numpy(W))
+    for _ in range(5):
+        ga.step(Ua, 1e-3)
+        gb.step(Ub, 1e-3)
+    np.testing.assert_array_equal(to_np(Ua), to_np(Ub))
+
+
+def test_step_adjoint_with_net_vs_oracle_jacobian(orc):
+    nx, ny = 20, 12
+    from paper_2601_04400_amd import Grid
+    c = orc.config(nx=nx, ny=ny, y1=ny / nx, bc=(3, 3, 3, 3))
+    g = Grid(nx, ny, domain=(0, 1, 0, ny / nx), bc=(3, 3, 3, 3), flux_net=True, adjoint=True)
+    net, ref, _ = make_net(orc, 5)
+    g.set_flux_net(net)
+    U = orc.prim_to_cons(c, inputs.smooth_prim(nx, ny, seed=8, amp=0.3, domain=(0, 1, 0, ny / nx)))
+    dt = 0.4 * orc.cfl_dt(c, U)
+    J = orc.rk3_step_jacobian(c, U, dt, net=ref)
+    J0 = orc.rk3_step_jacobian(c, U, dt)
+    lam = np.random.default_rng(3).normal(size=U.shape)
+    n = U.size
+    want = (J.T @ lam.ravel())[:n]
+    net_part = want - (J0.T @ lam.ravel())[:n]
+    assert np.max(np.abs(net_part)) > 1e-3 * np.max(np.abs(want))  # the network matters here
+    Ub = torch.from_numpy(lam).cuda().reshape(g.shape).clone()
+    g.step_adjoint(torch.from_numpy(U).cuda().reshape(g.shape), dt, Ub, g.param_bar())
+    got = to_np(Ub).ravel()
+    assert np.max(np.abs(got - want)) <= 4e-3 * np.max(np.abs(net_part)) + 1e-10 * np.max(np.abs(want))
+
+
+def test_training_reduces_loss_and_beats_plain_solver():
+    """Reduced learned-correction run: 16 random Riemann problems at 64^2
+    against 256^2 restricted by 4x4, m = 4 unrolled steps, the output layer
+    starting at zero (the uncorrected solver); the unrolled loss over the
+    training set falls, and on 8 held-out problems the corrected coarse
+    solver ends closer to the restricted fine solution than the uncorrected
+    one."""
+    import paper_2601_04400_amd.learn as L
+    data = L.Dataset(list(range(16)), nc=64, factor=4, nsnap=12)
+    net = L.FluxNet(L.init_theta(0, zero_output=True))
+    before = L.dataset_loss(net, data, m=4)
+    L.train(net, data, iters=400, m=4, lr=1e-3, log_every=50, log=lambda s: print(s, flush=True))
+    after = L.dataset_loss(net, data, m=4)
+    print("training-set loss", before, after, flush=True)
+    assert after < before
+    ev = L.evaluate(net, list(range(1000, 1008)), nc=64, factor=4, nsteps=12)
+    print(ev, flush=True)
+    assert ev["learned"]["l1_error"] < ev["plain"]["l1_error"]
