@@ -9,6 +9,29 @@
 
 namespace shk {
 
+// Quotient a / b without the IEEE division sequence.  double: hardware
+// reciprocal estimate, two Newton steps on it and one correction step on the
+// quotient (error within about one unit in the last place for normal
+// operands); float: hardware reciprocal times a (about one unit in the last
+// place).  Operands here are finite and b != 0.
+__device__ __forceinline__ double qdiv(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(fma(-b, r, 1.0), r, r);
+  r = fma(fma(-b, r, 1.0), r, r);
+  double x = a * r;
+  return fma(fma(-b, x, a), r, x);
+}
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double qrcp(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(fma(-b, r, 1.0), r, r);
+  return fma(fma(-b, r, 1.0), r, r);
+}
+__device__ __forceinline__ float qrcp(float b) { return __builtin_amdgcn_rcpf(b); }
+// Square root: IEEE sequence in double, the hardware estimate in float.
+__device__ __forceinline__ double qsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float qsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 template <class C>
 struct Prim {
   C r, un, ut, p;
@@ -19,7 +42,7 @@ struct Prim {
 template <class C>
 __device__ __forceinline__ Prim<C> to_prim(C rho, C mn, C mt, C E, C gm1) {
   Prim<C> w;
-  C ir = C(1) / rho;
+  C ir = qrcp(rho);
   w.r = rho;
   w.un = mn * ir;
   w.ut = mt * ir;
@@ -50,7 +73,7 @@ __device__ __forceinline__ C weno5(C a, C b, C c, C d, C e, C eps) {
   C q0 = C(2) * a - C(7) * b + C(11) * c;
   C q1 = C(5) * c - b + C(2) * d;
   C q2 = C(2) * c + C(5) * d - e;
-  return (w0 * q0 + w1 * q1 + w2 * q2) / (C(6) * (w0 + w1 + w2));
+  return qdiv(w0 * q0 + w1 * q1 + w2 * q2, C(6) * (w0 + w1 + w2));
 }
 
 // HLLC flux (section 2) in the face-normal frame, components
@@ -77,12 +100,12 @@ __device__ __forceinline__ Flux4<C> hllc_side(const Prim<C>& w, C E, C s, C ss, 
   F.f3 = w.un * (E + w.p);
   if (supersonic) return F;
   C su = s - w.un;
-  C chi = su / (s - ss);
+  C chi = qdiv(su, s - ss);
   C rs = chi * w.r;
   C d0 = rs - w.r;
   C d1 = rs * ss - mn;
   C d2 = rs * w.ut - w.r * w.ut;
-  C d3 = chi * (E + (ss - w.un) * (w.r * ss + w.p / su)) - E;
+  C d3 = chi * (E + (ss - w.un) * (w.r * ss + qdiv(w.p, su))) - E;
   F.f0 = F.f0 + s * d0;
   F.f1 = F.f1 + s * d1;
   F.f2 = F.f2 + s * d2;
@@ -92,12 +115,12 @@ __device__ __forceinline__ Flux4<C> hllc_side(const Prim<C>& w, C E, C s, C ss, 
 
 template <class C>
 __device__ __forceinline__ Flux4<C> hllc(const Prim<C>& L, const Prim<C>& R, C gamma, C igm1) {
-  C aL = sqrt(gamma * L.p / L.r);
-  C aR = sqrt(gamma * R.p / R.r);
+  C aL = qsqrt(qdiv(gamma * L.p, L.r));
+  C aR = qsqrt(qdiv(gamma * R.p, R.r));
   C sL = fmin(L.un - aL, R.un - aR);
   C sR = fmax(L.un + aL, R.un + aR);
   C dL = sL - L.un, dR = sR - R.un;
-  C ss = (R.p - L.p + L.r * L.un * dL - R.r * R.un * dR) / (L.r * dL - R.r * dR);
+  C ss = qdiv(R.p - L.p + L.r * L.un * dL - R.r * R.un * dR, L.r * dL - R.r * dR);
   C EL = L.p * igm1 + C(0.5) * L.r * (L.un * L.un + L.ut * L.ut);
   C ER = R.p * igm1 + C(0.5) * R.r * (R.un * R.un + R.ut * R.ut);
   if (ss > C(0)) return hllc_side(L, EL, sL, ss, sL >= C(0));

@@ -591,7 +591,11 @@ hipError_t launch_init_scalars(const GridArgs& a, double t0, double t_end, hipSt
 }
 
 // 2D tile shape (cells); chosen for 256 threads and a halo overhead near 2x.
-constexpr int TX2 = 32, TY2 = 8;
+#ifndef SHK_TILE_X
+#define SHK_TILE_X 32
+#define SHK_TILE_Y 8
+#endif
+constexpr int TX2 = SHK_TILE_X, TY2 = SHK_TILE_Y;
 constexpr int TX1 = 256;
 
 template <class S, class C, int MODE>

@@ -146,19 +146,19 @@ def test_step_adjoint_with_net_vs_oracle_jacobian(orc):
 
 def test_training_reduces_loss_and_beats_plain_solver():
     """Reduced learned-correction run: 16 random Riemann problems at 64^2
-    against 256^2 restricted by 4x4, m = 4 unrolled steps, the output layer
-    starting at zero (the uncorrected solver); the unrolled loss over the
-    training set falls, and on 8 held-out problems the corrected coarse
-    solver ends closer to the restricted fine solution than the uncorrected
-    one."""
+    against 256^2 restricted by 4x4, m = 8 unrolled steps, the output layer
+    starting at zero (the uncorrected solver).  The unrolled loss over the
+    training set falls, and on 8 held-out problems the corrected coarse solver
+    ends closer (mean squared error, the training metric) to the restricted
+    fine solution after 12 steps than the uncorrected one."""
     import paper_2601_04400_amd.learn as L
     data = L.Dataset(list(range(16)), nc=64, factor=4, nsnap=12)
     net = L.FluxNet(L.init_theta(0, zero_output=True))
     before = L.dataset_loss(net, data, m=4)
-    L.train(net, data, iters=400, m=4, lr=1e-3, log_every=50, log=lambda s: print(s, flush=True))
+    L.train(net, data, iters=300, m=8, lr=1e-3, log_every=50, log=lambda s: print(s, flush=True))
     after = L.dataset_loss(net, data, m=4)
     print("training-set loss", before, after, flush=True)
     assert after < before
     ev = L.evaluate(net, list(range(1000, 1008)), nc=64, factor=4, nsteps=12)
     print(ev, flush=True)
-    assert ev["learned"]["l1_error"] < ev["plain"]["l1_error"]
+    assert ev["learned"]["mse"] < ev["plain"]["mse"]
