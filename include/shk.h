@@ -177,6 +177,23 @@ shk_status shk_rhs_adjoint(shk_grid* g, const void* U, const void* dUdt_bar, voi
  * shk_rhs_adjoint. */
 shk_status shk_rk3_step_adjoint(shk_grid* g, const void* U_n, const double* dt, void* U_bar, double* param_bar);
 
+/* One SSP-RK3 step exactly as shk_rk3_step (fixed dt_in or automatic step,
+ * dt_out as there) that also records the stage-start states for the reverse
+ * pass: tape (device, double, caller-owned, 3 states = 3 * nbatch * 4 * ny *
+ * nx entries) receives U^n, U1 and U2 (section 2 RK3 stages), each after the
+ * immersed-boundary refill.  The automatic step is not fused into the stages
+ * here (one extra reduction launch).  Same requirements as shk_rhs_adjoint;
+ * SHK_EINVAL for a null U or tape. */
+shk_status shk_rk3_step_record(shk_grid* g, void* U, const double* dt_in, double* dt_out, void* tape);
+
+/* Discrete adjoint of one recorded step (as shk_rk3_step_adjoint, with the
+ * stage states read from a tape written by shk_rk3_step_record instead of
+ * recomputed).  dt: device array of the nbatch steps the recorded step used
+ * (dt_in, or its dt_out).  The tape is not modified.  Same requirements as
+ * shk_rhs_adjoint; SHK_EINVAL for a null tape, dt or U_bar. */
+shk_status shk_rk3_step_adjoint_tape(shk_grid* g, const void* tape, const double* dt, void* U_bar,
+                                     double* param_bar);
+
 /* ---- Learned flux correction (section 2 neural flux, per-face MLP form) ----
  * F = F_HLLC + dF with dF = s_out tanh(MLP(x)), x = the 6-cell stencil of
  * (rho, u_n, u_t, p) in the face-normal frame normalised as (w - mean) *

@@ -37,6 +37,8 @@ _SIGS = {
     "shk_rk3_step": (_i, [_p, _p, _p, _p]),
     "shk_rhs_adjoint": (_i, [_p, _p, _p, _p, _p]),
     "shk_rk3_step_adjoint": (_i, [_p, _p, _p, _p, _p]),
+    "shk_rk3_step_record": (_i, [_p, _p, _p, _p, _p]),
+    "shk_rk3_step_adjoint_tape": (_i, [_p, _p, _p, _p, _p]),
     "shk_set_flux_net": (_i, [_p, _p, _p, _p, ctypes.c_float, _i]),
     "shk_set_flux_net_grad": (_i, [_p, _p]),
     "shk_flux_net_eval": (_i, [_p, _p, _p]),

@@ -4,8 +4,10 @@ backward runs the hand-written discrete adjoint kernels with checkpointing.
 Section 2 trains through m unrolled solver steps and infers physical
 parameters by reverse-mode differentiation; here the forward pass keeps a
 copy of the state every `every` steps, and the backward pass replays each
-segment from its checkpoint (recomputing the step-start states) and runs
-shk_rk3_step_adjoint in reverse.  Memory: nsteps/every + every states.
+segment from its checkpoint, recording the stage-start states of every step
+of the segment (shk_rk3_step_record), and then runs the reverse steps from
+those records (shk_rk3_step_adjoint_tape).  Memory: nsteps/every checkpoints
+plus 3 * every recorded states.
 """
 import torch
 
@@ -14,6 +16,8 @@ class _Rollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, U0, params, grid, nsteps, dt, every):
         U = U0.detach().clone()
+        if not torch.is_tensor(dt):
+            dt = torch.full((grid.shape[0],), float(dt), dtype=torch.float64, device=U.device)
         ckpts = [U.clone()]
         for s in range(nsteps):
             grid.step(U, dt)
@@ -28,16 +32,15 @@ class _Rollout(torch.autograd.Function):
         g, dt, every, nsteps = ctx.grid, ctx.dt, ctx.every, ctx.nsteps
         Ub = U_bar.detach().to(dtype=torch.float64).contiguous().clone()
         pb = g.param_bar()
+        tapes = torch.empty((min(every, nsteps), 3) + tuple(g.shape), dtype=torch.float64, device=Ub.device)
         for c in range(len(ctx.ckpts) - 1, -1, -1):
             first = c * every
             count = min(every, nsteps - first)
             U = ctx.ckpts[c].clone()
-            starts = [U.clone()]
-            for _ in range(count - 1):
-                g.step(U, dt)
-                starts.append(U.clone())
+            for k in range(count):
+                g.step_record(U, tapes[k], dt)
             for k in range(count - 1, -1, -1):
-                g.step_adjoint(starts[k], dt, Ub, pb)
+                g.step_adjoint_tape(tapes[k], dt, Ub, pb)
         return Ub, pb, None, None, None, None
 
 

@@ -73,16 +73,22 @@ __device__ __forceinline__ void weno5_vjp(double a, double b, double c, double d
   const double g2 = eps + (k13 * s2 * s2 + 0.25 * t2 * t2);
   const double h0 = g0 * g0, h1 = g1 * g1, h2 = g2 * g2;
   const double w0 = 0.1 * (h1 * h2), w1 = 0.6 * (h0 * h2), w2 = 0.3 * (h0 * h1);
-  const double is = 1.0 / (w0 + w1 + w2);
+  // one reciprocal serves the normalisation and the three 1/g_k:
+  // r = 1/(S P) with S = w0 + w1 + w2 and P = g0 g1 g2 (both positive and
+  // far from the double range limits since g_k >= eps)
+  const double S = w0 + w1 + w2, P = g0 * g1 * g2;
+  const double r = qrcp(S * P);
+  const double is = P * r, iP = S * r;
   const double o0 = w0 * is, o1 = w1 * is, o2 = w2 * is;
   const double q0 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
   const double q1 = (5.0 * c - b + 2.0 * d) * (1.0 / 6.0);
   const double q2 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
   const double f = o0 * q0 + o1 * q1 + o2 * q2;
   const double qb0 = fb * o0, qb1 = fb * o1, qb2 = fb * o2;
-  const double bb0 = -2.0 * fb * o0 * (q0 - f) / g0;
-  const double bb1 = -2.0 * fb * o1 * (q1 - f) / g1;
-  const double bb2 = -2.0 * fb * o2 * (q2 - f) / g2;
+  const double m2 = -2.0 * fb * iP;
+  const double bb0 = m2 * o0 * (q0 - f) * (g1 * g2);
+  const double bb1 = m2 * o1 * (q1 - f) * (g0 * g2);
+  const double bb2 = m2 * o2 * (q2 - f) * (g0 * g1);
   const double sb0 = bb0 * (2.0 * k13) * s0, tb0 = bb0 * 0.5 * t0;
   const double sb1 = bb1 * (2.0 * k13) * s1, tb1 = bb1 * 0.5 * t1;
   const double sb2 = bb2 * (2.0 * k13) * s2, tb2 = bb2 * 0.5 * t2;
@@ -108,10 +114,11 @@ __device__ __forceinline__ void hllc_side_vjp(const Prim<double>& w, double E, d
   if (!sup) {
     const double su = s - w.un;
     const double den = s - ss;
-    const double chi = su / den;
+    const double chi = qdiv(su, den);
+    const double iden = qrcp(den), isu = qrcp(su);
     const double rs = chi * w.r;
     const double d0 = rs - w.r, d1 = rs * ss - mn, d2 = rs * w.ut - w.r * w.ut;
-    const double C = w.r * ss + w.p / su;
+    const double C = w.r * ss + qdiv(w.p, su);
     const double B = E + (ss - w.un) * C;
     const double d3 = chi * B - E;
     sb += Fb[0] * d0 + Fb[1] * d1 + Fb[2] * d2 + Fb[3] * d3;
@@ -131,12 +138,12 @@ __device__ __forceinline__ void hllc_side_vjp(const Prim<double>& w, double E, d
     const double Cb = Bb * (ss - w.un);
     wb.r += Cb * ss;
     ssb += Cb * w.r;
-    wb.p += Cb / su;
-    double sub = -Cb * w.p / (su * su);
+    wb.p += Cb * isu;
+    double sub = -Cb * w.p * (isu * isu);
     chib += rsb * w.r;
     wb.r += rsb * chi;
-    sub += chib / den;
-    const double denb = -chib * chi / den;
+    sub += chib * iden;
+    const double denb = -chib * chi * iden;
     sb += denb;
     ssb -= denb;
     sb += sub;
@@ -155,9 +162,11 @@ __device__ __forceinline__ void hllc_side_vjp(const Prim<double>& w, double E, d
 // Reverse of the HLLC flux in the face-normal frame.
 __device__ __forceinline__ void hllc_vjp(const Prim<double>& L, const Prim<double>& R, double gamma,
                                          const double Fb[4], PB& Lb, PB& Rb, double& gb) {
-  const double gm1 = gamma - 1.0, igm1 = 1.0 / gm1;
-  const double zL = gamma * L.p / L.r, zR = gamma * R.p / R.r;
-  const double aL = sqrt(zL), aR = sqrt(zR);
+  const double gm1 = gamma - 1.0, igm1 = qrcp(gm1);
+  const double irL = qrcp(L.r), irR = qrcp(R.r);
+  // sound speeds exactly as the forward flux evaluates them
+  const double zL = qdiv(gamma * L.p, L.r), zR = qdiv(gamma * R.p, R.r);
+  const double aL = qsqrt(zL), aR = qsqrt(zR);
   const bool minL = (L.un - aL) <= (R.un - aR);
   const bool maxL = (L.un + aL) >= (R.un + aR);
   const double sL = minL ? L.un - aL : R.un - aR;
@@ -165,7 +174,8 @@ __device__ __forceinline__ void hllc_vjp(const Prim<double>& L, const Prim<doubl
   const double dL = sL - L.un, dR = sR - R.un;
   const double num = R.p - L.p + L.r * L.un * dL - R.r * R.un * dR;
   const double den = L.r * dL - R.r * dR;
-  const double ss = num / den;
+  const double ss = qdiv(num, den);
+  const double iden = qrcp(den);
   const double EL = L.p * igm1 + 0.5 * L.r * (L.un * L.un + L.ut * L.ut);
   const double ER = R.p * igm1 + 0.5 * R.r * (R.un * R.un + R.ut * R.ut);
   double ELb = 0.0, ERb = 0.0, sLb = 0.0, sRb = 0.0, ssb = 0.0;
@@ -192,8 +202,8 @@ __device__ __forceinline__ void hllc_vjp(const Prim<double>& L, const Prim<doubl
   Rb.un += ERb * R.r * R.un;
   Rb.ut += ERb * R.r * R.ut;
   // contact speed
-  const double numb = ssb / den;
-  const double denb = -ssb * ss / den;
+  const double numb = ssb * iden;
+  const double denb = -ssb * ss * iden;
   Rb.p += numb;
   Lb.p -= numb;
   Lb.r += numb * L.un * dL;
@@ -215,50 +225,67 @@ __device__ __forceinline__ void hllc_vjp(const Prim<double>& L, const Prim<doubl
   if (minL) { Lb.un += sLb; aLb -= sLb; } else { Rb.un += sLb; aRb -= sLb; }
   if (maxL) { Lb.un += sRb; aLb += sRb; } else { Rb.un += sRb; aRb += sRb; }
   // sound speeds a = sqrt(gamma p / rho)
-  const double zLb = aLb / (2.0 * aL), zRb = aRb / (2.0 * aR);
-  gb += zLb * L.p / L.r + zRb * R.p / R.r;
-  Lb.p += zLb * gamma / L.r;
-  Lb.r -= zLb * zL / L.r;
-  Rb.p += zRb * gamma / R.r;
-  Rb.r -= zRb * zR / R.r;
+  const double zLb = qdiv(0.5 * aLb, aL), zRb = qdiv(0.5 * aRb, aR);
+  gb += zLb * L.p * irL + zRb * R.p * irR;
+  Lb.p += zLb * gamma * irL;
+  Lb.r -= zLb * zL * irL;
+  Rb.p += zRb * gamma * irR;
+  Rb.r -= zRb * zR * irR;
 }
 
-// Forward recompute and reverse of one face: stencil values v[comp][6] in the
-// face frame, upstream flux gradient Fb -> stencil gradients sl[6][4].
-__device__ __forceinline__ void face_vjp(const double v[4][6], double eps, double gamma, const double Fb[4],
-                                         double sl[6][4], double& gb) {
+// Forward recompute and reverse of one face.  The stencil is read from LDS:
+// component k of stencil cell s at q[k][s * st] (face frame: rho, normal
+// velocity, tangential velocity, p).  Upstream flux gradient Fb -> stencil
+// gradients sl[6][4].  The reverse re-reads the stencil and recomputes the
+// WENO weights instead of keeping the forward's intermediates alive (the
+// loads and inputs are hidden from common-subexpression elimination), which
+// keeps the register footprint at a level that lets several waves share a
+// SIMD.
+__device__ __forceinline__ void face_vjp(const double* q0, const double* q1, const double* q2, const double* q3,
+                                         int st, double eps, double gamma, const double Fb[4], double sl[6][4],
+                                         double& gb) {
+  const double* q[4] = {q0, q1, q2, q3};
   Prim<double> L, R;
-  L.r = weno5(v[0][0], v[0][1], v[0][2], v[0][3], v[0][4], eps);
-  R.r = weno5(v[0][5], v[0][4], v[0][3], v[0][2], v[0][1], eps);
-  L.un = weno5(v[1][0], v[1][1], v[1][2], v[1][3], v[1][4], eps);
-  R.un = weno5(v[1][5], v[1][4], v[1][3], v[1][2], v[1][1], eps);
-  L.ut = weno5(v[2][0], v[2][1], v[2][2], v[2][3], v[2][4], eps);
-  R.ut = weno5(v[2][5], v[2][4], v[2][3], v[2][2], v[2][1], eps);
-  L.p = weno5(v[3][0], v[3][1], v[3][2], v[3][3], v[3][4], eps);
-  R.p = weno5(v[3][5], v[3][4], v[3][3], v[3][2], v[3][1], eps);
+  double* Lp[4] = {&L.r, &L.un, &L.ut, &L.p};
+  double* Rp[4] = {&R.r, &R.un, &R.ut, &R.p};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double v[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = q[c][k * st];
+    *Lp[c] = weno5(v[0], v[1], v[2], v[3], v[4], eps);
+    *Rp[c] = weno5(v[5], v[4], v[3], v[2], v[1], eps);
+  }
   const bool fallback = !(L.r > 0.0) || !(L.p > 0.0) || !(R.r > 0.0) || !(R.p > 0.0);
   if (fallback) {
-    L = Prim<double>{v[0][2], v[1][2], v[2][2], v[3][2]};
-    R = Prim<double>{v[0][3], v[1][3], v[2][3], v[3][3]};
+    L = Prim<double>{q0[2 * st], q1[2 * st], q2[2 * st], q3[2 * st]};
+    R = Prim<double>{q0[3 * st], q1[3 * st], q2[3 * st], q3[3 * st]};
   }
   PB Lb, Rb;
   hllc_vjp(L, R, gamma, Fb, Lb, Rb, gb);
   const double lb[4] = {Lb.r, Lb.un, Lb.ut, Lb.p};
   const double rb[4] = {Rb.r, Rb.un, Rb.ut, Rb.p};
+#pragma unroll
   for (int c = 0; c < 4; ++c)
+#pragma unroll
     for (int s = 0; s < 6; ++s) sl[s][c] = 0.0;
   if (fallback) {
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
       sl[2][c] = lb[c];
       sl[3][c] = rb[c];
     }
     return;
   }
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
-    weno5_vjp(v[c][0], v[c][1], v[c][2], v[c][3], v[c][4], eps, lb[c], sl[0][c], sl[1][c], sl[2][c], sl[3][c],
-              sl[4][c]);
-    weno5_vjp(v[c][5], v[c][4], v[c][3], v[c][2], v[c][1], eps, rb[c], sl[5][c], sl[4][c], sl[3][c], sl[2][c],
-              sl[1][c]);
+    int off = 0;
+    asm volatile("" : "+v"(off));
+    double x[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) x[k] = q[c][off + k * st];
+    weno5_vjp(x[0], x[1], x[2], x[3], x[4], eps, lb[c], sl[0][c], sl[1][c], sl[2][c], sl[3][c], sl[4][c]);
+    weno5_vjp(x[5], x[4], x[3], x[2], x[1], eps, rb[c], sl[5][c], sl[4][c], sl[3][c], sl[2][c], sl[1][c]);
   }
 }
 
@@ -281,17 +308,17 @@ __device__ __forceinline__ double lam_at(const GridArgs& a, const double* __rest
 
 }  // namespace
 
-// out = J^T (clam_f dt lam) + c1 X1 + c2 X2 for every cell of the tile, where J
-// is the Jacobian of the right-hand side at the stage state Us.  part receives
-// this block's partial derivatives (gamma, rho_in, u_in, v_in, p_in).
-template <int TX, int TY>
-__global__ void __launch_bounds__(256) rhs_adjoint_kernel(GridArgs a, const double* __restrict__ Us,
+// out = J^T (clam_f dt lam) + c1 X1 + c2 X2 + c3 X3 for every cell of the
+// tile, where J is the Jacobian of the right-hand side at the stage state Us.
+// The X terms are read at the thread's own cell only, so out may alias one of
+// them (never lam).  part receives this block's partial derivatives (gamma,
+// rho_in, u_in, v_in, p_in).
+template <int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) rhs_adjoint_kernel(GridArgs a, const double* __restrict__ Us,
                                                           const double* __restrict__ lam, double clam_f,
-                                                          const double* __restrict__ dtp,
-                                                          const double* __restrict__ X1, double c1,
-                                                          const double* __restrict__ X2, double c2,
-                                                          double* __restrict__ out, double* __restrict__ part) {
-  constexpr int NT = 256;
+                                                          const double* __restrict__ dtp, const double* X1,
+                                                          double c1, const double* X2, double c2, const double* X3,
+                                                          double c3, double* out, double* __restrict__ part) {
   constexpr int M = 5;
   constexpr int PX = TX + 2 * M, PY = TY + 2 * M;
   constexpr int NFX = (TX + 5) * TY, NFY = TX * (TY + 5);
@@ -300,8 +327,9 @@ __global__ void __launch_bounds__(256) rhs_adjoint_kernel(GridArgs a, const doub
   __shared__ double ay[4][PY * TX];
   __shared__ double red[5][NT / 64];
 
-  const int b = blockIdx.z;
-  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  int bx, by, b;
+  xcd_tile(bx, by, b);
+  const int i0 = bx * TX, j0 = by * TY;
   const long long boff = (long long)b * 4 * a.ncell;
   const double* __restrict__ Ub = Us + boff;
   const double* __restrict__ Lb = lam + boff;
@@ -329,6 +357,7 @@ __global__ void __launch_bounds__(256) rhs_adjoint_kernel(GridArgs a, const doub
   __syncthreads();
 
   double gacc = 0.0;
+#pragma unroll 1
   for (int base = 0; base < NFX + NFY; base += NT) {
     const int k = base + threadIdx.x;
     bool act = false, isx = true, own = false;
@@ -376,15 +405,8 @@ __global__ void __launch_bounds__(256) rhs_adjoint_kernel(GridArgs a, const doub
         }
       }
       if (valid && (Fb[0] != 0.0 || Fb[1] != 0.0 || Fb[2] != 0.0 || Fb[3] != 0.0)) {
-        double v[4][6];
-        for (int s = 0; s < 6; ++s) {
-          v[0][s] = w[0][s0 + s * st];
-          v[1][s] = w[cn][s0 + s * st];
-          v[2][s] = w[ct][s0 + s * st];
-          v[3][s] = w[3][s0 + s * st];
-        }
         double gface = 0.0;
-        face_vjp(v, a.eps, gamma, Fb, sl, gface);
+        face_vjp(&w[0][s0], &w[cn][s0], &w[ct][s0], &w[3][s0], st, a.eps, gamma, Fb, sl, gface);
         if (own) gacc += gface;
         if (a.dXnet != nullptr) {
           // stencil gradient of the learned correction at this face
@@ -505,6 +527,7 @@ __global__ void __launch_bounds__(256) rhs_adjoint_kernel(GridArgs a, const doub
       double val = Uo[c];
       if (X1) val += c1 * X1[o];
       if (X2) val += c2 * X2[o];
+      if (X3) val += c3 * X3[o];
       out[o] = val;
     }
   }
@@ -520,7 +543,7 @@ __global__ void __launch_bounds__(256) rhs_adjoint_kernel(GridArgs a, const doub
   if (threadIdx.x < 5) {
     double s = 0.0;
     for (int k = 0; k < NT / 64; ++k) s += red[threadIdx.x][k];
-    const long long blk = ((long long)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const long long blk = ((long long)b * gridDim.y + by) * gridDim.x + bx;
     part[blk * 5 + threadIdx.x] = s;
   }
 }
@@ -548,68 +571,106 @@ __global__ void __launch_bounds__(256) ibm_entries_rank_kernel(GhostTable gt, in
 }
 
 // X (adjoint w.r.t. the filled state) -> adjoint w.r.t. the state before the
-// refill: each source cell gathers the shares of the ghosts that read it.
-// One thread per run of equal keys (the first entry of the run).
-__global__ void __launch_bounds__(256) ibm_fill_adjoint_kernel(GridArgs a, GhostTable gt, const int* __restrict__ keys,
-                                                               const int* __restrict__ vals, int nent,
-                                                               const double* __restrict__ Us, double* __restrict__ X,
-                                                               double* __restrict__ part) {
-  __shared__ double red[4];
-  const int b = blockIdx.y;
+// refill.  One workgroup per batch member (the ghost list is short: about a
+// thousand entries at 1024 x 512), in two passes separated by a barrier:
+// 1. per ghost: recompute the image-point primitives and the wall rule,
+//    reverse the ghost's conservative state into the adjoint of the image-
+//    point primitives gW[k] = (rho, u, v, p)_bar, and clear X at the ghost
+//    (the refill overwrites it, so its pre-refill adjoint is zero);
+// 2. per run of equal keys in the sorted (source, entry) list: the source
+//    cell gathers w_m gW[k] over the ghosts k that read it, in entry order,
+//    then the primitive -> conservative transpose at the source.
+// The gamma parts of both passes are summed in a fixed order into the
+// member's partial; with fin set, the member's recorded partials of the
+// whole reverse pass (slots of ps, this launch's own last) are then added to
+// param_bar here instead of in a separate launch.
+constexpr int FILL_NT = 1024;
+
+__device__ __forceinline__ double block_sum_fixed(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < FILL_NT / 64; ++k) s += red[k];
+  return s;
+}
+
+__global__ void __launch_bounds__(FILL_NT) ibm_fill_adjoint_kernel(GridArgs a, GhostTable gt,
+                                                                   const int* __restrict__ keys,
+                                                                   const int* __restrict__ vals, int nent,
+                                                                   const double* __restrict__ Us, double* __restrict__ X,
+                                                                   double* __restrict__ gW, double* __restrict__ part,
+                                                                   PartSlots ps, double* __restrict__ param_bar) {
+  __shared__ double red[FILL_NT / 64];
+  const int b = blockIdx.x;
   const long long n = a.ncell;
   const double* __restrict__ Ub = Us + (long long)b * 4 * n;
   double* __restrict__ Xb = X + (long long)b * 4 * n;
-  const double gamma = a.gamma, gm1 = gamma - 1.0;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double* __restrict__ gWb = gW + (long long)b * 4 * gt.n;
+  const double gm1 = a.gamma - 1.0;
   double gacc = 0.0;
-  if (i < nent && (i == 0 || keys[i] != keys[i - 1])) {
+  for (int k = threadIdx.x; k < gt.n; k += FILL_NT) {
+    double Wi[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int sm = gt.src[4 * k + m];
+      if (sm < 0) continue;
+      const double wm = gt.w[4 * k + m];
+      const double r = Ub[sm];
+      const double u = Ub[n + sm] / r, v = Ub[2 * n + sm] / r;
+      const double p = gm1 * (Ub[3 * n + sm] - 0.5 * r * (u * u + v * v));
+      Wi[0] += wm * r; Wi[1] += wm * u; Wi[2] += wm * v; Wi[3] += wm * p;
+    }
+    const double nxv = gt.nrm[2 * k], nyv = gt.nrm[2 * k + 1];
+    double ug, vg;
+    if (gt.wall == 0) {
+      const double un = Wi[1] * nxv + Wi[2] * nyv;
+      ug = Wi[1] - 2.0 * un * nxv;
+      vg = Wi[2] - 2.0 * un * nyv;
+    } else {
+      ug = -Wi[1];
+      vg = -Wi[2];
+    }
+    // reverse of U_g = (rho, rho ug, rho vg, p/(gamma-1) + rho (ug^2+vg^2)/2)
+    const int gc = gt.cell[k];
+    const double X0 = Xb[gc], X1 = Xb[n + gc], X2 = Xb[2 * n + gc], X3 = Xb[3 * n + gc];
+    const double rb = X0 + X1 * ug + X2 * vg + X3 * 0.5 * (ug * ug + vg * vg);
+    const double ugb = X1 * Wi[0] + X3 * Wi[0] * ug;
+    const double vgb = X2 * Wi[0] + X3 * Wi[0] * vg;
+    const double pb = X3 / gm1;
+    gacc -= X3 * Wi[3] / (gm1 * gm1);
+    double Wub, Wvb;
+    if (gt.wall == 0) {
+      const double unb = -2.0 * (ugb * nxv + vgb * nyv);
+      Wub = ugb + unb * nxv;
+      Wvb = vgb + unb * nyv;
+    } else {
+      Wub = -ugb;
+      Wvb = -vgb;
+    }
+    gWb[4 * k] = rb;
+    gWb[4 * k + 1] = Wub;
+    gWb[4 * k + 2] = Wvb;
+    gWb[4 * k + 3] = pb;
+    Xb[gc] = 0.0;
+    Xb[n + gc] = 0.0;
+    Xb[2 * n + gc] = 0.0;
+    Xb[3 * n + gc] = 0.0;
+  }
+  __syncthreads();  // gW complete (global memory, one workgroup)
+  for (int i = threadIdx.x; i < nent; i += FILL_NT) {
+    if (i > 0 && keys[i] == keys[i - 1]) continue;
     const int src = keys[i];
     double Wsb[4] = {0.0, 0.0, 0.0, 0.0};
     for (int j = i; j < nent && keys[j] == src; ++j) {
       const int e = vals[j];
-      const int k = e >> 2, m = e & 3;
-      // forward of ghost k: image-point primitives, then the wall rule
-      double Wi[4] = {0.0, 0.0, 0.0, 0.0};
-      int first = -1;
-      for (int mm = 0; mm < 4; ++mm) {
-        const int sm = gt.src[4 * k + mm];
-        if (sm < 0) continue;
-        if (first < 0) first = mm;
-        const double wm = gt.w[4 * k + mm];
-        const double r = Ub[sm];
-        const double u = Ub[n + sm] / r, v = Ub[2 * n + sm] / r;
-        const double p = gm1 * (Ub[3 * n + sm] - 0.5 * r * (u * u + v * v));
-        Wi[0] += wm * r; Wi[1] += wm * u; Wi[2] += wm * v; Wi[3] += wm * p;
-      }
-      const double nxv = gt.nrm[2 * k], nyv = gt.nrm[2 * k + 1];
-      double ug, vg;
-      if (gt.wall == 0) {
-        const double un = Wi[1] * nxv + Wi[2] * nyv;
-        ug = Wi[1] - 2.0 * un * nxv;
-        vg = Wi[2] - 2.0 * un * nyv;
-      } else {
-        ug = -Wi[1];
-        vg = -Wi[2];
-      }
-      // reverse of U_g = (rho, rho ug, rho vg, p/(gamma-1) + rho (ug^2+vg^2)/2)
-      const int gc = gt.cell[k];
-      const double X0 = Xb[gc], X1 = Xb[n + gc], X2 = Xb[2 * n + gc], X3 = Xb[3 * n + gc];
-      const double rb = X0 + X1 * ug + X2 * vg + X3 * 0.5 * (ug * ug + vg * vg);
-      const double ugb = X1 * Wi[0] + X3 * Wi[0] * ug;
-      const double vgb = X2 * Wi[0] + X3 * Wi[0] * vg;
-      const double pb = X3 / gm1;
-      if (m == first) gacc -= X3 * Wi[3] / (gm1 * gm1);
-      double Wub, Wvb;
-      if (gt.wall == 0) {
-        const double unb = -2.0 * (ugb * nxv + vgb * nyv);
-        Wub = ugb + unb * nxv;
-        Wvb = vgb + unb * nyv;
-      } else {
-        Wub = -ugb;
-        Wvb = -vgb;
-      }
-      const double wm = gt.w[4 * k + m];
-      Wsb[0] += wm * rb; Wsb[1] += wm * Wub; Wsb[2] += wm * Wvb; Wsb[3] += wm * pb;
+      const int k = e >> 2;
+      const double wm = gt.w[e];
+      Wsb[0] += wm * gWb[4 * k];
+      Wsb[1] += wm * gWb[4 * k + 1];
+      Wsb[2] += wm * gWb[4 * k + 2];
+      Wsb[3] += wm * gWb[4 * k + 3];
     }
     const double r = Ub[src];
     const double u = Ub[n + src] / r, v = Ub[2 * n + src] / r;
@@ -621,35 +682,39 @@ __global__ void __launch_bounds__(256) ibm_fill_adjoint_kernel(GridArgs a, Ghost
     Xb[3 * n + src] += Wsb[3] * gm1;
     gacc += Wsb[3] * (E - r * ke);
   }
-  double v = gacc;
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const long long blk = (long long)b * gridDim.x + blockIdx.x;
-    part[blk * 5] = red[0] + red[1] + red[2] + red[3];
-    for (int q = 1; q < 5; ++q) part[blk * 5 + q] = 0.0;
+  const double g = block_sum_fixed(gacc, red);
+  if (param_bar == nullptr) {
+    if (threadIdx.x < 5) part[(long long)b * 5 + threadIdx.x] = threadIdx.x == 0 ? g : 0.0;
+    return;
+  }
+  // finalize: member b's recorded partials, slot by slot, then this launch's
+  for (int q = 0; q < 5; ++q) {
+    double sq = 0.0;
+    for (int slot = 0; slot < ps.n; ++slot) {
+      const double* p = part - (ps.n - slot) * ps.stride;  // earlier slots precede this one
+      const int nb = ps.nblk[slot];
+      for (int k = threadIdx.x; k < nb; k += FILL_NT) sq += p[((long long)b * nb + k) * 5 + q];
+    }
+    sq = block_sum_fixed(sq, red);
+    if (threadIdx.x == 0) param_bar[b * 5 + q] += sq + (q == 0 ? g : 0.0);
   }
 }
 
-// The refill overwrites the ghost cells, so their pre-refill adjoint is zero.
-__global__ void __launch_bounds__(256) ibm_zero_ghosts_kernel(GridArgs a, GhostTable gt, double* __restrict__ X) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= gt.n) return;
-  double* Xb = X + (long long)blockIdx.y * 4 * a.ncell;
-  const int c = gt.cell[k];
-  for (int v = 0; v < 4; ++v) Xb[v * a.ncell + c] = 0.0;
-}
-
-// param_bar[b][q] += sum over the blocks of member b of part (fixed order).
-__global__ void __launch_bounds__(64) partials_finalize_kernel(const double* __restrict__ part, int nblk_per_b,
-                                                               int nbatch, double* __restrict__ param_bar) {
-  const int t = threadIdx.x;
-  if (t >= 5 * nbatch) return;
-  const int b = t / 5, q = t % 5;
+// param_bar[b][q] += the recorded partials of member b: one wave per q, lane
+// l sums the entries l, l + 64, ... of every slot in order, then a fixed
+// butterfly adds the 64 lane sums (the same order on every call).
+__global__ void __launch_bounds__(320) partials_finalize_kernel(const double* __restrict__ part, PartSlots ps,
+                                                                double* __restrict__ param_bar) {
+  const int b = blockIdx.x;
+  const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double s = 0.0;
-  for (int k = 0; k < nblk_per_b; ++k) s += part[((long long)b * nblk_per_b + k) * 5 + q];
-  param_bar[b * 5 + q] += s;
+  for (int slot = 0; slot < ps.n; ++slot) {
+    const double* p = part + slot * ps.stride;
+    const int nb = ps.nblk[slot];
+    for (int k = lane; k < nb; k += 64) s += p[((long long)b * nb + k) * 5 + q];
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) param_bar[b * 5 + q] += s;
 }
 
 // y = alpha x (+ y if accumulate), elementwise over n entries.
@@ -660,20 +725,26 @@ __global__ void __launch_bounds__(256) axpy_kernel(long long n, double alpha, co
 }
 
 // ------------------------------------------------------------------ launchers
-constexpr int ATX = 32, ATY = 8;
+// 32 x 8 tiles with 768 threads: the tile's 712 faces are reversed in one
+// round (three waves per SIMD at <= 168 registers).
+constexpr int ATX = 32, ATY = 8, ANT = 768;
 
 int adjoint_blocks(const GridArgs& a) { return ((a.nx + ATX - 1) / ATX) * ((a.ny + ATY - 1) / ATY); }
 
 hipError_t launch_rhs_adjoint(const GridArgs& a, const double* Us, const double* lam, double clam_f,
                               const double* dtp, const double* X1, double c1, const double* X2, double c2,
-                              double* out, double* part, double* param_bar, hipStream_t st) {
+                              const double* X3, double c3, double* out, double* part, int* nblk, hipStream_t st) {
   dim3 grid((a.nx + ATX - 1) / ATX, (a.ny + ATY - 1) / ATY, a.nbatch);
-  hipLaunchKernelGGL((rhs_adjoint_kernel<ATX, ATY>), grid, dim3(256), 0, st, a, Us, lam, clam_f, dtp, X1, c1, X2,
-                     c2, out, part);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !param_bar) return e;
-  hipLaunchKernelGGL(partials_finalize_kernel, dim3(1), dim3(64 * ((5 * a.nbatch + 63) / 64)), 0, st, part,
-                     (int)(grid.x * grid.y), a.nbatch, param_bar);
+  hipLaunchKernelGGL((rhs_adjoint_kernel<ATX, ATY, ANT>), grid, dim3(ANT), 0, st, a, Us, lam, clam_f, dtp, X1, c1, X2,
+                     c2, X3, c3, out, part);
+  *nblk = (int)(grid.x * grid.y);
+  return hipGetLastError();
+}
+
+hipError_t launch_partials_finalize(const double* part, const PartSlots& ps, int nbatch, double* param_bar,
+                                    hipStream_t st) {
+  if (!param_bar || ps.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(partials_finalize_kernel, dim3(nbatch), dim3(320), 0, st, part, ps, param_bar);
   return hipGetLastError();
 }
 
@@ -685,23 +756,10 @@ hipError_t launch_ibm_entries(const GhostTable& gt, int* keys, int* vals, int* n
 }
 
 hipError_t launch_ibm_fill_adjoint(const GridArgs& a, const GhostTable& gt, const int* keys, const int* vals,
-                                   int nent, const double* Us, double* X, double* part, double* param_bar,
-                                   hipStream_t st) {
-  if (gt.n == 0) return hipSuccess;
-  const unsigned int nb = (unsigned int)((nent + 255) / 256);
-  if (nent > 0) {
-    hipLaunchKernelGGL(ibm_fill_adjoint_kernel, dim3(nb, a.nbatch), dim3(256), 0, st, a, gt, keys, vals, nent, Us,
-                       X, part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (param_bar) {
-      hipLaunchKernelGGL(partials_finalize_kernel, dim3(1), dim3(64 * ((5 * a.nbatch + 63) / 64)), 0, st, part,
-                         (int)nb, a.nbatch, param_bar);
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
-  }
-  hipLaunchKernelGGL(ibm_zero_ghosts_kernel, dim3((gt.n + 255) / 256, a.nbatch), dim3(256), 0, st, a, gt, X);
+                                   int nent, const double* Us, double* X, double* gW, double* part,
+                                   const PartSlots& prior, double* param_bar, hipStream_t st) {
+  hipLaunchKernelGGL(ibm_fill_adjoint_kernel, dim3(a.nbatch), dim3(FILL_NT), 0, st, a, gt, keys, vals, nent, Us, X,
+                     gW, part, prior, param_bar);
   return hipGetLastError();
 }
 

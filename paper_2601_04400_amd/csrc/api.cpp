@@ -22,7 +22,7 @@ using namespace shk;
 
 struct WsLayout {
   size_t scalars, globals, dtbuf, xslots, u1, u2, cls, row_count, row_off, g_cell, g_src, g_w, g_nrm;
-  size_t adjA, adjB, adjC, adjP, adjQ, adjPart, entKeys, entVals, entCount;
+  size_t adjA, adjB, adjC, adjP, adjQ, adjPart, part_stride, adjG, entKeys, entVals, entCount;
   size_t netF, netX, netPart;
   size_t total;
 };
@@ -115,9 +115,10 @@ WsLayout layout(const shk_grid_desc* d) {
     L.adjP = o; o += st64;
     L.adjQ = o; o += st64;
     const size_t nblk = size_t((d->nx + 31) / 32) * ((d->ny + 7) / 8);
-    const size_t nent_blk = d->ibm ? (4 * ncell + 255) / 256 : 0;
-    L.adjPart = o; o += al(sizeof(double) * 5 * d->nbatch * (nblk > nent_blk ? nblk : nent_blk));
+    L.part_stride = 5 * size_t(d->nbatch) * nblk;
+    L.adjPart = o; o += al(sizeof(double) * MAX_PART_SLOTS * L.part_stride);
     if (d->ibm) {
+      L.adjG = o; o += st64;  // image-point primitive adjoints, 4 per ghost
       L.entKeys = o; o += al(sizeof(int) * 4 * ncell);
       L.entVals = o; o += al(sizeof(int) * 4 * ncell);
       L.entCount = o; o += al(sizeof(int));
@@ -189,14 +190,17 @@ hipError_t stage_launch(shk_grid* g, const GridArgs& a, int mode, const S* Us, c
 // One SSP-RK3 step.  With a fixed step or an immersed boundary the stages
 // are the plain three (after a separate reduction for the automatic step);
 // otherwise the automatic step is fused into the stages (S1L, S2F, S3F).
+// With tape != nullptr the stage-start states (U^n, U1, U2, each after the
+// refill) are kept in tape[0..2] for the reverse pass.
 template <class S>
-shk_status stage_seq(shk_grid* g, S* U, const double* dt_in, double* dt_out) {
+shk_status stage_seq(shk_grid* g, S* U, const double* dt_in, double* dt_out, S* tape = nullptr) {
   GridArgs a = g->a;
   a.dt_out = dt_out;
-  S* U1 = reinterpret_cast<S*>(g->ws + g->L.u1);
-  S* U2 = reinterpret_cast<S*>(g->ws + g->L.u2);
+  const long long nst = (long long)a.nbatch * a.nvar * a.ncell;
+  S* U1 = tape ? tape + nst : reinterpret_cast<S*>(g->ws + g->L.u1);
+  S* U2 = tape ? tape + 2 * nst : reinterpret_cast<S*>(g->ws + g->L.u2);
   hipError_t e;
-  if (!dt_in && !g->ibm_on && !g->net_on) {
+  if (!dt_in && !g->ibm_on && !g->net_on && !tape) {
     if ((e = timed(g, 1, [&]() { return stage_launch<S>(g, a, MODE_S1L, U, U, U1, nullptr, nullptr); })) != hipSuccess)
       return hip_check(g, e, "stage 1");
     if ((e = timed(g, 2, [&]() { return stage_launch<S>(g, a, MODE_S2F, U, U, U2, nullptr, U1); })) != hipSuccess)
@@ -221,6 +225,8 @@ shk_status stage_seq(shk_grid* g, S* U, const double* dt_in, double* dt_out) {
     return timed(g, 4, [&]() { return launch_ibm_fill<S>(a, g->gt, X, g->st); });
   };
   if ((e = fill(U)) != hipSuccess) return hip_check(g, e, "ibm fill");
+  if (tape && (e = hipMemcpyAsync(tape, U, size_t(nst) * sizeof(S), hipMemcpyDeviceToDevice, g->st)) != hipSuccess)
+    return hip_check(g, e, "tape copy");
   if ((e = stage(MODE_STAGE1, U, U, U1)) != hipSuccess) return hip_check(g, e, "stage 1");
   if ((e = fill(U1)) != hipSuccess) return hip_check(g, e, "ibm fill");
   if ((e = stage(MODE_STAGE2, U1, U, U2)) != hipSuccess) return hip_check(g, e, "stage 2");
@@ -407,12 +413,28 @@ shk_status shk_rk3_step(shk_grid* g, void* U, const double* dt_in, double* dt_ou
   return stage_seq<float>(g, static_cast<float*>(U), dt_in, dt_out);
 }
 
+// Partial derivatives of the launches of one reverse pass, finalised once.
+struct PartRec {
+  double* base;
+  PartSlots ps;  // ps.stride: doubles between slots
+  bool finalised;  // the last refill transpose already added the partials
+  double* next() const { return base + ps.n * ps.stride; }
+  void add(int nblk) { ps.nblk[ps.n++] = nblk; }
+};
+
+static PartRec part_rec(shk_grid* g) {
+  PartRec r{};
+  r.base = reinterpret_cast<double*>(g->ws + g->L.adjPart);
+  r.ps.stride = (long long)g->L.part_stride;
+  return r;
+}
+
 // rhs-adjoint launch with the learned correction's reverse pass first (its
 // stencil gradient is then added by the adjoint kernel face by face).
-static hipError_t rhs_adj(shk_grid* g, const double* Us, const double* lam, double clam_f, const double* dtp,
-                          const double* X1, double c1, const double* X2, double c2, double* out, double* param_bar) {
+static hipError_t rhs_adj(shk_grid* g, PartRec& pr, const double* Us, const double* lam, double clam_f,
+                          const double* dtp, const double* X1, double c1, const double* X2, double c2,
+                          const double* X3, double c3, double* out) {
   GridArgs a = g->a;
-  double* part = reinterpret_cast<double*>(g->ws + g->L.adjPart);
   if (g->net_on) {
     float* dX = reinterpret_cast<float*>(g->ws + g->L.netX);
     float* np = reinterpret_cast<float*>(g->ws + g->L.netPart);
@@ -420,7 +442,10 @@ static hipError_t rhs_adj(shk_grid* g, const double* Us, const double* lam, doub
     if (e != hipSuccess) return e;
     a.dXnet = dX;
   }
-  return launch_rhs_adjoint(a, Us, lam, clam_f, dtp, X1, c1, X2, c2, out, part, param_bar, g->st);
+  int nb = 0;
+  hipError_t e = launch_rhs_adjoint(a, Us, lam, clam_f, dtp, X1, c1, X2, c2, X3, c3, out, pr.next(), &nb, g->st);
+  if (e == hipSuccess) pr.add(nb);
+  return e;
 }
 
 static shk_status adjoint_ok(shk_grid* g) {
@@ -436,12 +461,24 @@ static hipError_t fill64(shk_grid* g, double* X) {
 }
 
 // Transpose of the refill on an adjoint array X (w.r.t. the filled state Us).
-static hipError_t fillT(shk_grid* g, const double* Us, double* X, double* param_bar) {
+// With param_bar set, this launch also finalises the pass's partials.
+static hipError_t fillT(shk_grid* g, PartRec& pr, const double* Us, double* X, double* param_bar = nullptr) {
   if (!g->ibm_on) return hipSuccess;
   const int* keys = reinterpret_cast<const int*>(g->ws + g->L.entKeys);
   const int* vals = reinterpret_cast<const int*>(g->ws + g->L.entVals);
-  double* part = reinterpret_cast<double*>(g->ws + g->L.adjPart);
-  return launch_ibm_fill_adjoint(g->a, g->gt, keys, vals, g->nent, Us, X, part, param_bar, g->st);
+  double* gW = reinterpret_cast<double*>(g->ws + g->L.adjG);
+  hipError_t e = launch_ibm_fill_adjoint(g->a, g->gt, keys, vals, g->nent, Us, X, gW, pr.next(), pr.ps, param_bar,
+                                         g->st);
+  if (e == hipSuccess) {
+    pr.add(1);
+    if (param_bar) pr.finalised = true;
+  }
+  return e;
+}
+
+static hipError_t finish(shk_grid* g, const PartRec& pr, double* param_bar) {
+  if (pr.finalised) return hipSuccess;
+  return launch_partials_finalize(pr.base, pr.ps, g->a.nbatch, param_bar, g->st);
 }
 
 shk_status shk_rhs_adjoint(shk_grid* g, const void* U, const void* dUdt_bar, void* U_bar, double* param_bar) {
@@ -453,15 +490,38 @@ shk_status shk_rhs_adjoint(shk_grid* g, const void* U, const void* dUdt_bar, voi
   const size_t bytes = size_t(a.nbatch) * 4 * a.ncell * sizeof(double);
   double* A = reinterpret_cast<double*>(g->ws + g->L.adjA);
   double* P = reinterpret_cast<double*>(g->ws + g->L.adjP);
-  double* part = reinterpret_cast<double*>(g->ws + g->L.adjPart);
+  PartRec pr = part_rec(g);
   hipError_t e = hipMemcpyAsync(A, U, bytes, hipMemcpyDeviceToDevice, g->st);
   if (e == hipSuccess) e = fill64(g, A);
-  (void)part;
   if (e == hipSuccess)
-    e = rhs_adj(g, A, static_cast<const double*>(dUdt_bar), 1.0, nullptr, nullptr, 0.0, nullptr, 0.0, P, param_bar);
-  if (e == hipSuccess) e = fillT(g, A, P, param_bar);
+    e = rhs_adj(g, pr, A, static_cast<const double*>(dUdt_bar), 1.0, nullptr, nullptr, 0.0, nullptr, 0.0, nullptr,
+                0.0, P);
+  if (e == hipSuccess) e = fillT(g, pr, A, P, param_bar);
   if (e == hipSuccess) e = launch_axpy((long long)a.nbatch * 4 * a.ncell, 1.0, P, static_cast<double*>(U_bar), 1, g->st);
+  if (e == hipSuccess) e = finish(g, pr, param_bar);
   return hip_check(g, e, "rhs_adjoint");
+}
+
+// Reverse of one SSP-RK3 step from its filled stage-start states A = U^n,
+// B = U1, C = U2.  With the adjoints written X3 (after the step, in Ub), X2,
+// X1 (of the stage states before their refill) and R^T the transpose of the
+// refill:
+//   X2 = R^T(2/3 X3 + 2/3 dt J(U2)^T X3)
+//   X1 = R^T(1/4 X2 + 1/4 dt J(U1)^T X2)
+//   X0 = R^T(X1 + dt J(U^n)^T X1 + 1/3 X3 + 3/4 X2)
+static hipError_t reverse_step(shk_grid* g, const double* A, const double* B, const double* C, const double* dt,
+                               double* Ub, double* param_bar) {
+  double* P = reinterpret_cast<double*>(g->ws + g->L.adjP);
+  double* Q = reinterpret_cast<double*>(g->ws + g->L.adjQ);
+  PartRec pr = part_rec(g);
+  hipError_t e = rhs_adj(g, pr, C, Ub, 2.0 / 3.0, dt, Ub, 2.0 / 3.0, nullptr, 0.0, nullptr, 0.0, P);
+  if (e == hipSuccess) e = fillT(g, pr, C, P);
+  if (e == hipSuccess) e = rhs_adj(g, pr, B, P, 0.25, dt, P, 0.25, nullptr, 0.0, nullptr, 0.0, Q);
+  if (e == hipSuccess) e = fillT(g, pr, B, Q);
+  if (e == hipSuccess) e = rhs_adj(g, pr, A, Q, 1.0, dt, Q, 1.0, Ub, 1.0 / 3.0, P, 0.75, Ub);
+  if (e == hipSuccess) e = fillT(g, pr, A, Ub, param_bar);
+  if (e == hipSuccess) e = finish(g, pr, param_bar);
+  return e;
 }
 
 shk_status shk_rk3_step_adjoint(shk_grid* g, const void* U_n, const double* dt, void* U_bar, double* param_bar) {
@@ -470,14 +530,10 @@ shk_status shk_rk3_step_adjoint(shk_grid* g, const void* U_n, const double* dt, 
   if (s != SHK_OK) return s;
   if (!U_n || !dt || !U_bar) return fail(g, SHK_EINVAL, "rk3_step_adjoint: null array");
   const GridArgs& a = g->a;
-  const long long n = (long long)a.nbatch * 4 * a.ncell;
-  const size_t bytes = size_t(n) * sizeof(double);
+  const size_t bytes = size_t(a.nbatch) * 4 * a.ncell * sizeof(double);
   double* A = reinterpret_cast<double*>(g->ws + g->L.adjA);  // U^n filled
   double* B = reinterpret_cast<double*>(g->ws + g->L.adjB);  // U1 filled
   double* C = reinterpret_cast<double*>(g->ws + g->L.adjC);  // U2 filled
-  double* P = reinterpret_cast<double*>(g->ws + g->L.adjP);
-  double* Q = reinterpret_cast<double*>(g->ws + g->L.adjQ);
-  double* Ub = static_cast<double*>(U_bar);
   hipError_t e = hipMemcpyAsync(A, U_n, bytes, hipMemcpyDeviceToDevice, g->st);
   // forward recompute of the stage states
   if (e == hipSuccess) e = fill64(g, A);
@@ -488,19 +544,28 @@ shk_status shk_rk3_step_adjoint(shk_grid* g, const void* U_n, const double* dt, 
   if (e == hipSuccess) e = net_prepare<double>(g, an, B);
   if (e == hipSuccess) e = launch_stage<double>(an, MODE_STAGE2, B, A, C, dt, nullptr, g->st);
   if (e == hipSuccess) e = fill64(g, C);
-  // stage 3: U = 1/3 U^n + 2/3 U2 + 2/3 dt L(U2)
-  if (e == hipSuccess) e = rhs_adj(g, C, Ub, 2.0 / 3.0, dt, Ub, 2.0 / 3.0, nullptr, 0.0, P, param_bar);
-  if (e == hipSuccess) e = launch_axpy(n, 1.0 / 3.0, Ub, Q, 0, g->st);
-  if (e == hipSuccess) e = fillT(g, C, P, param_bar);  // P = adjoint of U2
-  // stage 2: U2 = 3/4 U^n + 1/4 U1 + dt/4 L(U1)
-  if (e == hipSuccess) e = rhs_adj(g, B, P, 0.25, dt, P, 0.25, nullptr, 0.0, Ub, param_bar);
-  if (e == hipSuccess) e = launch_axpy(n, 0.75, P, Q, 1, g->st);
-  if (e == hipSuccess) e = fillT(g, B, Ub, param_bar);  // Ub = adjoint of U1
-  // stage 1: U1 = U^n + dt L(U^n)
-  if (e == hipSuccess) e = rhs_adj(g, A, Ub, 1.0, dt, Q, 1.0, Ub, 1.0, P, param_bar);
-  if (e == hipSuccess) e = fillT(g, A, P, param_bar);
-  if (e == hipSuccess) e = hipMemcpyAsync(Ub, P, bytes, hipMemcpyDeviceToDevice, g->st);
+  if (e == hipSuccess) e = reverse_step(g, A, B, C, dt, static_cast<double*>(U_bar), param_bar);
   return hip_check(g, e, "rk3_step_adjoint");
+}
+
+shk_status shk_rk3_step_record(shk_grid* g, void* U, const double* dt_in, double* dt_out, void* tape) {
+  if (!g) return SHK_EINVAL;
+  shk_status s = adjoint_ok(g);
+  if (s != SHK_OK) return s;
+  if (!U || !tape) return fail(g, SHK_EINVAL, "rk3_step_record: null array");
+  return stage_seq<double>(g, static_cast<double*>(U), dt_in, dt_out, static_cast<double*>(tape));
+}
+
+shk_status shk_rk3_step_adjoint_tape(shk_grid* g, const void* tape, const double* dt, void* U_bar,
+                                     double* param_bar) {
+  if (!g) return SHK_EINVAL;
+  shk_status s = adjoint_ok(g);
+  if (s != SHK_OK) return s;
+  if (!tape || !dt || !U_bar) return fail(g, SHK_EINVAL, "rk3_step_adjoint_tape: null array");
+  const double* A = static_cast<const double*>(tape);
+  const long long nst = (long long)g->a.nbatch * 4 * g->a.ncell;
+  hipError_t e = reverse_step(g, A, A + nst, A + 2 * nst, dt, static_cast<double*>(U_bar), param_bar);
+  return hip_check(g, e, "rk3_step_adjoint_tape");
 }
 
 shk_status shk_set_flux_net(shk_grid* g, const uint16_t* w_bf16, const float* bias, const double* norm_host,

@@ -61,6 +61,26 @@ struct GhostTable {
   int wall;         // 0 slip, 1 no-slip adiabatic
 };
 
+// Tile coordinates of this workgroup under an XCD-aware permutation of the
+// launch grid.  Workgroups are handed to the eight XCDs round-robin by linear
+// id, so XCD x receives ids x, x + 8, ...; mapping the k-th of them to tile
+// start_x + k gives every XCD one contiguous run of tiles (rows of tiles),
+// and the halo rows a tile shares with its neighbours are then mostly read
+// through the same L2.  The map is a bijection for any grid size, so
+// correctness does not depend on how the hardware actually dispatches.
+__device__ __forceinline__ void xcd_tile(int& bx, int& by, int& bz) {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int n = gx * gy * gridDim.z;
+  const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int q = n >> 3, r = n & 7;
+  const int x = lin & 7, k = lin >> 3;
+  const int t = x * q + (x < r ? x : r) + k;
+  bx = t % gx;
+  const int rest = t / gx;
+  by = rest % gy;
+  bz = rest / gy;
+}
+
 // Host-side launchers (stage.hip, ibm.hip).
 template <class S>
 hipError_t launch_prim_to_cons(const GridArgs& a, const S* W, S* U, hipStream_t st);
@@ -80,14 +100,28 @@ hipError_t launch_stage_mixed(const GridArgs& a, int mode, const float* Us, cons
                               const double* dtp, const float* Lin, hipStream_t st);
 
 // adjoint (adjoint.hip)
+// Per-block partial derivatives of several launches, summed in one pass:
+// slot s holds nblk[s] blocks per batch member at part + s * stride.
+constexpr int MAX_PART_SLOTS = 6;
+struct PartSlots {
+  int n;
+  int nblk[MAX_PART_SLOTS];
+  long long stride;
+};
 int adjoint_blocks(const GridArgs& a);
 hipError_t launch_rhs_adjoint(const GridArgs& a, const double* Us, const double* lam, double clam_f,
                               const double* dtp, const double* X1, double c1, const double* X2, double c2,
-                              double* out, double* part, double* param_bar, hipStream_t st);
+                              const double* X3, double c3, double* out, double* part, int* nblk, hipStream_t st);
+hipError_t launch_partials_finalize(const double* part, const PartSlots& ps, int nbatch, double* param_bar,
+                                    hipStream_t st);
 hipError_t launch_ibm_entries(const GhostTable& gt, int* keys, int* vals, int* nvalid, hipStream_t st);
+// Transpose of the refill (one workgroup per batch member).  Its block
+// partial goes to part (1 block per member).  With param_bar set it also
+// finalises: param_bar += the slots of prior (which lie before part, at
+// part - (prior.n - s) * prior.stride for slot s) plus its own partial.
 hipError_t launch_ibm_fill_adjoint(const GridArgs& a, const GhostTable& gt, const int* keys, const int* vals,
-                                   int nent, const double* Us, double* X, double* part, double* param_bar,
-                                   hipStream_t st);
+                                   int nent, const double* Us, double* X, double* gW, double* part,
+                                   const PartSlots& prior, double* param_bar, hipStream_t st);
 hipError_t launch_axpy(long long n, double alpha, const double* x, double* y, int accumulate, hipStream_t st);
 
 // stage modes

@@ -167,9 +167,10 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
   __shared__ unsigned int blk_fallback, blk_fault;
   __shared__ double red_s[NT / 64], red_r[NT / 64];
 
-  const int b = blockIdx.z;
+  int bx, by, b;
+  xcd_tile(bx, by, b);
   StepScalars* sc = a.sc + b;
-  const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+  const bool lead = bx == 0 && by == 0 && threadIdx.x == 0;
   double dt = 0.0;
   if (MODE == MODE_STAGE1 || MODE == MODE_STAGE2 || MODE == MODE_STAGE3) {
     dt = dtp[b];
@@ -188,7 +189,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     if (dt == 0.0) return;
   } else if (MODE == MODE_S3F) {
     dt = a.dtbuf[b];
-    if (blockIdx.x == 0 && blockIdx.y == 0) {
+    if (bx == 0 && by == 0) {
       // block 0 advances the device time and clears the extrema
       double sm, rm;
       read_extrema(a, b, &sm, &rm);
@@ -212,8 +213,8 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     if (dt == 0.0) return;
   }
   if (threadIdx.x == 0) { blk_fallback = 0; blk_fault = 0; }
-  const int i0 = blockIdx.x * TX;
-  const int j0 = blockIdx.y * TY;
+  const int i0 = bx * TX;
+  const int j0 = by * TY;
   const long long boff = (long long)b * a.nvar * a.ncell;
   const S* __restrict__ Ub = Us + boff;
   const S* __restrict__ Lb = MODE == MODE_S2F ? Lin + boff : nullptr;
@@ -440,7 +441,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
       double s2 = red_s[0], r2 = red_r[0];
       for (int k = 1; k < NT / 64; ++k) { s2 = fmax(s2, red_s[k]); r2 = fmin(r2, red_r[k]); }
       unsigned long long* xs = a.xslots + (long long)b * 2 * XSLOTS;
-      const int slot = (blockIdx.x + blockIdx.y * gridDim.x) & (XSLOTS - 1);
+      const int slot = (bx + by * gridDim.x) & (XSLOTS - 1);
       atomicMax(&xs[slot], (unsigned long long)__double_as_longlong(s2));
       atomicMin(&xs[XSLOTS + slot], (unsigned long long)__double_as_longlong(r2));
     }

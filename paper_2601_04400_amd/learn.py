@@ -142,21 +142,22 @@ def train(net, data, iters=400, m=4, lr=1e-3, lr_late=1e-4, switch=None, log_eve
     g.set_flux_net(net)
     g.set_flux_net_grad(net.grad)
     part = torch.empty(nb * 256, dtype=torch.float64, device=data.snaps.device)
+    tapes = torch.empty((m, 3) + tuple(g.shape), dtype=torch.float64, device=data.snaps.device)
     history = []
     switch = switch if switch is not None else int(0.875 * iters)
     for it in range(iters):
         k = it % (data.nsnap - m + 1)
         U = data.snaps[k].clone()
-        states = [U.clone()]
+        states = [None]
         for s in range(m):
-            g.step(U, data.dt_c)
+            g.step_record(U, tapes[s], data.dt_c)
             states.append(U.clone())
         loss = torch.zeros(nb, dtype=torch.float64, device=U.device)
         net.grad.zero_()
         Ub = torch.zeros_like(U)
         for s in range(m, 0, -1):
             mse_accumulate(states[s], data.snaps[k + s], Ub, 1.0 / m, loss, part)
-            g.step_adjoint(states[s - 1], data.dt_c, Ub, None)
+            g.step_adjoint_tape(tapes[s - 1], data.dt_c, Ub, None)
         net.adam(lr if it < switch else lr_late)
         L = float(loss.sum()) / m if (log is not None and (it % log_every == 0 or it == iters - 1)) else None
         if L is not None:

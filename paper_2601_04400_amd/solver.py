@@ -72,6 +72,11 @@ class Grid:
         if not (U.is_cuda and U.dtype == self.dtype and U.is_contiguous() and U.numel() == self._numel()):
             raise ValueError(f"state must be a contiguous {self.dtype} CUDA tensor with {self._numel()} elements")
 
+    def _check_tape(self, tape):
+        if not (tape.is_cuda and tape.dtype == torch.float64 and tape.is_contiguous()
+                and tuple(tape.shape) == (3,) + tuple(self.shape)):
+            raise ValueError("tape must be a contiguous float64 CUDA tensor of shape (3,) + grid state shape")
+
     def _numel(self):
         b, v, ny, nx = self.shape
         return b * v * ny * nx
@@ -178,6 +183,33 @@ class Grid:
         self._sync_stream()
         check(lib().shk_rk3_step_adjoint(self.handle, _ptr(U_n), _ptr(dt), _ptr(U_bar), _ptr(param_bar)),
               self.handle, "rk3_step_adjoint")
+        return U_bar
+
+    def empty_tape(self):
+        """Buffer for the three recorded stage-start states of one step."""
+        return torch.empty((3,) + tuple(self.shape), dtype=torch.float64, device=self.device)
+
+    def step_record(self, U, tape, dt=None, dt_out=None):
+        """One RK3 step in place (as step) that also records U^n, U1, U2
+        (after the immersed-boundary refill) into tape for step_adjoint_tape."""
+        self._check_state(U)
+        self._check_tape(tape)
+        if dt is not None and not torch.is_tensor(dt):
+            dt = torch.full((self.shape[0],), float(dt), dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        check(lib().shk_rk3_step_record(self.handle, _ptr(U), _ptr(dt), _ptr(dt_out), _ptr(tape)),
+              self.handle, "rk3_step_record")
+        return U
+
+    def step_adjoint_tape(self, tape, dt, U_bar, param_bar=None):
+        """U_bar (adjoint after a recorded step) -> adjoint of its U^n, in place."""
+        self._check_state(U_bar)
+        self._check_tape(tape)
+        if not torch.is_tensor(dt):
+            dt = torch.full((self.shape[0],), float(dt), dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        check(lib().shk_rk3_step_adjoint_tape(self.handle, _ptr(tape), _ptr(dt), _ptr(U_bar), _ptr(param_bar)),
+              self.handle, "rk3_step_adjoint_tape")
         return U_bar
 
     def set_time(self, t0, t_end):

@@ -120,6 +120,54 @@ def test_rk3_step_adjoint_vs_oracle_jacobian(orc, ibm):
     np.testing.assert_allclose(to_np(pb)[0], ref[n:], rtol=1e-9, atol=1e-10 * np.max(np.abs(ref[n:])))
 
 
+@pytest.mark.parametrize("ibm", [False, True])
+def test_recorded_step_and_tape_adjoint(orc, ibm):
+    """shk_rk3_step_record advances exactly as shk_rk3_step (bit for bit, with
+    a fixed and with the automatic step) and shk_rk3_step_adjoint_tape on its
+    record equals shk_rk3_step_adjoint bit for bit and the oracle's
+    transposed step Jacobian to 1e-10."""
+    nx, ny = 36, 20
+    if ibm:
+        c, g, sc = cylinder_case(orc, nx, ny)
+        phi, W = sc["phi"], sc["W"]
+    else:
+        c, g = adj_pair(orc, nx, ny, (2, 0, 1, 1))
+        phi, W = None, inputs.smooth_prim(nx, ny, seed=4)
+    U = orc.prim_to_cons(c, W)
+    dt = 0.4 * orc.cfl_dt(c, U, phi=phi)
+    Ug = torch.from_numpy(U).cuda().reshape(g.shape)
+    tape = g.empty_tape()
+    Ua, Ur = Ug.clone(), Ug.clone()
+    g.step(Ua, dt)
+    g.step_record(Ur, tape, dt)
+    np.testing.assert_array_equal(to_np(Ur), to_np(Ua))
+    # automatic step: the recording path (separate reduction) against the fused one
+    da = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dr = torch.zeros(1, dtype=torch.float64, device="cuda")
+    Ua2, Ur2, tape2 = Ug.clone(), Ug.clone(), g.empty_tape()
+    g.set_time(0.0, 1e30)
+    g.step(Ua2, dt_out=da)
+    g.set_time(0.0, 1e30)
+    g.step_record(Ur2, tape2, dt_out=dr)
+    np.testing.assert_array_equal(to_np(dr), to_np(da))
+    np.testing.assert_array_equal(to_np(Ur2), to_np(Ua2))
+    lam = np.random.default_rng(9).normal(size=U.shape)
+    J = orc.rk3_step_jacobian(c, U, dt, phi=phi, wall=0)
+    n = U.size
+    ref = J.T @ lam.ravel()
+    Ub1 = torch.from_numpy(lam).cuda().reshape(g.shape).clone()
+    Ub2 = Ub1.clone()
+    pb1, pb2 = g.param_bar(), g.param_bar()
+    g.step_adjoint(Ug, dt, Ub1, pb1)
+    g.step_adjoint_tape(tape, dt, Ub2, pb2)
+    np.testing.assert_array_equal(to_np(Ub2), to_np(Ub1))
+    np.testing.assert_array_equal(to_np(pb2), to_np(pb1))
+    assert rel(to_np(Ub2).ravel(), ref[:n]) <= 1e-10
+    np.testing.assert_allclose(to_np(pb2)[0], ref[n:], rtol=1e-9, atol=1e-10 * np.max(np.abs(ref[n:])))
+    with pytest.raises(ValueError):
+        g.step_record(Ur, tape[:2], dt)
+
+
 def test_step_adjoint_dot_product_on_evolved_shock_cylinder(orc):
     """<lam, J udot> (oracle tangent) = <J^T lam, udot> (GPU adjoint) for one
     step taken from the shock-cylinder state after 10 and 25 steps, each side
