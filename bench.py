@@ -30,6 +30,27 @@ FLOPS_PER_CELL_STAGE = 1314
 # HBM words per cell per step: stage 1 reads U and writes U1 (8 words),
 # stages 2 and 3 read U_s and U^n and write U_{s+1} (12 words each).
 WORDS_PER_CELL_STEP = 32
+# Measured HBM traffic of the fused stage kernels (FETCH_SIZE and WRITE_SIZE
+# per dispatch, mean of the three stage modes, bytes), scaled by the copy-
+# kernel calibration (fetch x 2.0, write x 1.0), for the stage-kernel sources
+# whose SHA-256 is given; reported as null for any other source or workload.
+MEASURED_TRAFFIC = {
+    "sources_sha256": "5c334daf253ba72a8aed5dcf5a6ef4e6140ad3d68c868380b2392c423381f41f",
+    "workload": (512, 512, "f64"),
+    "bytes_per_launch": 23530394,
+    "profile": "profiles/stage_kernel_quadrant512_f64.md",
+}
+STAGE_SOURCES = ("stage.hip", "flux.hpp", "xcd.hpp")
+
+
+def stage_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2601_04400_amd", "csrc")
+    for f in STAGE_SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def cpu_info():
@@ -102,6 +123,121 @@ def adjoint_ratio(n=256, steps=200, every=20):
     return res
 
 
+def copy_ceiling(mb=512, reps=10):
+    """Measured device-copy bandwidth (read + write bytes per second) of a
+    plain torch copy of `mb` MiB, HIP-event timed: the practical HBM ceiling."""
+    import torch
+    a = torch.ones(mb * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * a.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return round(gbs, 1)
+
+
+# Viscous stress and heat flux add about 45 operations per face (two faces
+# per cell and stage) to the inviscid count.
+FLOPS_PER_CELL_STAGE_VISCOUS = FLOPS_PER_CELL_STAGE + 90
+
+
+def cylinder_workload(args):
+    """Navier-Stokes Mach-3 planar shock on a circular cylinder (r = 0.1 at
+    (0.3, 0.5)) by the ghost-cell immersed boundary, no-slip adiabatic wall,
+    Re = 1000 on the diameter, Pr = 0.72, 1024 x 512 on [0,2] x [0,1], FP64,
+    automatic CFL-0.5 step; W untimed steps take the shock onto the cylinder,
+    then K timed steps.  One step = CFL reduction + 3 x (refill + stage)."""
+    import torch
+    from paper_2601_04400_amd import Grid, inputs, normal_shock_state
+    nx, ny, K, W = 1024, 512, args.steps, args.warmup
+    dom = (0.0, 2.0, 0.0, 1.0)
+    post, _, _ = normal_shock_state(3.0)
+    inflow = (post[0], post[1], 0.0, post[2])
+    sc = inputs.shock_cylinder(nx, ny, inflow, domain=dom, centre=(0.3, 0.5), radius=0.1, xs=0.1)
+    g = Grid(nx, ny, domain=dom, bc=sc["bc"], inflow=inflow, ibm=True, viscous=True,
+             mu=inputs.cylinder_viscosity(3.0), prandtl=0.72)
+    nghost = g.set_levelset(torch.from_numpy(sc["phi"]), wall=1)
+    U = g.prim_to_cons(torch.from_numpy(sc["W"]))
+    g.set_time(0.0, 1e30)
+    for _ in range(W):
+        g.step(U)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(K):
+        g.step(U)
+    ev1.record()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    g.profile(True)
+    for _ in range(K):
+        g.step(U)
+    prof = g.profile_read()
+    g.profile(False)
+    flags, fb = g.poll_faults()
+    t, _, steps = g.get_time()
+    n2 = nx * ny
+    stage_s = sum(prof[k][0] for k in ("stage1", "stage2", "stage3")) * 1e-3 / (3 * K)
+    tflops = FLOPS_PER_CELL_STAGE_VISCOUS * n2 / stage_s / 1e12
+    return {
+        "metric": METRIC, "value": n2 * K / el, "unit": "cell-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": el * 1e3 / K, "gpu_ms_per_step": gpu_ms / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "2D Navier-Stokes Mach-3 shock on a cylinder r=0.1 at (0.3,0.5), ghost-cell IBM, "
+                               "no-slip adiabatic, Re 1000, Pr 0.72, 1024x512 on [0,2]x[0,1], CFL 0.5, timed "
+                               f"after {W} steps (t = {t:.4f} at the end of the run)",
+                   "nx": nx, "ny": ny, "ghost_cells": nghost},
+        "stage_kernel": {"us_per_launch_event_bracketed": round(stage_s * 1e6, 3),
+                         "alu_TFLOPs": round(tflops, 2), "alu_frac": round(tflops / FP64_PEAK_TFLOPS, 4)},
+        "kernel_ms_event_bracketed": {k: round(v[0] / max(v[1], 1), 5) for k, v in prof.items() if v[1]},
+        "faults": {"flags": flags, "fallback_faces": fb}, "device_steps": steps,
+    }
+
+
+def sod_workload(args):
+    """1D Euler Sod shock tube, 200 cells on [0,1], transmissive, CFL 0.5,
+    to t = 0.2, FP64: time to solution from a resident state (latency-bound:
+    a few microseconds per launch), repeated reps times."""
+    import torch
+    from paper_2601_04400_amd import Grid, inputs
+    n, reps = 200, 20
+    g = Grid(n, ndim=1)
+    W = torch.from_numpy(inputs.sod_prim(n))
+    U0 = g.prim_to_cons(W)
+    U = U0.clone()
+    t, steps = g.advance(U, 0.2)  # warm-up and step count
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(reps):
+        U.copy_(U0)
+        g.set_time(0.0, 0.2)
+        for _ in range(steps):
+            g.step(U)
+    ev1.record()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    gpu_s = ev0.elapsed_time(ev1) * 1e-3 / reps
+    tt, done, st2 = g.get_time()
+    return {
+        "metric": METRIC, "value": n * steps / el, "unit": "cell-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": 1, "ms_per_step": el * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "1D Euler Sod shock tube, 200 cells on [0,1], gamma 1.4, transmissive, WENO5-JS+HLLC, "
+                               "SSP-RK3, CFL 0.5, t_end 0.2, FP64", "nx": n},
+        "time_to_solution_ms": round(el * 1e3, 3), "gpu_time_to_solution_ms": round(gpu_s * 1e3, 3),
+        "t_reached": tt, "done": done, "note": "launch-latency bound; not a bandwidth or ALU measurement",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +252,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint:forward cost measurement")
+    ap.add_argument("--workload", default="quadrant", choices=["quadrant", "cylinder", "sod"],
+                    help="quadrant: the four-quadrant Riemann problem (default); cylinder: the viscous "
+                         "shock-cylinder case at 1024x512; sod: the 200-cell shock tube (each prints its "
+                         "own line)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -143,6 +283,13 @@ def main():
                           "copies": args.steps, "GB_per_s": 2 * nbytes * args.steps / el / 1e9}), flush=True)
         return
 
+    if args.workload == "cylinder":
+        print(json.dumps(cylinder_workload(args)), flush=True)
+        return
+    if args.workload == "sod":
+        print(json.dumps(sod_workload(args)), flush=True)
+        return
+
     nx, ny, K, W = args.nx, args.ny, args.steps, args.warmup
     n2 = nx * ny
     g = Grid(nx, ny, prec=args.prec)
@@ -165,16 +312,21 @@ def main():
                 g.step(U)
         torch.cuda.synchronize()
 
-    # pass A: the measurement
+    # pass A: the measurement (wall clock, and HIP events on the stream the
+    # stage kernels run on: torch's current stream, which the grid adopts)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record()
     if graph is not None:
         graph.replay()
     else:
         for _ in range(K):
             g.step(U)
+    ev1.record()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
     ms_per_step = el * 1e3 / K
     value = n2 * K / el
 
@@ -187,21 +339,28 @@ def main():
     flags, fb = g.poll_faults()
 
     esize = 8 if args.prec == "f64" else 4
-    stage_ms = sum(prof[k][0] for k in ("stage1", "stage2", "stage3")) / K
-    launches = sum(prof[k][1] for k in ("stage1", "stage2", "stage3"))
-    bytes_step = WORDS_PER_CELL_STEP * esize * n2
-    gbs = bytes_step / (stage_ms * 1e-3) / 1e9
-    tflops = 3 * FLOPS_PER_CELL_STAGE * n2 / (stage_ms * 1e-3) / 1e12
+    # average stage-kernel launch: the timed region holds exactly 3 K stage
+    # launches and nothing else (the automatic step is fused into them)
+    launch_s = gpu_ms * 1e-3 / (3 * K)
+    bytes_launch = WORDS_PER_CELL_STEP * esize * n2 / 3
+    gbs = bytes_launch / launch_s / 1e9
+    tflops = FLOPS_PER_CELL_STAGE * n2 / launch_s / 1e12
     fpeak = FP64_PEAK_TFLOPS if args.prec in ("f64", "mixed") else FP32_PEAK_TFLOPS
+    traffic = None
+    if (MEASURED_TRAFFIC["workload"] == (nx, ny, args.prec)
+            and MEASURED_TRAFFIC["sources_sha256"] == stage_sources_sha256()):
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
     hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
     alu = {"bound": "alu", "achieved": round(tflops, 2), "peak": fpeak, "unit": "TFLOP/s",
-           "frac": round(tflops / fpeak, 4), "traffic": None}
+           "frac": round(tflops / fpeak, 4), "traffic": traffic}
     roof = alu if alu["frac"] >= hbm["frac"] else hbm
     roof = dict(roof)
     roof["kernel"] = "stage_kernel (3 launches per step)"
-    roof["stage_us_per_launch"] = round(stage_ms * 1e3 / 3, 3)
-    roof["launches_timed"] = launches
+    roof["stage_us_per_launch"] = round(launch_s * 1e6, 3)
+    roof["launches_timed"] = 3 * K
+    roof["algorithmic_bytes_per_launch"] = bytes_launch
+    roof["algorithmic_flops_per_launch"] = FLOPS_PER_CELL_STAGE * n2
     roof["other_bound"] = hbm if roof["bound"] == "alu" else alu
 
     out = {
@@ -211,9 +370,12 @@ def main():
         "config": {"workload": f"2D Euler four-quadrant Riemann problem {nx}x{ny} on [0,1]^2, gamma 1.4, "
                                "seeded +-5% quadrant states, transmissive, WENO5-JS+HLLC, SSP-RK3, CFL 0.5",
                    "nx": nx, "ny": ny, "prec": args.prec, "graph": bool(args.graph)},
-        "hbm_frac_of_peak": round(bytes_step * K / el / 1e9 / HBM_PEAK_GBS, 4),
+        "hbm_frac_of_peak": round(WORDS_PER_CELL_STEP * esize * n2 * K / el / 1e9 / HBM_PEAK_GBS, 4),
+        "hbm_copy_ceiling_GBs": copy_ceiling(),
         "roofline": roof,
-        "kernel_ms": {k: round(v[0] / max(v[1], 1), 5) for k, v in prof.items() if v[1]},
+        # per-launch times with an event pair around every launch (second
+        # pass; includes each pair's own overhead of about a microsecond)
+        "kernel_ms_event_bracketed": {k: round(v[0] / max(v[1], 1), 5) for k, v in prof.items() if v[1]},
         "faults": {"flags": flags, "fallback_faces": fb},
     }
     if not args.no_adjoint:

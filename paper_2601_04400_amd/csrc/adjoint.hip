@@ -20,6 +20,7 @@
 
 #include "flux.hpp"
 #include "grid.hpp"
+#include "xcd.hpp"
 
 namespace shk {
 
@@ -577,9 +578,10 @@ __global__ void __launch_bounds__(256) ibm_entries_rank_kernel(GhostTable gt, in
 //    reverse the ghost's conservative state into the adjoint of the image-
 //    point primitives gW[k] = (rho, u, v, p)_bar, and clear X at the ghost
 //    (the refill overwrites it, so its pre-refill adjoint is zero);
-// 2. per run of equal keys in the sorted (source, entry) list: the source
-//    cell gathers w_m gW[k] over the ghosts k that read it, in entry order,
-//    then the primitive -> conservative transpose at the source.
+// 2. per source cell (run heads[h] .. heads[h+1] of equal keys in the sorted
+//    (source, entry) list): the source gathers w_m gW[k] over the ghosts k
+//    that read it, in entry order, then the primitive -> conservative
+//    transpose at the source.
 // The gamma parts of both passes are summed in a fixed order into the
 // member's partial; with fin set, the member's recorded partials of the
 // whole reverse pass (slots of ps, this launch's own last) are then added to
@@ -598,7 +600,8 @@ __device__ __forceinline__ double block_sum_fixed(double v, double* red) {
 
 __global__ void __launch_bounds__(FILL_NT) ibm_fill_adjoint_kernel(GridArgs a, GhostTable gt,
                                                                    const int* __restrict__ keys,
-                                                                   const int* __restrict__ vals, int nent,
+                                                                   const int* __restrict__ vals,
+                                                                   const int* __restrict__ heads, int nsrc,
                                                                    const double* __restrict__ Us, double* __restrict__ X,
                                                                    double* __restrict__ gW, double* __restrict__ part,
                                                                    PartSlots ps, double* __restrict__ param_bar) {
@@ -659,18 +662,25 @@ __global__ void __launch_bounds__(FILL_NT) ibm_fill_adjoint_kernel(GridArgs a, G
     Xb[3 * n + gc] = 0.0;
   }
   __syncthreads();  // gW complete (global memory, one workgroup)
-  for (int i = threadIdx.x; i < nent; i += FILL_NT) {
-    if (i > 0 && keys[i] == keys[i - 1]) continue;
-    const int src = keys[i];
+  for (int h = threadIdx.x; h < nsrc; h += FILL_NT) {
+    const int i0 = heads[h], i1 = heads[h + 1];
+    const int src = keys[i0];
     double Wsb[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int j = i; j < nent && keys[j] == src; ++j) {
-      const int e = vals[j];
-      const int k = e >> 2;
-      const double wm = gt.w[e];
-      Wsb[0] += wm * gWb[4 * k];
-      Wsb[1] += wm * gWb[4 * k + 1];
-      Wsb[2] += wm * gWb[4 * k + 2];
-      Wsb[3] += wm * gWb[4 * k + 3];
+    for (int j0 = i0; j0 < i1; j0 += 4) {
+      // up to four entries per round with their loads issued together
+      int e[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) e[t] = j0 + t < i1 ? vals[j0 + t] : -1;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (e[t] < 0) continue;
+        const int k = e[t] >> 2;
+        const double wm = gt.w[e[t]];
+        Wsb[0] += wm * gWb[4 * k];
+        Wsb[1] += wm * gWb[4 * k + 1];
+        Wsb[2] += wm * gWb[4 * k + 2];
+        Wsb[3] += wm * gWb[4 * k + 3];
+      }
     }
     const double r = Ub[src];
     const double u = Ub[n + src] / r, v = Ub[2 * n + src] / r;
@@ -687,16 +697,19 @@ __global__ void __launch_bounds__(FILL_NT) ibm_fill_adjoint_kernel(GridArgs a, G
     if (threadIdx.x < 5) part[(long long)b * 5 + threadIdx.x] = threadIdx.x == 0 ? g : 0.0;
     return;
   }
-  // finalize: member b's recorded partials, slot by slot, then this launch's
-  for (int q = 0; q < 5; ++q) {
+  // finalize: wave q sums member b's recorded partials of quantity q (lane l
+  // takes the entries l, l + 64, ... of each slot in order, then a fixed
+  // butterfly), plus this launch's own gamma part
+  const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (q < 5) {
     double sq = 0.0;
     for (int slot = 0; slot < ps.n; ++slot) {
       const double* p = part - (ps.n - slot) * ps.stride;  // earlier slots precede this one
       const int nb = ps.nblk[slot];
-      for (int k = threadIdx.x; k < nb; k += FILL_NT) sq += p[((long long)b * nb + k) * 5 + q];
+      for (int k = lane; k < nb; k += 64) sq += p[((long long)b * nb + k) * 5 + q];
     }
-    sq = block_sum_fixed(sq, red);
-    if (threadIdx.x == 0) param_bar[b * 5 + q] += sq + (q == 0 ? g : 0.0);
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+    if (lane == 0) param_bar[b * 5 + q] += sq + (q == 0 ? g : 0.0);
   }
 }
 
@@ -756,10 +769,10 @@ hipError_t launch_ibm_entries(const GhostTable& gt, int* keys, int* vals, int* n
 }
 
 hipError_t launch_ibm_fill_adjoint(const GridArgs& a, const GhostTable& gt, const int* keys, const int* vals,
-                                   int nent, const double* Us, double* X, double* gW, double* part,
+                                   const int* heads, int nsrc, const double* Us, double* X, double* gW, double* part,
                                    const PartSlots& prior, double* param_bar, hipStream_t st) {
-  hipLaunchKernelGGL(ibm_fill_adjoint_kernel, dim3(a.nbatch), dim3(FILL_NT), 0, st, a, gt, keys, vals, nent, Us, X,
-                     gW, part, prior, param_bar);
+  hipLaunchKernelGGL(ibm_fill_adjoint_kernel, dim3(a.nbatch), dim3(FILL_NT), 0, st, a, gt, keys, vals, heads, nsrc,
+                     Us, X, gW, part, prior, param_bar);
   return hipGetLastError();
 }
 

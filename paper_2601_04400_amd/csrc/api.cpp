@@ -22,8 +22,8 @@ using namespace shk;
 
 struct WsLayout {
   size_t scalars, globals, dtbuf, xslots, u1, u2, cls, row_count, row_off, g_cell, g_src, g_w, g_nrm;
-  size_t adjA, adjB, adjC, adjP, adjQ, adjPart, part_stride, adjG, entKeys, entVals, entCount;
-  size_t netF, netX, netPart;
+  size_t adjA, adjB, adjC, adjP, adjQ, adjPart, part_stride, adjG, entKeys, entVals, entCount, entHeads;
+  size_t netX, netPart;
   size_t total;
 };
 
@@ -38,6 +38,7 @@ struct shk_grid {
   GhostTable gt;
   bool ibm_on;
   int nent = 0;  // valid (ghost, source) entries of the refill transpose
+  int nsrc = 0;  // distinct source cells among them
   NetArgs net{};
   bool net_on = false;
   float* net_grad = nullptr;
@@ -78,7 +79,8 @@ bool desc_ok(const shk_grid_desc* d, std::string* why) {
   if (d->viscous && d->ndim != 2) return bad("viscous terms need ndim 2");
   if (d->viscous && (!(d->mu >= 0.0) || !(d->prandtl > 0.0))) return bad("viscous needs mu >= 0, prandtl > 0");
   if (d->ibm && d->ndim != 2) return bad("immersed boundary needs ndim 2");
-  if (d->flux_net && (d->ndim != 2 || d->prec != SHK_F64)) return bad("flux net needs ndim 2 and SHK_F64");
+  if (d->flux_net && (d->ndim != 2 || d->prec != SHK_F64 || d->viscous))
+    return bad("flux net needs ndim 2, SHK_F64 and an inviscid grid");
   if (d->nu_art < 0.0) return bad("nu_art must be >= 0");
   return true;
 }
@@ -122,16 +124,14 @@ WsLayout layout(const shk_grid_desc* d) {
       L.entKeys = o; o += al(sizeof(int) * 4 * ncell);
       L.entVals = o; o += al(sizeof(int) * 4 * ncell);
       L.entCount = o; o += al(sizeof(int));
+      L.entHeads = o; o += al(sizeof(int) * (4 * ncell + 1));
     }
   }
   if (d->flux_net) {
     const size_t nface = size_t(d->nx + 1) * d->ny + size_t(d->nx) * (d->ny + 1);
-    L.netF = o; o += al(sizeof(float) * 4 * nface * d->nbatch);
     if (d->adjoint) {
       L.netX = o; o += al(sizeof(float) * 24 * nface * d->nbatch);
-      size_t nb = (nface + 255) / 256;
-      if (nb > 1024) nb = 1024;
-      L.netPart = o; o += al(sizeof(float) * NET_NP * nb * d->nbatch);
+      L.netPart = o; o += al(sizeof(float) * NET_NP * NET_BWD_BLOCKS);
     }
   }
   L.total = o;
@@ -168,19 +168,14 @@ hipError_t timed(shk_grid* g, int cls, F&& f) {
   return e;
 }
 
-// With the learned correction on, evaluate it for every face of the stage
-// state Us (face-batched MFMA pass) and let the stage kernel add it.
-template <class S>
-hipError_t net_prepare(shk_grid* g, GridArgs& a, const S* Us) {
-  if (!g->net_on) return hipSuccess;
-  float* dF = reinterpret_cast<float*>(g->ws + g->L.netF);
-  a.dF = dF;
-  return launch_net_forward(a, g->net, reinterpret_cast<const double*>(Us), dF, g->st);
-}
-
+// Stage launch; with the learned correction on, the kernel variant that
+// evaluates the network inside its tile (FP64 grids only).
 template <class S>
 hipError_t stage_launch(shk_grid* g, const GridArgs& a, int mode, const S* Us, const S* Un, S* Uo,
                         const double* dtp, const S* Lin) {
+  if (g->net_on)
+    return launch_stage_net(a, g->net, mode, reinterpret_cast<const double*>(Us),
+                            reinterpret_cast<const double*>(Un), reinterpret_cast<double*>(Uo), dtp, g->st);
   if (g->d.prec == SHK_MIXED)
     return launch_stage_mixed(a, mode, reinterpret_cast<const float*>(Us), reinterpret_cast<const float*>(Un),
                               reinterpret_cast<float*>(Uo), dtp, reinterpret_cast<const float*>(Lin), g->st);
@@ -216,8 +211,6 @@ shk_status stage_seq(shk_grid* g, S* U, const double* dt_in, double* dt_out, S* 
     dtp = a.dtbuf;
   }
   auto stage = [&](int mode, const S* Us, const S* Un, S* Uo) -> hipError_t {
-    hipError_t en = net_prepare<S>(g, a, Us);
-    if (en != hipSuccess) return en;
     return timed(g, mode, [&]() { return stage_launch<S>(g, a, mode, Us, Un, Uo, dtp, nullptr); });
   };
   auto fill = [&](S* X) -> hipError_t {
@@ -353,6 +346,7 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
   a.cls = cls;
   g->ibm_on = true;
   g->nent = 0;
+  g->nsrc = 0;
   if (g->d.adjoint && n > 0) {
     int* keys = reinterpret_cast<int*>(g->ws + g->L.entKeys);
     int* vals = reinterpret_cast<int*>(g->ws + g->L.entVals);
@@ -364,6 +358,20 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
     if (e == hipSuccess) e = hipStreamSynchronize(g->st);
     if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset (adjoint entries)");
     g->nent = nv;
+    // run heads of equal source keys (set-up only; host-side scan)
+    std::vector<int> hk(size_t(nv > 0 ? nv : 1)), heads;
+    if (nv > 0) e = hipMemcpyAsync(hk.data(), keys, sizeof(int) * nv, hipMemcpyDeviceToHost, g->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+    if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset (entry keys)");
+    heads.reserve(size_t(nv) + 1);
+    for (int i = 0; i < nv; ++i)
+      if (i == 0 || hk[i] != hk[i - 1]) heads.push_back(i);
+    heads.push_back(nv);
+    int* dh = reinterpret_cast<int*>(g->ws + g->L.entHeads);
+    e = hipMemcpyAsync(dh, heads.data(), sizeof(int) * heads.size(), hipMemcpyHostToDevice, g->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+    if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset (entry heads)");
+    g->nsrc = int(heads.size()) - 1;
   }
   return SHK_OK;
 }
@@ -388,10 +396,9 @@ shk_status shk_rhs(shk_grid* g, void* U, void* dUdt) {
   if (g->esize == 8) {
     GridArgs a = g->a;
     if (g->ibm_on) e = launch_ibm_fill<double>(a, g->gt, static_cast<double*>(U), g->st);
-    if (e == hipSuccess) e = net_prepare<double>(g, a, static_cast<double*>(U));
     if (e == hipSuccess)
-      e = launch_stage<double>(a, MODE_RHS, static_cast<double*>(U), static_cast<double*>(U),
-                               static_cast<double*>(dUdt), nullptr, nullptr, g->st);
+      e = stage_launch<double>(g, a, MODE_RHS, static_cast<double*>(U), static_cast<double*>(U),
+                               static_cast<double*>(dUdt), nullptr, nullptr);
   } else {
     if (g->ibm_on) e = launch_ibm_fill<float>(g->a, g->gt, static_cast<float*>(U), g->st);
     if (e == hipSuccess) {
@@ -467,8 +474,9 @@ static hipError_t fillT(shk_grid* g, PartRec& pr, const double* Us, double* X, d
   const int* keys = reinterpret_cast<const int*>(g->ws + g->L.entKeys);
   const int* vals = reinterpret_cast<const int*>(g->ws + g->L.entVals);
   double* gW = reinterpret_cast<double*>(g->ws + g->L.adjG);
-  hipError_t e = launch_ibm_fill_adjoint(g->a, g->gt, keys, vals, g->nent, Us, X, gW, pr.next(), pr.ps, param_bar,
-                                         g->st);
+  const int* heads = reinterpret_cast<const int*>(g->ws + g->L.entHeads);
+  hipError_t e = launch_ibm_fill_adjoint(g->a, g->gt, keys, vals, heads, g->nsrc, Us, X, gW, pr.next(), pr.ps,
+                                         param_bar, g->st);
   if (e == hipSuccess) {
     pr.add(1);
     if (param_bar) pr.finalised = true;
@@ -537,12 +545,9 @@ shk_status shk_rk3_step_adjoint(shk_grid* g, const void* U_n, const double* dt, 
   hipError_t e = hipMemcpyAsync(A, U_n, bytes, hipMemcpyDeviceToDevice, g->st);
   // forward recompute of the stage states
   if (e == hipSuccess) e = fill64(g, A);
-  GridArgs an = a;
-  if (e == hipSuccess) e = net_prepare<double>(g, an, A);
-  if (e == hipSuccess) e = launch_stage<double>(an, MODE_STAGE1, A, A, B, dt, nullptr, g->st);
+  if (e == hipSuccess) e = stage_launch<double>(g, a, MODE_STAGE1, A, A, B, dt, nullptr);
   if (e == hipSuccess) e = fill64(g, B);
-  if (e == hipSuccess) e = net_prepare<double>(g, an, B);
-  if (e == hipSuccess) e = launch_stage<double>(an, MODE_STAGE2, B, A, C, dt, nullptr, g->st);
+  if (e == hipSuccess) e = stage_launch<double>(g, a, MODE_STAGE2, B, A, C, dt, nullptr);
   if (e == hipSuccess) e = fill64(g, C);
   if (e == hipSuccess) e = reverse_step(g, A, B, C, dt, static_cast<double*>(U_bar), param_bar);
   return hip_check(g, e, "rk3_step_adjoint");

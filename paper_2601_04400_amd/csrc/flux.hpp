@@ -89,6 +89,9 @@ struct Flux4 {
   C f0, f1, f2, f3;
 };
 
+// One bracket, evaluated without branches: the star correction is always
+// formed and selected away on a supersonic side (its value there is never
+// used, whatever it is), so lanes of a wavefront never diverge here.
 template <class C>
 __device__ __forceinline__ Flux4<C> hllc_side(const Prim<C>& w, C E, C s, C ss, bool supersonic) {
   // physical flux of this side
@@ -98,7 +101,6 @@ __device__ __forceinline__ Flux4<C> hllc_side(const Prim<C>& w, C E, C s, C ss, 
   F.f1 = mn * w.un + w.p;
   F.f2 = mn * w.ut;
   F.f3 = w.un * (E + w.p);
-  if (supersonic) return F;
   C su = s - w.un;
   C chi = qdiv(su, s - ss);
   C rs = chi * w.r;
@@ -106,11 +108,12 @@ __device__ __forceinline__ Flux4<C> hllc_side(const Prim<C>& w, C E, C s, C ss, 
   C d1 = rs * ss - mn;
   C d2 = rs * w.ut - w.r * w.ut;
   C d3 = chi * (E + (ss - w.un) * (w.r * ss + qdiv(w.p, su))) - E;
-  F.f0 = F.f0 + s * d0;
-  F.f1 = F.f1 + s * d1;
-  F.f2 = F.f2 + s * d2;
-  F.f3 = F.f3 + s * d3;
-  return F;
+  Flux4<C> G;
+  G.f0 = supersonic ? F.f0 : F.f0 + s * d0;
+  G.f1 = supersonic ? F.f1 : F.f1 + s * d1;
+  G.f2 = supersonic ? F.f2 : F.f2 + s * d2;
+  G.f3 = supersonic ? F.f3 : F.f3 + s * d3;
+  return G;
 }
 
 template <class C>
@@ -123,12 +126,19 @@ __device__ __forceinline__ Flux4<C> hllc(const Prim<C>& L, const Prim<C>& R, C g
   C ss = qdiv(R.p - L.p + L.r * L.un * dL - R.r * R.un * dR, L.r * dL - R.r * dR);
   C EL = L.p * igm1 + C(0.5) * L.r * (L.un * L.un + L.ut * L.ut);
   C ER = R.p * igm1 + C(0.5) * R.r * (R.un * R.un + R.ut * R.ut);
-  if (ss > C(0)) return hllc_side(L, EL, sL, ss, sL >= C(0));
-  if (ss < C(0)) return hllc_side(R, ER, sR, ss, sR <= C(0));
-  Flux4<C> A = hllc_side(L, EL, sL, ss, sL >= C(0));
-  Flux4<C> B = hllc_side(R, ER, sR, ss, sR <= C(0));
-  return Flux4<C>{C(0.5) * (A.f0 + B.f0), C(0.5) * (A.f1 + B.f1), C(0.5) * (A.f2 + B.f2),
-                  C(0.5) * (A.f3 + B.f3)};
+  if (ss == C(0)) {
+    // contact exactly at rest: the mean of the two brackets (rare)
+    Flux4<C> A = hllc_side(L, EL, sL, ss, sL >= C(0));
+    Flux4<C> B = hllc_side(R, ER, sR, ss, sR <= C(0));
+    return Flux4<C>{C(0.5) * (A.f0 + B.f0), C(0.5) * (A.f1 + B.f1), C(0.5) * (A.f2 + B.f2),
+                    C(0.5) * (A.f3 + B.f3)};
+  }
+  // s* > 0: left bracket; s* < 0 (or not a number): right bracket.  The side
+  // is chosen first so only one bracket is evaluated per face.
+  const bool left = ss > C(0);
+  const Prim<C> W{left ? L.r : R.r, left ? L.un : R.un, left ? L.ut : R.ut, left ? L.p : R.p};
+  const C s = left ? sL : sR;
+  return hllc_side(W, left ? EL : ER, s, ss, left ? sL >= C(0) : sR <= C(0));
 }
 
 }  // namespace shk

@@ -45,7 +45,6 @@ struct GridArgs {
   double* dtbuf;               // [nbatch] step of the automatic time stepping
   double* dt_out;              // optional caller copy of the step (per call)
   unsigned long long* xslots;  // [nbatch][2][XSLOTS] spread extrema of the fused step
-  const float* dF;             // learned flux correction per face [nbatch][nface][4] or nullptr
   const float* dXnet;          // its stencil gradient per face [nbatch][nface][24] or nullptr
   long long nface;             // x-faces (nx+1)*ny then y-faces nx*(ny+1)
   Globals* glob;
@@ -61,25 +60,14 @@ struct GhostTable {
   int wall;         // 0 slip, 1 no-slip adiabatic
 };
 
-// Tile coordinates of this workgroup under an XCD-aware permutation of the
-// launch grid.  Workgroups are handed to the eight XCDs round-robin by linear
-// id, so XCD x receives ids x, x + 8, ...; mapping the k-th of them to tile
-// start_x + k gives every XCD one contiguous run of tiles (rows of tiles),
-// and the halo rows a tile shares with its neighbours are then mostly read
-// through the same L2.  The map is a bijection for any grid size, so
-// correctness does not depend on how the hardware actually dispatches.
-__device__ __forceinline__ void xcd_tile(int& bx, int& by, int& bz) {
-  const int gx = gridDim.x, gy = gridDim.y;
-  const int n = gx * gy * gridDim.z;
-  const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-  const int q = n >> 3, r = n & 7;
-  const int x = lin & 7, k = lin >> 3;
-  const int t = x * q + (x < r ? x : r) + k;
-  bx = t % gx;
-  const int rest = t / gx;
-  by = rest % gy;
-  bz = rest / gy;
-}
+// Learned face-flux correction: weights in the matrix-core layout (bf16),
+// biases, input normalisation and output scale.
+struct NetArgs {
+  const unsigned short* w;  // bf16 bits, device layout of mlp.hpp
+  const float* bias;
+  double mean[4], inv_std[4];
+  float out_scale;
+};
 
 // Host-side launchers (stage.hip, ibm.hip).
 template <class S>
@@ -96,6 +84,10 @@ hipError_t launch_ibm_classify(const GridArgs& a, const double* phi, uint8_t* cl
                                hipStream_t st);
 hipError_t launch_ibm_table(const GridArgs& a, const double* phi, const uint8_t* cls, const int* row_count,
                             int* row_off, GhostTable gt, hipStream_t st);
+// Stage kernel with the learned correction evaluated inside the tile (2D,
+// FP64, inviscid; modes MODE_RHS .. MODE_STAGE3).
+hipError_t launch_stage_net(const GridArgs& a, const NetArgs& n, int mode, const double* Us, const double* Un,
+                            double* Uout, const double* dtp, hipStream_t st);
 hipError_t launch_stage_mixed(const GridArgs& a, int mode, const float* Us, const float* Un, float* Uout,
                               const double* dtp, const float* Lin, hipStream_t st);
 
@@ -119,8 +111,9 @@ hipError_t launch_ibm_entries(const GhostTable& gt, int* keys, int* vals, int* n
 // partial goes to part (1 block per member).  With param_bar set it also
 // finalises: param_bar += the slots of prior (which lie before part, at
 // part - (prior.n - s) * prior.stride for slot s) plus its own partial.
+// heads[0..nsrc]: start of each source's run in the sorted entry list.
 hipError_t launch_ibm_fill_adjoint(const GridArgs& a, const GhostTable& gt, const int* keys, const int* vals,
-                                   int nent, const double* Us, double* X, double* gW, double* part,
+                                   const int* heads, int nsrc, const double* Us, double* X, double* gW, double* part,
                                    const PartSlots& prior, double* param_bar, hipStream_t st);
 hipError_t launch_axpy(long long n, double alpha, const double* x, double* y, int accumulate, hipStream_t st);
 

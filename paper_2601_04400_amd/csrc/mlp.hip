@@ -25,42 +25,11 @@
 #include "flux.hpp"
 #include "grid.hpp"
 #include "mlp.hpp"
+#include "mlp_dev.hpp"
 
 namespace shk {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
 namespace {
-
-__device__ __forceinline__ unsigned short f2bf(float x) {
-  unsigned int u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-
-__device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
-
-// A operand: rows r0..r0+15 (lane & 15), columns k0 + 4 (lane >> 4) + 0..3 of a
-// row-major bf16 matrix with leading dimension ld.
-__device__ __forceinline__ bf16x4 ldA(const unsigned short* m, int ld, int r0, int k0, int lane) {
-  const unsigned short* p = m + (r0 + (lane & 15)) * ld + k0 + 4 * (lane >> 4);
-  return bf16x4{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
-}
-
-// A operand of the transpose: (M^T)[r][k] = M[k][r].
-__device__ __forceinline__ bf16x4 ldAT(const unsigned short* m, int ld, int r0, int k0, int lane) {
-  const int r = r0 + (lane & 15), k = k0 + 4 * (lane >> 4);
-  return bf16x4{(short)m[k * ld + r], (short)m[(k + 1) * ld + r], (short)m[(k + 2) * ld + r],
-                (short)m[(k + 3) * ld + r]};
-}
-
-__device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
-  return bf16x4{(short)f2bf(a), (short)f2bf(b), (short)f2bf(c), (short)f2bf(d)};
-}
 
 // Primitive state (rho, u_n, u_t, p) of stencil cell s (0..5) of face f of
 // batch member Ub; x-faces first ((nx+1) per row), then y-faces (nx per row).
@@ -104,103 +73,18 @@ __device__ __forceinline__ void face_cell_prim(const GridArgs& a, const double* 
     if (fx & 1) q[1] = -q[1];
   }
   if (fy & 1) q[2] = -q[2];
-  const double ir = 1.0 / q[0];
-  const double u = q[1] * ir, v = q[2] * ir;
-  w[0] = q[0];
-  w[1] = isx ? u : v;
-  w[2] = isx ? v : u;
-  w[3] = (a.gamma - 1.0) * (q[3] - 0.5 * q[0] * (u * u + v * v));
+  // the same conversion as the stage kernel's tile load, so the network sees
+  // bit-identical inputs on both paths
+  const Prim<double> p = to_prim(q[0], q[1], q[2], q[3], a.gamma - 1.0);
+  w[0] = p.r;
+  w[1] = isx ? p.un : p.ut;
+  w[2] = isx ? p.ut : p.un;
+  w[3] = p.p;
 }
 
-// Network input tile for one 16-face tile: lane (q = lane>>4, face = lane&15)
-// holds inputs 4q..4q+3 (k-tile 0: cell q) and 16+4q.. (k-tile 1: cell 4+q).
 __device__ __forceinline__ void build_inputs(const GridArgs& a, const NetArgs& n, const double* __restrict__ Ub,
                                              long long f, int lane, bf16x4& x0, bf16x4& x1) {
-  const int q = lane >> 4;
-  double w[4];
-  face_cell_prim(a, Ub, f, q, w);
-  float xv[4];
-  for (int v = 0; v < 4; ++v) xv[v] = float((w[v] - n.mean[v]) * n.inv_std[v]);
-  x0 = pack4(xv[0], xv[1], xv[2], xv[3]);
-  if (q < 2) {
-    face_cell_prim(a, Ub, f, 4 + q, w);
-    for (int v = 0; v < 4; ++v) xv[v] = float((w[v] - n.mean[v]) * n.inv_std[v]);
-    x1 = pack4(xv[0], xv[1], xv[2], xv[3]);
-  } else {
-    x1 = bf16x4{0, 0, 0, 0};
-  }
-}
-
-__device__ __forceinline__ void load_net_lds(const NetArgs& n, unsigned short* sw, float* sb) {
-  for (int k = threadIdx.x; k < NET_NW; k += blockDim.x) sw[k] = n.w[k];
-  for (int k = threadIdx.x; k < NET_NB; k += blockDim.x) sb[k] = n.bias[k];
-}
-
-// Forward of one 64-face batch held by a wave.  Returns, for lanes with
-// lane>>4 == 0, the pre-tanh outputs z[ft][0..3] of face ft*16 + (lane&15);
-// optionally keeps the activations and ReLU masks for the reverse pass.
-struct Acts {
-  bf16x4 x[2][4];
-  bf16x4 h[3][4][4];        // layer, neuron tile, face tile
-  unsigned int mask[3][4];  // bit (nt*4 + i) of face tile ft: pre-activation > 0
-};
-
-__device__ __forceinline__ void net_forward_batch(const unsigned short* sw, const float* sb, int lane, Acts& A,
-                                                  f32x4 z[4]) {
-  const int q = lane >> 4;
-  // layer 1: 64 x 32
-#pragma unroll
-  for (int ft = 0; ft < 4; ++ft) A.mask[0][ft] = 0u;
-#pragma unroll
-  for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-    for (int ft = 0; ft < 4; ++ft) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      acc = mfma(ldA(sw + NET_OFF_W0, 32, nt * 16, 0, lane), A.x[0][ft], acc);
-      acc = mfma(ldA(sw + NET_OFF_W0, 32, nt * 16, 16, lane), A.x[1][ft], acc);
-      float hv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float pre = acc[i] + sb[NET_OFF_B0 + nt * 16 + 4 * q + i];
-        hv[i] = pre > 0.f ? pre : 0.f;
-        if (pre > 0.f) A.mask[0][ft] |= 1u << (nt * 4 + i);
-      }
-      A.h[0][nt][ft] = pack4(hv[0], hv[1], hv[2], hv[3]);
-    }
-  // layers 2 and 3: 64 x 64
-#pragma unroll
-  for (int l = 1; l < 3; ++l) {
-    const unsigned short* W = sw + (l == 1 ? NET_OFF_W1 : NET_OFF_W2);
-    const float* B = sb + (l == 1 ? NET_OFF_B1 : NET_OFF_B2);
-#pragma unroll
-    for (int ft = 0; ft < 4; ++ft) A.mask[l][ft] = 0u;
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-      for (int ft = 0; ft < 4; ++ft) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kt = 0; kt < 4; ++kt) acc = mfma(ldA(W, 64, nt * 16, kt * 16, lane), A.h[l - 1][kt][ft], acc);
-        float hv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float pre = acc[i] + B[nt * 16 + 4 * q + i];
-          hv[i] = pre > 0.f ? pre : 0.f;
-          if (pre > 0.f) A.mask[l][ft] |= 1u << (nt * 4 + i);
-        }
-        A.h[l][nt][ft] = pack4(hv[0], hv[1], hv[2], hv[3]);
-      }
-  }
-  // output layer: 16 (4 used) x 64
-#pragma unroll
-  for (int ft = 0; ft < 4; ++ft) {
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kt = 0; kt < 4; ++kt) acc = mfma(ldA(sw + NET_OFF_W3, 64, 0, kt * 16, lane), A.h[2][kt][ft], acc);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i] = acc[i] + sb[NET_OFF_B3 + 4 * q + i];
-    z[ft] = acc;
-  }
+  net_inputs(n, lane, [&](int s, double w[4]) { face_cell_prim(a, Ub, f, s, w); }, x0, x1);
 }
 
 }  // namespace
@@ -382,13 +266,9 @@ __global__ void __launch_bounds__(256) net_backward_kernel(GridArgs a, NetArgs n
   for (int k = threadIdx.x; k < NET_NP; k += blockDim.x) gsum[k] = 0.f;
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane >> 4, fl = lane & 15;
-  const int b = blockIdx.y;
-  const long long boff = (long long)b * 4 * a.ncell;
-  const double* __restrict__ Ub = U + boff;
-  const double* __restrict__ Lb = lam + boff;
-  const double clam = clam_f * (dtp ? dtp[b] : 1.0);
   const long long nxf = (long long)(a.nx + 1) * a.ny;
   const bool perx = a.bc[0] == BC_PERIODIC, pery = a.bc[2] == BC_PERIODIC;
+  const double* __restrict__ Lb = lam;
   auto lam_at = [&](int v, int gi, int gj) -> double {
     if (gi < 0 || gi >= a.nx) {
       if (!perx) return 0.0;
@@ -404,11 +284,18 @@ __global__ void __launch_bounds__(256) net_backward_kernel(GridArgs a, NetArgs n
   };
   unsigned short* trA = tr[wv][0];
   unsigned short* trH = tr[wv][1];
-  const int nbatches = (int)((nface + 63) / 64);
-  const int rounds = (nbatches + (int)gridDim.x * 4 - 1) / ((int)gridDim.x * 4);
-  for (int r = 0; r < rounds; ++r) {
-    const long long base = ((long long)r * gridDim.x * 4 + (long long)blockIdx.x * 4 + wv) * 64;
-    const bool live = base < nface;
+  // 64-face batches of all batch members, dealt to the blocks in a fixed
+  // order (every block runs the same number of rounds)
+  const long long per_b = (nface + 63) / 64;
+  const long long total = per_b * a.nbatch;
+  for (long long g0 = (long long)blockIdx.x * 4; g0 < total; g0 += (long long)gridDim.x * 4) {
+    const long long gb = g0 + wv;
+    const bool live = gb < total;
+    const int b = live ? (int)(gb / per_b) : 0;
+    const long long base = live ? (gb % per_b) * 64 : 0;
+    const double* __restrict__ Ub = U + (long long)b * 4 * a.ncell;
+    Lb = lam + (long long)b * 4 * a.ncell;
+    const double clam = clam_f * (dtp ? dtp[b] : 1.0);
     Acts A;
     f32x4 z[4];
     float Fb[4][4];
@@ -483,18 +370,28 @@ __global__ void __launch_bounds__(256) net_backward_kernel(GridArgs a, NetArgs n
     }
   }
   __syncthreads();
-  float* pb = part + ((long long)b * gridDim.x + blockIdx.x) * NET_NP;
+  float* pb = part + (long long)blockIdx.x * NET_NP;
   for (int k = threadIdx.x; k < NET_NP; k += blockDim.x) pb[k] = gsum[k];
 }
 
-// grad[k] += sum over blocks of part (fixed order), all batch members.
-__global__ void __launch_bounds__(256) net_grad_reduce_kernel(const float* __restrict__ part, int nblk,
-                                                              float* __restrict__ grad) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= NET_NP) return;
+// grad[k] += sum over the nblk block partials of part, in a fixed order:
+// each of the 16 waves of a workgroup sums every 16th partial of 64
+// parameters, then the 16 wave sums are added in wave order.
+__global__ void __launch_bounds__(1024) net_grad_reduce_kernel(const float* __restrict__ part, int nblk,
+                                                               float* __restrict__ grad) {
+  __shared__ double red[16][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int j = 0; j < nblk; ++j) s += part[(long long)j * NET_NP + k];
-  grad[k] += float(s);
+  if (k < NET_NP)
+    for (int j = wv; j < nblk; j += 16) s += part[(long long)j * NET_NP + k];
+  red[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && k < NET_NP) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += red[w][lane];
+    grad[k] += float(t);
+  }
 }
 
 // bf16 weights (padded MFMA layout) and biases from FP32 master parameters in
@@ -605,7 +502,14 @@ static unsigned int net_blocks(long long nface) {
   return (unsigned int)(nb < 1 ? 1 : nb);
 }
 
-unsigned int net_backward_blocks(const GridArgs& a) { return net_blocks(net_face_count(a)); }
+// Reverse pass: 64-face batches of all members over at most NET_BWD_BLOCKS
+// workgroups (one parameter partial each).
+unsigned int net_backward_blocks(const GridArgs& a) {
+  const long long batches = (net_face_count(a) + 63) / 64 * a.nbatch;
+  long long nb = (batches + 3) / 4;
+  if (nb > NET_BWD_BLOCKS) nb = NET_BWD_BLOCKS;
+  return (unsigned int)(nb < 1 ? 1 : nb);
+}
 
 hipError_t launch_net_forward(const GridArgs& a, const NetArgs& n, const double* U, float* dF, hipStream_t st) {
   const long long nf = net_face_count(a);
@@ -616,13 +520,11 @@ hipError_t launch_net_forward(const GridArgs& a, const NetArgs& n, const double*
 hipError_t launch_net_backward(const GridArgs& a, const NetArgs& n, const double* U, const double* lam, double clam_f,
                                const double* dtp, float* dX, float* part, float* grad, hipStream_t st) {
   const long long nf = net_face_count(a);
-  const unsigned int nb = net_blocks(nf);
-  hipLaunchKernelGGL(net_backward_kernel, dim3(nb, a.nbatch), dim3(256), 0, st, a, n, U, lam, clam_f, dtp, dX, part,
-                     nf);
+  const unsigned int nb = net_backward_blocks(a);
+  hipLaunchKernelGGL(net_backward_kernel, dim3(nb), dim3(256), 0, st, a, n, U, lam, clam_f, dtp, dX, part, nf);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !grad) return e;
-  hipLaunchKernelGGL(net_grad_reduce_kernel, dim3((NET_NP + 255) / 256), dim3(256), 0, st, part,
-                     (int)(nb * a.nbatch), grad);
+  hipLaunchKernelGGL(net_grad_reduce_kernel, dim3((NET_NP + 63) / 64), dim3(1024), 0, st, part, (int)nb, grad);
   return hipGetLastError();
 }
 

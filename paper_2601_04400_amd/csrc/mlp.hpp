@@ -16,12 +16,8 @@ constexpr int NET_G_W0 = 0, NET_G_B0 = 1536, NET_G_W1 = 1600, NET_G_B1 = 5696, N
 constexpr int NET_OFF_W0 = 0, NET_OFF_W1 = 2048, NET_OFF_W2 = 6144, NET_OFF_W3 = 10240, NET_NW = 11264;
 constexpr int NET_OFF_B0 = 0, NET_OFF_B1 = 64, NET_OFF_B2 = 128, NET_OFF_B3 = 192, NET_NB = 208;
 
-struct NetArgs {
-  const unsigned short* w;  // [NET_NW] bf16 bits
-  const float* bias;        // [NET_NB]
-  double mean[4], inv_std[4];
-  float out_scale;
-};
+
+constexpr int NET_BWD_BLOCKS = 512;  // workgroups (and parameter partials) of the reverse pass
 
 long long net_face_count(const GridArgs& a);
 unsigned int net_backward_blocks(const GridArgs& a);

@@ -15,6 +15,9 @@
 
 #include "flux.hpp"
 #include "grid.hpp"
+#include "xcd.hpp"
+#include "mlp.hpp"
+#include "mlp_dev.hpp"
 
 namespace shk {
 
@@ -147,11 +150,16 @@ __device__ __forceinline__ bool finite_val(C x) {
 //             tile is loaded (never stored); writes U2;
 //   MODE_S3F: stage 3 with the step of S2F; one block advances the device
 //             time and clears the extrema for the next step.
-template <class S, class C, int NDIM, int TX, int TY, bool VISC, int MODE>
+//
+// NET: the learned face-flux correction (section 2 neural flux, per-face
+// MLP) is evaluated inside the tile, on matrix cores, from the primitive
+// halo the tile has already loaded, and added to each face flux in the face
+// frame before the divergence.
+template <class S, class C, int NDIM, int TX, int TY, bool VISC, int MODE, bool NET = false>
 __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restrict__ Us,
                                                     const S* __restrict__ Un, S* __restrict__ Uout,
                                                     const double* __restrict__ dtp,
-                                                    const S* __restrict__ Lin) {
+                                                    const S* __restrict__ Lin, NetArgs net) {
   constexpr int NT = 256;
   constexpr int H = HALO;
   constexpr int PX = TX + 2 * H;
@@ -165,6 +173,9 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
   __shared__ C fxs[4][TY * (TX + 1)];
   __shared__ C fys[4][FYR * TX];
   __shared__ unsigned int blk_fallback, blk_fault;
+  static_assert(!NET || (NDIM == 2 && !VISC), "learned correction: 2D inviscid tiles");
+  __shared__ unsigned short net_w[NET ? NET_NW : 1];
+  __shared__ float net_b[NET ? NET_NB : 1];
   __shared__ double red_s[NT / 64], red_r[NT / 64];
 
   int bx, by, b;
@@ -227,6 +238,8 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     return C(S(C(Ub[e * a.ncell + c]) + cdt * C(Lb[e * a.ncell + c])));
   };
 
+  if (NET) load_net_lds(net, net_w, net_b);
+
   // 1. halo tile of primitives
   for (int k = threadIdx.x; k < PY * PX; k += NT) {
     const int lx = k % PX, ly = k / PX;
@@ -247,6 +260,84 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     w[3][k] = p.p;
   }
   __syncthreads();
+
+  // face k of the tile -> first stencil cell, stride, normal/tangential
+  // velocity arrays and the index of its flux slot
+  auto face_of = [&](int k, int& s0, int& st, int& cn, int& ct, int& oidx) {
+    if (k < NFX) {
+      const int fi = k % (TX + 1), y = k / (TX + 1);
+      s0 = (NDIM == 2 ? (y + H) * PX : 0) + fi;
+      st = 1; cn = 1; ct = 2;
+      oidx = y * (TX + 1) + fi;
+    } else {
+      const int kk = k - NFX;
+      const int x = kk % TX, fj = kk / TX;
+      s0 = fj * PX + x + H;
+      st = PX; cn = 2; ct = 1;
+      oidx = fj * TX + x;
+    }
+  };
+
+  if (NET) {
+    // 1b. learned correction of every face of the tile, 64 faces per wave
+    // and batch; the face-frame result is parked in the flux arrays, which
+    // the face pass reads back and adds to
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int NF = NFX + NFY;
+    bool net_bad = false;
+    for (int bb = wv; bb * 64 < NF; bb += NT / 64) {
+      Acts A;
+#pragma unroll
+      for (int ft = 0; ft < 4; ++ft) {
+        int k = bb * 64 + ft * 16 + (lane & 15);
+        if (k >= NF) k = NF - 1;
+        int s0, st, cn, ct, oidx;
+        face_of(k, s0, st, cn, ct, oidx);
+        net_inputs(net, lane, [&](int s, double wv4[4]) {
+          const int p = s0 + s * st;
+          wv4[0] = double(w[0][p]);
+          wv4[1] = double(w[cn][p]);
+          wv4[2] = double(w[ct][p]);
+          wv4[3] = double(w[3][p]);
+        }, A.x[0][ft], A.x[1][ft]);
+      }
+      f32x4 z[4];
+      net_forward_batch(net_w, net_b, lane, A, z);
+      if ((lane >> 4) == 0) {
+#pragma unroll
+        for (int ft = 0; ft < 4; ++ft) {
+          const int k = bb * 64 + ft * 16 + (lane & 15);
+          if (k >= NF) continue;
+          int s0, st, cn, ct, oidx;
+          face_of(k, s0, st, cn, ct, oidx);
+          float o[4];
+          bool ok = true;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            o[i] = net.out_scale * tanhf(z[ft][i]);
+            ok = ok && isfinite(o[i]);
+          }
+          if (!ok) {
+            // the uncorrected flux; flagged when the face is a real one
+            o[0] = o[1] = o[2] = o[3] = 0.f;
+            bool real;
+            if (k < NFX) real = i0 + k % (TX + 1) <= a.nx && j0 + k / (TX + 1) < a.ny;
+            else real = i0 + (k - NFX) % TX < a.nx && j0 + (k - NFX) / TX <= a.ny;
+            net_bad = net_bad || real;
+          }
+          if (k < NFX) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) fxs[i][oidx] = C(o[i]);
+          } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) fys[i][oidx] = C(o[i]);
+          }
+        }
+      }
+    }
+    if (net_bad) atomicOr(&blk_fault, 8u);
+    __syncthreads();
+  }
 
   // 2. face fluxes
   const C eps = C(a.eps);
@@ -325,23 +416,14 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
       F.f2 = F.f2 - tnt;
       F.f3 = F.f3 - (ubn * tnn + ubt * tnt - qn);
     }
-    if (a.dF != nullptr) {
-      // learned correction of this face (face frame), from the face-batched pass
-      long long gfi = -1;
+    if (NET) {
+      // learned correction of this face (face frame), parked by pass 1b
       if (isx) {
-        const int fi = k % (TX + 1), y = k / (TX + 1);
-        if (i0 + fi <= a.nx && j0 + y < a.ny) gfi = (long long)(j0 + y) * (a.nx + 1) + i0 + fi;
+        F.f0 = F.f0 + fxs[0][oidx]; F.f1 = F.f1 + fxs[1][oidx];
+        F.f2 = F.f2 + fxs[2][oidx]; F.f3 = F.f3 + fxs[3][oidx];
       } else {
-        const int kk = k - NFX, x = kk % TX, fj = kk / TX;
-        if (i0 + x < a.nx && j0 + fj <= a.ny)
-          gfi = (long long)(a.nx + 1) * a.ny + (long long)(j0 + fj) * a.nx + i0 + x;
-      }
-      if (gfi >= 0) {
-        const float* d = a.dF + ((long long)b * a.nface + gfi) * 4;
-        F.f0 = F.f0 + C(d[0]);
-        F.f1 = F.f1 + C(d[1]);
-        F.f2 = F.f2 + C(d[2]);
-        F.f3 = F.f3 + C(d[3]);
+        F.f0 = F.f0 + fys[0][oidx]; F.f1 = F.f1 + fys[1][oidx];
+        F.f2 = F.f2 + fys[2][oidx]; F.f3 = F.f3 + fys[3][oidx];
       }
     }
     if (isx) {
@@ -605,15 +687,15 @@ static hipError_t launch_mode(const GridArgs& a, const S* Us, const S* Un, S* Uo
   if (a.ndim == 1) {
     dim3 grid((a.nx + TX1 - 1) / TX1, 1, a.nbatch);
     hipLaunchKernelGGL((stage_kernel<S, C, 1, TX1, 1, false, MODE>), grid, dim3(256), 0, st, a, Us, Un, Uo,
-                       dtp, Lin);
+                       dtp, Lin, NetArgs{});
   } else {
     dim3 grid((a.nx + TX2 - 1) / TX2, (a.ny + TY2 - 1) / TY2, a.nbatch);
     if (a.viscous)
       hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, true, MODE>), grid, dim3(256), 0, st, a, Us, Un,
-                         Uo, dtp, Lin);
+                         Uo, dtp, Lin, NetArgs{});
     else
       hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, false, MODE>), grid, dim3(256), 0, st, a, Us, Un,
-                         Uo, dtp, Lin);
+                         Uo, dtp, Lin, NetArgs{});
   }
   return hipGetLastError();
 }
@@ -629,6 +711,27 @@ static hipError_t launch_stage_c(const GridArgs& a, int mode, const S* Us, const
     case MODE_S1L: return launch_mode<S, C, MODE_S1L>(a, Us, Un, Uo, dtp, Lin, st);
     case MODE_S2F: return launch_mode<S, C, MODE_S2F>(a, Us, Un, Uo, dtp, Lin, st);
     case MODE_S3F: return launch_mode<S, C, MODE_S3F>(a, Us, Un, Uo, dtp, Lin, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int MODE>
+static hipError_t launch_net_mode(const GridArgs& a, const NetArgs& n, const double* Us, const double* Un,
+                                  double* Uo, const double* dtp, hipStream_t st) {
+  dim3 grid((a.nx + TX2 - 1) / TX2, (a.ny + TY2 - 1) / TY2, a.nbatch);
+  hipLaunchKernelGGL((stage_kernel<double, double, 2, TX2, TY2, false, MODE, true>), grid, dim3(256), 0, st, a, Us,
+                     Un, Uo, dtp, nullptr, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_net(const GridArgs& a, const NetArgs& n, int mode, const double* Us, const double* Un,
+                            double* Uo, const double* dtp, hipStream_t st) {
+  if (a.ndim != 2 || a.viscous) return hipErrorInvalidValue;
+  switch (mode) {
+    case MODE_RHS: return launch_net_mode<MODE_RHS>(a, n, Us, Un, Uo, dtp, st);
+    case MODE_STAGE1: return launch_net_mode<MODE_STAGE1>(a, n, Us, Un, Uo, dtp, st);
+    case MODE_STAGE2: return launch_net_mode<MODE_STAGE2>(a, n, Us, Un, Uo, dtp, st);
+    case MODE_STAGE3: return launch_net_mode<MODE_STAGE3>(a, n, Us, Un, Uo, dtp, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -210,6 +210,7 @@ def evaluate(net, seeds, nc=128, factor=4, nsteps=24, cfl_frac=0.5, device="cuda
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         out[f"plain_{nm}"] = dict(errs(restrict(Um, 2)), ms_per_step=el * 1e3 / nsteps)
+    marks = sorted({max(1, nsteps // 3), max(1, 2 * nsteps // 3), nsteps})
     for name, use in (("plain", False), ("learned", True)):
         g = Grid(nc, nc, nbatch=len(seeds), flux_net=True, device=device)
         g.set_flux_net(net if use else None)
@@ -220,7 +221,15 @@ def evaluate(net, seeds, nc=128, factor=4, nsteps=24, cfl_frac=0.5, device="cuda
             g.step(U, data.dt_c)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        out[f"{name}_{nc}"] = dict(errs(U), ms_per_step=el * 1e3 / nsteps)
+        # error along the rollout (a second, untimed pass)
+        U = data.snaps[0].clone()
+        horizon = {}
+        for s in range(1, nsteps + 1):
+            g.step(U, data.dt_c)
+            if s in marks:
+                d = U - data.snaps[s]
+                horizon[s] = float((d * d).mean())
+        out[f"{name}_{nc}"] = dict(errs(U), ms_per_step=el * 1e3 / nsteps, mse_after_steps=horizon)
     out["learned"] = out[f"learned_{nc}"]
     out["plain"] = out[f"plain_{nc}"]
     return out

@@ -162,3 +162,67 @@ def test_training_reduces_loss_and_beats_plain_solver():
     ev = L.evaluate(net, list(range(1000, 1008)), nc=64, factor=4, nsteps=12)
     print(ev, flush=True)
     assert ev["learned"]["mse"] < ev["plain"]["mse"]
+
+
+def _divergence(dF, nx, ny, dx, dy):
+    """-(dF_x(i+1/2) - dF_x(i-1/2))/dx - (dF_y(j+1/2) - dF_y(j-1/2))/dy of a
+    per-face correction in the face frame (x-faces first, then y-faces)."""
+    nxf = (nx + 1) * ny
+    fx = dF[:nxf].reshape(ny, nx + 1, 4)
+    fy = dF[nxf:].reshape(ny + 1, nx, 4)
+    gx = fx[..., [0, 1, 2, 3]]          # face frame of an x-face = global order
+    gy = fy[..., [0, 2, 1, 3]]          # (rho, v, u, E) -> (rho, u, v, E)
+    div = -(gx[:, 1:, :] - gx[:, :-1, :]) / dx - (gy[1:, :, :] - gy[:-1, :, :]) / dy
+    return np.moveaxis(div, -1, 0)
+
+
+@pytest.mark.parametrize("bc", [(3, 3, 3, 3), (2, 0, 1, 1)])
+def test_in_tile_correction_equals_face_batched_pass(orc, bc):
+    """The stage kernel evaluates the network inside its tile; what it adds to
+    the right-hand side is minus the divergence of the per-face output of the
+    face-batched network kernel (same inputs bit for bit), up to FP64
+    rounding of the flux sums, on a grid of several tiles with ragged edges."""
+    from paper_2601_04400_amd import Grid
+    nx, ny = 45, 27
+    dom = (0.0, 1.0, 0.0, ny / nx)
+    inflow = (1.3, 0.7, -0.2, 1.1)
+    g = Grid(nx, ny, domain=dom, bc=bc, inflow=inflow, flux_net=True)
+    g0 = Grid(nx, ny, domain=dom, bc=bc, inflow=inflow)
+    net, _, _ = make_net(orc, 7)
+    g.set_flux_net(net)
+    c = orc.config(nx=nx, ny=ny, y1=dom[3], bc=bc, inflow=inflow)
+    U = orc.prim_to_cons(c, inputs.smooth_prim(nx, ny, seed=11, amp=0.3, domain=dom))
+    Ug = torch.from_numpy(U).cuda().reshape(g.shape)
+    L1 = to_np(g.rhs(Ug.clone()))[0]
+    L0 = to_np(g0.rhs(Ug.clone()))[0]
+    dF = to_np(g.flux_net_eval(Ug))[0].astype(np.float64)
+    div = _divergence(dF, nx, ny, 1.0 / nx, dom[3] / ny)
+    assert np.max(np.abs(div)) > 1e-3 * np.max(np.abs(L0))  # the correction matters here
+    assert np.max(np.abs(L1 - L0 - div)) <= 1e-11 * np.max(np.abs(L0))
+    flags, _ = g.poll_faults()
+    assert flags & 8 == 0
+
+
+def test_corrected_step_vs_oracle(orc):
+    """One SSP-RK3 step with the learned correction against the oracle's step
+    with its bfloat16-emulating network: the difference is bounded by one
+    bfloat16 unit of the correction's effect on the step (4e-3 of the change
+    the network makes) plus FP64 rounding."""
+    from paper_2601_04400_amd import Grid
+    nx, ny = 40, 24
+    dom = (0.0, 1.0, 0.0, ny / nx)
+    bc = (0, 0, 1, 1)
+    c = orc.config(nx=nx, ny=ny, y1=dom[3], bc=bc)
+    g = Grid(nx, ny, domain=dom, bc=bc, flux_net=True)
+    net, ref, _ = make_net(orc, 8)
+    g.set_flux_net(net)
+    U = orc.prim_to_cons(c, inputs.smooth_prim(nx, ny, seed=12, amp=0.3, domain=dom))
+    dt = 0.4 * orc.cfl_dt(c, U)
+    want, _ = orc.rk3_step(c, U, dt, net=ref)
+    plain, _ = orc.rk3_step(c, U, dt)
+    effect = np.max(np.abs(want - plain))
+    assert effect > 1e-6 * np.max(np.abs(want))
+    Ug = torch.from_numpy(U).cuda().reshape(g.shape).clone()
+    g.step(Ug, dt)
+    got = to_np(Ug)[0]
+    assert np.max(np.abs(got - want)) <= 4e-3 * effect + 1e-11 * np.max(np.abs(want))
