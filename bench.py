@@ -35,9 +35,9 @@ WORDS_PER_CELL_STEP = 32
 # kernel calibration (fetch x 2.0, write x 1.0), for the stage-kernel sources
 # whose SHA-256 is given; reported as null for any other source or workload.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "5c334daf253ba72a8aed5dcf5a6ef4e6140ad3d68c868380b2392c423381f41f",
+    "sources_sha256": "8c166842136a7677dd6459c46d72b79c964b6e65f0f03738c8c8ff25a0b33869",
     "workload": (512, 512, "f64"),
-    "bytes_per_launch": 23530394,
+    "bytes_per_launch": 23513065,
     "profile": "profiles/stage_kernel_quadrant512_f64.md",
 }
 STAGE_SOURCES = ("stage.hip", "flux.hpp", "xcd.hpp")

@@ -182,8 +182,9 @@ shk_status shk_rk3_step_adjoint(shk_grid* g, const void* U_n, const double* dt, 
  * pass: tape (device, double, caller-owned, 3 states = 3 * nbatch * 4 * ny *
  * nx entries) receives U^n, U1 and U2 (section 2 RK3 stages), each after the
  * immersed-boundary refill.  The automatic step is not fused into the stages
- * here (one extra reduction launch).  Same requirements as shk_rhs_adjoint;
- * SHK_EINVAL for a null U or tape. */
+ * here (one extra reduction launch).  A step of zero length (dt_in 0, or the
+ * end time already reached) leaves U and the tape untouched.  Same
+ * requirements as shk_rhs_adjoint; SHK_EINVAL for a null U or tape. */
 shk_status shk_rk3_step_record(shk_grid* g, void* U, const double* dt_in, double* dt_out, void* tape);
 
 /* Discrete adjoint of one recorded step (as shk_rk3_step_adjoint, with the

@@ -254,8 +254,7 @@ __device__ __forceinline__ void face_vjp(const double* q0, const double* q1, con
     double v[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) v[k] = q[c][k * st];
-    *Lp[c] = weno5(v[0], v[1], v[2], v[3], v[4], eps);
-    *Rp[c] = weno5(v[5], v[4], v[3], v[2], v[1], eps);
+    weno5_pair(v[0], v[1], v[2], v[3], v[4], v[5], eps, *Lp[c], *Rp[c]);
   }
   const bool fallback = !(L.r > 0.0) || !(L.p > 0.0) || !(R.r > 0.0) || !(R.p > 0.0);
   if (fallback) {
@@ -587,6 +586,7 @@ __global__ void __launch_bounds__(256) ibm_entries_rank_kernel(GhostTable gt, in
 // whole reverse pass (slots of ps, this launch's own last) are then added to
 // param_bar here instead of in a separate launch.
 constexpr int FILL_NT = 1024;
+constexpr int FILL_LDS_GHOSTS = 2048;  // image-point adjoints in LDS up to this many ghosts (64 KB)
 
 __device__ __forceinline__ double block_sum_fixed(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -598,6 +598,7 @@ __device__ __forceinline__ double block_sum_fixed(double v, double* red) {
   return s;
 }
 
+template <bool LDSW>
 __global__ void __launch_bounds__(FILL_NT) ibm_fill_adjoint_kernel(GridArgs a, GhostTable gt,
                                                                    const int* __restrict__ keys,
                                                                    const int* __restrict__ vals,
@@ -606,20 +607,37 @@ __global__ void __launch_bounds__(FILL_NT) ibm_fill_adjoint_kernel(GridArgs a, G
                                                                    double* __restrict__ gW, double* __restrict__ part,
                                                                    PartSlots ps, double* __restrict__ param_bar) {
   __shared__ double red[FILL_NT / 64];
+  extern __shared__ double gw_lds[];  // LDSW: the image-point adjoints stay in LDS
   const int b = blockIdx.x;
   const long long n = a.ncell;
   const double* __restrict__ Ub = Us + (long long)b * 4 * n;
   double* __restrict__ Xb = X + (long long)b * 4 * n;
-  double* __restrict__ gWb = gW + (long long)b * 4 * gt.n;
+  double* __restrict__ gWb = LDSW ? gw_lds : gW + (long long)b * 4 * gt.n;
   const double gm1 = a.gamma - 1.0;
   double gacc = 0.0;
+  // the recorded partials of the earlier launches of this reverse pass are
+  // summed by the last five waves first (they are idle in the two passes
+  // below unless the lists are long): wave 11 + q takes quantity q
+  const int qf = (int)(threadIdx.x >> 6) - (FILL_NT / 64 - 5), lanef = threadIdx.x & 63;
+  double sq = 0.0;
+  if (param_bar != nullptr && qf >= 0) {
+    for (int slot = 0; slot < ps.n; ++slot) {
+      const double* p = part - (ps.n - slot) * ps.stride;  // earlier slots precede this one
+      const int nb = ps.nblk[slot];
+      for (int k = lanef; k < nb; k += 64) sq += p[((long long)b * nb + k) * 5 + qf];
+    }
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+  }
   for (int k = threadIdx.x; k < gt.n; k += FILL_NT) {
     double Wi[4] = {0.0, 0.0, 0.0, 0.0};
+    // branch-free over the four corners (an unused one reads cell 0 with
+    // weight 0) so that all sixteen loads are in flight together
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const int sm = gt.src[4 * k + m];
-      if (sm < 0) continue;
-      const double wm = gt.w[4 * k + m];
+      const int s0 = gt.src[4 * k + m];
+      const bool use = s0 >= 0;
+      const int sm = use ? s0 : 0;
+      const double wm = use ? gt.w[4 * k + m] : 0.0;
       const double r = Ub[sm];
       const double u = Ub[n + sm] / r, v = Ub[2 * n + sm] / r;
       const double p = gm1 * (Ub[3 * n + sm] - 0.5 * r * (u * u + v * v));
@@ -661,8 +679,60 @@ __global__ void __launch_bounds__(FILL_NT) ibm_fill_adjoint_kernel(GridArgs a, G
     Xb[2 * n + gc] = 0.0;
     Xb[3 * n + gc] = 0.0;
   }
-  __syncthreads();  // gW complete (global memory, one workgroup)
-  for (int h = threadIdx.x; h < nsrc; h += FILL_NT) {
+  // the first source of every thread: everything that does not depend on gW
+  // is loaded before the barrier (X at a source is never written above:
+  // sources are fluid cells, ghosts are not)
+  const int h0 = threadIdx.x;
+  const bool has = h0 < nsrc;
+  int src0 = 0, i1_0 = 0, e0[4] = {-1, -1, -1, -1};
+  double w0[4] = {0.0, 0.0, 0.0, 0.0}, U0[4] = {1.0, 0.0, 0.0, 1.0}, X0[4] = {0.0, 0.0, 0.0, 0.0};
+  if (has) {
+    const int i0 = heads[h0];
+    i1_0 = heads[h0 + 1];
+    src0 = keys[i0];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) e0[t] = i0 + t < i1_0 ? vals[i0 + t] : -1;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) w0[t] = e0[t] >= 0 ? gt.w[e0[t]] : 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      U0[v] = Ub[v * n + src0];
+      X0[v] = Xb[v * n + src0];
+    }
+  }
+  __syncthreads();  // gW complete (LDS, or global memory of this workgroup)
+  if (has) {
+    const int i0 = heads[h0];
+    double Wsb[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (e0[t] < 0) continue;
+      const int k = e0[t] >> 2;
+      Wsb[0] += w0[t] * gWb[4 * k];
+      Wsb[1] += w0[t] * gWb[4 * k + 1];
+      Wsb[2] += w0[t] * gWb[4 * k + 2];
+      Wsb[3] += w0[t] * gWb[4 * k + 3];
+    }
+    for (int j = i0 + 4; j < i1_0; ++j) {
+      const int e = vals[j];
+      const int k = e >> 2;
+      const double wm = gt.w[e];
+      Wsb[0] += wm * gWb[4 * k];
+      Wsb[1] += wm * gWb[4 * k + 1];
+      Wsb[2] += wm * gWb[4 * k + 2];
+      Wsb[3] += wm * gWb[4 * k + 3];
+    }
+    const double r = U0[0];
+    const double u = U0[1] / r, v = U0[2] / r;
+    const double E = U0[3];
+    const double ke = 0.5 * (u * u + v * v);
+    Xb[src0] = X0[0] + (Wsb[0] - Wsb[1] * u / r - Wsb[2] * v / r + Wsb[3] * gm1 * ke);
+    Xb[n + src0] = X0[1] + (Wsb[1] / r - Wsb[3] * gm1 * u);
+    Xb[2 * n + src0] = X0[2] + (Wsb[2] / r - Wsb[3] * gm1 * v);
+    Xb[3 * n + src0] = X0[3] + Wsb[3] * gm1;
+    gacc += Wsb[3] * (E - r * ke);
+  }
+  for (int h = threadIdx.x + FILL_NT; h < nsrc; h += FILL_NT) {
     const int i0 = heads[h], i1 = heads[h + 1];
     const int src = keys[i0];
     double Wsb[4] = {0.0, 0.0, 0.0, 0.0};
@@ -697,20 +767,9 @@ __global__ void __launch_bounds__(FILL_NT) ibm_fill_adjoint_kernel(GridArgs a, G
     if (threadIdx.x < 5) part[(long long)b * 5 + threadIdx.x] = threadIdx.x == 0 ? g : 0.0;
     return;
   }
-  // finalize: wave q sums member b's recorded partials of quantity q (lane l
-  // takes the entries l, l + 64, ... of each slot in order, then a fixed
-  // butterfly), plus this launch's own gamma part
-  const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (q < 5) {
-    double sq = 0.0;
-    for (int slot = 0; slot < ps.n; ++slot) {
-      const double* p = part - (ps.n - slot) * ps.stride;  // earlier slots precede this one
-      const int nb = ps.nblk[slot];
-      for (int k = lane; k < nb; k += 64) sq += p[((long long)b * nb + k) * 5 + q];
-    }
-    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
-    if (lane == 0) param_bar[b * 5 + q] += sq + (q == 0 ? g : 0.0);
-  }
+  // finalize: the earlier launches' partials (lane sums in order, then a
+  // fixed butterfly) plus this launch's own gamma part
+  if (qf >= 0 && lanef == 0) param_bar[b * 5 + qf] += sq + (qf == 0 ? g : 0.0);
 }
 
 // param_bar[b][q] += the recorded partials of member b: one wave per q, lane
@@ -771,8 +830,14 @@ hipError_t launch_ibm_entries(const GhostTable& gt, int* keys, int* vals, int* n
 hipError_t launch_ibm_fill_adjoint(const GridArgs& a, const GhostTable& gt, const int* keys, const int* vals,
                                    const int* heads, int nsrc, const double* Us, double* X, double* gW, double* part,
                                    const PartSlots& prior, double* param_bar, hipStream_t st) {
-  hipLaunchKernelGGL(ibm_fill_adjoint_kernel, dim3(a.nbatch), dim3(FILL_NT), 0, st, a, gt, keys, vals, heads, nsrc,
-                     Us, X, gW, part, prior, param_bar);
+  if (gt.n <= FILL_LDS_GHOSTS) {
+    const size_t lds = sizeof(double) * 4 * size_t(gt.n > 0 ? gt.n : 1);
+    hipLaunchKernelGGL(ibm_fill_adjoint_kernel<true>, dim3(a.nbatch), dim3(FILL_NT), lds, st, a, gt, keys, vals, heads,
+                       nsrc, Us, X, gW, part, prior, param_bar);
+  } else {
+    hipLaunchKernelGGL(ibm_fill_adjoint_kernel<false>, dim3(a.nbatch), dim3(FILL_NT), 0, st, a, gt, keys, vals, heads,
+                       nsrc, Us, X, gW, part, prior, param_bar);
+  }
   return hipGetLastError();
 }
 

@@ -218,9 +218,9 @@ shk_status stage_seq(shk_grid* g, S* U, const double* dt_in, double* dt_out, S* 
     return timed(g, 4, [&]() { return launch_ibm_fill<S>(a, g->gt, X, g->st); });
   };
   if ((e = fill(U)) != hipSuccess) return hip_check(g, e, "ibm fill");
-  if (tape && (e = hipMemcpyAsync(tape, U, size_t(nst) * sizeof(S), hipMemcpyDeviceToDevice, g->st)) != hipSuccess)
-    return hip_check(g, e, "tape copy");
+  a.stage_in_copy = tape;  // stage 1 writes the refilled U^n to tape[0] as it reads it
   if ((e = stage(MODE_STAGE1, U, U, U1)) != hipSuccess) return hip_check(g, e, "stage 1");
+  a.stage_in_copy = nullptr;
   if ((e = fill(U1)) != hipSuccess) return hip_check(g, e, "ibm fill");
   if ((e = stage(MODE_STAGE2, U1, U, U2)) != hipSuccess) return hip_check(g, e, "stage 2");
   if ((e = fill(U2)) != hipSuccess) return hip_check(g, e, "ibm fill");

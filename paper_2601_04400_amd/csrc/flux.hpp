@@ -9,14 +9,14 @@
 
 namespace shk {
 
-// Quotient a / b without the IEEE division sequence.  double: hardware
-// reciprocal estimate, two Newton steps on it and one correction step on the
-// quotient (error within about one unit in the last place for normal
-// operands); float: hardware reciprocal times a (about one unit in the last
-// place).  Operands here are finite and b != 0.
+// Quotient a / b without the IEEE division sequence.  double: the hardware
+// reciprocal estimate (relative error below 2^-23) refined by one Newton
+// step (below 2^-46), then one correction step on the quotient, which leaves
+// an error of about one unit in the last place for normal operands; float:
+// hardware reciprocal times a (about one unit in the last place).  Operands
+// here are finite and b != 0.
 __device__ __forceinline__ double qdiv(double a, double b) {
   double r = __builtin_amdgcn_rcp(b);
-  r = fma(fma(-b, r, 1.0), r, r);
   r = fma(fma(-b, r, 1.0), r, r);
   double x = a * r;
   return fma(fma(-b, x, a), r, x);
@@ -50,30 +50,39 @@ __device__ __forceinline__ Prim<C> to_prim(C rho, C mn, C mt, C E, C gm1) {
   return w;
 }
 
-// WENO5-JS left-biased value at the face between c and d of the five cells
-// a b c d e (Jiang-Shu indicators, ideal weights 1/10, 6/10, 3/10, eps).
-// The nonlinear weights d_k/(eps+beta_k)^2 are normalised by multiplying
-// through with the product of the three squared denominators, which leaves
-// a single division per reconstruction.
+// Both WENO5-JS values at the face between c and d of the six cells
+// a b c d e f (Jiang-Shu indicators, ideal weights 1/10, 6/10, 3/10, eps):
+// the left-biased one from a..e and the right-biased one from the mirrored
+// stencil f..b.  The two share the curvature terms of the triples (b,c,d)
+// and (c,d,e) and two of the six candidate polynomials, which are formed
+// once.  The nonlinear weights d_k/(eps+beta_k)^2 are normalised by
+// multiplying through with the product of the three squared denominators,
+// which leaves a single division per value.
 template <class C>
-__device__ __forceinline__ C weno5(C a, C b, C c, C d, C e, C eps) {
+__device__ __forceinline__ void weno5_pair(C a, C b, C c, C d, C e, C f, C eps, C& left, C& right) {
   const C k13 = C(13) / C(12);
-  C s0 = a - C(2) * b + c, t0 = a - C(4) * b + C(3) * c;
-  C s1 = b - C(2) * c + d, t1 = b - d;
-  C s2 = c - C(2) * d + e, t2 = C(3) * c - C(4) * d + e;
-  C g0 = eps + (k13 * s0 * s0 + C(0.25) * t0 * t0);
-  C g1 = eps + (k13 * s1 * s1 + C(0.25) * t1 * t1);
-  C g2 = eps + (k13 * s2 * s2 + C(0.25) * t2 * t2);
-  g0 = g0 * g0;
-  g1 = g1 * g1;
-  g2 = g2 * g2;
-  C w0 = C(0.1) * (g1 * g2);
-  C w1 = C(0.6) * (g0 * g2);
-  C w2 = C(0.3) * (g0 * g1);
-  C q0 = C(2) * a - C(7) * b + C(11) * c;
-  C q1 = C(5) * c - b + C(2) * d;
-  C q2 = C(2) * c + C(5) * d - e;
-  return qdiv(w0 * q0 + w1 * q1 + w2 * q2, C(6) * (w0 + w1 + w2));
+  // curvature (second difference) of each triple, symmetric under mirroring
+  const C sA = a - C(2) * b + c, sB = b - C(2) * c + d, sC = c - C(2) * d + e, sD = d - C(2) * e + f;
+  const C kB = k13 * sB * sB, kC = k13 * sC * sC;
+  // left: triples A, B, C
+  C g0 = eps + (k13 * sA * sA + C(0.25) * (a - C(4) * b + C(3) * c) * (a - C(4) * b + C(3) * c));
+  C g1 = eps + (kB + C(0.25) * (b - d) * (b - d));
+  C g2 = eps + (kC + C(0.25) * (C(3) * c - C(4) * d + e) * (C(3) * c - C(4) * d + e));
+  // right (mirrored): triples D, C, B
+  C h0 = eps + (k13 * sD * sD + C(0.25) * (f - C(4) * e + C(3) * d) * (f - C(4) * e + C(3) * d));
+  C h1 = eps + (kC + C(0.25) * (e - c) * (e - c));
+  C h2 = eps + (kB + C(0.25) * (C(3) * d - C(4) * c + b) * (C(3) * d - C(4) * c + b));
+  // candidate polynomials (x6); the centred ones coincide across the pair
+  const C qm = C(5) * c - b + C(2) * d;  // left q1 = right q2
+  const C qp = C(2) * c + C(5) * d - e;  // left q2 = right q1
+  const C q0 = C(2) * a - C(7) * b + C(11) * c;
+  const C r0 = C(2) * f - C(7) * e + C(11) * d;
+  g0 = g0 * g0; g1 = g1 * g1; g2 = g2 * g2;
+  h0 = h0 * h0; h1 = h1 * h1; h2 = h2 * h2;
+  const C w0 = C(0.1) * (g1 * g2), w1 = C(0.6) * (g0 * g2), w2 = C(0.3) * (g0 * g1);
+  const C v0 = C(0.1) * (h1 * h2), v1 = C(0.6) * (h0 * h2), v2 = C(0.3) * (h0 * h1);
+  left = qdiv(w0 * q0 + w1 * qm + w2 * qp, C(6) * (w0 + w1 + w2));
+  right = qdiv(v0 * r0 + v1 * qp + v2 * qm, C(6) * (v0 + v1 + v2));
 }
 
 // HLLC flux (section 2) in the face-normal frame, components

@@ -44,6 +44,7 @@ struct GridArgs {
   StepScalars* sc;             // [nbatch]
   double* dtbuf;               // [nbatch] step of the automatic time stepping
   double* dt_out;              // optional caller copy of the step (per call)
+  void* stage_in_copy;         // MODE_STAGE1: optional copy of the stage input (storage type), or nullptr
   unsigned long long* xslots;  // [nbatch][2][XSLOTS] spread extrema of the fused step
   const float* dXnet;          // its stencil gradient per face [nbatch][nface][24] or nullptr
   long long nface;             // x-faces (nx+1)*ny then y-faces nx*(ny+1)

@@ -93,7 +93,7 @@ __device__ __forceinline__ void build_inputs(const GridArgs& a, const NetArgs& n
 // output is replaced by zero (the uncorrected flux) and flagged.
 __global__ void __launch_bounds__(256) net_forward_kernel(GridArgs a, NetArgs n, const double* __restrict__ U,
                                                           float* __restrict__ dF, long long nface) {
-  __shared__ unsigned short sw[NET_NW];
+  __shared__ __attribute__((aligned(16))) unsigned short sw[NET_NW];
   __shared__ float sb[NET_NB];
   load_net_lds(n, sw, sb);
   __syncthreads();
@@ -258,10 +258,10 @@ __global__ void __launch_bounds__(256) net_backward_kernel(GridArgs a, NetArgs n
                                                            const double* __restrict__ lam, double clam_f,
                                                            const double* __restrict__ dtp, float* __restrict__ dX,
                                                            float* __restrict__ part, long long nface) {
-  __shared__ unsigned short sw[NET_NW];
+  __shared__ __attribute__((aligned(16))) unsigned short sw[NET_NW];
   __shared__ float sb[NET_NB];
   __shared__ float gsum[NET_NP];
-  __shared__ unsigned short tr[4][2][16 * 16];  // per wave: dA tile, H tile, [row][face]
+  __shared__ __attribute__((aligned(16))) unsigned short tr[4][2][16 * 16];  // per wave: dA tile, H tile, [row][face]
   load_net_lds(n, sw, sb);
   for (int k = threadIdx.x; k < NET_NP; k += blockDim.x) gsum[k] = 0.f;
   __syncthreads();

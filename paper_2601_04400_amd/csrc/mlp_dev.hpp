@@ -12,22 +12,44 @@ namespace shk {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ unsigned short f2bf(float x) {
-  unsigned int u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
+// float -> bfloat16 bits, round to nearest even (the hardware conversion,
+// v_cvt_pk_bf16_f32 on gfx950).
+__device__ __forceinline__ unsigned short f2bf(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
 
 __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// K = 32 products (v_mfma_f32_16x16x32_bf16, twice the rate of the K = 16
+// form on gfx950).  The 32 k-slots of lane (q = lane >> 4) are ordered
+// 4q..4q+3, 16+4q..16+4q+3 within the block: the concatenation of two
+// K = 16 B tiles, i.e. of two D tiles of the layer below, so activations
+// still chain from layer to layer without leaving the registers; the A
+// operand reads the weight columns in the same order.
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ s16x8 cat8(bf16x4 lo, bf16x4 hi) { return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7); }
+
+__device__ __forceinline__ f32x4 mfma32(s16x8 a, s16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                 0, 0);
+}
+
+// A operand of K block kb: rows r0 + (lane & 15), columns 32 kb + 4q + 0..3
+// and 32 kb + 16 + 4q + 0..3 of a row-major bf16 matrix (ld multiple of 4,
+// 8-byte aligned).
+__device__ __forceinline__ s16x8 ldA32(const unsigned short* m, int ld, int r0, int kb, int lane) {
+  const unsigned short* p = m + (r0 + (lane & 15)) * ld + 32 * kb + 4 * (lane >> 4);
+  return cat8(*reinterpret_cast<const bf16x4*>(p), *reinterpret_cast<const bf16x4*>(p + 16));
+}
+
 // A operand: rows r0..r0+15 (lane & 15), columns k0 + 4 (lane >> 4) + 0..3 of a
 // row-major bf16 matrix with leading dimension ld.
+// (ld and k0 are multiples of 4 and m is 8-byte aligned: one 64-bit load.)
 __device__ __forceinline__ bf16x4 ldA(const unsigned short* m, int ld, int r0, int k0, int lane) {
   const unsigned short* p = m + (r0 + (lane & 15)) * ld + k0 + 4 * (lane >> 4);
-  return bf16x4{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
+  return *reinterpret_cast<const bf16x4*>(p);
 }
 
 // A operand of the transpose: (M^T)[r][k] = M[k][r].
@@ -89,13 +111,14 @@ __device__ __forceinline__ void net_forward_batch(const unsigned short* sw, cons
   for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
     for (int ft = 0; ft < 4; ++ft) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      acc = mfma(ldA(sw + NET_OFF_W0, 32, nt * 16, 0, lane), A.x[0][ft], acc);
-      acc = mfma(ldA(sw + NET_OFF_W0, 32, nt * 16, 16, lane), A.x[1][ft], acc);
+      // the accumulator starts at the bias of its four rows
+      const float* b0 = sb + NET_OFF_B0 + nt * 16 + 4 * q;
+      f32x4 acc = {b0[0], b0[1], b0[2], b0[3]};
+      acc = mfma32(ldA32(sw + NET_OFF_W0, 32, nt * 16, 0, lane), cat8(A.x[0][ft], A.x[1][ft]), acc);
       float hv[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float pre = acc[i] + sb[NET_OFF_B0 + nt * 16 + 4 * q + i];
+        const float pre = acc[i];
         hv[i] = pre > 0.f ? pre : 0.f;
         if (pre > 0.f) A.mask[0][ft] |= 1u << (nt * 4 + i);
       }
@@ -112,13 +135,15 @@ __device__ __forceinline__ void net_forward_batch(const unsigned short* sw, cons
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
       for (int ft = 0; ft < 4; ++ft) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const float* bl = B + nt * 16 + 4 * q;
+        f32x4 acc = {bl[0], bl[1], bl[2], bl[3]};
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt) acc = mfma(ldA(W, 64, nt * 16, kt * 16, lane), A.h[l - 1][kt][ft], acc);
+        for (int kb = 0; kb < 2; ++kb)
+          acc = mfma32(ldA32(W, 64, nt * 16, kb, lane), cat8(A.h[l - 1][2 * kb][ft], A.h[l - 1][2 * kb + 1][ft]), acc);
         float hv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const float pre = acc[i] + B[nt * 16 + 4 * q + i];
+          const float pre = acc[i];
           hv[i] = pre > 0.f ? pre : 0.f;
           if (pre > 0.f) A.mask[l][ft] |= 1u << (nt * 4 + i);
         }
@@ -128,11 +153,11 @@ __device__ __forceinline__ void net_forward_batch(const unsigned short* sw, cons
   // output layer: 16 (4 used) x 64
 #pragma unroll
   for (int ft = 0; ft < 4; ++ft) {
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const float* b3 = sb + NET_OFF_B3 + 4 * q;
+    f32x4 acc = {b3[0], b3[1], b3[2], b3[3]};
 #pragma unroll
-    for (int kt = 0; kt < 4; ++kt) acc = mfma(ldA(sw + NET_OFF_W3, 64, 0, kt * 16, lane), A.h[2][kt][ft], acc);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i] = acc[i] + sb[NET_OFF_B3 + 4 * q + i];
+    for (int kb = 0; kb < 2; ++kb)
+      acc = mfma32(ldA32(sw + NET_OFF_W3, 64, 0, kb, lane), cat8(A.h[2][2 * kb][ft], A.h[2][2 * kb + 1][ft]), acc);
     z[ft] = acc;
   }
 }

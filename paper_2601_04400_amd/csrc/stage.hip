@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
   __shared__ C fys[4][FYR * TX];
   __shared__ unsigned int blk_fallback, blk_fault;
   static_assert(!NET || (NDIM == 2 && !VISC), "learned correction: 2D inviscid tiles");
-  __shared__ unsigned short net_w[NET ? NET_NW : 1];
+  __shared__ __attribute__((aligned(16))) unsigned short net_w[NET ? NET_NW : 1];
   __shared__ float net_b[NET ? NET_NB : 1];
   __shared__ double red_s[NT / 64], red_r[NT / 64];
 
@@ -280,11 +280,11 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
 
   if (NET) {
     // 1b. learned correction of every face of the tile, 64 faces per wave
-    // and batch; the face-frame result is parked in the flux arrays, which
-    // the face pass reads back and adds to
+    // and batch on the matrix cores; the network output before its tanh is
+    // parked in the flux arrays (face frame), and the face pass, one face per
+    // thread, finishes it and adds it to the flux
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     constexpr int NF = NFX + NFY;
-    bool net_bad = false;
     for (int bb = wv; bb * 64 < NF; bb += NT / 64) {
       Acts A;
 #pragma unroll
@@ -310,32 +310,16 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
           if (k >= NF) continue;
           int s0, st, cn, ct, oidx;
           face_of(k, s0, st, cn, ct, oidx);
-          float o[4];
-          bool ok = true;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            o[i] = net.out_scale * tanhf(z[ft][i]);
-            ok = ok && isfinite(o[i]);
-          }
-          if (!ok) {
-            // the uncorrected flux; flagged when the face is a real one
-            o[0] = o[1] = o[2] = o[3] = 0.f;
-            bool real;
-            if (k < NFX) real = i0 + k % (TX + 1) <= a.nx && j0 + k / (TX + 1) < a.ny;
-            else real = i0 + (k - NFX) % TX < a.nx && j0 + (k - NFX) / TX <= a.ny;
-            net_bad = net_bad || real;
-          }
           if (k < NFX) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) fxs[i][oidx] = C(o[i]);
+            for (int i = 0; i < 4; ++i) fxs[i][oidx] = C(z[ft][i]);
           } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) fys[i][oidx] = C(o[i]);
+            for (int i = 0; i < 4; ++i) fys[i][oidx] = C(z[ft][i]);
           }
         }
       }
     }
-    if (net_bad) atomicOr(&blk_fault, 8u);
     __syncthreads();
   }
 
@@ -344,6 +328,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
   const C gam = C(a.gamma);
   const C igm1 = C(1.0 / (a.gamma - 1.0));
   unsigned int my_fallback = 0;
+  bool net_bad = false;
   for (int k = threadIdx.x; k < NFX + NFY; k += NT) {
     const bool isx = k < NFX;
     int s0, st, cn, ct, oidx;
@@ -367,27 +352,19 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     Prim<C> L, R;
     {
       const C* f = w[0] + s0;
-      C v0 = f[0], v1 = f[st], v2 = f[2 * st], v3 = f[3 * st], v4 = f[4 * st], v5 = f[5 * st];
-      L.r = weno5(v0, v1, v2, v3, v4, eps);
-      R.r = weno5(v5, v4, v3, v2, v1, eps);
+      weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.r, R.r);
     }
     {
       const C* f = w[cn] + s0;
-      C v0 = f[0], v1 = f[st], v2 = f[2 * st], v3 = f[3 * st], v4 = f[4 * st], v5 = f[5 * st];
-      L.un = weno5(v0, v1, v2, v3, v4, eps);
-      R.un = weno5(v5, v4, v3, v2, v1, eps);
+      weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.un, R.un);
     }
     {
       const C* f = w[ct] + s0;
-      C v0 = f[0], v1 = f[st], v2 = f[2 * st], v3 = f[3 * st], v4 = f[4 * st], v5 = f[5 * st];
-      L.ut = weno5(v0, v1, v2, v3, v4, eps);
-      R.ut = weno5(v5, v4, v3, v2, v1, eps);
+      weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.ut, R.ut);
     }
     {
       const C* f = w[3] + s0;
-      C v0 = f[0], v1 = f[st], v2 = f[2 * st], v3 = f[3 * st], v4 = f[4 * st], v5 = f[5 * st];
-      L.p = weno5(v0, v1, v2, v3, v4, eps);
-      R.p = weno5(v5, v4, v3, v2, v1, eps);
+      weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.p, R.p);
     }
     if (!(L.r > C(0)) || !(L.p > C(0)) || !(R.r > C(0)) || !(R.p > C(0))) {
       // positivity fallback: first-order states from the two adjacent cells
@@ -417,14 +394,25 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
       F.f3 = F.f3 - (ubn * tnn + ubt * tnt - qn);
     }
     if (NET) {
-      // learned correction of this face (face frame), parked by pass 1b
-      if (isx) {
-        F.f0 = F.f0 + fxs[0][oidx]; F.f1 = F.f1 + fxs[1][oidx];
-        F.f2 = F.f2 + fxs[2][oidx]; F.f3 = F.f3 + fxs[3][oidx];
-      } else {
-        F.f0 = F.f0 + fys[0][oidx]; F.f1 = F.f1 + fys[1][oidx];
-        F.f2 = F.f2 + fys[2][oidx]; F.f3 = F.f3 + fys[3][oidx];
+      // learned correction of this face (face frame): out_scale tanh of the
+      // network output parked by pass 1b; a non-finite value leaves the
+      // uncorrected flux and is flagged
+      float o[4];
+      bool ok = true;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float z = float(isx ? fxs[i][oidx] : fys[i][oidx]);
+        o[i] = net.out_scale * tanhf(z);
+        ok = ok && isfinite(o[i]);
       }
+      if (!ok) {
+        o[0] = o[1] = o[2] = o[3] = 0.f;
+        if (owned) net_bad = true;
+      }
+      F.f0 = F.f0 + C(o[0]);
+      F.f1 = F.f1 + C(o[1]);
+      F.f2 = F.f2 + C(o[2]);
+      F.f3 = F.f3 + C(o[3]);
     }
     if (isx) {
       fxs[0][oidx] = F.f0; fxs[1][oidx] = F.f1; fxs[2][oidx] = F.f2; fxs[3][oidx] = F.f3;
@@ -433,6 +421,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     }
   }
   if (my_fallback) atomicAdd(&blk_fallback, my_fallback);
+  if (NET && net_bad) atomicOr(&blk_fault, 8u);
   __syncthreads();
 
   // 3. flux difference and Runge-Kutta combination
@@ -499,7 +488,11 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
       if (MODE == MODE_RHS || MODE == MODE_S1L) {
         out = Lv[v];
       } else if (MODE == MODE_STAGE1) {
-        out = C(Ub[o]) + cdt * Lv[v];
+        const S u0 = Ub[o];
+        // the reverse pass keeps the (refilled) stage input: copied here
+        // from the value this thread reads anyway
+        if (a.stage_in_copy != nullptr) static_cast<S*>(a.stage_in_copy)[boff + o] = u0;
+        out = C(u0) + cdt * Lv[v];
       } else if (MODE == MODE_STAGE2) {
         out = C(0.75) * C(Unb[o]) + C(0.25) * C(Ub[o]) + C(0.25 * dt) * Lv[v];
       } else if (MODE == MODE_S2F) {

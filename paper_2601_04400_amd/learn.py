@@ -244,7 +244,7 @@ def main():
     ap.add_argument("--nc", type=int, default=128)
     ap.add_argument("--factor", type=int, default=4)
     ap.add_argument("--nsnap", type=int, default=24)
-    ap.add_argument("--m", type=int, default=8)
+    ap.add_argument("--m", type=int, default=16)
     ap.add_argument("--iters", type=int, default=400)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--lr-late", type=float, default=1e-4)

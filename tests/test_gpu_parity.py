@@ -221,3 +221,42 @@ def test_fused_automatic_step_equals_three_stage_path():
     np.testing.assert_array_equal(to_np(Ua), to_np(Ub))
     t, done, steps = g.get_time()
     assert steps == 6 and t == pytest.approx(float(sum(x.item() for x in dts)), rel=1e-14)
+
+
+def test_graph_replays_equal_eager_steps():
+    """Automatic-step RK3 steps captured in a HIP graph: every replay (with
+    eager work and synchronisations between replays) gives the eager steps'
+    state bit for bit, including the device time and step counter."""
+    from paper_2601_04400_amd import Grid
+    n, k = 72, 5
+    W = inputs.riemann2d_prim(n, n)
+    g = Grid(n, n)
+    U0 = g.prim_to_cons(torch.from_numpy(W))
+    Ue = U0.clone()
+    g.set_time(0.0, 1e30)
+    for _ in range(k):
+        g.step(Ue)
+    want = to_np(Ue)
+    t_want, _, s_want = g.get_time()
+    U = U0.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        g.set_time(0.0, 1e30)
+        g.step(U)  # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(k):
+            g.step(U)
+    for rep in range(3):
+        U.copy_(U0)
+        g.set_time(0.0, 1e30)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(to_np(U), want, err_msg=f"replay {rep}")
+        t, _, steps = g.get_time()
+        assert steps == s_want and t == t_want
+        Ue.mul_(1.0)  # eager work between replays
