@@ -130,6 +130,14 @@ shk_status shk_prim_to_cons(shk_grid* g, const void* W, void* U);
  * phi = NULL removes the immersed boundary. */
 shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall);
 
+/* Change the ratio of specific heats gamma and, unless inflow_prim is NULL,
+ * the inflow state (host, 4 doubles (rho, u, v, p)) of an existing grid, as
+ * a parameter fit does between its iterations (section 3, reverse learning
+ * of gamma).  Affects the calls enqueued after it; the level set, the
+ * workspace and the network are kept.  SHK_EINVAL for gamma <= 1 or a
+ * non-positive inflow density or pressure. */
+shk_status shk_set_params(shk_grid* g, double gamma, const double* inflow_prim);
+
 /* Number of ghost cells of the current immersed boundary (host output). */
 shk_status shk_ib_ghost_count(const shk_grid* g, int* n_host);
 
@@ -194,6 +202,22 @@ shk_status shk_rk3_step_record(shk_grid* g, void* U, const double* dt_in, double
  * shk_rhs_adjoint; SHK_EINVAL for a null tape, dt or U_bar. */
 shk_status shk_rk3_step_adjoint_tape(shk_grid* g, const void* tape, const double* dt, void* U_bar,
                                      double* param_bar);
+
+/* nsteps fixed-dt SSP-RK3 steps, each as shk_rk3_step_record: U advances in
+ * place and tapes (device, double, caller-owned, nsteps * 3 states) receive
+ * the stage-start states of step k at tapes + 3 k (one state = nbatch * 4 *
+ * ny * nx entries).  dt: device array of nbatch steps used by every step.
+ * The loop runs in the library (no per-step call overhead).  Same
+ * requirements as shk_rhs_adjoint; SHK_EINVAL for null arrays or
+ * nsteps < 0. */
+shk_status shk_rk3_steps_record(shk_grid* g, void* U, int nsteps, const double* dt, void* tapes);
+
+/* Reverse of nsteps recorded steps, last first: U_bar enters as the adjoint of
+ * the state after the last step and leaves as the adjoint of the state before
+ * the first; param_bar += the parameter derivatives of every step.  As
+ * nsteps calls of shk_rk3_step_adjoint_tape on tapes + 3 k, k = nsteps-1..0. */
+shk_status shk_rk3_steps_adjoint_tape(shk_grid* g, const void* tapes, int nsteps, const double* dt, void* U_bar,
+                                      double* param_bar);
 
 /* ---- Learned flux correction (section 2 neural flux, per-face MLP form) ----
  * F = F_HLLC + dF with dF = s_out tanh(MLP(x)), x = the 6-cell stencil of

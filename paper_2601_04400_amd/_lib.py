@@ -39,6 +39,9 @@ _SIGS = {
     "shk_rk3_step_adjoint": (_i, [_p, _p, _p, _p, _p]),
     "shk_rk3_step_record": (_i, [_p, _p, _p, _p, _p]),
     "shk_rk3_step_adjoint_tape": (_i, [_p, _p, _p, _p, _p]),
+    "shk_rk3_steps_record": (_i, [_p, _p, _i, _p, _p]),
+    "shk_set_params": (_i, [_p, _d, _p]),
+    "shk_rk3_steps_adjoint_tape": (_i, [_p, _p, _i, _p, _p, _p]),
     "shk_set_flux_net": (_i, [_p, _p, _p, _p, ctypes.c_float, _i]),
     "shk_set_flux_net_grad": (_i, [_p, _p]),
     "shk_flux_net_eval": (_i, [_p, _p, _p]),

@@ -33,14 +33,14 @@ class _Rollout(torch.autograd.Function):
         Ub = U_bar.detach().to(dtype=torch.float64).contiguous().clone()
         pb = g.param_bar()
         tapes = torch.empty((min(every, nsteps), 3) + tuple(g.shape), dtype=torch.float64, device=Ub.device)
+        if not torch.is_tensor(dt):
+            dt = g._dt_tensor(dt)
         for c in range(len(ctx.ckpts) - 1, -1, -1):
             first = c * every
             count = min(every, nsteps - first)
             U = ctx.ckpts[c].clone()
-            for k in range(count):
-                g.step_record(U, tapes[k], dt)
-            for k in range(count - 1, -1, -1):
-                g.step_adjoint_tape(tapes[k], dt, Ub, pb)
+            g.steps_record(U, tapes, count, dt)
+            g.steps_adjoint_tape(tapes, count, dt, Ub, pb)
         return Ub, pb, None, None, None, None
 
 

@@ -306,6 +306,59 @@ __device__ __forceinline__ double lam_at(const GridArgs& a, const double* __rest
   return lam[v * a.ncell + c];
 }
 
+// First half of the refill transpose for ghost k of one batch member: with
+// X the adjoint of the ghost's refilled conservative state, recompute the
+// image-point primitives and the wall rule from the sources in Ub and
+// return the adjoint of the image-point primitives, gW = (rho, u, v, p)_bar;
+// *gpart receives the gamma part of the ghost energy's reverse.
+__device__ __forceinline__ void ghost_reverse(const GridArgs& a, const GhostTable& gt, const double* __restrict__ Ub,
+                                              int k, const double X[4], double gWk[4], double* gpart) {
+  const long long n = a.ncell;
+  const double gm1 = a.gamma - 1.0;
+  double Wi[4] = {0.0, 0.0, 0.0, 0.0};
+  // branch-free over the four corners (an unused one reads cell 0 with
+  // weight 0) so that all sixteen loads are in flight together
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int s0 = gt.src[4 * k + m];
+    const bool use = s0 >= 0;
+    const int sm = use ? s0 : 0;
+    const double wm = use ? gt.w[4 * k + m] : 0.0;
+    const double r = Ub[sm];
+    const double u = Ub[n + sm] / r, v = Ub[2 * n + sm] / r;
+    const double p = gm1 * (Ub[3 * n + sm] - 0.5 * r * (u * u + v * v));
+    Wi[0] += wm * r; Wi[1] += wm * u; Wi[2] += wm * v; Wi[3] += wm * p;
+  }
+  const double nxv = gt.nrm[2 * k], nyv = gt.nrm[2 * k + 1];
+  double ug, vg;
+  if (gt.wall == 0) {
+    const double un = Wi[1] * nxv + Wi[2] * nyv;
+    ug = Wi[1] - 2.0 * un * nxv;
+    vg = Wi[2] - 2.0 * un * nyv;
+  } else {
+    ug = -Wi[1];
+    vg = -Wi[2];
+  }
+  // reverse of U_g = (rho, rho ug, rho vg, p/(gamma-1) + rho (ug^2+vg^2)/2)
+  const double rb = X[0] + X[1] * ug + X[2] * vg + X[3] * 0.5 * (ug * ug + vg * vg);
+  const double ugb = X[1] * Wi[0] + X[3] * Wi[0] * ug;
+  const double vgb = X[2] * Wi[0] + X[3] * Wi[0] * vg;
+  *gpart = -X[3] * Wi[3] / (gm1 * gm1);
+  double Wub, Wvb;
+  if (gt.wall == 0) {
+    const double unb = -2.0 * (ugb * nxv + vgb * nyv);
+    Wub = ugb + unb * nxv;
+    Wvb = vgb + unb * nyv;
+  } else {
+    Wub = -ugb;
+    Wvb = -vgb;
+  }
+  gWk[0] = rb;
+  gWk[1] = Wub;
+  gWk[2] = Wvb;
+  gWk[3] = X[3] / gm1;
+}
+
 }  // namespace
 
 // out = J^T (clam_f dt lam) + c1 X1 + c2 X2 + c3 X3 for every cell of the
@@ -318,11 +371,13 @@ __global__ void __launch_bounds__(NT) rhs_adjoint_kernel(GridArgs a, const doubl
                                                           const double* __restrict__ lam, double clam_f,
                                                           const double* __restrict__ dtp, const double* X1,
                                                           double c1, const double* X2, double c2, const double* X3,
-                                                          double c3, double* out, double* __restrict__ part) {
+                                                          double c3, double* out, double* __restrict__ part,
+                                                          GhostTable gt, double* __restrict__ gW) {
   constexpr int M = 5;
   constexpr int PX = TX + 2 * M, PY = TY + 2 * M;
   constexpr int NFX = (TX + 5) * TY, NFY = TX * (TY + 5);
   __shared__ double w[4][PY * PX];
+  __shared__ double lw[4][PY * PX];  // right-hand-side adjoint on the same cross-shaped tile
   __shared__ double ax[4][TY * PX];
   __shared__ double ay[4][PY * TX];
   __shared__ double red[5][NT / 64];
@@ -344,11 +399,16 @@ __global__ void __launch_bounds__(NT) rhs_adjoint_kernel(GridArgs a, const doubl
     if (!inx && !iny) continue;
     double q[4];
     adj_load_cons(a, Ub, i0 - M + lx, j0 - M + ly, q);
+    double lv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lv[c] = lam_at(a, Lb, c, i0 - M + lx, j0 - M + ly);
     const Prim<double> p = to_prim(q[0], q[1], q[2], q[3], gm1);
     w[0][k] = p.r;
     w[1][k] = p.un;
     w[2][k] = p.ut;
     w[3][k] = p.p;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lw[c][k] = lv[c];
   }
   for (int k = threadIdx.x; k < TY * PX; k += NT)
     for (int c = 0; c < 4; ++c) ax[c][k] = 0.0;
@@ -381,10 +441,11 @@ __global__ void __launch_bounds__(NT) rhs_adjoint_kernel(GridArgs a, const doubl
         row = y; pos0 = fl - 3;
         if (valid) {
           const double sc = clam * a.inv_dx;
-          Fb[0] = sc * (lam_at(a, Lb, 0, gf, gj) - lam_at(a, Lb, 0, gf - 1, gj));
-          Fb[1] = sc * (lam_at(a, Lb, 1, gf, gj) - lam_at(a, Lb, 1, gf - 1, gj));
-          Fb[2] = sc * (lam_at(a, Lb, 2, gf, gj) - lam_at(a, Lb, 2, gf - 1, gj));
-          Fb[3] = sc * (lam_at(a, Lb, 3, gf, gj) - lam_at(a, Lb, 3, gf - 1, gj));
+          const int pr = (y + M) * PX + fl;  // cell gf; gf - 1 is pr - 1
+          Fb[0] = sc * (lw[0][pr] - lw[0][pr - 1]);
+          Fb[1] = sc * (lw[1][pr] - lw[1][pr - 1]);
+          Fb[2] = sc * (lw[2][pr] - lw[2][pr - 1]);
+          Fb[3] = sc * (lw[3][pr] - lw[3][pr - 1]);
         }
       } else {
         const int kk = k - NFX;
@@ -398,10 +459,11 @@ __global__ void __launch_bounds__(NT) rhs_adjoint_kernel(GridArgs a, const doubl
         row = x; pos0 = gl - 3;
         if (valid) {
           const double sc = clam * a.inv_dy;
-          Fb[0] = sc * (lam_at(a, Lb, 0, gi, gf) - lam_at(a, Lb, 0, gi, gf - 1));
-          Fb[1] = sc * (lam_at(a, Lb, 2, gi, gf) - lam_at(a, Lb, 2, gi, gf - 1));
-          Fb[2] = sc * (lam_at(a, Lb, 1, gi, gf) - lam_at(a, Lb, 1, gi, gf - 1));
-          Fb[3] = sc * (lam_at(a, Lb, 3, gi, gf) - lam_at(a, Lb, 3, gi, gf - 1));
+          const int pt = gl * PX + x + M, pb = pt - PX;  // cells gf and gf - 1
+          Fb[0] = sc * (lw[0][pt] - lw[0][pb]);
+          Fb[1] = sc * (lw[2][pt] - lw[2][pb]);
+          Fb[2] = sc * (lw[1][pt] - lw[1][pb]);
+          Fb[3] = sc * (lw[3][pt] - lw[3][pb]);
         }
       }
       if (valid && (Fb[0] != 0.0 || Fb[1] != 0.0 || Fb[2] != 0.0 || Fb[3] != 0.0)) {
@@ -510,26 +572,39 @@ __global__ void __launch_bounds__(NT) rhs_adjoint_kernel(GridArgs a, const doubl
         }
       }
     }
-    // W = (rho, m_x/rho, m_y/rho, (gamma-1)(E - (m_x^2 + m_y^2)/(2 rho)))
+    // W = (rho, m_x/rho, m_y/rho, (gamma-1)(E - (m_x^2 + m_y^2)/(2 rho))),
+    // with the cell's primitives from the tile (E - rho |u|^2/2 = p/(gamma-1))
     const long long cell = (long long)gj * a.nx + gi;
-    const double r = Ub[cell];
-    const double u = Ub[a.ncell + cell] / r, vv = Ub[2 * a.ncell + cell] / r;
-    const double E = Ub[3 * a.ncell + cell];
+    const int lc = (y + M) * PX + x + M;
+    const double r = w[0][lc], u = w[1][lc], vv = w[2][lc], pc = w[3][lc];
+    const double ir = qrcp(r);
     const double ke = 0.5 * (u * u + vv * vv);
     double Uo[4];
-    Uo[0] = Wb[0] - Wb[1] * u / r - Wb[2] * vv / r + Wb[3] * gm1 * ke;
-    Uo[1] = Wb[1] / r - Wb[3] * gm1 * u;
-    Uo[2] = Wb[2] / r - Wb[3] * gm1 * vv;
+    Uo[0] = Wb[0] - Wb[1] * u * ir - Wb[2] * vv * ir + Wb[3] * gm1 * ke;
+    Uo[1] = Wb[1] * ir - Wb[3] * gm1 * u;
+    Uo[2] = Wb[2] * ir - Wb[3] * gm1 * vv;
     Uo[3] = Wb[3] * gm1;
-    gacc += Wb[3] * (E - r * ke);
+    gacc += Wb[3] * qdiv(pc, gm1);
+    double val[4];
     for (int c = 0; c < 4; ++c) {
       const long long o = boff + c * a.ncell + cell;
-      double val = Uo[c];
-      if (X1) val += c1 * X1[o];
-      if (X2) val += c2 * X2[o];
-      if (X3) val += c3 * X3[o];
-      out[o] = val;
+      val[c] = Uo[c];
+      if (X1) val[c] += c1 * X1[o];
+      if (X2) val[c] += c2 * X2[o];
+      if (X3) val[c] += c3 * X3[o];
     }
+    const int gk = gW != nullptr ? a.ghost_of[cell] : -1;
+    if (gk >= 0) {
+      // a ghost: its refilled value is overwritten by the refill, so its
+      // adjoint passes to the image point (gW) and its own entry is zero
+      double gWk[4], gp;
+      ghost_reverse(a, gt, Ub, gk, val, gWk, &gp);
+      double* g4 = gW + ((long long)b * gt.n + gk) * 4;
+      g4[0] = gWk[0]; g4[1] = gWk[1]; g4[2] = gWk[2]; g4[3] = gWk[3];
+      gacc += gp;
+      val[0] = val[1] = val[2] = val[3] = 0.0;
+    }
+    for (int c = 0; c < 4; ++c) out[boff + c * a.ncell + cell] = val[c];
   }
 
   // block partial derivatives, reduced in a fixed order
@@ -570,23 +645,18 @@ __global__ void __launch_bounds__(256) ibm_entries_rank_kernel(GhostTable gt, in
   atomicAdd(nvalid, 1);
 }
 
-// X (adjoint w.r.t. the filled state) -> adjoint w.r.t. the state before the
-// refill.  One workgroup per batch member (the ghost list is short: about a
-// thousand entries at 1024 x 512), in two passes separated by a barrier:
-// 1. per ghost: recompute the image-point primitives and the wall rule,
-//    reverse the ghost's conservative state into the adjoint of the image-
-//    point primitives gW[k] = (rho, u, v, p)_bar, and clear X at the ghost
-//    (the refill overwrites it, so its pre-refill adjoint is zero);
-// 2. per source cell (run heads[h] .. heads[h+1] of equal keys in the sorted
-//    (source, entry) list): the source gathers w_m gW[k] over the ghosts k
-//    that read it, in entry order, then the primitive -> conservative
-//    transpose at the source.
-// The gamma parts of both passes are summed in a fixed order into the
-// member's partial; with fin set, the member's recorded partials of the
-// whole reverse pass (slots of ps, this launch's own last) are then added to
-// param_bar here instead of in a separate launch.
+// Second half of the refill transpose, one workgroup per batch member: the
+// adjoint kernel has already turned the adjoint of every ghost's refilled
+// state into the adjoint gW[k] = (rho, u, v, p)_bar of its image-point
+// primitives (and cleared the ghost's own entry).  Here each source cell
+// (run heads[h] .. heads[h+1] of equal keys in the sorted (source, entry)
+// list) gathers w_m gW[k] over the ghosts k that read it, in entry order,
+// followed by the primitive -> conservative transpose at the source.  The
+// gamma parts are summed in a fixed order into the member's partial; with
+// param_bar set, the member's recorded partials of the whole reverse pass
+// (slots of ps, this launch's own last) are then added to param_bar here
+// instead of in a separate launch.
 constexpr int FILL_NT = 1024;
-constexpr int FILL_LDS_GHOSTS = 2048;  // image-point adjoints in LDS up to this many ghosts (64 KB)
 
 __device__ __forceinline__ double block_sum_fixed(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -598,26 +668,25 @@ __device__ __forceinline__ double block_sum_fixed(double v, double* red) {
   return s;
 }
 
-template <bool LDSW>
 __global__ void __launch_bounds__(FILL_NT) ibm_fill_adjoint_kernel(GridArgs a, GhostTable gt,
                                                                    const int* __restrict__ keys,
                                                                    const int* __restrict__ vals,
                                                                    const int* __restrict__ heads, int nsrc,
                                                                    const double* __restrict__ Us, double* __restrict__ X,
-                                                                   double* __restrict__ gW, double* __restrict__ part,
-                                                                   PartSlots ps, double* __restrict__ param_bar) {
+                                                                   const double* __restrict__ gW,
+                                                                   double* __restrict__ part, PartSlots ps,
+                                                                   double* __restrict__ param_bar) {
   __shared__ double red[FILL_NT / 64];
-  extern __shared__ double gw_lds[];  // LDSW: the image-point adjoints stay in LDS
   const int b = blockIdx.x;
   const long long n = a.ncell;
   const double* __restrict__ Ub = Us + (long long)b * 4 * n;
   double* __restrict__ Xb = X + (long long)b * 4 * n;
-  double* __restrict__ gWb = LDSW ? gw_lds : gW + (long long)b * 4 * gt.n;
+  const double* __restrict__ gWb = gW + (long long)b * 4 * gt.n;
   const double gm1 = a.gamma - 1.0;
   double gacc = 0.0;
   // the recorded partials of the earlier launches of this reverse pass are
-  // summed by the last five waves first (they are idle in the two passes
-  // below unless the lists are long): wave 11 + q takes quantity q
+  // summed by the last five waves (idle below unless the source list is
+  // long): wave 11 + q takes quantity q
   const int qf = (int)(threadIdx.x >> 6) - (FILL_NT / 64 - 5), lanef = threadIdx.x & 63;
   double sq = 0.0;
   if (param_bar != nullptr && qf >= 0) {
@@ -628,111 +697,7 @@ __global__ void __launch_bounds__(FILL_NT) ibm_fill_adjoint_kernel(GridArgs a, G
     }
     for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
   }
-  for (int k = threadIdx.x; k < gt.n; k += FILL_NT) {
-    double Wi[4] = {0.0, 0.0, 0.0, 0.0};
-    // branch-free over the four corners (an unused one reads cell 0 with
-    // weight 0) so that all sixteen loads are in flight together
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int s0 = gt.src[4 * k + m];
-      const bool use = s0 >= 0;
-      const int sm = use ? s0 : 0;
-      const double wm = use ? gt.w[4 * k + m] : 0.0;
-      const double r = Ub[sm];
-      const double u = Ub[n + sm] / r, v = Ub[2 * n + sm] / r;
-      const double p = gm1 * (Ub[3 * n + sm] - 0.5 * r * (u * u + v * v));
-      Wi[0] += wm * r; Wi[1] += wm * u; Wi[2] += wm * v; Wi[3] += wm * p;
-    }
-    const double nxv = gt.nrm[2 * k], nyv = gt.nrm[2 * k + 1];
-    double ug, vg;
-    if (gt.wall == 0) {
-      const double un = Wi[1] * nxv + Wi[2] * nyv;
-      ug = Wi[1] - 2.0 * un * nxv;
-      vg = Wi[2] - 2.0 * un * nyv;
-    } else {
-      ug = -Wi[1];
-      vg = -Wi[2];
-    }
-    // reverse of U_g = (rho, rho ug, rho vg, p/(gamma-1) + rho (ug^2+vg^2)/2)
-    const int gc = gt.cell[k];
-    const double X0 = Xb[gc], X1 = Xb[n + gc], X2 = Xb[2 * n + gc], X3 = Xb[3 * n + gc];
-    const double rb = X0 + X1 * ug + X2 * vg + X3 * 0.5 * (ug * ug + vg * vg);
-    const double ugb = X1 * Wi[0] + X3 * Wi[0] * ug;
-    const double vgb = X2 * Wi[0] + X3 * Wi[0] * vg;
-    const double pb = X3 / gm1;
-    gacc -= X3 * Wi[3] / (gm1 * gm1);
-    double Wub, Wvb;
-    if (gt.wall == 0) {
-      const double unb = -2.0 * (ugb * nxv + vgb * nyv);
-      Wub = ugb + unb * nxv;
-      Wvb = vgb + unb * nyv;
-    } else {
-      Wub = -ugb;
-      Wvb = -vgb;
-    }
-    gWb[4 * k] = rb;
-    gWb[4 * k + 1] = Wub;
-    gWb[4 * k + 2] = Wvb;
-    gWb[4 * k + 3] = pb;
-    Xb[gc] = 0.0;
-    Xb[n + gc] = 0.0;
-    Xb[2 * n + gc] = 0.0;
-    Xb[3 * n + gc] = 0.0;
-  }
-  // the first source of every thread: everything that does not depend on gW
-  // is loaded before the barrier (X at a source is never written above:
-  // sources are fluid cells, ghosts are not)
-  const int h0 = threadIdx.x;
-  const bool has = h0 < nsrc;
-  int src0 = 0, i1_0 = 0, e0[4] = {-1, -1, -1, -1};
-  double w0[4] = {0.0, 0.0, 0.0, 0.0}, U0[4] = {1.0, 0.0, 0.0, 1.0}, X0[4] = {0.0, 0.0, 0.0, 0.0};
-  if (has) {
-    const int i0 = heads[h0];
-    i1_0 = heads[h0 + 1];
-    src0 = keys[i0];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) e0[t] = i0 + t < i1_0 ? vals[i0 + t] : -1;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) w0[t] = e0[t] >= 0 ? gt.w[e0[t]] : 0.0;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      U0[v] = Ub[v * n + src0];
-      X0[v] = Xb[v * n + src0];
-    }
-  }
-  __syncthreads();  // gW complete (LDS, or global memory of this workgroup)
-  if (has) {
-    const int i0 = heads[h0];
-    double Wsb[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if (e0[t] < 0) continue;
-      const int k = e0[t] >> 2;
-      Wsb[0] += w0[t] * gWb[4 * k];
-      Wsb[1] += w0[t] * gWb[4 * k + 1];
-      Wsb[2] += w0[t] * gWb[4 * k + 2];
-      Wsb[3] += w0[t] * gWb[4 * k + 3];
-    }
-    for (int j = i0 + 4; j < i1_0; ++j) {
-      const int e = vals[j];
-      const int k = e >> 2;
-      const double wm = gt.w[e];
-      Wsb[0] += wm * gWb[4 * k];
-      Wsb[1] += wm * gWb[4 * k + 1];
-      Wsb[2] += wm * gWb[4 * k + 2];
-      Wsb[3] += wm * gWb[4 * k + 3];
-    }
-    const double r = U0[0];
-    const double u = U0[1] / r, v = U0[2] / r;
-    const double E = U0[3];
-    const double ke = 0.5 * (u * u + v * v);
-    Xb[src0] = X0[0] + (Wsb[0] - Wsb[1] * u / r - Wsb[2] * v / r + Wsb[3] * gm1 * ke);
-    Xb[n + src0] = X0[1] + (Wsb[1] / r - Wsb[3] * gm1 * u);
-    Xb[2 * n + src0] = X0[2] + (Wsb[2] / r - Wsb[3] * gm1 * v);
-    Xb[3 * n + src0] = X0[3] + Wsb[3] * gm1;
-    gacc += Wsb[3] * (E - r * ke);
-  }
-  for (int h = threadIdx.x + FILL_NT; h < nsrc; h += FILL_NT) {
+  for (int h = threadIdx.x; h < nsrc; h += FILL_NT) {
     const int i0 = heads[h], i1 = heads[h + 1];
     const int src = keys[i0];
     double Wsb[4] = {0.0, 0.0, 0.0, 0.0};
@@ -767,9 +732,18 @@ __global__ void __launch_bounds__(FILL_NT) ibm_fill_adjoint_kernel(GridArgs a, G
     if (threadIdx.x < 5) part[(long long)b * 5 + threadIdx.x] = threadIdx.x == 0 ? g : 0.0;
     return;
   }
-  // finalize: the earlier launches' partials (lane sums in order, then a
-  // fixed butterfly) plus this launch's own gamma part
+  // finalize: the earlier launches' partials plus this launch's gamma part
   if (qf >= 0 && lanef == 0) param_bar[b * 5 + qf] += sq + (qf == 0 ? g : 0.0);
+}
+
+// The ghost index of every cell (-1 for the others), for the adjoint kernel.
+__global__ void __launch_bounds__(256) ghost_index_kernel(GridArgs a, int* __restrict__ ghost_of) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < a.ncell) ghost_of[c] = -1;
+}
+__global__ void __launch_bounds__(256) ghost_index_scatter_kernel(GhostTable gt, int* __restrict__ ghost_of) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < gt.n) ghost_of[gt.cell[k]] = k;
 }
 
 // param_bar[b][q] += the recorded partials of member b: one wave per q, lane
@@ -805,11 +779,21 @@ int adjoint_blocks(const GridArgs& a) { return ((a.nx + ATX - 1) / ATX) * ((a.ny
 
 hipError_t launch_rhs_adjoint(const GridArgs& a, const double* Us, const double* lam, double clam_f,
                               const double* dtp, const double* X1, double c1, const double* X2, double c2,
-                              const double* X3, double c3, double* out, double* part, int* nblk, hipStream_t st) {
+                              const double* X3, double c3, double* out, double* part, int* nblk,
+                              const GhostTable& gt, double* gW, hipStream_t st) {
   dim3 grid((a.nx + ATX - 1) / ATX, (a.ny + ATY - 1) / ATY, a.nbatch);
+  if (gW != nullptr && (a.ghost_of == nullptr || gt.n == 0)) gW = nullptr;
   hipLaunchKernelGGL((rhs_adjoint_kernel<ATX, ATY, ANT>), grid, dim3(ANT), 0, st, a, Us, lam, clam_f, dtp, X1, c1, X2,
-                     c2, X3, c3, out, part);
+                     c2, X3, c3, out, part, gt, gW);
   *nblk = (int)(grid.x * grid.y);
+  return hipGetLastError();
+}
+
+hipError_t launch_ghost_index(const GridArgs& a, const GhostTable& gt, int* ghost_of, hipStream_t st) {
+  hipLaunchKernelGGL(ghost_index_kernel, dim3((unsigned int)((a.ncell + 255) / 256)), dim3(256), 0, st, a, ghost_of);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || gt.n == 0) return e;
+  hipLaunchKernelGGL(ghost_index_scatter_kernel, dim3((gt.n + 255) / 256), dim3(256), 0, st, gt, ghost_of);
   return hipGetLastError();
 }
 
@@ -828,16 +812,10 @@ hipError_t launch_ibm_entries(const GhostTable& gt, int* keys, int* vals, int* n
 }
 
 hipError_t launch_ibm_fill_adjoint(const GridArgs& a, const GhostTable& gt, const int* keys, const int* vals,
-                                   const int* heads, int nsrc, const double* Us, double* X, double* gW, double* part,
-                                   const PartSlots& prior, double* param_bar, hipStream_t st) {
-  if (gt.n <= FILL_LDS_GHOSTS) {
-    const size_t lds = sizeof(double) * 4 * size_t(gt.n > 0 ? gt.n : 1);
-    hipLaunchKernelGGL(ibm_fill_adjoint_kernel<true>, dim3(a.nbatch), dim3(FILL_NT), lds, st, a, gt, keys, vals, heads,
-                       nsrc, Us, X, gW, part, prior, param_bar);
-  } else {
-    hipLaunchKernelGGL(ibm_fill_adjoint_kernel<false>, dim3(a.nbatch), dim3(FILL_NT), 0, st, a, gt, keys, vals, heads,
-                       nsrc, Us, X, gW, part, prior, param_bar);
-  }
+                                   const int* heads, int nsrc, const double* Us, double* X, const double* gW,
+                                   double* part, const PartSlots& prior, double* param_bar, hipStream_t st) {
+  hipLaunchKernelGGL(ibm_fill_adjoint_kernel, dim3(a.nbatch), dim3(FILL_NT), 0, st, a, gt, keys, vals, heads, nsrc, Us,
+                     X, gW, part, prior, param_bar);
   return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ using namespace shk;
 
 struct WsLayout {
   size_t scalars, globals, dtbuf, xslots, u1, u2, cls, row_count, row_off, g_cell, g_src, g_w, g_nrm;
-  size_t adjA, adjB, adjC, adjP, adjQ, adjPart, part_stride, adjG, entKeys, entVals, entCount, entHeads;
+  size_t adjA, adjB, adjC, adjP, adjQ, adjPart, part_stride, adjG, ghostOf, entKeys, entVals, entCount, entHeads;
   size_t netX, netPart;
   size_t total;
 };
@@ -121,6 +121,7 @@ WsLayout layout(const shk_grid_desc* d) {
     L.adjPart = o; o += al(sizeof(double) * MAX_PART_SLOTS * L.part_stride);
     if (d->ibm) {
       L.adjG = o; o += st64;  // image-point primitive adjoints, 4 per ghost
+      L.ghostOf = o; o += al(sizeof(int) * ncell);
       L.entKeys = o; o += al(sizeof(int) * 4 * ncell);
       L.entVals = o; o += al(sizeof(int) * 4 * ncell);
       L.entCount = o; o += al(sizeof(int));
@@ -136,6 +137,18 @@ WsLayout layout(const shk_grid_desc* d) {
   }
   L.total = o;
   return L;
+}
+
+// gamma-dependent arguments: gamma, conductivity, conservative inflow state.
+static void set_physics(const shk_grid_desc& d, GridArgs& a) {
+  a.gamma = d.gamma;
+  a.kappa = d.viscous ? d.mu * d.gamma / ((d.gamma - 1.0) * a.prandtl) : 0.0;
+  const double* w = d.inflow_prim;
+  const double v = d.ndim == 2 ? w[2] : 0.0;
+  a.inflow_cons[0] = w[0];
+  a.inflow_cons[1] = w[0] * w[1];
+  a.inflow_cons[2] = w[0] * v;
+  a.inflow_cons[3] = w[3] / (d.gamma - 1.0) + 0.5 * w[0] * (w[1] * w[1] + v * v);
 }
 
 shk_status fail(shk_grid* g, shk_status s, const std::string& m) {
@@ -269,17 +282,9 @@ shk_status shk_init_grid(const shk_grid_desc* desc, void* workspace, size_t ws_b
   a.inv_dx = 1.0 / a.dx; a.inv_dy = 1.0 / a.dy;
   a.gamma = d.gamma; a.eps = d.weno_eps; a.cfl = d.cfl;
   a.viscous = d.viscous; a.mu = d.mu; a.prandtl = d.prandtl > 0 ? d.prandtl : 1.0;
-  a.kappa = d.viscous ? d.mu * d.gamma / ((d.gamma - 1.0) * a.prandtl) : 0.0;
   a.nu_art = d.nu_art;
   for (int k = 0; k < 4; ++k) a.bc[k] = d.bc[k];
-  {
-    const double* w = d.inflow_prim;
-    const double v = d.ndim == 2 ? w[2] : 0.0;
-    a.inflow_cons[0] = w[0];
-    a.inflow_cons[1] = w[0] * w[1];
-    a.inflow_cons[2] = w[0] * v;
-    a.inflow_cons[3] = w[3] / (d.gamma - 1.0) + 0.5 * w[0] * (w[1] * w[1] + v * v);
-  }
+  set_physics(g->d, a);
   a.cls = nullptr;
   a.sc = reinterpret_cast<StepScalars*>(g->ws + L.scalars);
   a.glob = reinterpret_cast<Globals*>(g->ws + L.globals);
@@ -318,6 +323,7 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
   if (!phi) {
     g->ibm_on = false;
     g->a.cls = nullptr;
+    g->a.ghost_of = nullptr;
     g->gt.n = 0;
     return SHK_OK;
   }
@@ -347,6 +353,7 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
   g->ibm_on = true;
   g->nent = 0;
   g->nsrc = 0;
+  a.ghost_of = nullptr;
   if (g->d.adjoint && n > 0) {
     int* keys = reinterpret_cast<int*>(g->ws + g->L.entKeys);
     int* vals = reinterpret_cast<int*>(g->ws + g->L.entVals);
@@ -372,7 +379,24 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
     if (e == hipSuccess) e = hipStreamSynchronize(g->st);
     if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset (entry heads)");
     g->nsrc = int(heads.size()) - 1;
+    int* gof = reinterpret_cast<int*>(g->ws + g->L.ghostOf);
+    e = launch_ghost_index(a, gt, gof, g->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+    if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset (ghost index)");
+    a.ghost_of = gof;
   }
+  return SHK_OK;
+}
+
+shk_status shk_set_params(shk_grid* g, double gamma, const double* inflow_prim) {
+  if (!g) return SHK_EINVAL;
+  if (!(gamma > 1.0)) return fail(g, SHK_EINVAL, "set_params: gamma must exceed 1");
+  if (inflow_prim && (!(inflow_prim[0] > 0.0) || !(inflow_prim[3] > 0.0)))
+    return fail(g, SHK_EINVAL, "set_params: inflow density and pressure must be positive");
+  g->d.gamma = gamma;
+  if (inflow_prim)
+    for (int k = 0; k < 4; ++k) g->d.inflow_prim[k] = inflow_prim[k];
+  set_physics(g->d, g->a);
   return SHK_OK;
 }
 
@@ -438,6 +462,8 @@ static PartRec part_rec(shk_grid* g) {
 
 // rhs-adjoint launch with the learned correction's reverse pass first (its
 // stencil gradient is then added by the adjoint kernel face by face).
+// With the immersed boundary the launch also runs the ghost half of the
+// refill transpose (fillT below finishes it).
 static hipError_t rhs_adj(shk_grid* g, PartRec& pr, const double* Us, const double* lam, double clam_f,
                           const double* dtp, const double* X1, double c1, const double* X2, double c2,
                           const double* X3, double c3, double* out) {
@@ -450,7 +476,9 @@ static hipError_t rhs_adj(shk_grid* g, PartRec& pr, const double* Us, const doub
     a.dXnet = dX;
   }
   int nb = 0;
-  hipError_t e = launch_rhs_adjoint(a, Us, lam, clam_f, dtp, X1, c1, X2, c2, X3, c3, out, pr.next(), &nb, g->st);
+  double* gW = g->ibm_on ? reinterpret_cast<double*>(g->ws + g->L.adjG) : nullptr;
+  hipError_t e = launch_rhs_adjoint(a, Us, lam, clam_f, dtp, X1, c1, X2, c2, X3, c3, out, pr.next(), &nb, g->gt, gW,
+                                    g->st);
   if (e == hipSuccess) pr.add(nb);
   return e;
 }
@@ -467,13 +495,13 @@ static hipError_t fill64(shk_grid* g, double* X) {
   return g->ibm_on ? launch_ibm_fill<double>(g->a, g->gt, X, g->st) : hipSuccess;
 }
 
-// Transpose of the refill on an adjoint array X (w.r.t. the filled state Us).
-// With param_bar set, this launch also finalises the pass's partials.
+// Source half of the refill transpose on an adjoint array X (w.r.t. the
+// filled state Us); with param_bar set it also finalises the pass's partials.
 static hipError_t fillT(shk_grid* g, PartRec& pr, const double* Us, double* X, double* param_bar = nullptr) {
-  if (!g->ibm_on) return hipSuccess;
+  if (!g->ibm_on || g->nent == 0) return hipSuccess;
   const int* keys = reinterpret_cast<const int*>(g->ws + g->L.entKeys);
   const int* vals = reinterpret_cast<const int*>(g->ws + g->L.entVals);
-  double* gW = reinterpret_cast<double*>(g->ws + g->L.adjG);
+  const double* gW = reinterpret_cast<const double*>(g->ws + g->L.adjG);
   const int* heads = reinterpret_cast<const int*>(g->ws + g->L.entHeads);
   hipError_t e = launch_ibm_fill_adjoint(g->a, g->gt, keys, vals, heads, g->nsrc, Us, X, gW, pr.next(), pr.ps,
                                          param_bar, g->st);
@@ -513,7 +541,7 @@ shk_status shk_rhs_adjoint(shk_grid* g, const void* U, const void* dUdt_bar, voi
 // Reverse of one SSP-RK3 step from its filled stage-start states A = U^n,
 // B = U1, C = U2.  With the adjoints written X3 (after the step, in Ub), X2,
 // X1 (of the stage states before their refill) and R^T the transpose of the
-// refill:
+// refill (its ghost half inside each adjoint launch):
 //   X2 = R^T(2/3 X3 + 2/3 dt J(U2)^T X3)
 //   X1 = R^T(1/4 X2 + 1/4 dt J(U1)^T X2)
 //   X0 = R^T(X1 + dt J(U^n)^T X1 + 1/3 X3 + 3/4 X2)
@@ -571,6 +599,35 @@ shk_status shk_rk3_step_adjoint_tape(shk_grid* g, const void* tape, const double
   const long long nst = (long long)g->a.nbatch * 4 * g->a.ncell;
   hipError_t e = reverse_step(g, A, A + nst, A + 2 * nst, dt, static_cast<double*>(U_bar), param_bar);
   return hip_check(g, e, "rk3_step_adjoint_tape");
+}
+
+shk_status shk_rk3_steps_record(shk_grid* g, void* U, int nsteps, const double* dt, void* tapes) {
+  if (!g) return SHK_EINVAL;
+  shk_status s = adjoint_ok(g);
+  if (s != SHK_OK) return s;
+  if (!U || !dt || !tapes || nsteps < 0) return fail(g, SHK_EINVAL, "rk3_steps_record: null array or nsteps < 0");
+  const long long nst = (long long)g->a.nbatch * 4 * g->a.ncell;
+  for (int k = 0; k < nsteps; ++k) {
+    s = stage_seq<double>(g, static_cast<double*>(U), dt, nullptr, static_cast<double*>(tapes) + 3 * nst * k);
+    if (s != SHK_OK) return s;
+  }
+  return SHK_OK;
+}
+
+shk_status shk_rk3_steps_adjoint_tape(shk_grid* g, const void* tapes, int nsteps, const double* dt, void* U_bar,
+                                      double* param_bar) {
+  if (!g) return SHK_EINVAL;
+  shk_status s = adjoint_ok(g);
+  if (s != SHK_OK) return s;
+  if (!tapes || !dt || !U_bar || nsteps < 0)
+    return fail(g, SHK_EINVAL, "rk3_steps_adjoint_tape: null array or nsteps < 0");
+  const long long nst = (long long)g->a.nbatch * 4 * g->a.ncell;
+  for (int k = nsteps - 1; k >= 0; --k) {
+    const double* A = static_cast<const double*>(tapes) + 3 * nst * k;
+    hipError_t e = reverse_step(g, A, A + nst, A + 2 * nst, dt, static_cast<double*>(U_bar), param_bar);
+    if (e != hipSuccess) return hip_check(g, e, "rk3_steps_adjoint_tape");
+  }
+  return SHK_OK;
 }
 
 shk_status shk_set_flux_net(shk_grid* g, const uint16_t* w_bf16, const float* bias, const double* norm_host,

@@ -45,6 +45,7 @@ struct GridArgs {
   double* dtbuf;               // [nbatch] step of the automatic time stepping
   double* dt_out;              // optional caller copy of the step (per call)
   void* stage_in_copy;         // MODE_STAGE1: optional copy of the stage input (storage type), or nullptr
+  const int* ghost_of;         // immersed boundary, adjoint grids: ghost index of each cell or -1 (else nullptr)
   unsigned long long* xslots;  // [nbatch][2][XSLOTS] spread extrema of the fused step
   const float* dXnet;          // its stencil gradient per face [nbatch][nface][24] or nullptr
   long long nface;             // x-faces (nx+1)*ny then y-faces nx*(ny+1)
@@ -102,20 +103,27 @@ struct PartSlots {
   long long stride;
 };
 int adjoint_blocks(const GridArgs& a);
+// With the immersed boundary (gW != nullptr, a.ghost_of set) the kernel also
+// runs the first half of the refill transpose for the ghost cells it owns:
+// their image-point adjoints go to gW and their own entries of out to zero.
 hipError_t launch_rhs_adjoint(const GridArgs& a, const double* Us, const double* lam, double clam_f,
                               const double* dtp, const double* X1, double c1, const double* X2, double c2,
-                              const double* X3, double c3, double* out, double* part, int* nblk, hipStream_t st);
+                              const double* X3, double c3, double* out, double* part, int* nblk,
+                              const GhostTable& gt, double* gW, hipStream_t st);
+hipError_t launch_ghost_index(const GridArgs& a, const GhostTable& gt, int* ghost_of, hipStream_t st);
 hipError_t launch_partials_finalize(const double* part, const PartSlots& ps, int nbatch, double* param_bar,
                                     hipStream_t st);
 hipError_t launch_ibm_entries(const GhostTable& gt, int* keys, int* vals, int* nvalid, hipStream_t st);
-// Transpose of the refill (one workgroup per batch member).  Its block
-// partial goes to part (1 block per member).  With param_bar set it also
-// finalises: param_bar += the slots of prior (which lie before part, at
-// part - (prior.n - s) * prior.stride for slot s) plus its own partial.
-// heads[0..nsrc]: start of each source's run in the sorted entry list.
+// Second half of the refill transpose (one workgroup per batch member): the
+// source cells gather the image-point adjoints gW left by the adjoint
+// kernel.  Its block partial goes to part (1 block per member).  With
+// param_bar set it also finalises: param_bar += the slots of prior (which lie
+// before part, at part - (prior.n - s) * prior.stride for slot s) plus its
+// own partial.  heads[0..nsrc]: start of each source's run in the sorted
+// entry list.
 hipError_t launch_ibm_fill_adjoint(const GridArgs& a, const GhostTable& gt, const int* keys, const int* vals,
-                                   const int* heads, int nsrc, const double* Us, double* X, double* gW, double* part,
-                                   const PartSlots& prior, double* param_bar, hipStream_t st);
+                                   const int* heads, int nsrc, const double* Us, double* X, const double* gW,
+                                   double* part, const PartSlots& prior, double* param_bar, hipStream_t st);
 hipError_t launch_axpy(long long n, double alpha, const double* x, double* y, int accumulate, hipStream_t st);
 
 // stage modes

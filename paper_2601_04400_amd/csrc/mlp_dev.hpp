@@ -95,22 +95,26 @@ __device__ __forceinline__ void load_net_lds(const NetArgs& n, unsigned short* s
 // Forward of one 64-face batch held by a wave.  Returns, for lanes with
 // lane>>4 == 0, the pre-tanh outputs z[ft][0..3] of face ft*16 + (lane&15);
 // optionally keeps the activations and ReLU masks for the reverse pass.
-struct Acts {
-  bf16x4 x[2][4];
-  bf16x4 h[3][4][4];        // layer, neuron tile, face tile
-  unsigned int mask[3][4];  // bit (nt*4 + i) of face tile ft: pre-activation > 0
+template <int FT = 4>
+struct ActsT {
+  bf16x4 x[2][FT];
+  bf16x4 h[3][4][FT];        // layer, neuron tile, face tile
+  unsigned int mask[3][FT];  // bit (nt*4 + i) of face tile ft: pre-activation > 0
 };
+typedef ActsT<4> Acts;
 
-__device__ __forceinline__ void net_forward_batch(const unsigned short* sw, const float* sb, int lane, Acts& A,
-                                                  f32x4 z[4]) {
+// FT face tiles of 16 faces per call (FT = 4: 64 faces per wave).
+template <int FT = 4>
+__device__ __forceinline__ void net_forward_batch(const unsigned short* sw, const float* sb, int lane, ActsT<FT>& A,
+                                                  f32x4 z[FT]) {
   const int q = lane >> 4;
   // layer 1: 64 x 32
 #pragma unroll
-  for (int ft = 0; ft < 4; ++ft) A.mask[0][ft] = 0u;
+  for (int ft = 0; ft < FT; ++ft) A.mask[0][ft] = 0u;
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-    for (int ft = 0; ft < 4; ++ft) {
+    for (int ft = 0; ft < FT; ++ft) {
       // the accumulator starts at the bias of its four rows
       const float* b0 = sb + NET_OFF_B0 + nt * 16 + 4 * q;
       f32x4 acc = {b0[0], b0[1], b0[2], b0[3]};
@@ -130,11 +134,11 @@ __device__ __forceinline__ void net_forward_batch(const unsigned short* sw, cons
     const unsigned short* W = sw + (l == 1 ? NET_OFF_W1 : NET_OFF_W2);
     const float* B = sb + (l == 1 ? NET_OFF_B1 : NET_OFF_B2);
 #pragma unroll
-    for (int ft = 0; ft < 4; ++ft) A.mask[l][ft] = 0u;
+    for (int ft = 0; ft < FT; ++ft) A.mask[l][ft] = 0u;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-      for (int ft = 0; ft < 4; ++ft) {
+      for (int ft = 0; ft < FT; ++ft) {
         const float* bl = B + nt * 16 + 4 * q;
         f32x4 acc = {bl[0], bl[1], bl[2], bl[3]};
 #pragma unroll
@@ -152,7 +156,7 @@ __device__ __forceinline__ void net_forward_batch(const unsigned short* sw, cons
   }
   // output layer: 16 (4 used) x 64
 #pragma unroll
-  for (int ft = 0; ft < 4; ++ft) {
+  for (int ft = 0; ft < FT; ++ft) {
     const float* b3 = sb + NET_OFF_B3 + 4 * q;
     f32x4 acc = {b3[0], b3[1], b3[2], b3[3]};
 #pragma unroll

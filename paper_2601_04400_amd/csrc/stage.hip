@@ -279,17 +279,19 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
   };
 
   if (NET) {
-    // 1b. learned correction of every face of the tile, 64 faces per wave
-    // and batch on the matrix cores; the network output before its tanh is
-    // parked in the flux arrays (face frame), and the face pass, one face per
-    // thread, finishes it and adds it to the flux
+    // 1b. learned correction of every face of the tile on the matrix cores,
+    // 32 faces per wave and batch (the tile's 552 faces split evenly over
+    // the four waves); the network output before its tanh is parked in the
+    // flux arrays (face frame), and the face pass, one face per thread,
+    // finishes it and adds it to the flux
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     constexpr int NF = NFX + NFY;
-    for (int bb = wv; bb * 64 < NF; bb += NT / 64) {
-      Acts A;
+    constexpr int FT = 2;
+    for (int bb = wv; bb * 16 * FT < NF; bb += NT / 64) {
+      ActsT<FT> A;
 #pragma unroll
-      for (int ft = 0; ft < 4; ++ft) {
-        int k = bb * 64 + ft * 16 + (lane & 15);
+      for (int ft = 0; ft < FT; ++ft) {
+        int k = bb * 16 * FT + ft * 16 + (lane & 15);
         if (k >= NF) k = NF - 1;
         int s0, st, cn, ct, oidx;
         face_of(k, s0, st, cn, ct, oidx);
@@ -301,12 +303,12 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
           wv4[3] = double(w[3][p]);
         }, A.x[0][ft], A.x[1][ft]);
       }
-      f32x4 z[4];
-      net_forward_batch(net_w, net_b, lane, A, z);
+      f32x4 z[FT];
+      net_forward_batch<FT>(net_w, net_b, lane, A, z);
       if ((lane >> 4) == 0) {
 #pragma unroll
-        for (int ft = 0; ft < 4; ++ft) {
-          const int k = bb * 64 + ft * 16 + (lane & 15);
+        for (int ft = 0; ft < FT; ++ft) {
+          const int k = bb * 16 * FT + ft * 16 + (lane & 15);
           if (k >= NF) continue;
           int s0, st, cn, ct, oidx;
           face_of(k, s0, st, cn, ct, oidx);

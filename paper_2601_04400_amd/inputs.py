@@ -144,6 +144,19 @@ def shock_cylinder(nx, ny, post, domain=(0.0, 2.0, 0.0, 1.0), centre=(0.3, 0.5),
     return dict(W=W, phi=phi, domain=domain, bc=(2, 0, 1, 1), inflow=tuple(post))
 
 
+def paper_shock_cylinder(nx, ny):
+    """The section 3 shock-cylinder set-up: [-0.5, 4] x [0, 2], cylinder of
+    radius 0.25 at (0.6, 1), initial state (7, 4, 0, 29) for x < 0.3 and
+    (1.4, 0, 0, 1) elsewhere (a Mach-5 shock, eq. Sod_ST), inflow of the left
+    state on the left, outflow on the right, reflective walls at the bottom
+    and top, slip wall on the cylinder."""
+    dom = (-0.5, 4.0, 0.0, 2.0)
+    post, pre = (7.0, 4.0, 0.0, 29.0), (1.4, 0.0, 0.0, 1.0)
+    W = shock_prim(nx, ny, dom, 0.3, post, pre)
+    phi = circle_phi(nx, ny, dom, (0.6, 1.0), 0.25)
+    return dict(W=W, phi=phi, domain=dom, bc=(2, 0, 1, 1), inflow=post)
+
+
 def cylinder_viscosity(mach, reynolds=1000.0, diameter=0.2, rho1=1.4, a1=1.0):
     """Dynamic viscosity giving Reynolds number `reynolds` on the cylinder
     diameter with the pre-shock density and the shock speed M a1."""

@@ -212,6 +212,46 @@ class Grid:
               self.handle, "rk3_step_adjoint_tape")
         return U_bar
 
+    def _check_tapes(self, tapes, nsteps):
+        if not (tapes.is_cuda and tapes.dtype == torch.float64 and tapes.is_contiguous()
+                and tuple(tapes.shape[1:]) == (3,) + tuple(self.shape) and tapes.shape[0] >= nsteps):
+            raise ValueError("tapes must be a contiguous float64 CUDA tensor of shape (>= nsteps, 3) + grid state shape")
+
+    def _dt_tensor(self, dt):
+        if not torch.is_tensor(dt):
+            dt = torch.full((self.shape[0],), float(dt), dtype=torch.float64, device=self.device)
+        return dt
+
+    def steps_record(self, U, tapes, nsteps, dt):
+        """nsteps fixed-dt RK3 steps in place, recording step k into tapes[k]
+        (one library call for all of them)."""
+        self._check_state(U)
+        self._check_tapes(tapes, nsteps)
+        dt = self._dt_tensor(dt)
+        self._sync_stream()
+        check(lib().shk_rk3_steps_record(self.handle, _ptr(U), int(nsteps), _ptr(dt), _ptr(tapes)),
+              self.handle, "rk3_steps_record")
+        return U
+
+    def steps_adjoint_tape(self, tapes, nsteps, dt, U_bar, param_bar=None):
+        """Reverse of nsteps recorded steps (last first), in place on U_bar."""
+        self._check_state(U_bar)
+        self._check_tapes(tapes, nsteps)
+        dt = self._dt_tensor(dt)
+        self._sync_stream()
+        check(lib().shk_rk3_steps_adjoint_tape(self.handle, _ptr(tapes), int(nsteps), _ptr(dt), _ptr(U_bar),
+                                               _ptr(param_bar)), self.handle, "rk3_steps_adjoint_tape")
+        return U_bar
+
+    def set_params(self, gamma, inflow=None):
+        """New gamma (and inflow primitive state) for the calls that follow."""
+        arr = None if inflow is None else (ctypes.c_double * 4)(*[float(x) for x in inflow])
+        check(lib().shk_set_params(self.handle, float(gamma), arr), self.handle, "set_params")
+        self.desc.gamma = float(gamma)
+        if inflow is not None:
+            for k in range(4):
+                self.desc.inflow_prim[k] = float(inflow[k])
+
     def set_time(self, t0, t_end):
         self._sync_stream()
         check(lib().shk_set_time(self.handle, float(t0), float(t_end)), self.handle, "set_time")
