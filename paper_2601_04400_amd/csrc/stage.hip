@@ -176,6 +176,10 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
   static_assert(!NET || (NDIM == 2 && !VISC), "learned correction: 2D inviscid tiles");
   __shared__ __attribute__((aligned(16))) unsigned short net_w[NET ? NET_NW : 1];
   __shared__ float net_b[NET ? NET_NB : 1];
+  // normalised network inputs of every halo cell, bfloat16, in the x-face
+  // frame (rho, u, v, p) and the y-face frame (rho, v, u, p): each cell feeds
+  // twelve faces, so it is converted once here
+  __shared__ bf16x4 net_in[NET ? 2 : 1][NET ? PY * PX : 1];
   __shared__ double red_s[NT / 64], red_r[NT / 64];
 
   int bx, by, b;
@@ -258,6 +262,18 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     w[1][k] = p.un;
     w[2][k] = p.ut;
     w[3][k] = p.p;
+    if (NET) {
+      const double pv[4] = {double(p.r), double(p.un), double(p.ut), double(p.p)};
+      float xn[4], yn[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int vy = v == 1 ? 2 : (v == 2 ? 1 : v);  // y-face frame
+        xn[v] = float((pv[v] - net.mean[v]) * net.inv_std[v]);
+        yn[v] = float((pv[vy] - net.mean[v]) * net.inv_std[v]);
+      }
+      net_in[0][k] = pack4(xn[0], xn[1], xn[2], xn[3]);
+      net_in[1][k] = pack4(yn[0], yn[1], yn[2], yn[3]);
+    }
   }
   __syncthreads();
 
@@ -295,13 +311,11 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
         if (k >= NF) k = NF - 1;
         int s0, st, cn, ct, oidx;
         face_of(k, s0, st, cn, ct, oidx);
-        net_inputs(net, lane, [&](int s, double wv4[4]) {
-          const int p = s0 + s * st;
-          wv4[0] = double(w[0][p]);
-          wv4[1] = double(w[cn][p]);
-          wv4[2] = double(w[ct][p]);
-          wv4[3] = double(w[3][p]);
-        }, A.x[0][ft], A.x[1][ft]);
+        // B operand: lane (q, face) takes stencil cell q (k-tile 0) and 4 + q
+        // (k-tile 1, q < 2), already normalised in this face's frame
+        const int q = lane >> 4, fr = k < NFX ? 0 : 1;
+        A.x[0][ft] = net_in[fr][s0 + q * st];
+        A.x[1][ft] = q < 2 ? net_in[fr][s0 + (4 + q) * st] : bf16x4{0, 0, 0, 0};
       }
       f32x4 z[FT];
       net_forward_batch<FT>(net_w, net_b, lane, A, z);
