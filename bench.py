@@ -35,9 +35,9 @@ WORDS_PER_CELL_STEP = 32
 # kernel calibration (fetch x 2.0, write x 1.0), for the stage-kernel sources
 # whose SHA-256 is given; reported as null for any other source or workload.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "890d059070c38d7315818fe14a6606e8033a03907409d8d552b85773183d7c00",
+    "sources_sha256": "ecfeefe09afefa1a486d2e95fe3b0af3e108467e7b87177c89feaeed01a511ea",
     "workload": (512, 512, "f64"),
-    "bytes_per_launch": 23516784,
+    "bytes_per_launch": 23516774,
     "profile": "profiles/stage_kernel_quadrant512_f64.md",
 }
 STAGE_SOURCES = ("stage.hip", "flux.hpp", "xcd.hpp")
@@ -89,7 +89,9 @@ def adjoint_ratio(n=256, steps=200, every=20):
     """Adjoint:forward cost on the inviscid shock-cylinder sensitivity problem
     (256^2, 200 fixed steps, checkpoints every 20): wall time of the backward
     pass (segment replays included) over the forward pass, the median of
-    three measured repetitions after a warm-up one."""
+    five measured repetitions after a warm-up one; with the replays on a
+    replica grid overlapping the reverse pass (reported) and in one stream
+    (serial_replay)."""
     import torch
     from paper_2601_04400_amd import Grid, inputs, normal_shock_state
     from paper_2601_04400_amd.adjoint import rollout
@@ -105,26 +107,37 @@ def adjoint_ratio(n=256, steps=200, every=20):
     g.step(U0.clone(), dt_out=d)
     dt = 0.6 * float(d.cpu()[0])
     params = torch.tensor([[1.4, *inflow]], dtype=torch.float64, device="cuda", requires_grad=True)
-    runs = []
-    for rep in range(4):  # the first is a warm-up; the median of the other three is reported
-        U0.grad = None
-        U0.requires_grad_(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        U = rollout(g, U0, params, steps, dt, every)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        U.backward(torch.ones_like(U))
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        if rep > 0:
-            runs.append(((t2 - t1) / (t1 - t0), t1 - t0, t2 - t1))
-    runs.sort()
+
+    def measure(overlap):
+        runs = []
+        for rep in range(6):  # the first is a warm-up; the median of the other five is reported
+            U0.grad = None
+            U0.requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            U = rollout(g, U0, params, steps, dt, every, overlap=overlap)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            U.backward(torch.ones_like(U))
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if rep > 0:
+                runs.append(((t2 - t1) / (t1 - t0), t1 - t0, t2 - t1))
+        runs.sort()
+        return runs
+
+    runs = measure(True)
+    serial = measure(False)
     r, f, b = runs[len(runs) // 2]
+    rs, fs, bs = serial[len(serial) // 2]
     res = {"forward_ms": round(f * 1e3, 3), "backward_ms": round(b * 1e3, 3), "ratio": round(r, 3),
-           "ratios_measured": [round(x[0], 3) for x in runs]}
+           "measured_fwd_bwd_ms": [[round(x[1] * 1e3, 3), round(x[2] * 1e3, 3)] for x in runs],
+           "serial_replay": {"forward_ms": round(fs * 1e3, 3), "backward_ms": round(bs * 1e3, 3),
+                             "ratio": round(rs, 3)}}
     res["workload"] = (f"inviscid Mach-3 shock on a cylinder, {n}x{n}, {steps} fixed RK3 steps, "
-                       f"checkpoint every {every}, slip immersed boundary; backward includes segment replays")
+                       f"checkpoint every {every}, slip immersed boundary; backward includes segment replays "
+                       f"(on a replica grid and second stream, overlapping the reverse pass; serial_replay: "
+                       f"the same backward with replays and reverse steps in one stream)")
     return res
 
 

@@ -33,18 +33,20 @@ namespace {
 
 // Primitive state (rho, u_n, u_t, p) of stencil cell s (0..5) of face f of
 // batch member Ub; x-faces first ((nx+1) per row), then y-faces (nx per row).
+// The faces of one batch member are indexed in 32 bits.
 __device__ __forceinline__ void face_cell_prim(const GridArgs& a, const double* __restrict__ Ub, long long f, int s,
                                                double w[4]) {
-  const long long nxf = (long long)(a.nx + 1) * a.ny;
+  const int fi = (int)f, nxf = (a.nx + 1) * a.ny;
   int gi, gj;
-  bool isx = f < nxf;
+  bool isx = fi < nxf;
   if (isx) {
-    gj = (int)(f / (a.nx + 1));
-    gi = (int)(f % (a.nx + 1)) - 3 + s;
+    gj = fi / (a.nx + 1);
+    gi = fi - gj * (a.nx + 1) - 3 + s;
   } else {
-    const long long g = f - nxf;
-    gj = (int)(g / a.nx) - 3 + s;
-    gi = (int)(g % a.nx);
+    const int g = fi - nxf;
+    const int r = g / a.nx;
+    gi = g - r * a.nx;
+    gj = r - 3 + s;
   }
   double q[4];
   // boundary rules as in the stage kernel
@@ -131,119 +133,75 @@ __global__ void __launch_bounds__(256) net_forward_kernel(GridArgs a, NetArgs n,
 
 namespace {
 
-struct BwdCtx {
-  const unsigned short* sw;
-  float* gsum;
-  unsigned short* trA;
-  unsigned short* trH;
-  int lane, wv;
-  bool live;
-};
+// Row stride (bf16 elements) of the per-wave transpose tiles: a multiple of 4
+// (8-byte operand reads) that puts rows 4q apart in distinct LDS banks.
+constexpr int TR_LD = 20;
 
-// Reverse of layer L (0 = first hidden, 3 = output): adds the parameter
-// gradient of the wave's 64 faces to the block's LDS sums (waves in a fixed
-// order), then maps dA to the gradient of the layer input, applying the ReLU
-// mask of the layer below (or returning it in dX for the network input).
-template <int L>
-__device__ __forceinline__ void bwd_layer(const BwdCtx& c, const Acts& A, f32x4 (&dA)[4][4],
-                                          f32x4 (*dX)[4] = nullptr) {
-  constexpr int NOUT = L == 3 ? 1 : 4;
-  constexpr int NIN = L == 0 ? 2 : 4;
-  constexpr int LD = L == 0 ? 32 : 64;
-  constexpr int IN_REAL = L == 0 ? 24 : 64;
-  constexpr int OUT_REAL = L == 3 ? 4 : 64;
-  constexpr int OFFW = L == 0 ? NET_OFF_W0 : L == 1 ? NET_OFF_W1 : L == 2 ? NET_OFF_W2 : NET_OFF_W3;
-  constexpr int GW = L == 0 ? NET_G_W0 : L == 1 ? NET_G_W1 : L == 2 ? NET_G_W2 : NET_G_W3;
-  constexpr int GB = L == 0 ? NET_G_B0 : L == 1 ? NET_G_B1 : L == 2 ? NET_G_B2 : NET_G_B3;
-  const int lane = c.lane, q = lane >> 4, fl = lane & 15;
-  const unsigned short* W = c.sw + OFFW;
-  f32x4 gw[NOUT][NIN];
-  float gb[NOUT][4];
+// 16 x 16 tile in D layout (lane (column c = lane & 15, q = lane >> 4) holds
+// rows 4q..4q+3 of column c) -> MFMA operand layout (lane (row r, q) holds
+// columns 4q..4q+3 of row r of the same tile, i.e. the tile transposed),
+// through a per-wave LDS tile.  Within one wave the LDS operations run in
+// program order, so only the compiler needs a barrier.
+__device__ __forceinline__ bf16x4 transpose_bf(unsigned short* t, bf16x4 v, int lane) {
+  const int q = lane >> 4, c = lane & 15;
 #pragma unroll
-  for (int ot = 0; ot < NOUT; ++ot) {
+  for (int i = 0; i < 4; ++i) t[(4 * q + i) * TR_LD + c] = (unsigned short)v[i];
+  __builtin_amdgcn_wave_barrier();
+  const bf16x4 r = *reinterpret_cast<const bf16x4*>(t + c * TR_LD + 4 * q);
+  __builtin_amdgcn_wave_barrier();
+  return r;
+}
+
+__device__ __forceinline__ bf16x4 transpose_f(unsigned short* t, f32x4 v, int lane) {
+  return transpose_bf(t, pack4(v[0], v[1], v[2], v[3]), lane);
+}
+
+__device__ __forceinline__ s16x8 pack8(f32x4 lo, f32x4 hi) {
+  return cat8(pack4(lo[0], lo[1], lo[2], lo[3]), pack4(hi[0], hi[1], hi[2], hi[3]));
+}
+
+// ReLU mask of the layer below: bit (tile * 4 + i) of m.
+__device__ __forceinline__ f32x4 relu_mask(f32x4 v, unsigned int m, int tile) {
+  f32x4 r;
 #pragma unroll
-    for (int it = 0; it < NIN; ++it) gw[ot][it] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < 4; ++i) r[i] = ((m >> (tile * 4 + i)) & 1u) ? v[i] : 0.f;
+  return r;
+}
+
+// Sum over the 16 faces of a row group (lanes q*16 .. q*16+15), in a fixed
+// order, of a per-lane value.
+__device__ __forceinline__ float face_sum16(float v) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      float s = 0.f;
+  for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 16);
+  return v;
+}
+
+// Weight gradient of a hidden layer (64 outputs x 64 inputs) for one
+// 16-face tile: dW += dA . H^T, a contraction over the faces.
+__device__ __forceinline__ void hidden_grad(unsigned short* tr, const f32x4 (&dA)[4], const bf16x4 (&h)[4][1],
+                                            f32x4 (&g)[4][4], int lane) {
+  bf16x4 aT[4], hT[4];
 #pragma unroll
-      for (int ft = 0; ft < 4; ++ft) s += dA[ot][ft][i];
-      for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);  // the 16 faces of a lane group
-      gb[ot][i] = s;
-    }
-  }
-  if (c.live) {
+  for (int ot = 0; ot < 4; ++ot) aT[ot] = transpose_f(tr + ot * 16 * TR_LD, dA[ot], lane);
 #pragma unroll
-    for (int ft = 0; ft < 4; ++ft) {
+  for (int it = 0; it < 4; ++it) hT[it] = transpose_bf(tr + (4 + it) * 16 * TR_LD, h[it][0], lane);
 #pragma unroll
-      for (int ot = 0; ot < NOUT; ++ot) {
-        // dA tile (rows = outputs, columns = faces) -> A operand [output][face]
+  for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) c.trA[(4 * q + i) * 16 + fl] = f2bf(dA[ot][ft][i]);
-        __builtin_amdgcn_wave_barrier();
-        const bf16x4 aop = ldA(c.trA, 16, 0, 0, lane);
-        __builtin_amdgcn_wave_barrier();
+    for (int it = 0; it < 4; ++it) g[ot][it] = mfma(aT[ot], hT[it], g[ot][it]);
+}
+
+// dH = W^T . dA for a 64 x 64 layer (W^T rows in LDS), masked by the ReLU
+// of the layer below.
+__device__ __forceinline__ void hidden_input_grad(const unsigned short* wT, const f32x4 (&dA)[4], unsigned int mask,
+                                                  f32x4 (&dB)[4], int lane) {
+  const s16x8 b0 = pack8(dA[0], dA[1]), b1 = pack8(dA[2], dA[3]);
 #pragma unroll
-        for (int it = 0; it < NIN; ++it) {
-          const bf16x4 hin = L == 0 ? A.x[it][ft] : A.h[L == 0 ? 0 : L - 1][it][ft];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) c.trH[(4 * q + i) * 16 + fl] = (unsigned short)hin[i];
-          __builtin_amdgcn_wave_barrier();
-          const bf16x4 bop = ldA(c.trH, 16, 0, 0, lane);  // B[face][input]
-          __builtin_amdgcn_wave_barrier();
-          gw[ot][it] = mfma(aop, bop, gw[ot][it]);
-        }
-      }
-    }
-  }
-  for (int w2 = 0; w2 < 4; ++w2) {
-    if (c.wv == w2 && c.live) {
-#pragma unroll
-      for (int ot = 0; ot < NOUT; ++ot) {
-#pragma unroll
-        for (int it = 0; it < NIN; ++it)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int o = ot * 16 + 4 * q + i, in = it * 16 + fl;
-            if (o < OUT_REAL && in < IN_REAL) c.gsum[GW + o * IN_REAL + in] += gw[ot][it][i];
-          }
-        if (fl == 0)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int o = ot * 16 + 4 * q + i;
-            if (o < OUT_REAL) c.gsum[GB + o] += gb[ot][i];
-          }
-      }
-    }
-    __syncthreads();
-  }
-  // input gradient: dH = W^T dA, then the ReLU mask of the layer below
-  f32x4 dH[NIN][4];
-#pragma unroll
-  for (int it = 0; it < NIN; ++it)
-#pragma unroll
-    for (int ft = 0; ft < 4; ++ft) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ot = 0; ot < NOUT; ++ot) {
-        const bf16x4 bop = pack4(dA[ot][ft][0], dA[ot][ft][1], dA[ot][ft][2], dA[ot][ft][3]);
-        acc = mfma(ldAT(W, LD, it * 16, ot * 16, lane), bop, acc);
-      }
-      dH[it][ft] = acc;
-    }
-  if (L > 0) {
-#pragma unroll
-    for (int it = 0; it < 4; ++it)
-#pragma unroll
-      for (int ft = 0; ft < 4; ++ft)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          dA[it][ft][i] = ((A.mask[L == 0 ? 0 : L - 1][ft] >> (it * 4 + i)) & 1u) ? dH[it < NIN ? it : 0][ft][i] : 0.f;
-  } else {
-#pragma unroll
-    for (int it = 0; it < 2; ++it)
-#pragma unroll
-      for (int ft = 0; ft < 4; ++ft) dX[it][ft] = dH[it][ft];
+  for (int it = 0; it < 4; ++it) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma32(ldA32(wT, 64, it * 16, 0, lane), b0, acc);
+    acc = mfma32(ldA32(wT, 64, it * 16, 1, lane), b1, acc);
+    dB[it] = relu_mask(acc, mask, it);
   }
 }
 
@@ -252,124 +210,227 @@ __device__ __forceinline__ void bwd_layer(const BwdCtx& c, const Acts& A, f32x4 
 // Reverse of the correction.  The upstream gradient of every face flux is
 // formed from the right-hand-side adjoint lam (scaled by clam_f * dt[b]), as
 // in the flux-difference transpose.  Writes the stencil gradient of every
-// face (dX[b][face][6][4], face frame, w.r.t. the primitive states) and adds
-// this block's parameter gradient to part[block][NET_NP] (fixed order).
+// face (dX[b][face][6][4], face frame, w.r.t. the primitive states) and this
+// block's parameter gradient to part[block][NET_NP].
+//
+// Each wave takes 16-face tiles of all batch members in a fixed order and
+// runs the network forward and backward on one tile at a time.  The weight
+// gradients of all four layers stay in the wave's MFMA accumulators for the
+// whole kernel (176 values per lane); the bias gradients are FP32 running
+// sums of each lane's own pre-activation gradients (52 per lane), summed
+// over the lanes of a row group at the end.  Then the four waves
+// add their sums in wave order: the result is reproducible bit for bit.  The
+// reverse products dH = W^T dA read a transposed copy of the weights.
 __global__ void __launch_bounds__(256) net_backward_kernel(GridArgs a, NetArgs n, const double* __restrict__ U,
                                                            const double* __restrict__ lam, double clam_f,
                                                            const double* __restrict__ dtp, float* __restrict__ dX,
                                                            float* __restrict__ part, long long nface) {
   __shared__ __attribute__((aligned(16))) unsigned short sw[NET_NW];
+  __shared__ __attribute__((aligned(16))) unsigned short swT[NET_NW];  // W0^T [32][64], W1^T, W2^T, W3^T [64][16]
   __shared__ float sb[NET_NB];
+  __shared__ __attribute__((aligned(16))) unsigned short tr[4][8 * 16 * TR_LD];
   __shared__ float gsum[NET_NP];
-  __shared__ __attribute__((aligned(16))) unsigned short tr[4][2][16 * 16];  // per wave: dA tile, H tile, [row][face]
   load_net_lds(n, sw, sb);
+  for (int k = threadIdx.x; k < NET_NW; k += blockDim.x) {
+    int src;
+    if (k < NET_OFF_W1) {
+      const int i = k / 64, o = k % 64;
+      src = NET_OFF_W0 + o * 32 + i;
+    } else if (k < NET_OFF_W3) {
+      const int base = k < NET_OFF_W2 ? NET_OFF_W1 : NET_OFF_W2, i = (k - base) / 64, o = (k - base) % 64;
+      src = base + o * 64 + i;
+    } else {
+      const int i = (k - NET_OFF_W3) / 16, o = (k - NET_OFF_W3) % 16;
+      src = NET_OFF_W3 + o * 64 + i;
+    }
+    swT[k] = n.w[src];
+  }
   for (int k = threadIdx.x; k < NET_NP; k += blockDim.x) gsum[k] = 0.f;
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane >> 4, fl = lane & 15;
-  const long long nxf = (long long)(a.nx + 1) * a.ny;
+  unsigned short* trw = tr[wv];
+  const int nxf = (a.nx + 1) * a.ny;
   const bool perx = a.bc[0] == BC_PERIODIC, pery = a.bc[2] == BC_PERIODIC;
-  const double* __restrict__ Lb = lam;
-  auto lam_at = [&](int v, int gi, int gj) -> double {
-    if (gi < 0 || gi >= a.nx) {
-      if (!perx) return 0.0;
-      gi = ((gi % a.nx) + a.nx) % a.nx;
-    }
-    if (gj < 0 || gj >= a.ny) {
-      if (!pery) return 0.0;
-      gj = ((gj % a.ny) + a.ny) % a.ny;
-    }
-    const long long c = (long long)gj * a.nx + gi;
-    if (a.cls != nullptr && a.cls[c] != CELL_FLUID) return 0.0;
-    return Lb[v * a.ncell + c];
-  };
-  unsigned short* trA = tr[wv][0];
-  unsigned short* trH = tr[wv][1];
-  // 64-face batches of all batch members, dealt to the blocks in a fixed
-  // order (every block runs the same number of rounds)
-  const long long per_b = (nface + 63) / 64;
+  f32x4 g0[4][2], g1[4][4], g2[4][4], g3[4];
+  f32x4 bs0[4], bs1[4], bs2[4], bs3;  // bias sums of the lane's own faces: [neuron tile] rows 4q..4q+3
+  bs3 = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) bs0[ot] = bs1[ot] = bs2[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) {
+    g3[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int it = 0; it < 4; ++it) g1[ot][it] = g2[ot][it] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int it = 0; it < 2; ++it) g0[ot][it] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  const long long per_b = (nface + 15) / 16;
   const long long total = per_b * a.nbatch;
-  for (long long g0 = (long long)blockIdx.x * 4; g0 < total; g0 += (long long)gridDim.x * 4) {
-    const long long gb = g0 + wv;
-    const bool live = gb < total;
-    const int b = live ? (int)(gb / per_b) : 0;
-    const long long base = live ? (gb % per_b) * 64 : 0;
+  for (long long t = (long long)blockIdx.x * 4 + wv; t < total; t += (long long)gridDim.x * 4) {
+    const int b = (int)(t / per_b);
+    const long long f = (t % per_b) * 16 + fl;
+    const bool fok = f < nface;
+    const long long fc = fok ? f : nface - 1;
     const double* __restrict__ Ub = U + (long long)b * 4 * a.ncell;
-    Lb = lam + (long long)b * 4 * a.ncell;
-    const double clam = clam_f * (dtp ? dtp[b] : 1.0);
-    Acts A;
-    f32x4 z[4];
-    float Fb[4][4];
-    for (int ft = 0; ft < 4; ++ft)
-      for (int i = 0; i < 4; ++i) Fb[ft][i] = 0.f;
-    if (live) {
-      for (int ft = 0; ft < 4; ++ft) {
-        long long f = base + ft * 16 + fl;
-        if (f >= nface) f = nface - 1;
-        build_inputs(a, n, Ub, f, lane, A.x[0][ft], A.x[1][ft]);
+    const double* __restrict__ Lb = lam + (long long)b * 4 * a.ncell;
+    // the adjoint of the two cells beside the face (zero outside the domain
+    // unless periodic, and in solid cells)
+    auto lam_cell = [&](int gi, int gj, double l[4]) {
+      bool ok = true;
+      if (gi < 0 || gi >= a.nx) {
+        ok = perx;
+        gi += gi < 0 ? a.nx : -a.nx;
       }
-      net_forward_batch(sw, sb, lane, A, z);
-      // upstream gradient of the face fluxes (face frame), lanes q == 0
-      for (int ft = 0; ft < 4; ++ft) {
-        const long long f = base + ft * 16 + fl;
-        for (int i = 0; i < 4; ++i) Fb[ft][i] = 0.f;
-        if (q != 0 || f >= nface) continue;
-        double fb[4];
-        if (f < nxf) {
-          const int gj = (int)(f / (a.nx + 1)), gf = (int)(f % (a.nx + 1));
-          const double sc = clam * a.inv_dx;
-          fb[0] = sc * (lam_at(0, gf, gj) - lam_at(0, gf - 1, gj));
-          fb[1] = sc * (lam_at(1, gf, gj) - lam_at(1, gf - 1, gj));
-          fb[2] = sc * (lam_at(2, gf, gj) - lam_at(2, gf - 1, gj));
-          fb[3] = sc * (lam_at(3, gf, gj) - lam_at(3, gf - 1, gj));
-        } else {
-          const long long g = f - nxf;
-          const int gf = (int)(g / a.nx), gi = (int)(g % a.nx);
-          const double sc = clam * a.inv_dy;
-          fb[0] = sc * (lam_at(0, gi, gf) - lam_at(0, gi, gf - 1));
-          fb[1] = sc * (lam_at(2, gi, gf) - lam_at(2, gi, gf - 1));
-          fb[2] = sc * (lam_at(1, gi, gf) - lam_at(1, gi, gf - 1));
-          fb[3] = sc * (lam_at(3, gi, gf) - lam_at(3, gi, gf - 1));
-        }
-        for (int i = 0; i < 4; ++i) {
-          const float t = tanhf(z[ft][i]);
-          Fb[ft][i] = float(fb[i]) * n.out_scale * (1.f - t * t);
+      if (gj < 0 || gj >= a.ny) {
+        ok = ok && pery;
+        gj += gj < 0 ? a.ny : -a.ny;
+      }
+      const int c = gj * a.nx + gi;
+      if (ok && a.cls != nullptr) ok = a.cls[c] == CELL_FLUID;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) l[v] = ok ? Lb[(long long)v * a.ncell + c] : 0.0;
+    };
+    // upstream gradient of the face flux (face frame), lanes q == 0; loaded
+    // before the forward so the loads overlap it
+    double fb[4] = {0.0, 0.0, 0.0, 0.0};
+    if (q == 0 && fok) {
+      const double clam = clam_f * (dtp ? dtp[b] : 1.0);
+      const int fi = (int)f;
+      double lo[4], hi[4];
+      if (fi < nxf) {
+        const int gj = fi / (a.nx + 1), gf = fi - gj * (a.nx + 1);
+        lam_cell(gf - 1, gj, lo);
+        lam_cell(gf, gj, hi);
+        const double sc = clam * a.inv_dx;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) fb[v] = sc * (hi[v] - lo[v]);
+      } else {
+        const int g = fi - nxf, gf = g / a.nx, gi = g - gf * a.nx;
+        lam_cell(gi, gf - 1, lo);
+        lam_cell(gi, gf, hi);
+        const double sc = clam * a.inv_dy;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int vy = v == 1 ? 2 : (v == 2 ? 1 : v);
+          fb[v] = sc * (hi[vy] - lo[vy]);
         }
       }
     }
-    // reverse layer by layer; dA holds the gradient w.r.t. the current layer's
-    // pre-activations (D layout)
-    f32x4 dA[4][4];  // [neuron tile][face tile]
+    ActsT<1> A;
+    f32x4 z[1];
+    build_inputs(a, n, Ub, fc, lane, A.x[0][0], A.x[1][0]);
+    net_forward_batch<1>(sw, sb, lane, A, z);
+    f32x4 d3 = {0.f, 0.f, 0.f, 0.f};
+    if (q == 0)
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+      for (int i = 0; i < 4; ++i) {
+        const float th = tanhf(z[0][i]);
+        d3[i] = float(fb[i]) * n.out_scale * (1.f - th * th);
+      }
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    f32x4 dA[4], dB[4];
+    // output layer (16 rows, 4 used): weight and bias gradient, then dH2
+    {
+      const bf16x4 aT = transpose_f(trw, d3, lane);
 #pragma unroll
-      for (int ft = 0; ft < 4; ++ft) dA[nt][ft] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int it = 0; it < 4; ++it)
+        g3[it] = mfma(aT, transpose_bf(trw + (4 + it) * 16 * TR_LD, A.h[2][it][0], lane), g3[it]);
+      bs3 += d3;
+      const bf16x4 b3 = pack4(d3[0], d3[1], d3[2], d3[3]);
 #pragma unroll
-    for (int ft = 0; ft < 4; ++ft)
-      if (q == 0) dA[0][ft] = f32x4{Fb[ft][0], Fb[ft][1], Fb[ft][2], Fb[ft][3]};
-    BwdCtx c{sw, gsum, trA, trH, lane, wv, live};
-    bwd_layer<3>(c, A, dA);
-    bwd_layer<2>(c, A, dA);
-    bwd_layer<1>(c, A, dA);
-    f32x4 dXt[2][4];
-    bwd_layer<0>(c, A, dA, dXt);
-    if (live) {
-      // stencil gradient: input 4*(it*4+q)+i = cell it*4+q, variable i
+      for (int it = 0; it < 4; ++it)
+        dA[it] = relu_mask(mfma(ldA(swT + NET_OFF_W3, 16, it * 16, 0, lane), b3, zero), A.mask[2][0], it);
+    }
+    hidden_grad(trw, dA, A.h[1], g2, lane);
 #pragma unroll
-      for (int ft = 0; ft < 4; ++ft) {
-        const long long f = base + ft * 16 + fl;
-        if (f >= nface) continue;
+    for (int ot = 0; ot < 4; ++ot) bs2[ot] += dA[ot];
+    hidden_input_grad(swT + NET_OFF_W2, dA, A.mask[1][0], dB, lane);
+    hidden_grad(trw, dB, A.h[0], g1, lane);
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) bs1[ot] += dB[ot];
+    hidden_input_grad(swT + NET_OFF_W1, dB, A.mask[0][0], dA, lane);
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) bs0[ot] += dA[ot];
+    // first layer (inputs 0..23; 24..31 are zero padding)
+    {
+      bf16x4 aT[4];
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot) aT[ot] = transpose_f(trw + ot * 16 * TR_LD, dA[ot], lane);
+      const bf16x4 xT0 = transpose_bf(trw + 4 * 16 * TR_LD, A.x[0][0], lane);
+      const bf16x4 xT1 = transpose_bf(trw + 5 * 16 * TR_LD, A.x[1][0], lane);
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot) {
+        g0[ot][0] = mfma(aT[ot], xT0, g0[ot][0]);
+        g0[ot][1] = mfma(aT[ot], xT1, g0[ot][1]);
+      }
+      // stencil gradient dX = W0^T dA (every lane takes part in the products;
+      // the stores are masked)
+      const s16x8 b0 = pack8(dA[0], dA[1]), b1 = pack8(dA[2], dA[3]);
+      f32x4 dx[2];
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        dx[it] = mfma32(ldA32(swT + NET_OFF_W0, 64, it * 16, 0, lane), b0, zero);
+        dx[it] = mfma32(ldA32(swT + NET_OFF_W0, 64, it * 16, 1, lane), b1, dx[it]);
+      }
+      if (fok) {
         float* out = dX + ((long long)b * nface + f) * 24;
 #pragma unroll
         for (int it = 0; it < 2; ++it) {
+          // input 4*(it*4+q)+i = stencil cell it*4+q, variable i
           const int cell = it * 4 + q;
-          if (cell >= 6) continue;
+          if (cell < 6)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) out[cell * 4 + i] = dXt[it][ft][i] * float(n.inv_std[i]);
+            for (int i = 0; i < 4; ++i) out[cell * 4 + i] = dx[it][i] * float(n.inv_std[i]);
         }
       }
     }
   }
-  __syncthreads();
+  // the waves' sums into the block's, in wave order
+  for (int w2 = 0; w2 < 4; ++w2) {
+    if (wv == w2) {
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int o = ot * 16 + 4 * q + i;
+#pragma unroll
+          for (int it = 0; it < 4; ++it) {
+            const int in = it * 16 + fl;
+            gsum[NET_G_W1 + o * 64 + in] += g1[ot][it][i];
+            gsum[NET_G_W2 + o * 64 + in] += g2[ot][it][i];
+          }
+#pragma unroll
+          for (int it = 0; it < 2; ++it) {
+            const int in = it * 16 + fl;
+            if (in < 24) gsum[NET_G_W0 + o * 24 + in] += g0[ot][it][i];
+          }
+        }
+      if (q == 0)
+#pragma unroll
+        for (int it = 0; it < 4; ++it)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) gsum[NET_G_W3 + i * 64 + it * 16 + fl] += g3[it][i];
+      // bias sums: the 16 faces of a row group, then lanes fl == 0 add
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int o = ot * 16 + 4 * q + i;
+          const float s0 = face_sum16(bs0[ot][i]), s1 = face_sum16(bs1[ot][i]), s2 = face_sum16(bs2[ot][i]);
+          if (fl == 0) {
+            gsum[NET_G_B0 + o] += s0;
+            gsum[NET_G_B1 + o] += s1;
+            gsum[NET_G_B2 + o] += s2;
+          }
+        }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float s3 = face_sum16(bs3[i]);
+        if (q == 0 && fl == 0) gsum[NET_G_B3 + i] += s3;
+      }
+    }
+    __syncthreads();
+  }
   float* pb = part + (long long)blockIdx.x * NET_NP;
   for (int k = threadIdx.x; k < NET_NP; k += blockDim.x) pb[k] = gsum[k];
 }
@@ -505,14 +566,15 @@ static unsigned int net_blocks(long long nface) {
 // Reverse pass: 64-face batches of all members over at most NET_BWD_BLOCKS
 // workgroups (one parameter partial each).
 unsigned int net_backward_blocks(const GridArgs& a) {
-  const long long batches = (net_face_count(a) + 63) / 64 * a.nbatch;
-  long long nb = (batches + 3) / 4;
+  const long long tiles = (net_face_count(a) + 15) / 16 * a.nbatch;
+  long long nb = (tiles + 3) / 4;
   if (nb > NET_BWD_BLOCKS) nb = NET_BWD_BLOCKS;
   return (unsigned int)(nb < 1 ? 1 : nb);
 }
 
 hipError_t launch_net_forward(const GridArgs& a, const NetArgs& n, const double* U, float* dF, hipStream_t st) {
   const long long nf = net_face_count(a);
+  if (nf > 0x7fffffffLL) return hipErrorInvalidValue;  // faces of a batch member are indexed in 32 bits
   hipLaunchKernelGGL(net_forward_kernel, dim3(net_blocks(nf), a.nbatch), dim3(256), 0, st, a, n, U, dF, nf);
   return hipGetLastError();
 }
@@ -520,6 +582,7 @@ hipError_t launch_net_forward(const GridArgs& a, const NetArgs& n, const double*
 hipError_t launch_net_backward(const GridArgs& a, const NetArgs& n, const double* U, const double* lam, double clam_f,
                                const double* dtp, float* dX, float* part, float* grad, hipStream_t st) {
   const long long nf = net_face_count(a);
+  if (nf > 0x7fffffffLL) return hipErrorInvalidValue;  // faces of a batch member are indexed in 32 bits
   const unsigned int nb = net_backward_blocks(a);
   hipLaunchKernelGGL(net_backward_kernel, dim3(nb), dim3(256), 0, st, a, n, U, lam, clam_f, dtp, dX, part, nf);
   hipError_t e = hipGetLastError();

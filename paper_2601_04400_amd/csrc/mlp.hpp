@@ -17,7 +17,9 @@ constexpr int NET_OFF_W0 = 0, NET_OFF_W1 = 2048, NET_OFF_W2 = 6144, NET_OFF_W3 =
 constexpr int NET_OFF_B0 = 0, NET_OFF_B1 = 64, NET_OFF_B2 = 128, NET_OFF_B3 = 192, NET_NB = 208;
 
 
-constexpr int NET_BWD_BLOCKS = 512;  // workgroups (and parameter partials) of the reverse pass
+// workgroups (and parameter partials) of the reverse pass: one per compute
+// unit (its registers and LDS allow one workgroup per unit)
+constexpr int NET_BWD_BLOCKS = 256;
 
 long long net_face_count(const GridArgs& a);
 unsigned int net_backward_blocks(const GridArgs& a);

@@ -28,6 +28,9 @@ class Grid:
                  cfl=0.5, weno_eps=1e-6, viscous=False, mu=0.0, prandtl=0.72, nu_art=0.0,
                  bc=(TRANSMISSIVE,) * 4, inflow=(1.0, 0.0, 0.0, 1.0), ibm=False, adjoint=False,
                  flux_net=False, device="cuda"):
+        self._args = dict(nx=nx, ny=ny, ndim=ndim, nbatch=nbatch, domain=domain, prec=prec, gamma=gamma, cfl=cfl,
+                          weno_eps=weno_eps, viscous=viscous, mu=mu, prandtl=prandtl, nu_art=nu_art, bc=bc,
+                          inflow=inflow, ibm=ibm, adjoint=adjoint, flux_net=flux_net, device=device)
         d = GridDesc()
         d.ndim, d.nx, d.ny, d.nbatch = ndim, nx, (1 if ndim == 1 else ny), nbatch
         d.x0, d.x1 = domain[0], domain[1]
@@ -55,7 +58,10 @@ class Grid:
               None, "init_grid")
         self.handle = h
         self.phi = None
+        self.wall = 0
         self.net = None
+        self.version = 0  # bumped by a new level set or network (see replica)
+        self._replica = None
         self.nface = (nx + 1) * d.ny + nx * (d.ny + 1)
 
     def __del__(self):
@@ -93,6 +99,7 @@ class Grid:
         return U
 
     def set_levelset(self, phi, wall=0):
+        self.version += 1
         if phi is None:
             check(lib().shk_set_ib_levelset(self.handle, None, 0), self.handle, "set_ib_levelset")
             self.phi = None
@@ -101,6 +108,7 @@ class Grid:
         if phi.numel() != self.desc.nx * self.desc.ny:
             raise ValueError("level set must have ny*nx entries")
         self.phi = phi  # the table is built from it; keep it alive
+        self.wall = int(wall)
         self._sync_stream()
         check(lib().shk_set_ib_levelset(self.handle, _ptr(phi), int(wall)), self.handle, "set_ib_levelset")
         n = ctypes.c_int()
@@ -133,6 +141,7 @@ class Grid:
     # -- learned flux correction
     def set_flux_net(self, net):
         """Attach a learn.FluxNet (its device buffers must stay alive) or None."""
+        self.version += 1
         if net is None:
             check(lib().shk_set_flux_net(self.handle, None, None, None, 0.0, 0), self.handle, "set_flux_net")
             self.net = None
@@ -251,6 +260,44 @@ class Grid:
         if inflow is not None:
             for k in range(4):
                 self.desc.inflow_prim[k] = float(inflow[k])
+
+    def replica(self):
+        """A second grid with this one's description, immersed boundary,
+        physical parameters and network, but its own workspace and HIP stream
+        (default priority): fixed-step replays issued on it run concurrently
+        with this grid's work.  Cached: rebuilt after a new level set or
+        network, given this grid's gamma and inflow state on every call."""
+        d = self.desc
+        gamma, inflow = d.gamma, tuple(d.inflow_prim[k] for k in range(4))
+        r = self._replica
+        if r is not None and r[0] == self.version:
+            g = r[1]
+            if g.desc.gamma != gamma or tuple(g.desc.inflow_prim[k] for k in range(4)) != inflow:
+                g.set_params(gamma, inflow)
+            return g, r[2]
+        args = dict(self._args, gamma=gamma, inflow=inflow)
+        side = torch.cuda.Stream(device=self.device)
+        with torch.cuda.stream(side):
+            g = Grid(**args)
+            if self.phi is not None:
+                g.set_levelset(self.phi, self.wall)
+            if self.net is not None:
+                g.set_flux_net(self.net)
+        side.synchronize()
+        self._replica = (self.version, g, side)
+        return g, side
+
+    def replay_buffers(self, nsteps):
+        """Two tape buffers of nsteps recorded steps and a work state for
+        replays on the replica, kept for later backward passes (no
+        allocation, and no deferred frees across streams, per pass)."""
+        shape = (nsteps, 3) + tuple(self.shape)
+        b = getattr(self, "_replay_bufs", None)
+        if b is None or tuple(b[0][0].shape) != shape:
+            self._replay_bufs = None
+            tapes = [torch.empty(shape, dtype=torch.float64, device=self.device) for _ in range(2)]
+            self._replay_bufs = (tapes, torch.empty(self.shape, dtype=torch.float64, device=self.device))
+        return self._replay_bufs
 
     def set_time(self, t0, t_end):
         self._sync_stream()

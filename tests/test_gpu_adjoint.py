@@ -10,7 +10,9 @@
   oracle's forward-mode tangent: 1e-9;
 * the full-size case (256^2, 200 steps, checkpoints every 20) against
   central finite differences with h = 1e-6: 1e-6, and bit-for-bit
-  reproducibility of the adjoint.
+  reproducibility of the adjoint;
+* the backward with segment replays on a replica grid and second stream
+  equals the serial backward bit for bit (also after a parameter change).
 """
 import numpy as np
 import pytest
@@ -282,6 +284,40 @@ def test_shock_cylinder_sensitivity_vs_oracle_tangent(orc):
     assert abs(Jg - Jo) <= 1e-10 * abs(Jo)
     assert abs(dMg - dMo) <= 1e-9 * abs(dMo), (dMg, dMo)
     assert abs(dgg - dgo) <= 1e-9 * abs(dgo), (dgg, dgo)
+
+
+def test_overlapped_replay_equals_serial_backward():
+    """Replays on the replica grid (second stream, two tape buffers) give the
+    serial backward's gradients bit for bit: 96^2, 30 steps, checkpoints
+    every 7 (five segments, the last one ragged); then again after
+    set_params changed gamma, which must rebuild the replica."""
+    from paper_2601_04400_amd import Grid, normal_shock_state
+    from paper_2601_04400_amd.adjoint import rollout
+    n, steps, dt, every = 96, 30, 1.2e-3, 7
+    dom, phi = c3_setup(n, n)
+    post, _, _ = normal_shock_state(3.0)
+    inflow = (post[0], post[1], 0.0, post[2])
+    g = Grid(n, n, domain=dom, bc=(2, 0, 1, 1), inflow=inflow, ibm=True, adjoint=True)
+    g.set_levelset(torch.from_numpy(phi), wall=0)
+    W = torch.from_numpy(inputs.shock_prim(n, n, dom, 0.1, inflow, (1.4, 0.0, 0.0, 1.0)))
+    w = torch.from_numpy(np.random.default_rng(3).normal(size=(1, 4, n, n))).cuda()
+
+    def grads(gamma, overlap):
+        U0 = g.prim_to_cons(W)
+        U0.requires_grad_(True)
+        params = torch.tensor([[gamma, *inflow]], dtype=torch.float64, device="cuda", requires_grad=True)
+        U = rollout(g, U0, params, steps, dt, every, overlap=overlap)
+        (U * w).sum().backward()
+        return to_np(U0.grad), to_np(params.grad)
+
+    for gamma in (1.4, 1.5):
+        if gamma != 1.4:
+            g.set_params(gamma)
+        us, ps = grads(gamma, False)
+        uo, po = grads(gamma, True)
+        assert np.isfinite(us).all() and np.abs(ps).max() > 0
+        assert np.array_equal(us, uo) and np.array_equal(ps, po), gamma
+        assert g.replica()[0].desc.gamma == gamma
 
 
 def test_shock_cylinder_full_size_adjoint_vs_finite_differences():
