@@ -45,6 +45,12 @@ def lib():
         _lib.orc_net_destroy.argtypes = [_p]
         _lib.orc_net_forward.argtypes = [_p, _i, _p, _p]
         _lib.orc_net_backward.argtypes = [_p, _i, _p, _p, _p, _p]
+        _lib.orc_cnn_create.restype = _p
+        _lib.orc_cnn_create.argtypes = [_p, _p, _p, _d, _i]
+        _lib.orc_cnn_destroy.argtypes = [_p]
+        _lib.orc_cnn_forward.argtypes = [_p, _i, _i, _i, _i, _p, _p]
+        _lib.orc_cnn_backward.argtypes = [_p, _i, _i, _i, _i, _p, _p, _p, _p]
+        _lib.orc_cnn_images.argtypes = [_p, _p, _p, _i, _p, _p, _p]
     return _lib
 
 
@@ -290,3 +296,57 @@ class Net:
         dst = np.empty_like(st)
         lib().orc_net_backward(_p(self.handle), _i(st.shape[0]), _ptr(st), _ptr(dFbar), _ptr(g), _ptr(dst))
         return g, dst
+
+
+CNN_PARAMS = 6388
+
+
+class Cnn:
+    """The convolutional learned correction (section 2's 2D form), evaluated
+    in double precision with optional bfloat16 rounding of every product
+    operand.  Pass it as `net` to rhs / rk3_step / the Jacobians."""
+
+    def __init__(self, params, mean, inv_std, out_scale, emulate_bf16=True):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == CNN_PARAMS
+        self._keep = (p, _arr(mean, (4,)), _arr(inv_std, (4,)))
+        self.handle = lib().orc_cnn_create(_ptr(p), _ptr(self._keep[1]), _ptr(self._keep[2]),
+                                           _d(out_scale), _i(1 if emulate_bf16 else 0))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.orc_cnn_destroy(_p(self.handle))
+            self.handle = None
+
+    def forward(self, x, wrap=(False, False)):
+        """x: normalised inputs [H][W][4] -> corrections [H][W][4]; wrap:
+        (rows, columns) periodic."""
+        x = _arr(x)
+        H, W = x.shape[:2]
+        out = np.empty((H, W, 4))
+        lib().orc_cnn_forward(_p(self.handle), _i(H), _i(W), _i(int(wrap[0])), _i(int(wrap[1])), _ptr(x), _ptr(out))
+        return out
+
+    def backward(self, x, dout, wrap=(False, False)):
+        """(parameter gradient, input gradient) for upstream gradient dout."""
+        x, dout = _arr(x), _arr(dout)
+        H, W = x.shape[:2]
+        g = np.zeros(CNN_PARAMS)
+        dx = np.empty((H, W, 4))
+        lib().orc_cnn_backward(_p(self.handle), _i(H), _i(W), _i(int(wrap[0])), _i(int(wrap[1])), _ptr(x),
+                               _ptr(dout), _ptr(g), _ptr(dx))
+        return g, dx
+
+
+def cnn_images(c, U, net, phi=None, wall=0):
+    """The convolutional network's input images of state U: x-faces
+    [ny][wx][4] and transposed y-faces [nx][wy][4] (wx = nx + 1, or nx when x
+    is periodic; likewise wy)."""
+    U = _arr(U)
+    wx = c.nx if c.bc[0] == 3 else c.nx + 1
+    wy = c.ny if c.bc[2] == 3 else c.ny + 1
+    Xx = np.empty((c.ny, wx, 4))
+    Xy = np.empty((c.nx, wy, 4))
+    assert lib().orc_cnn_images(ctypes.byref(c), _ptr(U), _ptr(_phi(c, phi)), _i(wall), _p(net.handle),
+                                _ptr(Xx), _ptr(Xy)) == 0
+    return Xx, Xy

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <new>
 
+#include "cnn.hpp"
 #include "exact_riemann.hpp"
 #include "mlp.hpp"
 #include "solver.hpp"
@@ -27,11 +28,15 @@ bool config_ok(const Config* c) {
   return true;
 }
 
-const FluxNet* as_net(const void* p) { return static_cast<const FluxNet*>(p); }
+// Correction handles cross the C boundary as the Correction* the create
+// functions return (cast to void*).
+const Correction* as_net(const void* p) { return static_cast<const Correction*>(p); }
+const FluxNet* as_mlp(const void* p) { return static_cast<const FluxNet*>(as_net(p)); }
+const FluxCnn* as_cnn(const void* p) { return static_cast<const FluxCnn*>(as_net(p)); }
 
 template <class T>
 void run_rhs(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f, Field<T>& L,
-             const FluxNet* net, long* fb) {
+             const Correction* net, long* fb) {
   ibm_fill(c, P, ib, f);
   rhs(c, P, ib, f, L, net, fb);
 }
@@ -350,10 +355,10 @@ void* orc_net_create(const float* params, const double* mean4, const double* inv
   for (int k = 0; k < 4; ++k) { n->mean[k] = mean4[k]; n->inv_std[k] = inv_std4[k]; }
   n->out_scale = out_scale;
   n->emulate_bf16 = emulate_bf16 != 0;
-  return n;
+  return static_cast<Correction*>(n);
 }
 
-void orc_net_destroy(void* n) { delete static_cast<FluxNet*>(n); }
+void orc_net_destroy(void* n) { delete static_cast<FluxNet*>(static_cast<Correction*>(n)); }
 
 int orc_net_param_count() {
   return NET_HID * NET_IN + NET_HID + 2 * (NET_HID * NET_HID + NET_HID) + NET_OUT * NET_HID + NET_OUT;
@@ -364,7 +369,7 @@ void orc_net_forward(const void* net, int nface, const double* st, double* dF) {
     double s[6][4];
     for (int a = 0; a < 6; ++a)
       for (int v = 0; v < 4; ++v) s[a][v] = st[(size_t(f) * 6 + a) * 4 + v];
-    flux_net_apply(as_net(net), s, dF + size_t(f) * 4);
+    flux_net_apply(as_mlp(net), s, dF + size_t(f) * 4);
   }
 }
 
@@ -374,11 +379,70 @@ void orc_net_backward(const void* net, int nface, const double* st, const double
     double s[6][4], d[6][4];
     for (int a = 0; a < 6; ++a)
       for (int v = 0; v < 4; ++v) s[a][v] = st[(size_t(f) * 6 + a) * 4 + v];
-    flux_net_backward(*as_net(net), s, dFbar + size_t(f) * 4, g, d);
+    flux_net_backward(*as_mlp(net), s, dFbar + size_t(f) * 4, g, d);
     if (dst)
       for (int a = 0; a < 6; ++a)
         for (int v = 0; v < 4; ++v) dst[(size_t(f) * 6 + a) * 4 + v] = d[a][v];
   }
+}
+
+// ------------------------------------------------------- convolutional net
+// Parameters in the order W1 [16][3][3][4], b1, W2 [32][3][3][16], b2,
+// W3 [4][3][3][32], b3 (6388 values); mean4 / inv_std4 normalise the
+// conservative face inputs.
+void* orc_cnn_create(const float* params, const double* mean4, const double* inv_std4, double out_scale,
+                     int emulate_bf16) {
+  FluxCnn* n = new (std::nothrow) FluxCnn;
+  if (!n) return nullptr;
+  const float* p = params;
+  auto take = [&](std::vector<double>& v, size_t k) { v.assign(p, p + k); p += k; };
+  take(n->W1, 16 * 9 * 4); take(n->b1, 16);
+  take(n->W2, 32 * 9 * 16); take(n->b2, 32);
+  take(n->W3, 4 * 9 * 32); take(n->b3, 4);
+  for (int k = 0; k < 4; ++k) { n->mean[k] = mean4[k]; n->inv_std[k] = inv_std4[k]; }
+  n->out_scale = out_scale;
+  n->emulate_bf16 = emulate_bf16 != 0;
+  return static_cast<Correction*>(n);
+}
+
+void orc_cnn_destroy(void* n) { delete static_cast<FluxCnn*>(static_cast<Correction*>(n)); }
+
+int orc_cnn_param_count() { return CNN_PARAMS; }
+
+// The convolutional network's input images of state U (2D): Xx [ny][wx][4]
+// and Xy [nx][wy][4] (y-faces transposed), normalised with net's map; wx is
+// nx + 1, or nx when x is periodic (likewise wy).
+int orc_cnn_images(const Config* c, const double* U, const double* phi, int wall, const void* net, double* Xx,
+                   double* Xy) {
+  if (!config_ok(c) || c->ndim != 2 || !net || as_net(net)->kind != CORR_CNN) return 1;
+  Ibm ib = build_ibm(*c, phi, wall);
+  Params<double> P = params_from<double>(*c);
+  Field<double> f(c->nx, c->ny), L(c->nx, c->ny);
+  load_state(*c, U, f);
+  ibm_fill(*c, P, ib, f);
+  std::vector<double> im[2];
+  rhs(*c, P, ib, f, L, as_net(net), nullptr, im);
+  std::copy(im[0].begin(), im[0].end(), Xx);
+  std::copy(im[1].begin(), im[1].end(), Xy);
+  return 0;
+}
+
+// One image [H][W][4] of normalised inputs -> corrections [H][W][4];
+// wrap_r / wrap_c: the rows / columns are periodic.
+void orc_cnn_forward(const void* net, int H, int W, int wrap_r, int wrap_c, const double* x, double* out) {
+  std::vector<double> xv(x, x + size_t(H) * W * 4), o;
+  const bool wrap[2] = {wrap_r != 0, wrap_c != 0};
+  cnn_apply(*as_cnn(net), xv, H, W, wrap, o);
+  std::copy(o.begin(), o.end(), out);
+}
+
+// Reverse of one image: g += parameter gradient, dx = input gradient.
+void orc_cnn_backward(const void* net, int H, int W, int wrap_r, int wrap_c, const double* x, const double* dOut,
+                      double* g, double* dx) {
+  std::vector<double> xv(x, x + size_t(H) * W * 4), dv(dOut, dOut + size_t(H) * W * 4), d;
+  const bool wrap[2] = {wrap_r != 0, wrap_c != 0};
+  cnn_backward(*as_cnn(net), xv, H, W, wrap, dv, g, d);
+  if (dx) std::copy(d.begin(), d.end(), dx);
 }
 
 }  // extern "C"

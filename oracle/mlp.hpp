@@ -16,6 +16,7 @@
 #include <cstring>
 #include <vector>
 
+#include "correction.hpp"
 #include "dual.hpp"
 
 namespace orc {
@@ -24,7 +25,8 @@ using std::tanh;
 
 constexpr int NET_IN = 24, NET_HID = 64, NET_OUT = 4;
 
-struct FluxNet {
+struct FluxNet : Correction {
+  FluxNet() { kind = CORR_MLP; }
   // Row-major weights: W0 [64][24], W1 [64][64], W2 [64][64], W3 [4][64].
   std::vector<double> W0, W1, W2, W3, b0, b1, b2, b3;
   double mean[4] = {0, 0, 0, 0}, inv_std[4] = {1, 1, 1, 1};

@@ -28,6 +28,7 @@
 #include <cstring>
 #include <vector>
 
+#include "correction.hpp"
 #include "dual.hpp"
 
 namespace orc {
@@ -403,19 +404,26 @@ void ibm_fill(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f) {
 }
 
 // ------------------------------------------------------------- face fluxes
-// Optional learned correction hook: dF = net(stencil) added to the HLLC flux.
-// The stencil is 6 cells x (rho, u_n, u_t, p) in the face-normal frame; the
-// returned correction is in the same frame.
+// Optional learned correction hooks (correction.hpp tags which one): the
+// per-face network dF = net(stencil), stencil = 6 cells x (rho, u_n, u_t, p)
+// in the face-normal frame, or the convolutional network over the images of
+// x-faces and (transposed) y-faces; either correction is in the face frame
+// and is added to the HLLC flux.
 struct FluxNet;  // defined in mlp.hpp
 template <class T>
 void flux_net_apply(const FluxNet* net, const T stencil[6][4], T dF[4]);
+struct FluxCnn;  // defined in cnn.hpp
+template <class T>
+void cnn_apply(const FluxCnn& n, const std::vector<T>& x, int H, int Wd, const bool wrap[2], std::vector<T>& out);
+template <class T>
+T cnn_norm(const FluxCnn* n, int v, const T& x);  // (x - mean[v]) * inv_std[v]
 
 // Numerical flux across one face.  Wst holds the 6 primitive cell states
 // i-2..i+3 along the face normal, already rotated so that component 1 is the
 // normal velocity and component 2 the tangential one.
 template <class T>
 void face_flux(const Config& c, const Params<T>& P, const T Wst[6][4], const FluxNet* net,
-               T F[4], long* fallback_count) {
+               T F[4], long* fallback_count, T* WLout = nullptr, T* WRout = nullptr) {
   T WL[4], WR[4];
   for (int v = 0; v < 4; ++v) {
     T f5[5] = {Wst[0][v], Wst[1][v], Wst[2][v], Wst[3][v], Wst[4][v]};
@@ -429,6 +437,8 @@ void face_flux(const Config& c, const Params<T>& P, const T Wst[6][4], const Flu
     for (int v = 0; v < 4; ++v) { WL[v] = Wst[2][v]; WR[v] = Wst[3][v]; }
     if (fallback_count) ++*fallback_count;
   }
+  if (WLout)
+    for (int v = 0; v < 4; ++v) { WLout[v] = WL[v]; WRout[v] = WR[v]; }
   hllc_x(WL, WR, P.gamma, F);
   if (net) {
     T dF[4];
@@ -473,7 +483,9 @@ void viscous_face(const Config& c, const T& gamma,
 // cells.  Each face flux is computed once, so the update telescopes exactly.
 template <class T>
 void rhs(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f, Field<T>& L,
-         const FluxNet* net, long* fallback_count) {
+         const Correction* corr, long* fallback_count, std::vector<T>* images = nullptr) {
+  const FluxNet* net = corr && corr->kind == CORR_MLP ? reinterpret_cast<const FluxNet*>(corr) : nullptr;
+  const FluxCnn* cnn = corr && corr->kind == CORR_CNN ? reinterpret_cast<const FluxCnn*>(corr) : nullptr;
   apply_bc(c, P, f);
   const int nx = c.nx, ny = c.ny;
   const double dx = dx_of(c), dy = dy_of(c);
@@ -491,12 +503,26 @@ void rhs(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f, Field<
 
   // x-faces: face index fi = 0..nx is the left face of cell fi.
   std::vector<T> Fx(size_t(4) * (nx + 1) * ny), Fy;
+  // inputs of the convolutional correction: per face, the normalised
+  // conservative mean of the two reconstructed states (face frame)
+  // (a periodic axis holds each face once: the last face is the first)
+  const bool perx = c.bc[0] == BC_PERIODIC, pery = c.ndim == 2 && c.bc[2] == BC_PERIODIC;
+  const int wx = perx ? nx : nx + 1, wy = pery ? ny : ny + 1;
+  std::vector<T> Xx, Xy;
+  if (cnn) Xx.resize(size_t(4) * wx * ny);
+  auto cnn_input = [&](const T WL[4], const T WR[4], T* x) {
+    T UL[4], UR[4];
+    prim_to_cons(WL, P.gamma, UL);
+    prim_to_cons(WR, P.gamma, UR);
+    for (int v = 0; v < 4; ++v) x[v] = cnn_norm(cnn, v, T(0.5) * (UL[v] + UR[v]));
+  };
   for (int j = 0; j < ny; ++j)
     for (int fi = 0; fi <= nx; ++fi) {
       T st[6][4];
       for (int s = 0; s < 6; ++s) Wat(fi - 3 + s, j, st[s]);
-      T F[4];
-      face_flux(c, P, st, net, F, fallback_count);
+      T F[4], WL[4], WR[4];
+      face_flux(c, P, st, net, F, fallback_count, WL, WR);
+      if (cnn && fi < wx) cnn_input(WL, WR, &Xx[(size_t(j) * wx + fi) * 4]);
       if (c.viscous) {
         T a[4], b[4], ap[4], am[4], bp[4], bm[4], Fv[4];
         Wat(fi - 1, j, a); Wat(fi, j, b);
@@ -510,6 +536,7 @@ void rhs(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f, Field<
   // y-faces: rotate (u, v) -> (v, u), compute, rotate the momentum back.
   if (c.ndim == 2) {
     Fy.resize(size_t(4) * nx * (ny + 1));
+    if (cnn) Xy.resize(size_t(4) * nx * wy);
     for (int fj = 0; fj <= ny; ++fj)
       for (int i = 0; i < nx; ++i) {
         T st[6][4];
@@ -518,8 +545,9 @@ void rhs(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f, Field<
           Wat(i, fj - 3 + s, W);
           st[s][0] = W[0]; st[s][1] = W[2]; st[s][2] = W[1]; st[s][3] = W[3];
         }
-        T G[4];
-        face_flux(c, P, st, net, G, fallback_count);
+        T G[4], WL[4], WR[4];
+        face_flux(c, P, st, net, G, fallback_count, WL, WR);
+        if (cnn && fj < wy) cnn_input(WL, WR, &Xy[(size_t(i) * wy + fj) * 4]);  // transposed image
         if (c.viscous) {
           T a[4], b[4], ap[4], am[4], bp[4], bm[4], Fv[4], t[4];
           auto rot = [&](int ii, int jj, T o[4]) { Wat(ii, jj, t); o[0] = t[0]; o[1] = t[2]; o[2] = t[1]; o[3] = t[3]; };
@@ -532,6 +560,31 @@ void rhs(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f, Field<
         T Gs[4] = {G[0], G[2], G[1], G[3]};
         for (int v = 0; v < 4; ++v) Fy[(size_t(v) * (ny + 1) + fj) * nx + i] = Gs[v];
       }
+  }
+  if (cnn && images) {  // the network's input images (x-faces, transposed y-faces)
+    images[0] = Xx;
+    images[1] = Xy;
+  }
+  if (cnn) {
+    std::vector<T> ox, oy;
+    const bool wrapx[2] = {pery, perx}, wrapy[2] = {perx, pery};
+    cnn_apply(*cnn, Xx, ny, wx, wrapx, ox);
+    for (int j = 0; j < ny; ++j)
+      for (int fi = 0; fi <= nx; ++fi)
+        for (int v = 0; v < 4; ++v) {
+          T& F = Fx[(size_t(v) * ny + j) * (nx + 1) + fi];
+          F = F + ox[(size_t(j) * wx + fi % wx) * 4 + v];
+        }
+    if (c.ndim == 2) {
+      cnn_apply(*cnn, Xy, nx, wy, wrapy, oy);
+      const int glob[4] = {0, 2, 1, 3};  // face frame (rho, n, t, E) -> (rho, x, y, E)
+      for (int i = 0; i < nx; ++i)
+        for (int fj = 0; fj <= ny; ++fj)
+          for (int v = 0; v < 4; ++v) {
+            T& G = Fy[(size_t(glob[v]) * (ny + 1) + fj) * nx + i];
+            G = G + oy[(size_t(i) * wy + fj % wy) * 4 + v];
+          }
+    }
   }
   for (int v = 0; v < 4; ++v)
     for (int j = 0; j < ny; ++j)
@@ -557,7 +610,7 @@ void rhs(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f, Field<
 // IBM ghost cells are refilled in place before every stage's RHS.
 template <class T>
 void rk3_step(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& un, const T& dt,
-              const FluxNet* net, long* fb) {
+              const Correction* net, long* fb) {
   Field<T> L(c.nx, c.ny), u1(c.nx, c.ny), u2(c.nx, c.ny);
   ibm_fill(c, P, ib, un);
   rhs(c, P, ib, un, L, net, fb);

@@ -101,24 +101,57 @@ def riemann_batch(seeds, n, device="cuda"):
     return torch.from_numpy(W).to(device)
 
 
-class Dataset:
-    """Coarse (restricted) snapshots of fine runs: snaps[k] = d(U_fine(k dt_c))."""
+def sod_rows_prim(nx, rows):
+    """Sod's shock tube along x on [0, 1] as `rows` identical rows of a 2D
+    grid (primitive variables, batch of one)."""
+    W1 = inputs.sod_prim(nx)  # (rho, u, p) x 1 x nx
+    W = np.zeros((1, 4, rows, nx))
+    W[0, 0], W[0, 1], W[0, 3] = W1[0, 0], W1[1, 0], W1[2, 0]
+    return W
 
-    def __init__(self, seeds, nc=128, factor=4, nsnap=24, cfl_frac=0.5, device="cuda", keep_fine_ic=False):
-        nf = nc * factor
-        nb = len(seeds)
-        W = riemann_batch(seeds, nf, device)
-        gf = Grid(nf, nf, nbatch=nb, device=device)
+
+class Dataset:
+    """Coarse (restricted) snapshots of fine runs: snaps[k] = d(U_fine(k dt_c)).
+
+    case "riemann": random four-quadrant problems (one per seed) on nc^2
+    against (nc * factor)^2, transmissive boundaries, coarse step
+    cfl_frac x the CFL step of each initial coarse state.
+    case "sod" (the 1D problem of section 3; seeds ignored): Sod's shock tube
+    with nc cells against nc * factor, as `rows` identical rows of a 2D grid
+    (transmissive boundaries make every y-face of a column see one stencil,
+    so the y-flux differences -- with or without the correction -- vanish
+    exactly and each row evolves as the 1D problem); coarse step t_end / nsnap.
+    """
+
+    def __init__(self, seeds, nc=128, factor=4, nsnap=24, cfl_frac=0.5, device="cuda", keep_fine_ic=False,
+                 case="riemann", rows=4, t_end=0.25):
+        self.case = case
+        if case == "riemann":
+            nb = len(seeds)
+            nxc = nyc = nc
+            W = riemann_batch(seeds, nc * factor, device)
+            self.domain = (0.0, 1.0, 0.0, 1.0)
+        elif case == "sod":
+            nb, nxc, nyc = 1, nc, rows
+            W = torch.from_numpy(sod_rows_prim(nc * factor, rows * factor)).to(device)
+            self.domain = (0.0, 1.0, 0.0, rows / nc)
+        else:
+            raise ValueError("case must be 'riemann' or 'sod'")
+        self.nx, self.ny = nxc, nyc
+        gf = Grid(nxc * factor, nyc * factor, nbatch=nb, domain=self.domain, device=device)
         Uf = gf.prim_to_cons(W)
         self.fine_ic = Uf.clone() if keep_fine_ic else None
         self.factor = factor
-        gc = Grid(nc, nc, nbatch=nb, device=device)
+        gc = self.grid(nb, device=device)
         U0c = restrict(Uf, factor)
-        # coarse step: a fraction of the CFL step of the initial coarse state
-        d = torch.zeros(nb, dtype=torch.float64, device=device)
-        gc.set_time(0.0, 1e30)
-        gc.step(U0c.clone(), dt_out=d)
-        self.dt_c = (cfl_frac * d).contiguous()
+        if case == "riemann":
+            # coarse step: a fraction of the CFL step of the initial coarse state
+            d = torch.zeros(nb, dtype=torch.float64, device=device)
+            gc.set_time(0.0, 1e30)
+            gc.step(U0c.clone(), dt_out=d)
+            self.dt_c = (cfl_frac * d).contiguous()
+        else:
+            self.dt_c = torch.full((1,), t_end / nsnap, dtype=torch.float64, device=device)
         dt_f = (self.dt_c / factor).contiguous()
         snaps = [U0c]
         torch.cuda.synchronize()
@@ -129,16 +162,23 @@ class Dataset:
             snaps.append(restrict(Uf, factor))
         torch.cuda.synchronize()
         self.fine_ms_per_coarse_step = (time.perf_counter() - t0) * 1e3 / max(nsnap, 1)
-        self.snaps = torch.stack(snaps)  # [nsnap+1][nb][4][nc][nc]
+        self.snaps = torch.stack(snaps)  # [nsnap+1][nb][4][ny][nx]
         self.nc, self.nb, self.nsnap = nc, nb, nsnap
         torch.cuda.synchronize()
 
+    def grid(self, nb=None, **kw):
+        """A coarse grid of this data set's geometry (transmissive)."""
+        return Grid(self.nx, self.ny, nbatch=nb or self.nb, domain=self.domain, **kw)
 
-def train(net, data, iters=400, m=4, lr=1e-3, lr_late=1e-4, switch=None, log_every=50, log=None):
+
+def train(net, data, iters=400, m=4, lr=1e-3, lr_late=1e-4, switch=None, log_every=50, log=None, last=None):
     """Unrolled m-step training: loss = 1/m sum_s ||U^{n+s} - T^{n+s}||^2
-    (mean over entries, summed over the batch), gradient by the adjoint."""
-    nc, nb = data.nc, data.nb
-    g = Grid(nc, nc, nbatch=nb, adjoint=True, flux_net=True, device=data.snaps.device)
+    (mean over entries, summed over the batch), gradient by the adjoint.
+    Windows cycle over the start snapshots 0 .. last - m (last: the final
+    snapshot used, default the data set's last)."""
+    nb = data.nb
+    last = data.nsnap if last is None else last
+    g = data.grid(adjoint=True, flux_net=True, device=data.snaps.device)
     g.set_flux_net(net)
     g.set_flux_net_grad(net.grad)
     part = torch.empty(nb * 256, dtype=torch.float64, device=data.snaps.device)
@@ -146,7 +186,7 @@ def train(net, data, iters=400, m=4, lr=1e-3, lr_late=1e-4, switch=None, log_eve
     history = []
     switch = switch if switch is not None else int(0.875 * iters)
     for it in range(iters):
-        k = it % (data.nsnap - m + 1)
+        k = it % (last - m + 1)
         U = data.snaps[k].clone()
         states = [None]
         for s in range(m):
@@ -167,15 +207,16 @@ def train(net, data, iters=400, m=4, lr=1e-3, lr_late=1e-4, switch=None, log_eve
     return history
 
 
-def dataset_loss(net, data, m=4):
-    """Unrolled m-step loss summed over every start index of the data set
-    (net = None: the uncorrected solver)."""
-    nc, nb = data.nc, data.nb
-    g = Grid(nc, nc, nbatch=nb, flux_net=True, device=data.snaps.device)
+def dataset_loss(net, data, m=4, last=None):
+    """Unrolled m-step loss summed over every start index 0 .. last - m of
+    the data set (net = None: the uncorrected solver)."""
+    nb = data.nb
+    last = data.nsnap if last is None else last
+    g = data.grid(flux_net=True, device=data.snaps.device)
     g.set_flux_net(net)
     part = torch.empty(nb * 256, dtype=torch.float64, device=data.snaps.device)
     loss = torch.zeros(nb, dtype=torch.float64, device=data.snaps.device)
-    for k in range(data.nsnap - m + 1):
+    for k in range(last - m + 1):
         U = data.snaps[k].clone()
         for s in range(1, m + 1):
             g.step(U, data.dt_c)
@@ -235,6 +276,58 @@ def evaluate(net, seeds, nc=128, factor=4, nsteps=24, cfl_frac=0.5, device="cuda
     return out
 
 
+def evaluate_sod(net, data, marks):
+    """Error of the coarse Sod solver with and without the correction against
+    the restricted fine solution at the given snapshot indices (mean squared
+    error over the conserved entries and mean absolute density error), with
+    the time per coarse step."""
+    out = {}
+    for name, use in (("plain", False), ("learned", True)):
+        g = data.grid(flux_net=True, device=data.snaps.device)
+        g.set_flux_net(net if use else None)
+        U = data.snaps[0].clone()
+        errs = {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(1, max(marks) + 1):
+            g.step(U, data.dt_c)
+            if s in marks:
+                d = U - data.snaps[s]
+                errs[s] = {"mse": float((d * d).mean()), "rho_l1": float(d[:, 0].abs().mean())}
+        torch.cuda.synchronize()
+        out[name] = {"errors": errs, "ms_per_step": (time.perf_counter() - t0) * 1e3 / max(marks)}
+    return out
+
+
+def main_sod(a):
+    """Section 3's 1D learned flux: Sod's shock tube with N = 500 cells
+    against N = 1000 restricted, trained on t <= 0.2 and evaluated to 0.25."""
+    import json
+    t0 = time.perf_counter()
+    n_eval = a.nsnap_sod
+    n_train = int(round(n_eval * 0.2 / 0.25))
+    data = Dataset(None, nc=a.nc_sod, factor=2, nsnap=n_eval, case="sod", rows=4, t_end=0.25)
+    print(f"data: Sod {a.nc_sod} vs {2 * a.nc_sod} cells, {n_eval} coarse steps to t = 0.25, "
+          f"{time.perf_counter() - t0:.1f} s", flush=True)
+    net = FluxNet(init_theta(0, zero_output=True))
+    before = dataset_loss(net, data, m=a.m_sod, last=n_train)
+    t1 = time.perf_counter()
+    hist = train(net, data, iters=a.iters_sod, m=a.m_sod, lr=a.lr, lr_late=a.lr_late, log_every=100,
+                 log=lambda s: print(s, flush=True), last=n_train)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    after = dataset_loss(net, data, m=a.m_sod, last=n_train)
+    ev = evaluate_sod(net, data, [n_train // 2, n_train, n_eval])
+    res = {"case": "sod", "coarse": a.nc_sod, "fine": 2 * a.nc_sod, "steps_train": n_train, "steps_eval": n_eval,
+           "unroll_m": a.m_sod, "iters": a.iters_sod, "train_seconds": round(train_s, 2),
+           "train_ms_per_iter": round(train_s * 1e3 / a.iters_sod, 3), "training_loss_before": before,
+           "training_loss_after": after, "eval": ev, "history": hist}
+    print(json.dumps({k: v for k, v in res.items() if k != "history"}), flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+
+
 def main():
     import argparse
     import json
@@ -249,7 +342,14 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--lr-late", type=float, default=1e-4)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--case", choices=("riemann", "sod"), default="riemann")
+    ap.add_argument("--nc-sod", type=int, default=500)
+    ap.add_argument("--nsnap-sod", type=int, default=625)
+    ap.add_argument("--m-sod", type=int, default=64)
+    ap.add_argument("--iters-sod", type=int, default=1000)
     a = ap.parse_args()
+    if a.case == "sod":
+        return main_sod(a)
     t0 = time.perf_counter()
     data = Dataset(list(range(a.train_seeds)), nc=a.nc, factor=a.factor, nsnap=a.nsnap)
     print(f"data: {a.train_seeds} problems, {a.nsnap} coarse snapshots, {time.perf_counter() - t0:.1f} s", flush=True)

@@ -451,3 +451,126 @@ def test_zero_net_leaves_solver_unchanged(orc):
     L0, _, _ = orc.rhs(c, U)
     L1, _, _ = orc.rhs(c, U, net=net)
     np.testing.assert_array_equal(L0, L1)
+
+
+# ------------------------------------------------------- convolutional net
+def bf16_np(a):
+    """Round to bfloat16 (nearest even) through float32, for building the
+    independent reference below."""
+    f = np.asarray(a, dtype=np.float32).copy()
+    u = f.view(np.uint32)
+    u += np.uint32(0x7FFF) + ((u >> 16) & np.uint32(1))
+    u &= np.uint32(0xFFFF0000)
+    return f.astype(np.float64)
+
+
+def cnn_params(seed, scale=0.3):
+    return (np.random.default_rng(seed).normal(size=6388) * scale).astype(np.float32)
+
+
+def split_cnn(p):
+    p = p.astype(np.float64)
+    out, k = [], 0
+    for cout, cin in ((16, 4), (32, 16), (4, 32)):
+        W = p[k:k + cout * 9 * cin].reshape(cout, 3, 3, cin)
+        k += cout * 9 * cin
+        b = p[k:k + cout]
+        k += cout
+        out.append((W, b))
+    return out
+
+
+def cnn_scipy(p, x, out_scale, wrap, emulate):
+    """The three 3x3 layers by scipy.signal.correlate2d per channel pair
+    ('same' output, zero fill or wrap-around per image)."""
+    from scipy.signal import correlate2d
+    rb = bf16_np if emulate else (lambda a: a)
+    h = x
+    layers = split_cnn(p)
+    for li, (W, b) in enumerate(layers):
+        cout, cin = W.shape[0], W.shape[3]
+        H, Wd = h.shape[:2]
+        out = np.zeros((H, Wd, cout))
+        hin = rb(h)
+        for co in range(cout):
+            for ci in range(cin):
+                img = hin[:, :, ci]
+                if wrap[0] or wrap[1]:
+                    # pad by hand: wrap along periodic axes, zeros elsewhere
+                    pad = np.pad(img, 1, mode="constant")
+                    if wrap[0]:
+                        pad[0, 1:-1], pad[-1, 1:-1] = img[-1], img[0]
+                    if wrap[1]:
+                        pad[1:-1, 0], pad[1:-1, -1] = img[:, -1], img[:, 0]
+                    if wrap[0] and wrap[1]:
+                        pad[0, 0], pad[0, -1], pad[-1, 0], pad[-1, -1] = img[-1, -1], img[-1, 0], img[0, -1], img[0, 0]
+                    out[:, :, co] += correlate2d(pad, rb(W[co, :, :, ci]), mode="valid")
+                else:
+                    out[:, :, co] += correlate2d(img, rb(W[co, :, :, ci]), mode="same", boundary="fill")
+            out[:, :, co] += b[co]
+        h = np.maximum(out, 0.0) if li < 2 else out
+    return out_scale * np.tanh(h)
+
+
+@pytest.mark.parametrize("emulate", [False, True])
+@pytest.mark.parametrize("wrap", [(False, False), (True, False), (False, True), (True, True)])
+def test_cnn_forward_matches_scipy_correlation(orc, emulate, wrap):
+    """Section 2's convolutional correction (3x3 layers 4-16-32-4, ReLU, ReLU,
+    tanh, SAME zero padding or wrap-around along periodic axes) against an
+    independent evaluation by scipy's 2D correlation."""
+    p = cnn_params(3)
+    x = np.random.default_rng(4).normal(size=(6, 9, 4))
+    net = orc.Cnn(p, [0, 0, 0, 0], [1, 1, 1, 1], 0.2, emulate_bf16=emulate)
+    got = net.forward(x, wrap=wrap)
+    want = cnn_scipy(p, x, 0.2, wrap, emulate)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    assert orc.lib().orc_cnn_param_count() == 6388  # 576 + 16 + 4608 + 32 + 1152 + 4
+
+
+@pytest.mark.parametrize("wrap", [(False, False), (True, True)])
+def test_cnn_backward_matches_central_differences(orc, wrap):
+    """Hand-written reverse mode of the convolutional correction (emulation
+    off) against central differences: parameters (float32 steps) and inputs."""
+    p = cnn_params(5)
+    rng = np.random.default_rng(6)
+    x = rng.normal(size=(5, 7, 4))
+    dout = rng.normal(size=(5, 7, 4))
+    mk = lambda pp: orc.Cnn(pp, [0, 0, 0, 0], [1, 1, 1, 1], 0.2, emulate_bf16=False)
+    g, dx = mk(p).backward(x, dout, wrap=wrap)
+    J = lambda pp, xx: float(np.sum(mk(pp).forward(xx, wrap=wrap) * dout))
+    h = 2.0 ** -12
+    for k in list(rng.choice(6388, size=30, replace=False)) + [591, 4631, 6387]:  # b1[15], b2[31], b3[3]
+        pp, pm = p.copy(), p.copy()
+        pp[k] += np.float32(h)
+        pm[k] -= np.float32(h)
+        fd = (J(pp, x) - J(pm, x)) / (float(pp[k]) - float(pm[k]))
+        assert abs(fd - g[k]) <= 1e-4 * max(1e-2, abs(g[k])), k
+    for idx in [(0, 0, 0), (2, 3, 1), (4, 6, 3), (1, 5, 2)]:
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += 1e-6
+        xm[idx] -= 1e-6
+        fd = (J(p, xp) - J(p, xm)) / 2e-6
+        assert abs(fd - dx[idx]) <= 1e-7 * max(1.0, abs(dx[idx]))
+
+
+def test_cnn_solver_invariants(orc):
+    """The convolutional correction inside the right-hand side: a zero output
+    layer leaves the solver unchanged bit for bit; on a periodic grid the
+    corrected scheme is conservative (the seam face is one pixel); and the
+    y-direction is the x-direction turned by 90 degrees -- the transposed
+    state (u and v swapped) gives the transposed right-hand side."""
+    n = 12
+    c = orc.config(nx=n, ny=n, bc=(3, 3, 3, 3))
+    W = inputs.smooth_prim(n, n, seed=2, amp=0.3)
+    U = orc.prim_to_cons(c, W)
+    zero = cnn_params(1)
+    zero[576 + 16 + 4608 + 32:] = 0.0
+    net0 = orc.Cnn(zero, [1, 0, 0, 2.5], [1, 2, 2, 0.5], 0.1)
+    np.testing.assert_array_equal(orc.rhs(c, U)[0], orc.rhs(c, U, net=net0)[0])
+    net = orc.Cnn(cnn_params(9), [1, 0, 0, 2.5], [1, 2, 2, 0.5], 0.1)
+    L = orc.rhs(c, U, net=net)[0]
+    assert np.max(np.abs(L - orc.rhs(c, U)[0])) > 1e-3 * np.max(np.abs(L))  # the network matters here
+    assert np.max(np.abs(L.sum(axis=(1, 2)))) <= 1e-12 * np.max(np.abs(L)) * n * n
+    Ut = U.transpose(0, 2, 1)[[0, 2, 1, 3]].copy()
+    Lt = orc.rhs(c, Ut, net=net)[0]
+    np.testing.assert_allclose(Lt, L.transpose(0, 2, 1)[[0, 2, 1, 3]], rtol=0, atol=1e-12 * np.max(np.abs(L)))
