@@ -91,7 +91,8 @@ typedef struct {
   double inflow_prim[4]; /* (rho, u, v, p) used by SHK_BC_INFLOW              */
   int ibm;             /* 1: reserve immersed-boundary tables in the workspace */
   int adjoint;         /* 1: reserve adjoint buffers in the workspace          */
-  int flux_net;        /* 1: reserve learned-flux buffers (ndim 2, SHK_F64)   */
+  int flux_net;        /* 1: per-face network, 2: convolutional network -- reserve
+                          its buffers (ndim 2, SHK_F64, inviscid)            */
 } shk_grid_desc;
 
 /* Bytes of device workspace a grid with this descriptor needs (0 on a bad
@@ -262,6 +263,57 @@ shk_status shk_flux_net_vjp(shk_grid* g, const void* U, const void* lam, float* 
 
 /* Device form (bf16 weights, FP32 biases) from theta; all device arrays. */
 shk_status shk_flux_net_pack(const float* theta, uint16_t* w_bf16, float* bias, void* hip_stream);
+
+/* ---- Learned flux correction, convolutional form (section 2: the paper's
+ * 2D neural flux, a fully convolutional network of three 3x3 layers) ----
+ * Channels 4 -> 16 -> 32 -> 4, ReLU, ReLU, tanh x s_out, 6388 parameters, one
+ * parameter set for both directions.  Its pixels are faces: image 0 = the
+ * x-faces (ny rows, nx + 1 columns), image 1 = the y-faces transposed (nx
+ * rows, ny + 1 columns), so the face normal runs along the columns of both;
+ * a periodic axis holds each face once (nx columns; the last face of a row
+ * is its first) and wraps the 3x3 windows, other boundaries pad them with
+ * zeros.  A pixel's input is the conservative form of the mean of the
+ * face's two WENO5 states (after the positivity fallback), face frame
+ * (rho, rho u_n, rho u_t, E), normalised as (x - mean) * inv_std; its
+ * output is the face-frame correction added to the HLLC flux.  bf16
+ * weights, FP32 accumulation on the matrix cores.
+ * Parameter vector theta (FP32, 6388 entries): W1[16][3][3][4], b1[16],
+ * W2[32][3][3][16], b2[32], W3[4][3][3][32], b3[4] (W[out][dy][dx][in]).
+ * Device form (shk_flux_cnn_pack writes it): 18432 bf16 values (forward and
+ * input-gradient weight matrices) and 64 FP32 biases. */
+
+/* Enable (enable = 1) or disable the convolutional correction; arguments as
+ * for shk_set_flux_net (device w_bf16 [18432], bias [64]; host norm_host =
+ * {mean[4], inv_std[4]} of the conservative inputs; out_scale > 0).  While
+ * enabled, every stage evaluates the network over the face images of its
+ * state before the stage kernel, and the adjoint entry points include its
+ * reverse pass; the parameter gradient goes to the buffer set by
+ * shk_set_flux_net_grad (6388 floats).  A non-finite output falls back to the
+ * uncorrected flux at that face and sets SHK_FAULT_NET.  Requires
+ * desc.flux_net = 2 (SHK_ESTATE otherwise). */
+shk_status shk_set_flux_cnn(shk_grid* g, const uint16_t* w_bf16, const float* bias, const double* norm_host,
+                            float out_scale, int enable);
+
+/* Network output for every face of state U: dF (device, [nbatch][nface][4]
+ * floats, face frame, faces ordered as for shk_flux_net_eval). */
+shk_status shk_flux_cnn_eval(shk_grid* g, const void* U, float* dF);
+
+/* Reverse of the network alone, as shk_flux_net_vjp: dX (device,
+ * [nbatch][nface][6][4]) = gradient w.r.t. each face's stencil primitives
+ * through its input (the last face of a periodic row repeats the first);
+ * adds the parameter gradient to grad (6388 floats, may be NULL).  The face
+ * adjoints are (lam_right - lam_left) / h with the periodic wrap, so the
+ * first face of a periodic row carries both of its uses. */
+shk_status shk_flux_cnn_vjp(shk_grid* g, const void* U, const void* lam, float* dX, float* grad);
+
+/* The network's input images of state U as floats (their bf16 values):
+ * images (device, [nbatch][npix][4]), image 0's pixels row by row, then
+ * image 1's.  *npix receives the pixels per batch member; with U and images
+ * both NULL only *npix is set. */
+shk_status shk_flux_cnn_images(shk_grid* g, const void* U, float* images, int* npix);
+
+/* Device form (bf16 weight matrices, FP32 biases) from theta. */
+shk_status shk_flux_cnn_pack(const float* theta, uint16_t* w_bf16, float* bias, void* hip_stream);
 
 /* One Adam step on n parameters (device arrays; step counts from 1). */
 shk_status shk_adam(float* theta, const float* grad, float* m, float* v, int n, float lr, float beta1, float beta2,

@@ -47,6 +47,11 @@ _SIGS = {
     "shk_flux_net_eval": (_i, [_p, _p, _p]),
     "shk_flux_net_vjp": (_i, [_p, _p, _p, _p, _p]),
     "shk_flux_net_pack": (_i, [_p, _p, _p, _p]),
+    "shk_set_flux_cnn": (_i, [_p, _p, _p, _p, ctypes.c_float, _i]),
+    "shk_flux_cnn_eval": (_i, [_p, _p, _p]),
+    "shk_flux_cnn_vjp": (_i, [_p, _p, _p, _p, _p]),
+    "shk_flux_cnn_images": (_i, [_p, _p, _p, _p]),
+    "shk_flux_cnn_pack": (_i, [_p, _p, _p, _p]),
     "shk_adam": (_i, [_p, _p, _p, _p, _i, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _i, _p]),
     "shk_restrict": (_i, [_p, _p, _i, _i, _i, _i, _i, _p]),
     "shk_mse": (_i, [_p, _p, _p, _d, ctypes.c_longlong, _i, _p, _p, _p]),

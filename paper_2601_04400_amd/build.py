@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libshk.so")
-SOURCES = ["api.cpp", "stage.hip", "ibm.hip", "adjoint.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "stage.hip", "ibm.hip", "adjoint.hip", "mlp.hip", "cnn.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=on",

@@ -18,6 +18,7 @@
 // reproducible bit for bit, without atomics.
 #include <hip/hip_runtime.h>
 
+#include "face_dev.hpp"
 #include "flux.hpp"
 #include "grid.hpp"
 #include "xcd.hpp"
@@ -58,47 +59,6 @@ __device__ __forceinline__ void adj_load_cons(const GridArgs& a, const double* _
     if (fx & 1) q[1] = -q[1];
   }
   if (fy & 1) q[2] = -q[2];
-}
-
-// Reverse of one WENO5-JS reconstruction f(a,b,c,d,e) (the forward value is
-// recomputed): d f / d beta_k = -2 omega_k (q_k - f) / (eps + beta_k).
-__device__ __forceinline__ void weno5_vjp(double a, double b, double c, double d, double e, double eps,
-                                          double fb, double& ga, double& gb, double& gc, double& gd,
-                                          double& ge) {
-  const double k13 = 13.0 / 12.0;
-  const double s0 = a - 2.0 * b + c, t0 = a - 4.0 * b + 3.0 * c;
-  const double s1 = b - 2.0 * c + d, t1 = b - d;
-  const double s2 = c - 2.0 * d + e, t2 = 3.0 * c - 4.0 * d + e;
-  const double g0 = eps + (k13 * s0 * s0 + 0.25 * t0 * t0);
-  const double g1 = eps + (k13 * s1 * s1 + 0.25 * t1 * t1);
-  const double g2 = eps + (k13 * s2 * s2 + 0.25 * t2 * t2);
-  const double h0 = g0 * g0, h1 = g1 * g1, h2 = g2 * g2;
-  const double w0 = 0.1 * (h1 * h2), w1 = 0.6 * (h0 * h2), w2 = 0.3 * (h0 * h1);
-  // one reciprocal serves the normalisation and the three 1/g_k:
-  // r = 1/(S P) with S = w0 + w1 + w2 and P = g0 g1 g2 (both positive and
-  // far from the double range limits since g_k >= eps)
-  const double S = w0 + w1 + w2, P = g0 * g1 * g2;
-  const double r = qrcp(S * P);
-  const double is = P * r, iP = S * r;
-  const double o0 = w0 * is, o1 = w1 * is, o2 = w2 * is;
-  const double q0 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
-  const double q1 = (5.0 * c - b + 2.0 * d) * (1.0 / 6.0);
-  const double q2 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
-  const double f = o0 * q0 + o1 * q1 + o2 * q2;
-  const double qb0 = fb * o0, qb1 = fb * o1, qb2 = fb * o2;
-  const double m2 = -2.0 * fb * iP;
-  const double bb0 = m2 * o0 * (q0 - f) * (g1 * g2);
-  const double bb1 = m2 * o1 * (q1 - f) * (g0 * g2);
-  const double bb2 = m2 * o2 * (q2 - f) * (g0 * g1);
-  const double sb0 = bb0 * (2.0 * k13) * s0, tb0 = bb0 * 0.5 * t0;
-  const double sb1 = bb1 * (2.0 * k13) * s1, tb1 = bb1 * 0.5 * t1;
-  const double sb2 = bb2 * (2.0 * k13) * s2, tb2 = bb2 * 0.5 * t2;
-  ga += qb0 * (2.0 / 6.0) + sb0 + tb0;
-  gb += qb0 * (-7.0 / 6.0) + qb1 * (-1.0 / 6.0) - 2.0 * sb0 - 4.0 * tb0 + sb1 + tb1;
-  gc += qb0 * (11.0 / 6.0) + qb1 * (5.0 / 6.0) + qb2 * (2.0 / 6.0) + sb0 + 3.0 * tb0 - 2.0 * sb1 + sb2 +
-        3.0 * tb2;
-  gd += qb1 * (2.0 / 6.0) + qb2 * (5.0 / 6.0) + sb1 - tb1 - 2.0 * sb2 - 4.0 * tb2;
-  ge += qb2 * (-1.0 / 6.0) + sb2 + tb2;
 }
 
 struct PB {

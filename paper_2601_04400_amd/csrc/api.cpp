@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/shk.h"
+#include "cnn.hpp"
 #include "grid.hpp"
 #include "mlp.hpp"
 
@@ -23,7 +24,7 @@ using namespace shk;
 struct WsLayout {
   size_t scalars, globals, dtbuf, xslots, u1, u2, cls, row_count, row_off, g_cell, g_src, g_w, g_nrm;
   size_t adjA, adjB, adjC, adjP, adjQ, adjPart, part_stride, adjG, ghostOf, entKeys, entVals, entCount, entHeads;
-  size_t netX, netPart;
+  size_t netX, netPart, cnnDF, cnnBufs;
   size_t total;
 };
 
@@ -41,7 +42,9 @@ struct shk_grid {
   int nsrc = 0;  // distinct source cells among them
   NetArgs net{};
   bool net_on = false;
-  float* net_grad = nullptr;
+  CnnArgs cnn{};
+  bool cnn_on = false;
+  float* net_grad = nullptr;  // parameter gradient of whichever network is set
   std::string err;
   // kernel timing (shk_profile)
   bool prof = false;
@@ -79,8 +82,10 @@ bool desc_ok(const shk_grid_desc* d, std::string* why) {
   if (d->viscous && d->ndim != 2) return bad("viscous terms need ndim 2");
   if (d->viscous && (!(d->mu >= 0.0) || !(d->prandtl > 0.0))) return bad("viscous needs mu >= 0, prandtl > 0");
   if (d->ibm && d->ndim != 2) return bad("immersed boundary needs ndim 2");
+  if (d->flux_net < 0 || d->flux_net > 2) return bad("flux_net must be 0, 1 or 2");
   if (d->flux_net && (d->ndim != 2 || d->prec != SHK_F64 || d->viscous))
     return bad("flux net needs ndim 2, SHK_F64 and an inviscid grid");
+  if (d->flux_net == 2 && (d->nx > 16384 || d->ny > 16384)) return bad("convolutional net: nx, ny <= 16384");
   if (d->nu_art < 0.0) return bad("nu_art must be >= 0");
   return true;
 }
@@ -134,6 +139,13 @@ WsLayout layout(const shk_grid_desc* d) {
       L.netX = o; o += al(sizeof(float) * 24 * nface * d->nbatch);
       L.netPart = o; o += al(sizeof(float) * NET_NP * NET_BWD_BLOCKS);
     }
+    if (d->flux_net == 2) {
+      GridArgs a{};
+      a.nx = d->nx; a.ny = d->ny; a.nbatch = d->nbatch;
+      for (int k = 0; k < 4; ++k) a.bc[k] = d->bc[k];
+      L.cnnDF = o; o += al(sizeof(float) * 4 * nface * d->nbatch);
+      L.cnnBufs = o; o += al(cnn_workspace_bytes(a));
+    }
   }
   L.total = o;
   return L;
@@ -181,11 +193,22 @@ hipError_t timed(shk_grid* g, int cls, F&& f) {
   return e;
 }
 
-// Stage launch; with the learned correction on, the kernel variant that
-// evaluates the network inside its tile (FP64 grids only).
+// Stage launch; with the per-face network on, the kernel variant that
+// evaluates it inside its tile; with the convolutional network on, the
+// network over the face images of Us first and the variant that adds its
+// per-face output (FP64 grids only).
 template <class S>
 hipError_t stage_launch(shk_grid* g, const GridArgs& a, int mode, const S* Us, const S* Un, S* Uo,
                         const double* dtp, const S* Lin) {
+  if (g->cnn_on) {
+    GridArgs ax = a;
+    ax.dFext = reinterpret_cast<float*>(g->ws + g->L.cnnDF);
+    hipError_t e = launch_cnn_forward(ax, g->cnn, reinterpret_cast<const double*>(Us),
+                                      const_cast<float*>(ax.dFext), cnn_bufs(ax, g->ws + g->L.cnnBufs), g->st);
+    if (e != hipSuccess) return e;
+    return launch_stage_ext(ax, mode, reinterpret_cast<const double*>(Us), reinterpret_cast<const double*>(Un),
+                            reinterpret_cast<double*>(Uo), dtp, g->st);
+  }
   if (g->net_on)
     return launch_stage_net(a, g->net, mode, reinterpret_cast<const double*>(Us),
                             reinterpret_cast<const double*>(Un), reinterpret_cast<double*>(Uo), dtp, g->st);
@@ -208,7 +231,7 @@ shk_status stage_seq(shk_grid* g, S* U, const double* dt_in, double* dt_out, S* 
   S* U1 = tape ? tape + nst : reinterpret_cast<S*>(g->ws + g->L.u1);
   S* U2 = tape ? tape + 2 * nst : reinterpret_cast<S*>(g->ws + g->L.u2);
   hipError_t e;
-  if (!dt_in && !g->ibm_on && !g->net_on && !tape) {
+  if (!dt_in && !g->ibm_on && !g->net_on && !g->cnn_on && !tape) {
     if ((e = timed(g, 1, [&]() { return stage_launch<S>(g, a, MODE_S1L, U, U, U1, nullptr, nullptr); })) != hipSuccess)
       return hip_check(g, e, "stage 1");
     if ((e = timed(g, 2, [&]() { return stage_launch<S>(g, a, MODE_S2F, U, U, U2, nullptr, U1); })) != hipSuccess)
@@ -474,6 +497,13 @@ static hipError_t rhs_adj(shk_grid* g, PartRec& pr, const double* Us, const doub
     hipError_t e = launch_net_backward(a, g->net, Us, lam, clam_f, dtp, dX, np, g->net_grad, g->st);
     if (e != hipSuccess) return e;
     a.dXnet = dX;
+  } else if (g->cnn_on) {
+    float* dX = reinterpret_cast<float*>(g->ws + g->L.netX);
+    float* dF = reinterpret_cast<float*>(g->ws + g->L.cnnDF);
+    hipError_t e = launch_cnn_backward(a, g->cnn, Us, lam, clam_f, dtp, dX, dF, cnn_bufs(a, g->ws + g->L.cnnBufs),
+                                       g->net_grad, g->st);
+    if (e != hipSuccess) return e;
+    a.dXnet = dX;
   }
   int nb = 0;
   double* gW = g->ibm_on ? reinterpret_cast<double*>(g->ws + g->L.adjG) : nullptr;
@@ -637,7 +667,7 @@ shk_status shk_set_flux_net(shk_grid* g, const uint16_t* w_bf16, const float* bi
     g->net_on = false;
     return SHK_OK;
   }
-  if (!g->d.flux_net) return fail(g, SHK_ESTATE, "set_flux_net: grid created without desc.flux_net = 1");
+  if (g->d.flux_net != 1) return fail(g, SHK_ESTATE, "set_flux_net: grid created without desc.flux_net = 1");
   if (!w_bf16 || !bias || !norm_host) return fail(g, SHK_EINVAL, "set_flux_net: null array");
   NetArgs n{};
   n.w = reinterpret_cast<const unsigned short*>(w_bf16);
@@ -673,6 +703,66 @@ shk_status shk_flux_net_vjp(shk_grid* g, const void* U, const void* lam, float* 
                    launch_net_backward(g->a, g->net, static_cast<const double*>(U), static_cast<const double*>(lam),
                                        1.0, nullptr, dX, np, grad, g->st),
                    "flux_net_vjp");
+}
+
+shk_status shk_set_flux_cnn(shk_grid* g, const uint16_t* w_bf16, const float* bias, const double* norm_host,
+                            float out_scale, int enable) {
+  if (!g) return SHK_EINVAL;
+  if (!enable) {
+    g->cnn_on = false;
+    return SHK_OK;
+  }
+  if (g->d.flux_net != 2) return fail(g, SHK_ESTATE, "set_flux_cnn: grid created without desc.flux_net = 2");
+  if (!w_bf16 || !bias || !norm_host) return fail(g, SHK_EINVAL, "set_flux_cnn: null array");
+  if (!(out_scale > 0.0f)) return fail(g, SHK_EINVAL, "set_flux_cnn: out_scale must be positive");
+  CnnArgs n{};
+  n.w = reinterpret_cast<const unsigned short*>(w_bf16);
+  n.bias = bias;
+  for (int k = 0; k < 4; ++k) {
+    n.mean[k] = norm_host[k];
+    n.inv_std[k] = norm_host[4 + k];
+  }
+  n.out_scale = out_scale;
+  g->cnn = n;
+  g->cnn_on = true;
+  return SHK_OK;
+}
+
+shk_status shk_flux_cnn_eval(shk_grid* g, const void* U, float* dF) {
+  if (!g || !U || !dF) return SHK_EINVAL;
+  if (!g->cnn_on) return fail(g, SHK_ESTATE, "flux_cnn_eval: no convolutional net set");
+  return hip_check(g,
+                   launch_cnn_forward(g->a, g->cnn, static_cast<const double*>(U), dF,
+                                      cnn_bufs(g->a, g->ws + g->L.cnnBufs), g->st),
+                   "flux_cnn_eval");
+}
+
+shk_status shk_flux_cnn_vjp(shk_grid* g, const void* U, const void* lam, float* dX, float* grad) {
+  if (!g || !U || !lam || !dX) return SHK_EINVAL;
+  if (!g->cnn_on) return fail(g, SHK_ESTATE, "flux_cnn_vjp: no convolutional net set");
+  float* dF = reinterpret_cast<float*>(g->ws + g->L.cnnDF);
+  return hip_check(g,
+                   launch_cnn_backward(g->a, g->cnn, static_cast<const double*>(U), static_cast<const double*>(lam),
+                                       1.0, nullptr, dX, dF, cnn_bufs(g->a, g->ws + g->L.cnnBufs), grad, g->st),
+                   "flux_cnn_vjp");
+}
+
+shk_status shk_flux_cnn_images(shk_grid* g, const void* U, float* images, int* npix) {
+  if (!g || !npix) return SHK_EINVAL;
+  *npix = cnn_geom(g->a).npix;
+  if (!U && !images) return SHK_OK;  // size query
+  if (!U || !images) return SHK_EINVAL;
+  if (!g->cnn_on) return fail(g, SHK_ESTATE, "flux_cnn_images: no convolutional net set");
+  return hip_check(g,
+                   launch_cnn_images(g->a, g->cnn, static_cast<const double*>(U),
+                                     cnn_bufs(g->a, g->ws + g->L.cnnBufs), images, g->st),
+                   "flux_cnn_images");
+}
+
+shk_status shk_flux_cnn_pack(const float* theta, uint16_t* w_bf16, float* bias, void* hip_stream) {
+  if (!theta || !w_bf16 || !bias) return SHK_EINVAL;
+  return launch_cnn_pack(theta, reinterpret_cast<unsigned short*>(w_bf16), bias,
+                         reinterpret_cast<hipStream_t>(hip_stream)) == hipSuccess ? SHK_OK : SHK_EHIP;
 }
 
 shk_status shk_flux_net_pack(const float* theta, uint16_t* w_bf16, float* bias, void* hip_stream) {

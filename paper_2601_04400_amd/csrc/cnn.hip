@@ -1,0 +1,712 @@
+// Convolutional learned flux correction on gfx950 matrix cores (bfloat16
+// MFMA, FP32 accumulation): section 2's 2D neural flux, three 3x3 layers
+// (4 -> 16 -> 32 -> 4 channels; ReLU, ReLU, tanh; 6,388 parameters) applied
+// pixel by pixel to the normalised WENO-reconstructed states, one parameter
+// set for both directions.
+//
+// The pixels are faces.  Image 0 holds the x-faces (ny rows, nx + 1
+// columns), image 1 the y-faces transposed (nx rows, ny + 1 columns), so the
+// face normal runs along the columns of both; a face's input is the
+// normalised conservative mean of its two reconstructed states in the face
+// frame, its output the face-frame flux correction out_scale * tanh(z).  The
+// 3x3 windows are padded with zeros at domain boundaries and wrap around
+// across periodic ones, where the image holds each face once (the last face
+// of a periodic row is its first).
+//
+// Every layer is an implicit GEMM on 16 x 16 pixel tiles staged in LDS with
+// a one-pixel halo: D[out channel][pixel] = W[out channel][tap, in channel]
+// . X[tap, in channel][pixel] with v_mfma_f32_16x16x16_bf16, one pixel row
+// of a tile per product (N = 16), channels last so that an operand slice is
+// one 8-byte LDS read.  The reverse pass runs the same kernel with the
+// mirrored, channel-swapped weights for the input gradients (masked by the
+// forward ReLU) and a second kernel for the weight gradients, a contraction
+// over pixels whose operands are read channel-major from LDS.  Parameter
+// gradients go to one FP32 partial per workgroup (fixed tile order per
+// workgroup, fixed wave order inside it) and are summed in a fixed order:
+// the gradients are reproducible bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "cnn.hpp"
+#include "face_dev.hpp"
+#include "flux.hpp"
+#include "grid.hpp"
+#include "mlp_dev.hpp"
+
+namespace shk {
+
+namespace {
+
+enum { EPI_FWD_HIDDEN = 0, EPI_FWD_OUT = 1, EPI_BWD_HIDDEN = 2, EPI_BWD_IN = 3 };
+
+struct ConvOut {
+  unsigned short* out_bf;            // bf16 image of COUT channels (hidden epilogues)
+  float* out_f;                      // FP32 image of 4 channels (EPI_BWD_IN) or tanh values (EPI_FWD_OUT)
+  const unsigned short* mask_src;    // forward activation of the same pixels (EPI_BWD_HIDDEN)
+  float* part;                       // [CNN_BLOCKS][CNN_NP] (EPI_BWD_HIDDEN: bias sums)
+  int part_off;
+  int cout;                          // real output channels
+  float out_scale;
+  float* dF;                         // [nbatch][nface][4] (EPI_FWD_OUT)
+  long long nface;
+  int nx, ny;
+  unsigned int* fault;
+};
+
+// Pixel index along an image axis of n pixels for a 3x3 window position k
+// (k in -1 .. n): wrapped along a periodic axis, -1 (zero padding) outside
+// otherwise.  Positions further out are never read by a valid output.
+__device__ __forceinline__ int pix_src(int k, int n, int wrap) {
+  if (k >= 0 && k < n) return k;
+  if (!wrap || k < -1 || k > n) return -1;
+  return k < 0 ? n - 1 : 0;
+}
+
+struct TileLoc {
+  int b, img, r0, c0, H, W, wr, wc;
+  long long pbase;  // pixel index of the image's first pixel in the member-major buffer
+};
+
+__device__ __forceinline__ TileLoc tile_loc(const CnnGeom& g, long long t) {
+  TileLoc L;
+  L.b = (int)(t / g.tiles);
+  int tt = (int)(t % g.tiles);
+  const int t0 = g.tilesR[0] * g.tilesC[0];
+  L.img = tt < t0 ? 0 : 1;
+  if (L.img) tt -= t0;
+  L.H = g.H[L.img];
+  L.W = g.W[L.img];
+  L.wr = g.wrapR[L.img];
+  L.wc = g.wrapC[L.img];
+  L.r0 = (tt / g.tilesC[L.img]) * 16;
+  L.c0 = (tt % g.tilesC[L.img]) * 16;
+  L.pbase = (long long)L.b * g.npix + (L.img ? g.H[0] * g.W[0] : 0);
+  return L;
+}
+
+// The face of pixel (R, C) of an image, in the solver's face numbering
+// (x-faces (nx + 1) per row, then y-faces nx per row).
+__device__ __forceinline__ long long pixel_face(int img, int R, int C, int nx, int ny) {
+  return img == 0 ? (long long)R * (nx + 1) + C : (long long)(nx + 1) * ny + (long long)C * nx + R;
+}
+
+// One 3x3 layer as an implicit GEMM over 16 x 16 pixel tiles (see the file
+// comment); MT output-channel tiles of 16, KB K-blocks of 16 (k = tap * CIN
+// + channel, taps >= 9 are zero padding).  Workgroups take tiles of every
+// batch member and both images in a fixed order.
+template <int CIN, int MT, int KB, int EPI>
+__global__ void __launch_bounds__(256) cnn_conv_kernel(CnnGeom g, const unsigned short* __restrict__ in,
+                                                       const unsigned short* __restrict__ wm,
+                                                       const float* __restrict__ bias, ConvOut o) {
+  static_assert(CIN % 4 == 0, "channels come in groups of four");
+  __shared__ __attribute__((aligned(16))) unsigned short sw[MT * 16 * KB * 16];
+  __shared__ __attribute__((aligned(16))) unsigned short tile[18 * 18 * CIN];
+  __shared__ float red[4][MT * 16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane >> 4, fl = lane & 15;
+  for (int k = threadIdx.x; k < MT * 16 * KB * 16; k += blockDim.x) sw[k] = wm[k];
+  f32x4 bs[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) bs[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bool bad = false;
+  const long long ntile = (long long)g.tiles * g.nbatch;
+  for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const TileLoc L = tile_loc(g, t);
+    __syncthreads();  // the previous tile's readers are done (and the weights are in)
+    for (int k = threadIdx.x; k < 18 * 18 * (CIN / 4); k += blockDim.x) {
+      const int pq = k / (CIN / 4), cq = k - pq * (CIN / 4);
+      const int tr = pq / 18, tc = pq - tr * 18;
+      const int R = pix_src(L.r0 + tr - 1, L.H, L.wr), C = pix_src(L.c0 + tc - 1, L.W, L.wc);
+      bf16x4 v = {0, 0, 0, 0};
+      if (R >= 0 && C >= 0) v = *reinterpret_cast<const bf16x4*>(in + (L.pbase + (long long)R * L.W + C) * CIN + 4 * cq);
+      *reinterpret_cast<bf16x4*>(tile + pq * CIN + 4 * cq) = v;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < 4; ++rr) {
+      const int r = wv * 4 + rr;
+      if (L.r0 + r >= L.H) break;  // uniform over the wave
+      f32x4 acc[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        if (bias != nullptr) {
+          const float* bp = bias + mt * 16 + 4 * q;
+          acc[mt] = f32x4{bp[0], bp[1], bp[2], bp[3]};
+        } else {
+          acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        const int k0 = kb * 16 + 4 * q, tap = k0 / CIN, ci0 = k0 - tap * CIN;
+        bf16x4 B = {0, 0, 0, 0};
+        if (tap < 9) {
+          const int dr = tap / 3, dc = tap - 3 * dr;
+          B = *reinterpret_cast<const bf16x4*>(tile + ((r + dr) * 18 + fl + dc) * CIN + ci0);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma(ldA(sw, KB * 16, mt * 16, kb * 16, lane), B, acc[mt]);
+      }
+      // lane (pixel fl of the row, q) holds output channels 16 mt + 4q .. + 3
+      const int R = L.r0 + r, C = L.c0 + fl;
+      const bool valid = C < L.W;
+      const long long pix = L.pbase + (long long)R * L.W + C;
+      if (EPI == EPI_FWD_HIDDEN) {
+        if (valid)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const f32x4 a = acc[mt];
+            *reinterpret_cast<bf16x4*>(o.out_bf + pix * (MT * 16) + mt * 16 + 4 * q) =
+                pack4(fmaxf(a[0], 0.f), fmaxf(a[1], 0.f), fmaxf(a[2], 0.f), fmaxf(a[3], 0.f));
+          }
+      } else if (EPI == EPI_FWD_OUT) {
+        if (valid && q == 0) {
+          float th[4], out[4];
+          bool ok = true;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            th[i] = tanhf(acc[0][i]);
+            out[i] = o.out_scale * th[i];
+            ok = ok && isfinite(out[i]);
+          }
+          if (!ok) {  // the uncorrected flux, with zero derivative
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { out[i] = 0.f; th[i] = 1.f; }
+            bad = true;
+          }
+          *reinterpret_cast<f32x4*>(o.out_f + pix * 4) = f32x4{th[0], th[1], th[2], th[3]};
+          float* d = o.dF + ((long long)L.b * o.nface + pixel_face(L.img, R, C, o.nx, o.ny)) * 4;
+          *reinterpret_cast<f32x4*>(d) = f32x4{out[0], out[1], out[2], out[3]};
+          if (L.wc && C == 0) {  // the last face of a periodic row is this one
+            float* d2 = o.dF + ((long long)L.b * o.nface + pixel_face(L.img, R, L.W, o.nx, o.ny)) * 4;
+            *reinterpret_cast<f32x4*>(d2) = f32x4{out[0], out[1], out[2], out[3]};
+          }
+        }
+      } else if (EPI == EPI_BWD_HIDDEN) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int c0 = mt * 16 + 4 * q;
+          f32x4 d = acc[mt];
+          if (valid) {
+            const bf16x4 h = *reinterpret_cast<const bf16x4*>(o.mask_src + pix * (MT * 16) + c0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) d[i] = h[i] > 0 ? d[i] : 0.f;  // bf16 bits: positive iff > 0 as int16
+            *reinterpret_cast<bf16x4*>(o.out_bf + pix * (MT * 16) + c0) = pack4(d[0], d[1], d[2], d[3]);
+            bs[mt] = bs[mt] + d;
+          }
+        }
+      } else {  // EPI_BWD_IN
+        if (valid && q == 0) *reinterpret_cast<f32x4*>(o.out_f + pix * 4) = acc[0];
+      }
+    }
+  }
+  if (EPI == EPI_FWD_OUT && bad) atomicOr(o.fault, 8u);
+  if (EPI == EPI_BWD_HIDDEN) {
+    // this workgroup's bias sums: the 16 pixels of a row group, then the
+    // four waves in order
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float s = bs[mt][i];
+        for (int m = 8; m >= 1; m >>= 1) s += __shfl_xor(s, m, 16);
+        if (fl == 0) red[wv][mt * 16 + 4 * q + i] = s;
+      }
+    __syncthreads();
+    if ((int)threadIdx.x < o.cout)
+      o.part[(long long)blockIdx.x * CNN_NP + o.part_off + threadIdx.x] =
+          ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+  }
+}
+
+// Weight gradient of one layer: D[out channel][tap, in channel] = sum over
+// pixels of dA[pixel][out] X[pixel + tap][in], a contraction over the 16
+// pixels of a tile row per product.  The operands are staged channel-major
+// (pixels contiguous): dA without halo, X with a one-pixel halo.
+template <int CIN, int COUT, int MT, int NT>
+__global__ void __launch_bounds__(256) cnn_wgrad_kernel(CnnGeom g, const unsigned short* __restrict__ dA,
+                                                        const unsigned short* __restrict__ X,
+                                                        float* __restrict__ part, int woff) {
+  constexpr int K9 = 9 * CIN;
+  __shared__ __attribute__((aligned(16))) unsigned short tA[MT * 16][256];
+  __shared__ unsigned short tX[CIN][18 * 18];
+  __shared__ float red[COUT * K9];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane >> 4, fl = lane & 15;
+  f32x4 acc[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const long long ntile = (long long)g.tiles * g.nbatch;
+  for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const TileLoc L = tile_loc(g, t);
+    __syncthreads();
+    for (int k = threadIdx.x; k < MT * 16 * 256; k += blockDim.x) {
+      const int ch = k >> 8, p = k & 255;
+      const int R = L.r0 + (p >> 4), C = L.c0 + (p & 15);
+      unsigned short v = 0;
+      if (ch < COUT && R < L.H && C < L.W) v = dA[(L.pbase + (long long)R * L.W + C) * COUT + ch];
+      tA[ch][p] = v;
+    }
+    for (int k = threadIdx.x; k < CIN * 324; k += blockDim.x) {
+      const int pq = k / CIN, ci = k - pq * CIN;
+      const int tr = pq / 18, tc = pq - tr * 18;
+      const int R = pix_src(L.r0 + tr - 1, L.H, L.wr), C = pix_src(L.c0 + tc - 1, L.W, L.wc);
+      unsigned short v = 0;
+      if (R >= 0 && C >= 0) v = X[(L.pbase + (long long)R * L.W + C) * CIN + ci];
+      tX[ci][pq] = v;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < 4; ++rr) {
+      const int r = wv * 4 + rr;
+      if (L.r0 + r >= L.H) break;  // uniform over the wave
+      bf16x4 A[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) A[mt] = *reinterpret_cast<const bf16x4*>(&tA[mt * 16 + fl][r * 16 + 4 * q]);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int k = nt * 16 + fl, tap = k / CIN, ci = k - tap * CIN;
+        bf16x4 B = {0, 0, 0, 0};
+        if (tap < 9) {
+          const int dr = tap / 3, dc = tap - 3 * dr;
+          const unsigned short* p = &tX[ci][(r + dr) * 18 + 4 * q + dc];
+          B = bf16x4{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma(A[mt], B, acc[mt][nt]);
+      }
+    }
+  }
+  // the four waves' sums in order, then this workgroup's partial
+  for (int w2 = 0; w2 < 4; ++w2) {
+    __syncthreads();
+    if (wv == w2) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int co = mt * 16 + 4 * q + i, k = nt * 16 + fl;
+            if (co < COUT && k < K9) {
+              float& s = red[co * K9 + k];
+              s = w2 == 0 ? acc[mt][nt][i] : s + acc[mt][nt][i];
+            }
+          }
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < COUT * K9; k += blockDim.x)
+    part[(long long)blockIdx.x * CNN_NP + woff + k] = red[k];
+}
+
+// The adjoint of the two cells beside a face: zero outside the domain unless
+// periodic, and in solid cells.
+__device__ __forceinline__ void lam_cell(const GridArgs& a, const double* __restrict__ Lb, int gi, int gj,
+                                         double l[4]) {
+  bool ok = true;
+  if (gi < 0 || gi >= a.nx) {
+    ok = a.bc[0] == BC_PERIODIC;
+    gi += gi < 0 ? a.nx : -a.nx;
+  }
+  if (gj < 0 || gj >= a.ny) {
+    ok = ok && a.bc[2] == BC_PERIODIC;
+    gj += gj < 0 ? a.ny : -a.ny;
+  }
+  const long long c = (long long)gj * a.nx + gi;
+  if (ok && a.cls != nullptr) ok = a.cls[c] == CELL_FLUID;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) l[v] = ok ? Lb[v * a.ncell + c] : 0.0;
+}
+
+// Upstream gradient of one face's flux (face frame) from the RHS adjoint.
+__device__ __forceinline__ void face_bar(const GridArgs& a, const double* __restrict__ Lb, double clam, int img,
+                                         int R, int C, double fb[4]) {
+  double lo[4], hi[4];
+  if (img == 0) {  // x-face C of row R: cells C - 1 and C
+    lam_cell(a, Lb, C - 1, R, lo);
+    lam_cell(a, Lb, C, R, hi);
+    const double sc = clam * a.inv_dx;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) fb[v] = sc * (hi[v] - lo[v]);
+  } else {  // y-face C of column R: cells C - 1 and C
+    lam_cell(a, Lb, R, C - 1, lo);
+    lam_cell(a, Lb, R, C, hi);
+    const double sc = clam * a.inv_dy;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int vy = v == 1 ? 2 : (v == 2 ? 1 : v);
+      fb[v] = sc * (hi[vy] - lo[vy]);
+    }
+  }
+}
+
+struct PixelLoc {
+  int b, img, R, C, W, wc;
+};
+
+__device__ __forceinline__ PixelLoc pixel_loc(const CnnGeom& g, long long p) {
+  PixelLoc P;
+  P.b = (int)(p / g.npix);
+  int q = (int)(p - (long long)P.b * g.npix);
+  const int n0 = g.H[0] * g.W[0];
+  P.img = q < n0 ? 0 : 1;
+  if (P.img) q -= n0;
+  P.W = g.W[P.img];
+  P.wc = g.wrapC[P.img];
+  P.R = q / P.W;
+  P.C = q - P.R * P.W;
+  return P;
+}
+
+// Normalised network input of every pixel: the conservative mean of the two
+// reconstructed face states (positivity fallback as in the stage kernel),
+// face frame, bfloat16.
+__global__ void __launch_bounds__(256) cnn_inputs_kernel(GridArgs a, CnnGeom g, CnnArgs n,
+                                                         const double* __restrict__ U,
+                                                         unsigned short* __restrict__ x) {
+  const long long total = (long long)g.npix * g.nbatch;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+       p += (long long)gridDim.x * blockDim.x) {
+    const PixelLoc P = pixel_loc(g, p);
+    const double* __restrict__ Ub = U + (long long)P.b * 4 * a.ncell;
+    const long long f = pixel_face(P.img, P.R, P.C, a.nx, a.ny);
+    double w[6][4];
+    for (int s = 0; s < 6; ++s) face_cell_prim(a, Ub, f, s, w[s]);
+    double L[4], R[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) weno5_pair(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], a.eps, L[v], R[v]);
+    if (!(L[0] > 0.0) || !(L[3] > 0.0) || !(R[0] > 0.0) || !(R[3] > 0.0))
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { L[v] = w[2][v]; R[v] = w[3][v]; }
+    const double gm1 = a.gamma - 1.0;
+    const double uL[4] = {L[0], L[0] * L[1], L[0] * L[2], L[3] / gm1 + 0.5 * L[0] * (L[1] * L[1] + L[2] * L[2])};
+    const double uR[4] = {R[0], R[0] * R[1], R[0] * R[2], R[3] / gm1 + 0.5 * R[0] * (R[1] * R[1] + R[2] * R[2])};
+    float xv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xv[v] = float((0.5 * (uL[v] + uR[v]) - n.mean[v]) * n.inv_std[v]);
+    *reinterpret_cast<bf16x4*>(x + p * 4) = pack4(xv[0], xv[1], xv[2], xv[3]);
+  }
+}
+
+// Output-layer gradient dz = dF_bar out_scale (1 - tanh^2) per pixel,
+// bfloat16, and this workgroup's sums of dz (bias b3).  dF_bar of a face is
+// (lam_right - lam_left) / h with the periodic wrap, which for the first
+// face of a periodic row already holds both of its uses (as the first and as
+// the last face of the row).
+__global__ void __launch_bounds__(256) cnn_head_kernel(GridArgs a, CnnGeom g, float out_scale,
+                                                       const double* __restrict__ lam, double clam_f,
+                                                       const double* __restrict__ dtp, const float* __restrict__ th,
+                                                       unsigned short* __restrict__ dz, float* __restrict__ part) {
+  __shared__ float red[4][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float bsum[4] = {0.f, 0.f, 0.f, 0.f};
+  const long long total = (long long)g.npix * g.nbatch;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+       p += (long long)gridDim.x * blockDim.x) {
+    const PixelLoc P = pixel_loc(g, p);
+    const double* __restrict__ Lb = lam + (long long)P.b * 4 * a.ncell;
+    const double clam = clam_f * (dtp ? dtp[P.b] : 1.0);
+    double fb[4];
+    face_bar(a, Lb, clam, P.img, P.R, P.C, fb);
+    const f32x4 t = *reinterpret_cast<const f32x4*>(th + p * 4);
+    float d[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      d[i] = float(fb[i]) * out_scale * (1.f - t[i] * t[i]);
+      bsum[i] += d[i];
+    }
+    *reinterpret_cast<bf16x4*>(dz + p * 4) = pack4(d[0], d[1], d[2], d[3]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float s = bsum[i];
+    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+    if (lane == 0) red[wv][i] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4)
+    part[(long long)blockIdx.x * CNN_NP + CNN_G_B3 + threadIdx.x] =
+        ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+}
+
+// Stencil gradient of every face (face frame, w.r.t. the six primitive
+// states) from the gradient of its pixel's normalised input: the mean of
+// the conservative forms of the two reconstructed states, through the
+// WENO5 reverse (or the fallback's adjacent cells).  The last face of a
+// periodic row is the first one seen from the other side and gets the same
+// stencil gradient (the adjoint kernel takes each of the two copies for the
+// cells on its own side).
+__global__ void __launch_bounds__(256) cnn_input_grad_kernel(GridArgs a, CnnGeom g, CnnArgs n,
+                                                             const double* __restrict__ U,
+                                                             const float* __restrict__ dx, float* __restrict__ dX,
+                                                             long long nface) {
+  const long long total = (long long)g.npix * g.nbatch;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+       p += (long long)gridDim.x * blockDim.x) {
+    const PixelLoc P = pixel_loc(g, p);
+    const double* __restrict__ Ub = U + (long long)P.b * 4 * a.ncell;
+    const long long f = pixel_face(P.img, P.R, P.C, a.nx, a.ny);
+    double w[6][4];
+    for (int s = 0; s < 6; ++s) face_cell_prim(a, Ub, f, s, w[s]);
+    double L[4], R[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) weno5_pair(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], a.eps, L[v], R[v]);
+    const bool fallback = !(L[0] > 0.0) || !(L[3] > 0.0) || !(R[0] > 0.0) || !(R[3] > 0.0);
+    if (fallback)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { L[v] = w[2][v]; R[v] = w[3][v]; }
+    const f32x4 d = *reinterpret_cast<const f32x4*>(dx + p * 4);
+    double du[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) du[v] = 0.5 * double(d[v]) * n.inv_std[v];
+    // transpose of d(rho, rho u_n, rho u_t, E)/d(rho, u_n, u_t, p) at each side
+    const double ig = 1.0 / (a.gamma - 1.0);
+    auto side = [&](const double W[4], double o[4]) {
+      o[0] = du[0] + du[1] * W[1] + du[2] * W[2] + du[3] * 0.5 * (W[1] * W[1] + W[2] * W[2]);
+      o[1] = du[1] * W[0] + du[3] * W[0] * W[1];
+      o[2] = du[2] * W[0] + du[3] * W[0] * W[2];
+      o[3] = du[3] * ig;
+    };
+    double lb[4], rb[4];
+    side(L, lb);
+    side(R, rb);
+    double sl[6][4];
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sl[s][v] = 0.0;
+    if (fallback) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { sl[2][v] = lb[v]; sl[3][v] = rb[v]; }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        weno5_vjp(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], a.eps, lb[v], sl[0][v], sl[1][v], sl[2][v], sl[3][v],
+                  sl[4][v]);
+        weno5_vjp(w[5][v], w[4][v], w[3][v], w[2][v], w[1][v], a.eps, rb[v], sl[5][v], sl[4][v], sl[3][v], sl[2][v],
+                  sl[1][v]);
+      }
+    }
+    float* o = dX + ((long long)P.b * nface + f) * 24;
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o[s * 4 + v] = float(sl[s][v]);
+    if (P.wc && P.C == 0) {
+      float* o2 = dX + ((long long)P.b * nface + pixel_face(P.img, P.R, P.W, a.nx, a.ny)) * 24;
+#pragma unroll
+      for (int s = 0; s < 6; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o2[s * 4 + v] = float(sl[s][v]);
+    }
+  }
+}
+
+// The input images as floats (their bf16 values), for tests.
+__global__ void __launch_bounds__(256) cnn_unpack_kernel(const unsigned short* __restrict__ x, float* __restrict__ out,
+                                                         long long n) {
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+    out[k] = __uint_as_float((unsigned int)x[k] << 16);
+}
+
+// grad[k] += the CNN_BLOCKS partials of parameter k in block order (16 waves
+// each take every 16th partial, then the wave sums in wave order).
+__global__ void __launch_bounds__(1024) cnn_grad_reduce_kernel(const float* __restrict__ part, float* __restrict__ grad) {
+  __shared__ double red[16][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + lane;
+  double s = 0.0;
+  if (k < CNN_NP)
+    for (int j = wv; j < CNN_BLOCKS; j += 16) s += part[(long long)j * CNN_NP + k];
+  red[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && k < CNN_NP) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += red[w][lane];
+    grad[k] += float(t);
+  }
+}
+
+// bf16 weight matrices and biases from the FP32 master parameters.
+__global__ void __launch_bounds__(256) cnn_pack_kernel(const float* __restrict__ theta, unsigned short* __restrict__ w,
+                                                       float* __restrict__ bias) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < CNN_NW) {
+    float v = 0.f;
+    auto W1 = [&](int co, int tap, int ci) { return theta[CNN_G_W1 + (co * 9 + tap) * 4 + ci]; };
+    auto W2 = [&](int co, int tap, int ci) { return theta[CNN_G_W2 + (co * 9 + tap) * 16 + ci]; };
+    auto W3 = [&](int co, int tap, int ci) { return theta[CNN_G_W3 + (co * 9 + tap) * 32 + ci]; };
+    if (k < CNN_F2) {  // F1 [16][48]
+      const int row = k / 48, kk = k % 48, tap = kk / 4, ci = kk % 4;
+      if (tap < 9) v = W1(row, tap, ci);
+    } else if (k < CNN_F3) {  // F2 [32][144]
+      const int kk0 = k - CNN_F2, row = kk0 / 144, kk = kk0 % 144;
+      v = W2(row, kk / 16, kk % 16);
+    } else if (k < CNN_B3) {  // F3 [16][288]
+      const int kk0 = k - CNN_F3, row = kk0 / 288, kk = kk0 % 288;
+      if (row < 4) v = W3(row, kk / 32, kk % 32);
+    } else if (k < CNN_B2) {  // B3 [32][48]: row = layer-3 input channel
+      const int kk0 = k - CNN_B3, row = kk0 / 48, kk = kk0 % 48, tap = kk / 4, co = kk % 4;
+      if (tap < 9) v = W3(co, 8 - tap, row);
+    } else if (k < CNN_B1) {  // B2 [16][288]
+      const int kk0 = k - CNN_B2, row = kk0 / 288, kk = kk0 % 288;
+      v = W2(kk % 32, 8 - kk / 32, row);
+    } else {  // B1 [16][144]
+      const int kk0 = k - CNN_B1, row = kk0 / 144, kk = kk0 % 144;
+      if (row < 4) v = W1(kk % 16, 8 - kk / 16, row);
+    }
+    w[k] = f2bf(v);
+  }
+  if (k < CNN_NB) {
+    float v = 0.f;
+    if (k < 16) v = theta[CNN_G_B1 + k];
+    else if (k < 48) v = theta[CNN_G_B2 + k - 16];
+    else if (k < 52) v = theta[CNN_G_B3 + k - 48];
+    bias[k] = v;
+  }
+}
+
+unsigned int pixel_blocks(const CnnGeom& g) {
+  const long long n = ((long long)g.npix * g.nbatch + 255) / 256;
+  return (unsigned int)(n < 1 ? 1 : (n > 4096 ? 4096 : n));
+}
+
+unsigned int tile_blocks(const CnnGeom& g) {
+  const long long n = (long long)g.tiles * g.nbatch;
+  return (unsigned int)(n < 1 ? 1 : (n > 8192 ? 8192 : n));
+}
+
+}  // namespace
+
+CnnGeom cnn_geom(const GridArgs& a) {
+  CnnGeom g{};
+  const int perx = a.bc[0] == BC_PERIODIC, pery = a.bc[2] == BC_PERIODIC;
+  g.H[0] = a.ny;
+  g.W[0] = perx ? a.nx : a.nx + 1;
+  g.wrapR[0] = pery;
+  g.wrapC[0] = perx;
+  g.H[1] = a.nx;
+  g.W[1] = pery ? a.ny : a.ny + 1;
+  g.wrapR[1] = perx;
+  g.wrapC[1] = pery;
+  for (int i = 0; i < 2; ++i) {
+    g.tilesR[i] = (g.H[i] + 15) / 16;
+    g.tilesC[i] = (g.W[i] + 15) / 16;
+  }
+  g.npix = g.H[0] * g.W[0] + g.H[1] * g.W[1];
+  g.tiles = g.tilesR[0] * g.tilesC[0] + g.tilesR[1] * g.tilesC[1];
+  g.nbatch = a.nbatch;
+  return g;
+}
+
+static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t cnn_workspace_bytes(const GridArgs& a) {
+  const CnnGeom g = cnn_geom(a);
+  const size_t np = (size_t)g.npix * a.nbatch;
+  // bf16 images: 4 + 16 + 32 + 4 + 32 + 16 channels; FP32: tanh and input gradient
+  return al256(np * 4 * 2) + al256(np * 16 * 2) + al256(np * 32 * 2) + al256(np * 4 * 2) + al256(np * 32 * 2) +
+         al256(np * 16 * 2) + al256(np * 4 * 4) + al256(np * 4 * 4) + al256((size_t)CNN_BLOCKS * CNN_NP * 4);
+}
+
+CnnBufs cnn_bufs(const GridArgs& a, char* base) {
+  const CnnGeom g = cnn_geom(a);
+  const size_t np = (size_t)g.npix * a.nbatch;
+  CnnBufs b{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { char* p = base + o; o += al256(bytes); return p; };
+  b.x = reinterpret_cast<unsigned short*>(take(np * 4 * 2));
+  b.h1 = reinterpret_cast<unsigned short*>(take(np * 16 * 2));
+  b.h2 = reinterpret_cast<unsigned short*>(take(np * 32 * 2));
+  b.dz = reinterpret_cast<unsigned short*>(take(np * 4 * 2));
+  b.da2 = reinterpret_cast<unsigned short*>(take(np * 32 * 2));
+  b.da1 = reinterpret_cast<unsigned short*>(take(np * 16 * 2));
+  b.t = reinterpret_cast<float*>(take(np * 4 * 4));
+  b.dx = reinterpret_cast<float*>(take(np * 4 * 4));
+  b.part = reinterpret_cast<float*>(take((size_t)CNN_BLOCKS * CNN_NP * 4));
+  return b;
+}
+
+hipError_t launch_cnn_pack(const float* theta, unsigned short* w, float* bias, hipStream_t st) {
+  hipLaunchKernelGGL(cnn_pack_kernel, dim3((CNN_NW + 255) / 256), dim3(256), 0, st, theta, w, bias);
+  return hipGetLastError();
+}
+
+hipError_t launch_cnn_forward(const GridArgs& a, const CnnArgs& n, const double* U, float* dF, const CnnBufs& b,
+                              hipStream_t st) {
+  const CnnGeom g = cnn_geom(a);
+  hipLaunchKernelGGL(cnn_inputs_kernel, dim3(pixel_blocks(g)), dim3(256), 0, st, a, g, n, U, b.x);
+  ConvOut o{};
+  o.out_bf = b.h1;
+  hipLaunchKernelGGL((cnn_conv_kernel<4, 1, 3, EPI_FWD_HIDDEN>), dim3(tile_blocks(g)), dim3(256), 0, st, g, b.x,
+                     n.w + CNN_F1, n.bias + CNN_BB1, o);
+  o.out_bf = b.h2;
+  hipLaunchKernelGGL((cnn_conv_kernel<16, 2, 9, EPI_FWD_HIDDEN>), dim3(tile_blocks(g)), dim3(256), 0, st, g, b.h1,
+                     n.w + CNN_F2, n.bias + CNN_BB2, o);
+  ConvOut o3{};
+  o3.out_f = b.t;
+  o3.out_scale = n.out_scale;
+  o3.dF = dF;
+  o3.nface = (long long)(a.nx + 1) * a.ny + (long long)a.nx * (a.ny + 1);
+  o3.nx = a.nx;
+  o3.ny = a.ny;
+  o3.fault = &a.glob->fault;
+  hipLaunchKernelGGL((cnn_conv_kernel<32, 1, 18, EPI_FWD_OUT>), dim3(tile_blocks(g)), dim3(256), 0, st, g, b.h2,
+                     n.w + CNN_F3, n.bias + CNN_BB3, o3);
+  return hipGetLastError();
+}
+
+hipError_t launch_cnn_backward(const GridArgs& a, const CnnArgs& n, const double* U, const double* lam,
+                               double clam_f, const double* dtp, float* dX, float* dF, const CnnBufs& b, float* grad,
+                               hipStream_t st) {
+  hipError_t e = launch_cnn_forward(a, n, U, dF, b, st);
+  if (e != hipSuccess) return e;
+  const CnnGeom g = cnn_geom(a);
+  const long long nface = (long long)(a.nx + 1) * a.ny + (long long)a.nx * (a.ny + 1);
+  hipLaunchKernelGGL(cnn_head_kernel, dim3(CNN_BLOCKS), dim3(256), 0, st, a, g, n.out_scale, lam, clam_f, dtp, b.t,
+                     b.dz, b.part);
+  ConvOut o{};
+  o.part = b.part;
+  // layer 3: input gradient (32 channels, masked by the layer-2 ReLU) and weights
+  o.out_bf = b.da2;
+  o.mask_src = b.h2;
+  o.part_off = CNN_G_B2;
+  o.cout = 32;
+  hipLaunchKernelGGL((cnn_conv_kernel<4, 2, 3, EPI_BWD_HIDDEN>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.dz,
+                     n.w + CNN_B3, nullptr, o);
+  hipLaunchKernelGGL((cnn_wgrad_kernel<32, 4, 1, 18>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.dz, b.h2, b.part,
+                     CNN_G_W3);
+  // layer 2
+  o.out_bf = b.da1;
+  o.mask_src = b.h1;
+  o.part_off = CNN_G_B1;
+  o.cout = 16;
+  hipLaunchKernelGGL((cnn_conv_kernel<32, 1, 18, EPI_BWD_HIDDEN>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.da2,
+                     n.w + CNN_B2, nullptr, o);
+  hipLaunchKernelGGL((cnn_wgrad_kernel<16, 32, 2, 9>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.da2, b.h1, b.part,
+                     CNN_G_W2);
+  // layer 1: gradient of the normalised inputs, and weights
+  ConvOut o1{};
+  o1.out_f = b.dx;
+  hipLaunchKernelGGL((cnn_conv_kernel<16, 1, 9, EPI_BWD_IN>), dim3(tile_blocks(g)), dim3(256), 0, st, g, b.da1,
+                     n.w + CNN_B1, nullptr, o1);
+  hipLaunchKernelGGL((cnn_wgrad_kernel<4, 16, 1, 3>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.da1, b.x, b.part,
+                     CNN_G_W1);
+  hipLaunchKernelGGL(cnn_input_grad_kernel, dim3(pixel_blocks(g)), dim3(256), 0, st, a, g, n, U, b.dx, dX, nface);
+  e = hipGetLastError();
+  if (e != hipSuccess || grad == nullptr) return e;
+  hipLaunchKernelGGL(cnn_grad_reduce_kernel, dim3((CNN_NP + 63) / 64), dim3(1024), 0, st, b.part, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_cnn_images(const GridArgs& a, const CnnArgs& n, const double* U, const CnnBufs& b, float* out,
+                             hipStream_t st) {
+  const CnnGeom g = cnn_geom(a);
+  hipLaunchKernelGGL(cnn_inputs_kernel, dim3(pixel_blocks(g)), dim3(256), 0, st, a, g, n, U, b.x);
+  const long long cnt = (long long)g.npix * g.nbatch * 4;
+  hipLaunchKernelGGL(cnn_unpack_kernel, dim3((unsigned int)((cnt + 255) / 256 > 4096 ? 4096 : (cnt + 255) / 256)),
+                     dim3(256), 0, st, b.x, out, cnt);
+  return hipGetLastError();
+}
+
+}  // namespace shk

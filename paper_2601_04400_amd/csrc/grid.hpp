@@ -48,6 +48,7 @@ struct GridArgs {
   const int* ghost_of;         // immersed boundary, adjoint grids: ghost index of each cell or -1 (else nullptr)
   unsigned long long* xslots;  // [nbatch][2][XSLOTS] spread extrema of the fused step
   const float* dXnet;          // its stencil gradient per face [nbatch][nface][24] or nullptr
+  const float* dFext;          // precomputed face correction [nbatch][nface][4] (face frame) or nullptr
   long long nface;             // x-faces (nx+1)*ny then y-faces nx*(ny+1)
   Globals* glob;
 };
@@ -90,6 +91,8 @@ hipError_t launch_ibm_table(const GridArgs& a, const double* phi, const uint8_t*
 // FP64, inviscid; modes MODE_RHS .. MODE_STAGE3).
 hipError_t launch_stage_net(const GridArgs& a, const NetArgs& n, int mode, const double* Us, const double* Un,
                             double* Uout, const double* dtp, hipStream_t st);
+hipError_t launch_stage_ext(const GridArgs& a, int mode, const double* Us, const double* Un, double* Uo,
+                            const double* dtp, hipStream_t st);
 hipError_t launch_stage_mixed(const GridArgs& a, int mode, const float* Us, const float* Un, float* Uout,
                               const double* dtp, const float* Lin, hipStream_t st);
 
@@ -129,5 +132,8 @@ hipError_t launch_axpy(long long n, double alpha, const double* x, double* y, in
 // stage modes
 enum : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2, MODE_STAGE3 = 3,
              MODE_S1L = 4, MODE_S2F = 5, MODE_S3F = 6 };
+// learned correction inside the stage kernel: none, the per-face network
+// evaluated in the tile, or a precomputed per-face correction (dFext)
+enum : int { NET_NONE = 0, NET_MLP = 1, NET_EXT = 2 };
 
 }  // namespace shk

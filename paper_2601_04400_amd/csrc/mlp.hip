@@ -22,6 +22,7 @@
 
 #include <cmath>
 
+#include "face_dev.hpp"
 #include "flux.hpp"
 #include "grid.hpp"
 #include "mlp.hpp"
@@ -30,59 +31,6 @@
 namespace shk {
 
 namespace {
-
-// Primitive state (rho, u_n, u_t, p) of stencil cell s (0..5) of face f of
-// batch member Ub; x-faces first ((nx+1) per row), then y-faces (nx per row).
-// The faces of one batch member are indexed in 32 bits.
-__device__ __forceinline__ void face_cell_prim(const GridArgs& a, const double* __restrict__ Ub, long long f, int s,
-                                               double w[4]) {
-  const int fi = (int)f, nxf = (a.nx + 1) * a.ny;
-  int gi, gj;
-  bool isx = fi < nxf;
-  if (isx) {
-    gj = fi / (a.nx + 1);
-    gi = fi - gj * (a.nx + 1) - 3 + s;
-  } else {
-    const int g = fi - nxf;
-    const int r = g / a.nx;
-    gi = g - r * a.nx;
-    gj = r - 3 + s;
-  }
-  double q[4];
-  // boundary rules as in the stage kernel
-  int fx = 0, fy = 0;
-  auto src = [](int g, int n, int lo, int hi, int& flag) {
-    if (g >= 0 && g < n) return g;
-    const bool l = g < 0;
-    const int bc = l ? lo : hi;
-    const int depth = l ? -g : g - (n - 1);
-    int r;
-    switch (bc) {
-      case BC_REFL: r = l ? depth - 1 : n - depth; flag |= 1; break;
-      case BC_INFLOW: r = l ? 0 : n - 1; flag = 2; break;
-      case BC_PERIODIC: r = ((g % n) + n) % n; break;
-      default: r = l ? 0 : n - 1; break;
-    }
-    return r < 0 ? 0 : (r >= n ? n - 1 : r);
-  };
-  const int si = src(gi, a.nx, a.bc[0], a.bc[1], fx);
-  const int sj = src(gj, a.ny, a.bc[2], a.bc[3], fy);
-  if (fx == 2 || fy == 2) {
-    for (int v = 0; v < 4; ++v) q[v] = a.inflow_cons[v];
-  } else {
-    const long long c = (long long)sj * a.nx + si;
-    q[0] = Ub[c]; q[1] = Ub[a.ncell + c]; q[2] = Ub[2 * a.ncell + c]; q[3] = Ub[3 * a.ncell + c];
-    if (fx & 1) q[1] = -q[1];
-  }
-  if (fy & 1) q[2] = -q[2];
-  // the same conversion as the stage kernel's tile load, so the network sees
-  // bit-identical inputs on both paths
-  const Prim<double> p = to_prim(q[0], q[1], q[2], q[3], a.gamma - 1.0);
-  w[0] = p.r;
-  w[1] = isx ? p.un : p.ut;
-  w[2] = isx ? p.ut : p.un;
-  w[3] = p.p;
-}
 
 __device__ __forceinline__ void build_inputs(const GridArgs& a, const NetArgs& n, const double* __restrict__ Ub,
                                              long long f, int lane, bf16x4& x0, bf16x4& x1) {

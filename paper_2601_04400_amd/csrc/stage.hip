@@ -151,11 +151,13 @@ __device__ __forceinline__ bool finite_val(C x) {
 //   MODE_S3F: stage 3 with the step of S2F; one block advances the device
 //             time and clears the extrema for the next step.
 //
-// NET: the learned face-flux correction (section 2 neural flux, per-face
-// MLP) is evaluated inside the tile, on matrix cores, from the primitive
-// halo the tile has already loaded, and added to each face flux in the face
-// frame before the divergence.
-template <class S, class C, int NDIM, int TX, int TY, bool VISC, int MODE, bool NET = false>
+// NET (learned face-flux correction, section 2 neural flux; added to each
+// face flux in the face frame before the divergence):
+//   NET_MLP: the per-face MLP, evaluated inside the tile on matrix cores from
+//            the primitive halo the tile has already loaded;
+//   NET_EXT: a correction computed beforehand for every face (the
+//            convolutional network), read from a.dFext.
+template <class S, class C, int NDIM, int TX, int TY, bool VISC, int MODE, int NET = NET_NONE>
 __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restrict__ Us,
                                                     const S* __restrict__ Un, S* __restrict__ Uout,
                                                     const double* __restrict__ dtp,
@@ -173,13 +175,14 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
   __shared__ C fxs[4][TY * (TX + 1)];
   __shared__ C fys[4][FYR * TX];
   __shared__ unsigned int blk_fallback, blk_fault;
-  static_assert(!NET || (NDIM == 2 && !VISC), "learned correction: 2D inviscid tiles");
-  __shared__ __attribute__((aligned(16))) unsigned short net_w[NET ? NET_NW : 1];
-  __shared__ float net_b[NET ? NET_NB : 1];
+  static_assert(NET == NET_NONE || (NDIM == 2 && !VISC), "learned correction: 2D inviscid tiles");
+  constexpr bool MLP = NET == NET_MLP;
+  __shared__ __attribute__((aligned(16))) unsigned short net_w[MLP ? NET_NW : 1];
+  __shared__ float net_b[MLP ? NET_NB : 1];
   // normalised network inputs of every halo cell, bfloat16, in the x-face
   // frame (rho, u, v, p) and the y-face frame (rho, v, u, p): each cell feeds
   // twelve faces, so it is converted once here
-  __shared__ bf16x4 net_in[NET ? 2 : 1][NET ? PY * PX : 1];
+  __shared__ bf16x4 net_in[MLP ? 2 : 1][MLP ? PY * PX : 1];
   __shared__ double red_s[NT / 64], red_r[NT / 64];
 
   int bx, by, b;
@@ -242,7 +245,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     return C(S(C(Ub[e * a.ncell + c]) + cdt * C(Lb[e * a.ncell + c])));
   };
 
-  if (NET) load_net_lds(net, net_w, net_b);
+  if (MLP) load_net_lds(net, net_w, net_b);
 
   // 1. halo tile of primitives
   for (int k = threadIdx.x; k < PY * PX; k += NT) {
@@ -262,7 +265,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     w[1][k] = p.un;
     w[2][k] = p.ut;
     w[3][k] = p.p;
-    if (NET) {
+    if (MLP) {
       const double pv[4] = {double(p.r), double(p.un), double(p.ut), double(p.p)};
       float xn[4], yn[4];
 #pragma unroll
@@ -294,7 +297,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     }
   };
 
-  if (NET) {
+  if (MLP) {
     // 1b. learned correction of every face of the tile on the matrix cores,
     // 32 faces per wave and batch (the tile's 552 faces split evenly over
     // the four waves); the network output before its tanh is parked in the
@@ -349,6 +352,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     const bool isx = k < NFX;
     int s0, st, cn, ct, oidx;
     bool owned;  // this tile is the one that reports the face (fallback count)
+    long long gface = -1;  // NET_EXT: the face's index, -1 outside the domain
     if (isx) {
       const int fi = k % (TX + 1), y = k / (TX + 1);
       s0 = (NDIM == 2 ? (y + H) * PX : 0) + fi;
@@ -356,6 +360,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
       oidx = y * (TX + 1) + fi;
       const int gf = i0 + fi;
       owned = j0 + y < a.ny && gf <= a.nx && (fi < TX || gf == a.nx);
+      if (NET == NET_EXT && j0 + y < a.ny && gf <= a.nx) gface = (long long)(j0 + y) * (a.nx + 1) + gf;
     } else {
       const int kk = k - NFX;
       const int x = kk % TX, fj = kk / TX;
@@ -364,6 +369,8 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
       oidx = fj * TX + x;
       const int gf = j0 + fj;
       owned = i0 + x < a.nx && gf <= a.ny && (fj < TY || gf == a.ny);
+      if (NET == NET_EXT && i0 + x < a.nx && gf <= a.ny)
+        gface = (long long)(a.nx + 1) * a.ny + (long long)gf * a.nx + i0 + x;
     }
     Prim<C> L, R;
     {
@@ -409,7 +416,14 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
       F.f2 = F.f2 - tnt;
       F.f3 = F.f3 - (ubn * tnn + ubt * tnt - qn);
     }
-    if (NET) {
+    if (NET == NET_EXT && gface >= 0) {
+      const float* d = a.dFext + ((long long)b * a.nface + gface) * 4;
+      F.f0 = F.f0 + C(d[0]);
+      F.f1 = F.f1 + C(d[1]);
+      F.f2 = F.f2 + C(d[2]);
+      F.f3 = F.f3 + C(d[3]);
+    }
+    if (MLP) {
       // learned correction of this face (face frame): out_scale tanh of the
       // network output parked by pass 1b; a non-finite value leaves the
       // uncorrected flux and is flagged
@@ -437,7 +451,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     }
   }
   if (my_fallback) atomicAdd(&blk_fallback, my_fallback);
-  if (NET && net_bad) atomicOr(&blk_fault, 8u);
+  if (MLP && net_bad) atomicOr(&blk_fault, 8u);
   __syncthreads();
 
   // 3. flux difference and Runge-Kutta combination
@@ -724,25 +738,37 @@ static hipError_t launch_stage_c(const GridArgs& a, int mode, const S* Us, const
   }
 }
 
-template <int MODE>
+template <int MODE, int NETK>
 static hipError_t launch_net_mode(const GridArgs& a, const NetArgs& n, const double* Us, const double* Un,
                                   double* Uo, const double* dtp, hipStream_t st) {
   dim3 grid((a.nx + TX2 - 1) / TX2, (a.ny + TY2 - 1) / TY2, a.nbatch);
-  hipLaunchKernelGGL((stage_kernel<double, double, 2, TX2, TY2, false, MODE, true>), grid, dim3(256), 0, st, a, Us,
+  hipLaunchKernelGGL((stage_kernel<double, double, 2, TX2, TY2, false, MODE, NETK>), grid, dim3(256), 0, st, a, Us,
                      Un, Uo, dtp, nullptr, n);
   return hipGetLastError();
+}
+
+template <int NETK>
+static hipError_t launch_net_modes(const GridArgs& a, const NetArgs& n, int mode, const double* Us,
+                                   const double* Un, double* Uo, const double* dtp, hipStream_t st) {
+  switch (mode) {
+    case MODE_RHS: return launch_net_mode<MODE_RHS, NETK>(a, n, Us, Un, Uo, dtp, st);
+    case MODE_STAGE1: return launch_net_mode<MODE_STAGE1, NETK>(a, n, Us, Un, Uo, dtp, st);
+    case MODE_STAGE2: return launch_net_mode<MODE_STAGE2, NETK>(a, n, Us, Un, Uo, dtp, st);
+    case MODE_STAGE3: return launch_net_mode<MODE_STAGE3, NETK>(a, n, Us, Un, Uo, dtp, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_stage_net(const GridArgs& a, const NetArgs& n, int mode, const double* Us, const double* Un,
                             double* Uo, const double* dtp, hipStream_t st) {
   if (a.ndim != 2 || a.viscous) return hipErrorInvalidValue;
-  switch (mode) {
-    case MODE_RHS: return launch_net_mode<MODE_RHS>(a, n, Us, Un, Uo, dtp, st);
-    case MODE_STAGE1: return launch_net_mode<MODE_STAGE1>(a, n, Us, Un, Uo, dtp, st);
-    case MODE_STAGE2: return launch_net_mode<MODE_STAGE2>(a, n, Us, Un, Uo, dtp, st);
-    case MODE_STAGE3: return launch_net_mode<MODE_STAGE3>(a, n, Us, Un, Uo, dtp, st);
-    default: return hipErrorInvalidValue;
-  }
+  return launch_net_modes<NET_MLP>(a, n, mode, Us, Un, Uo, dtp, st);
+}
+
+hipError_t launch_stage_ext(const GridArgs& a, int mode, const double* Us, const double* Un, double* Uo,
+                            const double* dtp, hipStream_t st) {
+  if (a.ndim != 2 || a.viscous || a.dFext == nullptr) return hipErrorInvalidValue;
+  return launch_net_modes<NET_EXT>(a, NetArgs{}, mode, Us, Un, Uo, dtp, st);
 }
 
 // double storage: double arithmetic.  float storage: float arithmetic unless

@@ -56,6 +56,8 @@ def init_theta(seed=0, zero_output=False):
 class FluxNet:
     """FP32 master parameters with Adam state and the bf16 device form."""
 
+    kind = "mlp"
+
     def __init__(self, theta, mean=DEFAULT_MEAN, inv_std=None, out_scale=DEFAULT_OUT_SCALE, device="cuda"):
         self.theta = torch.as_tensor(np.asarray(theta, dtype=np.float32)).to(device).contiguous()
         assert self.theta.numel() == NP
@@ -80,6 +82,71 @@ class FluxNet:
         self.pack()
 
 
+CNN_NP, CNN_NW, CNN_NB = 6388, 18432, 64
+# Fixed normalisation of the convolutional network's conservative inputs
+# (rho, rho u_n, rho u_t, E) from the sampling ranges of the training states.
+CNN_MEAN = (0.8, 0.0, 0.0, 2.2)
+CNN_STD = (0.4, 0.6, 0.6, 1.2)
+
+
+def init_cnn_theta(seed=0, zero_output=False):
+    """He-style random parameters of the convolutional correction in theta
+    order (W1, b1, W2, b2, W3, b3; W[out][3][3][in]), FP32, host."""
+    g = np.random.default_rng(seed)
+    parts = []
+    for cout, cin in ((16, 4), (32, 16), (4, 32)):
+        W = g.normal(size=(cout, 3, 3, cin)) * math.sqrt(2.0 / (9 * cin))
+        if cout == 4:
+            W = W * (0.0 if zero_output else 0.1)
+        parts += [W.ravel(), np.zeros(cout)]
+    theta = np.concatenate(parts).astype(np.float32)
+    assert theta.size == CNN_NP
+    return theta
+
+
+class FluxCnn:
+    """The convolutional correction (section 2's 2D form): FP32 master
+    parameters with Adam state and the bf16 device form."""
+
+    kind = "cnn"
+
+    def __init__(self, theta, mean=CNN_MEAN, inv_std=None, out_scale=DEFAULT_OUT_SCALE, device="cuda"):
+        self.theta = torch.as_tensor(np.asarray(theta, dtype=np.float32)).to(device).contiguous()
+        assert self.theta.numel() == CNN_NP
+        self.mean = tuple(float(x) for x in mean)
+        self.inv_std = tuple(float(x) for x in (inv_std or [1.0 / s for s in CNN_STD]))
+        self.out_scale = float(out_scale)
+        self.w = torch.empty(CNN_NW, dtype=torch.int16, device=device)
+        self.bias = torch.empty(CNN_NB, dtype=torch.float32, device=device)
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
+        self.grad = torch.zeros_like(self.theta)
+        self.step_count = 0
+        self.pack()
+
+    def pack(self):
+        check(lib().shk_flux_cnn_pack(_p(self.theta), _p(self.w), _p(self.bias), _stream()), None, "flux_cnn_pack")
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_count += 1
+        check(lib().shk_adam(_p(self.theta), _p(self.grad), _p(self.m), _p(self.v), CNN_NP, lr, beta1, beta2, eps,
+                             self.step_count, _stream()), None, "adam")
+        self.pack()
+
+
+def net_kind(net):
+    """desc.flux_net of a grid that can carry this network."""
+    return 2 if getattr(net, "kind", "mlp") == "cnn" else 1
+
+
+def attach(g, net):
+    """Set (or clear, net None) the correction of grid g."""
+    if g.desc.flux_net == 2:
+        g.set_flux_cnn(net)
+    else:
+        g.set_flux_net(net)
+
+
 def restrict(fine, factor):
     """Block average (device doubles [nb][nv][ny][nx]) by factor."""
     nb, nv, ny, nx = fine.shape
@@ -95,9 +162,13 @@ def mse_accumulate(U, T, G, scale, loss, part):
     check(lib().shk_mse(_p(U), _p(T), _p(G), float(scale), per, nb, _p(part), _p(loss), _stream()), None, "mse")
 
 
-def riemann_batch(seeds, n, device="cuda"):
-    """Primitive fields of random four-quadrant problems (one per seed)."""
-    W = np.stack([inputs.riemann2d_prim(n, n, states=S) for S in inputs.riemann_batch_states(seeds)])
+def riemann_batch(seeds, n, device="cuda", ny=None):
+    """Primitive fields of random four-quadrant problems (one per seed) on
+    n x ny cells of [0, 1] x [0, ny / n], quadrants split at the centre."""
+    ny = ny or n
+    dom = (0.0, 1.0, 0.0, ny / n)
+    W = np.stack([inputs.riemann2d_prim(n, ny, states=S, split=(0.5, 0.5 * ny / n), domain=dom)
+                  for S in inputs.riemann_batch_states(seeds)])
     return torch.from_numpy(W).to(device)
 
 
@@ -113,9 +184,10 @@ def sod_rows_prim(nx, rows):
 class Dataset:
     """Coarse (restricted) snapshots of fine runs: snaps[k] = d(U_fine(k dt_c)).
 
-    case "riemann": random four-quadrant problems (one per seed) on nc^2
-    against (nc * factor)^2, transmissive boundaries, coarse step
-    cfl_frac x the CFL step of each initial coarse state.
+    case "riemann": random four-quadrant problems (one per seed) on nc x ny
+    coarse cells (ny = nc unless given) against factor times finer,
+    transmissive boundaries, coarse step cfl_frac x the CFL step of each
+    initial coarse state.
     case "sod" (the 1D problem of section 3; seeds ignored): Sod's shock tube
     with nc cells against nc * factor, as `rows` identical rows of a 2D grid
     (transmissive boundaries make every y-face of a column see one stencil,
@@ -124,13 +196,13 @@ class Dataset:
     """
 
     def __init__(self, seeds, nc=128, factor=4, nsnap=24, cfl_frac=0.5, device="cuda", keep_fine_ic=False,
-                 case="riemann", rows=4, t_end=0.25):
+                 case="riemann", rows=4, t_end=0.25, ny=None):
         self.case = case
         if case == "riemann":
             nb = len(seeds)
-            nxc = nyc = nc
-            W = riemann_batch(seeds, nc * factor, device)
-            self.domain = (0.0, 1.0, 0.0, 1.0)
+            nxc, nyc = nc, ny or nc
+            W = riemann_batch(seeds, nc * factor, device, ny=nyc * factor)
+            self.domain = (0.0, 1.0, 0.0, nyc / nc)
         elif case == "sod":
             nb, nxc, nyc = 1, nc, rows
             W = torch.from_numpy(sod_rows_prim(nc * factor, rows * factor)).to(device)
@@ -178,8 +250,8 @@ def train(net, data, iters=400, m=4, lr=1e-3, lr_late=1e-4, switch=None, log_eve
     snapshot used, default the data set's last)."""
     nb = data.nb
     last = data.nsnap if last is None else last
-    g = data.grid(adjoint=True, flux_net=True, device=data.snaps.device)
-    g.set_flux_net(net)
+    g = data.grid(adjoint=True, flux_net=net_kind(net), device=data.snaps.device)
+    attach(g, net)
     g.set_flux_net_grad(net.grad)
     part = torch.empty(nb * 256, dtype=torch.float64, device=data.snaps.device)
     tapes = torch.empty((m, 3) + tuple(g.shape), dtype=torch.float64, device=data.snaps.device)
@@ -212,8 +284,8 @@ def dataset_loss(net, data, m=4, last=None):
     the data set (net = None: the uncorrected solver)."""
     nb = data.nb
     last = data.nsnap if last is None else last
-    g = data.grid(flux_net=True, device=data.snaps.device)
-    g.set_flux_net(net)
+    g = data.grid(flux_net=net_kind(net), device=data.snaps.device)
+    attach(g, net)
     part = torch.empty(nb * 256, dtype=torch.float64, device=data.snaps.device)
     loss = torch.zeros(nb, dtype=torch.float64, device=data.snaps.device)
     for k in range(last - m + 1):
@@ -224,14 +296,14 @@ def dataset_loss(net, data, m=4, last=None):
     return float(loss.sum()) / m
 
 
-def evaluate(net, seeds, nc=128, factor=4, nsteps=24, cfl_frac=0.5, device="cuda"):
+def evaluate(net, seeds, nc=128, factor=4, nsteps=24, cfl_frac=0.5, device="cuda", ny=None):
     """Held-out error of the coarse solver with and without the correction
     against the restricted fine solution after nsteps coarse steps (mean
     squared error over all conserved entries -- the training metric -- and
     mean absolute error), with the time per coarse step of each and of the
     finer solvers (half spacing, and the fine reference itself)."""
     data = Dataset(seeds, nc=nc, factor=factor, nsnap=nsteps, cfl_frac=cfl_frac, device=device,
-                   keep_fine_ic=True)
+                   keep_fine_ic=True, ny=ny)
     target = data.snaps[-1]
 
     def errs(U):
@@ -241,7 +313,7 @@ def evaluate(net, seeds, nc=128, factor=4, nsteps=24, cfl_frac=0.5, device="cuda
                                     "note": "the reference itself (restricted fine solution)"}}
     if factor >= 4:
         nm = nc * 2
-        gm = Grid(nm, nm, nbatch=len(seeds), device=device)
+        gm = Grid(nm, nm * data.ny // nc, nbatch=len(seeds), domain=data.domain, device=device)
         Um = restrict(data.fine_ic, factor // 2)
         dtm = (data.dt_c / 2).contiguous()
         torch.cuda.synchronize()
@@ -253,8 +325,8 @@ def evaluate(net, seeds, nc=128, factor=4, nsteps=24, cfl_frac=0.5, device="cuda
         out[f"plain_{nm}"] = dict(errs(restrict(Um, 2)), ms_per_step=el * 1e3 / nsteps)
     marks = sorted({max(1, nsteps // 3), max(1, 2 * nsteps // 3), nsteps})
     for name, use in (("plain", False), ("learned", True)):
-        g = Grid(nc, nc, nbatch=len(seeds), flux_net=True, device=device)
-        g.set_flux_net(net if use else None)
+        g = data.grid(len(seeds), flux_net=net_kind(net), device=device)
+        attach(g, net if use else None)
         U = data.snaps[0].clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -283,8 +355,8 @@ def evaluate_sod(net, data, marks):
     the time per coarse step."""
     out = {}
     for name, use in (("plain", False), ("learned", True)):
-        g = data.grid(flux_net=True, device=data.snaps.device)
-        g.set_flux_net(net if use else None)
+        g = data.grid(flux_net=net_kind(net), device=data.snaps.device)
+        attach(g, net if use else None)
         U = data.snaps[0].clone()
         errs = {}
         torch.cuda.synchronize()
@@ -343,6 +415,8 @@ def main():
     ap.add_argument("--lr-late", type=float, default=1e-4)
     ap.add_argument("--out", default=None)
     ap.add_argument("--case", choices=("riemann", "sod"), default="riemann")
+    ap.add_argument("--net", choices=("mlp", "cnn"), default="mlp")
+    ap.add_argument("--ny", type=int, default=None, help="coarse rows (default: nc)")
     ap.add_argument("--nc-sod", type=int, default=500)
     ap.add_argument("--nsnap-sod", type=int, default=625)
     ap.add_argument("--m-sod", type=int, default=64)
@@ -351,9 +425,9 @@ def main():
     if a.case == "sod":
         return main_sod(a)
     t0 = time.perf_counter()
-    data = Dataset(list(range(a.train_seeds)), nc=a.nc, factor=a.factor, nsnap=a.nsnap)
+    data = Dataset(list(range(a.train_seeds)), nc=a.nc, factor=a.factor, nsnap=a.nsnap, ny=a.ny)
     print(f"data: {a.train_seeds} problems, {a.nsnap} coarse snapshots, {time.perf_counter() - t0:.1f} s", flush=True)
-    net = FluxNet(init_theta(0, zero_output=True))
+    net = FluxCnn(init_cnn_theta(0, zero_output=True)) if a.net == "cnn" else FluxNet(init_theta(0, zero_output=True))
     before = dataset_loss(net, data, m=a.m)
     t1 = time.perf_counter()
     hist = train(net, data, iters=a.iters, m=a.m, lr=a.lr, lr_late=a.lr_late, log_every=50,
@@ -361,9 +435,9 @@ def main():
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
     after = dataset_loss(net, data, m=a.m)
-    ev = evaluate(net, list(range(1000, 1000 + a.heldout)), nc=a.nc, factor=a.factor, nsteps=a.nsnap)
-    res = {"train_problems": a.train_seeds, "heldout_problems": a.heldout, "coarse": a.nc,
-           "fine": a.nc * a.factor, "unroll_m": a.m, "iters": a.iters, "train_seconds": round(train_s, 2),
+    ev = evaluate(net, list(range(1000, 1000 + a.heldout)), nc=a.nc, factor=a.factor, nsteps=a.nsnap, ny=a.ny)
+    res = {"net": a.net, "train_problems": a.train_seeds, "heldout_problems": a.heldout, "coarse": a.nc,
+           "coarse_rows": data.ny, "fine": a.nc * a.factor, "unroll_m": a.m, "iters": a.iters, "train_seconds": round(train_s, 2),
            "train_ms_per_iter": round(train_s * 1e3 / a.iters, 3), "training_loss_before": before,
            "training_loss_after": after, "heldout": ev, "history": hist}
     print(json.dumps(res), flush=True)

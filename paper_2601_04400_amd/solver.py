@@ -151,6 +151,51 @@ class Grid:
               self.handle, "set_flux_net")
         self.net = net
 
+    def set_flux_cnn(self, net):
+        """Attach a learn.FluxCnn (the convolutional correction; grid created
+        with flux_net=2) or None."""
+        self.version += 1
+        if net is None:
+            check(lib().shk_set_flux_cnn(self.handle, None, None, None, 0.0, 0), self.handle, "set_flux_cnn")
+            self.net = None
+            return
+        norm = (ctypes.c_double * 8)(*net.mean, *net.inv_std)
+        check(lib().shk_set_flux_cnn(self.handle, _ptr(net.w), _ptr(net.bias), norm, float(net.out_scale), 1),
+              self.handle, "set_flux_cnn")
+        self.net = net
+
+    def flux_cnn_eval(self, U):
+        self._check_state(U)
+        dF = torch.empty((self.shape[0], self.nface, 4), dtype=torch.float32, device=self.device)
+        self._sync_stream()
+        check(lib().shk_flux_cnn_eval(self.handle, _ptr(U), _ptr(dF)), self.handle, "flux_cnn_eval")
+        return dF
+
+    def flux_cnn_vjp(self, U, lam, grad=None):
+        self._check_state(U)
+        self._check_state(lam)
+        dX = torch.empty((self.shape[0], self.nface, 6, 4), dtype=torch.float32, device=self.device)
+        self._sync_stream()
+        check(lib().shk_flux_cnn_vjp(self.handle, _ptr(U), _ptr(lam), _ptr(dX), _ptr(grad)), self.handle,
+              "flux_cnn_vjp")
+        return dX
+
+    def flux_cnn_images(self, U):
+        """The network's input images (x-faces [ny][wx], transposed y-faces
+        [nx][wy], 4 channels) as float tensors per batch member."""
+        self._check_state(U)
+        n = ctypes.c_int()
+        check(lib().shk_flux_cnn_images(self.handle, None, None, ctypes.byref(n)), self.handle, "flux_cnn_images")
+        out = torch.empty((self.shape[0], n.value, 4), dtype=torch.float32, device=self.device)
+        self._sync_stream()
+        check(lib().shk_flux_cnn_images(self.handle, _ptr(U), _ptr(out), ctypes.byref(n)), self.handle,
+              "flux_cnn_images")
+        d = self.desc
+        wx = d.nx if d.bc[0] == PERIODIC else d.nx + 1
+        wy = d.ny if d.bc[2] == PERIODIC else d.ny + 1
+        n0 = d.ny * wx
+        return out[:, :n0].reshape(-1, d.ny, wx, 4), out[:, n0:].reshape(-1, d.nx, wy, 4)
+
     def set_flux_net_grad(self, grad):
         check(lib().shk_set_flux_net_grad(self.handle, _ptr(grad)), self.handle, "set_flux_net_grad")
 
@@ -282,7 +327,7 @@ class Grid:
             if self.phi is not None:
                 g.set_levelset(self.phi, self.wall)
             if self.net is not None:
-                g.set_flux_net(self.net)
+                (g.set_flux_cnn if getattr(self.net, "kind", "mlp") == "cnn" else g.set_flux_net)(self.net)
         side.synchronize()
         self._replica = (self.version, g, side)
         return g, side
