@@ -25,7 +25,7 @@ class Config(ctypes.Structure):
         ("x0", _d), ("x1", _d), ("y0", _d), ("y1", _d),
         ("gamma", _d), ("cfl", _d), ("weno_eps", _d),
         ("viscous", _i), ("mu", _d), ("prandtl", _d), ("nu_art", _d),
-        ("bc", _i * 4), ("inflow", _d * 4),
+        ("bc", _i * 4), ("inflow", _d * 4), ("weno_char", _i),
     ]
 
 
@@ -51,12 +51,13 @@ def lib():
         _lib.orc_cnn_forward.argtypes = [_p, _i, _i, _i, _i, _p, _p]
         _lib.orc_cnn_backward.argtypes = [_p, _i, _i, _i, _i, _p, _p, _p, _p]
         _lib.orc_cnn_images.argtypes = [_p, _p, _p, _i, _p, _p, _p]
+        _lib.orc_char_basis.argtypes = [_d, _p, _p, _p, _p]
     return _lib
 
 
 def config(ndim=2, nx=64, ny=64, x0=0.0, x1=1.0, y0=0.0, y1=1.0, gamma=1.4, cfl=0.5,
            weno_eps=1e-6, viscous=0, mu=0.0, prandtl=0.72, nu_art=0.0,
-           bc=(0, 0, 0, 0), inflow=(1.0, 0.0, 0.0, 1.0)):
+           bc=(0, 0, 0, 0), inflow=(1.0, 0.0, 0.0, 1.0), weno_char=0):
     c = Config()
     c.ndim, c.nx, c.ny = ndim, nx, (1 if ndim == 1 else ny)
     c.x0, c.x1, c.y0, c.y1 = x0, x1, y0, y1
@@ -65,6 +66,7 @@ def config(ndim=2, nx=64, ny=64, x0=0.0, x1=1.0, y0=0.0, y1=1.0, gamma=1.4, cfl=
     for k in range(4):
         c.bc[k] = bc[k]
         c.inflow[k] = inflow[k]
+    c.weno_char = int(weno_char)
     return c
 
 
@@ -350,3 +352,12 @@ def cnn_images(c, U, net, phi=None, wall=0):
     assert lib().orc_cnn_images(ctypes.byref(c), _ptr(U), _ptr(_phi(c, phi)), _i(wall), _p(net.handle),
                                 _ptr(Xx), _ptr(Xy)) == 0
     return Xx, Xy
+
+
+def char_basis(Wa, Wb, gamma=1.4):
+    """Left and right eigenvector matrices (face frame) of the characteristic
+    reconstruction at the Roe average of primitive states Wa, Wb."""
+    Wa, Wb = _arr(Wa, (4,)), _arr(Wb, (4,))
+    L, R = np.empty((4, 4)), np.empty((4, 4))
+    lib().orc_char_basis(_d(gamma), _ptr(Wa), _ptr(Wb), _ptr(L), _ptr(R))
+    return L, R

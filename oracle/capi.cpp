@@ -339,6 +339,15 @@ int orc_shock_tangent(const Config* c, const double* phi, int wall, double mach,
   return 0;
 }
 
+// Characteristic basis at the Roe average of two primitive states (face
+// frame): L and R row-major 4 x 4.
+void orc_char_basis(double gamma, const double* Wa, const double* Wb, double* L, double* R) {
+  double Lm[4][4], Rm[4][4];
+  char_basis(Wa, Wb, gamma, Lm, Rm);
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) { L[i * 4 + j] = Lm[i][j]; R[i * 4 + j] = Rm[i][j]; }
+}
+
 // ------------------------------------------------------------ flux net
 // Parameters in the order W0 [64][24], b0, W1 [64][64], b1, W2 [64][64], b2,
 // W3 [4][64], b3 (10180 values).

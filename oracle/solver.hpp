@@ -51,6 +51,7 @@ struct Config {
   double mu, prandtl, nu_art;  // dynamic viscosity, Prandtl number, Laplacian nu
   int bc[4];                 // x-lo, x-hi, y-lo, y-hi (enum Bc)
   double inflow[4];          // (rho, u, v, p) of an inflow boundary
+  int weno_char;             // 1 => WENO5 on characteristic variables (else on primitives)
 };
 
 // The differentiable physical parameters (gamma and the inflow state).
@@ -174,6 +175,74 @@ template <class T>
 T weno5_right(const T f6[6], double eps) {  // f6 = f_{i-2..i+3}
   T m[5] = {f6[5], f6[4], f6[3], f6[2], f6[1]};
   return weno5_left(m, eps);
+}
+
+// ------------------------------------------- characteristic-wise WENO5
+// The variant the paper leaves open: reconstruction in characteristic
+// variables.  At a face the conservative stencil (face frame, u normal) is
+// projected on the left eigenvectors of the face-normal flux Jacobian at the
+// Roe average of the two adjacent cells, each characteristic field is
+// reconstructed by WENO5-JS, and the two face states are projected back.
+// Right eigenvectors (columns, for u - c, u, u, u + c), q = (u^2 + v^2)/2:
+//   (1, u - c, v, H - u c), (1, u, v, q), (0, 0, 1, v), (1, u + c, v, H + u c)
+// and the left ones (rows of the inverse), b1 = (gamma - 1)/c^2, b2 = b1 q:
+//   ((b2 + u/c)/2, -(b1 u + 1/c)/2, -b1 v/2, b1/2), (1 - b2, b1 u, b1 v, -b1),
+//   (-v, 0, 1, 0), ((b2 - u/c)/2, -(b1 u - 1/c)/2, -b1 v/2, b1/2).
+template <class T>
+void char_basis(const T Wa[4], const T Wb[4], const T& gamma, T Lm[4][4], T Rm[4][4]) {
+  const T ra = sqrt(Wa[0]), rb_ = sqrt(Wb[0]);
+  const T Ha = gamma / (gamma - 1.0) * Wa[3] / Wa[0] + 0.5 * (Wa[1] * Wa[1] + Wa[2] * Wa[2]);
+  const T Hb = gamma / (gamma - 1.0) * Wb[3] / Wb[0] + 0.5 * (Wb[1] * Wb[1] + Wb[2] * Wb[2]);
+  const T u = (ra * Wa[1] + rb_ * Wb[1]) / (ra + rb_);
+  const T v = (ra * Wa[2] + rb_ * Wb[2]) / (ra + rb_);
+  const T H = (ra * Ha + rb_ * Hb) / (ra + rb_);
+  const T q = 0.5 * (u * u + v * v);
+  const T c = sqrt((gamma - 1.0) * (H - q));
+  const T b1 = (gamma - 1.0) / (c * c), b2 = b1 * q;
+  const T R[4][4] = {{T(1.0), T(1.0), T(0.0), T(1.0)},
+                     {u - c, u, T(0.0), u + c},
+                     {v, v, T(1.0), v},
+                     {H - u * c, q, v, H + u * c}};
+  const T L[4][4] = {{0.5 * (b2 + u / c), -0.5 * (b1 * u + 1.0 / c), -0.5 * b1 * v, 0.5 * b1},
+                     {1.0 - b2, b1 * u, b1 * v, -b1},
+                     {-v, T(0.0), T(1.0), T(0.0)},
+                     {0.5 * (b2 - u / c), -0.5 * (b1 * u - 1.0 / c), -0.5 * b1 * v, 0.5 * b1}};
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) { Lm[i][j] = L[i][j]; Rm[i][j] = R[i][j]; }
+}
+
+// Face states (primitive, face frame) from the six-cell stencil by the
+// characteristic-wise reconstruction.
+template <class T>
+void char_weno(const T Wst[6][4], const T& gamma, double eps, T WL[4], T WR[4]) {
+  T U[6][4], w[6][4], L[4][4], R[4][4];
+  for (int s = 0; s < 6; ++s) prim_to_cons(Wst[s], gamma, U[s]);
+  char_basis(Wst[2], Wst[3], gamma, L, R);
+  for (int s = 0; s < 6; ++s)
+    for (int m = 0; m < 4; ++m) {
+      T acc = T(0.0);
+      for (int k = 0; k < 4; ++k) acc = acc + L[m][k] * U[s][k];
+      w[s][m] = acc;
+    }
+  T wl[4], wr[4];
+  for (int m = 0; m < 4; ++m) {
+    T f5[5] = {w[0][m], w[1][m], w[2][m], w[3][m], w[4][m]};
+    T f6[6] = {w[0][m], w[1][m], w[2][m], w[3][m], w[4][m], w[5][m]};
+    wl[m] = weno5_left(f5, eps);
+    wr[m] = weno5_right(f6, eps);
+  }
+  T UL[4], UR[4];
+  for (int k = 0; k < 4; ++k) {
+    T al = T(0.0), ar = T(0.0);
+    for (int m = 0; m < 4; ++m) {
+      al = al + R[k][m] * wl[m];
+      ar = ar + R[k][m] * wr[m];
+    }
+    UL[k] = al;
+    UR[k] = ar;
+  }
+  cons_to_prim(UL, gamma, WL);
+  cons_to_prim(UR, gamma, WR);
 }
 
 // ------------------------------------------------------------------- HLLC
@@ -425,11 +494,15 @@ template <class T>
 void face_flux(const Config& c, const Params<T>& P, const T Wst[6][4], const FluxNet* net,
                T F[4], long* fallback_count, T* WLout = nullptr, T* WRout = nullptr) {
   T WL[4], WR[4];
-  for (int v = 0; v < 4; ++v) {
-    T f5[5] = {Wst[0][v], Wst[1][v], Wst[2][v], Wst[3][v], Wst[4][v]};
-    T f6[6] = {Wst[0][v], Wst[1][v], Wst[2][v], Wst[3][v], Wst[4][v], Wst[5][v]};
-    WL[v] = weno5_left(f5, c.weno_eps);
-    WR[v] = weno5_right(f6, c.weno_eps);
+  if (c.weno_char) {
+    char_weno(Wst, P.gamma, c.weno_eps, WL, WR);
+  } else {
+    for (int v = 0; v < 4; ++v) {
+      T f5[5] = {Wst[0][v], Wst[1][v], Wst[2][v], Wst[3][v], Wst[4][v]};
+      T f6[6] = {Wst[0][v], Wst[1][v], Wst[2][v], Wst[3][v], Wst[4][v], Wst[5][v]};
+      WL[v] = weno5_left(f5, c.weno_eps);
+      WR[v] = weno5_right(f6, c.weno_eps);
+    }
   }
   // Positivity fallback: a non-positive reconstructed density or pressure
   // reverts both states of this face to the adjacent cell values.
