@@ -162,6 +162,12 @@ def copy_ceiling(mb=512, reps=10):
 # Viscous stress and heat flux add about 45 operations per face (two faces
 # per cell and stage) to the inviscid count.
 FLOPS_PER_CELL_STAGE_VISCOUS = FLOPS_PER_CELL_STAGE + 90
+# The characteristic-wise reconstruction adds per face: the Roe average and
+# the eigenvector entries (~40), the conservative form of the six stencil
+# cells (6 x 8), their projection (6 x 4 x 7), the back-projection of both
+# states (2 x 28) and their primitives (2 x 8): ~330 per face, two faces per
+# cell.
+FLOPS_PER_CELL_STAGE_CHAR = FLOPS_PER_CELL_STAGE + 660
 
 
 def cylinder_workload(args):
@@ -338,6 +344,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="instead: time a plain device copy of MB megabytes (counter calibration)")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "mixed"])
+    ap.add_argument("--weno", default="prim", choices=["prim", "char"],
+                    help="WENO5 on primitive (default) or characteristic variables (FP64)")
     ap.add_argument("--graph", action="store_true", help="replay the timed steps from a HIP graph")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -385,7 +393,8 @@ def main():
 
     nx, ny, K, W = args.nx, args.ny, args.steps, args.warmup
     n2 = nx * ny
-    g = Grid(nx, ny, prec=args.prec)
+    char = args.weno == "char"
+    g = Grid(nx, ny, prec=args.prec, weno_char=char)
     U = g.prim_to_cons(torch.from_numpy(inputs.riemann2d_prim(nx, ny)))
     g.set_time(0.0, 1e30)  # no end time inside the run: every step is a full step
     for _ in range(W):
@@ -437,10 +446,11 @@ def main():
     launch_s = gpu_ms * 1e-3 / (3 * K)
     bytes_launch = WORDS_PER_CELL_STEP * esize * n2 / 3
     gbs = bytes_launch / launch_s / 1e9
-    tflops = FLOPS_PER_CELL_STAGE * n2 / launch_s / 1e12
+    flops_cell = FLOPS_PER_CELL_STAGE_CHAR if char else FLOPS_PER_CELL_STAGE
+    tflops = flops_cell * n2 / launch_s / 1e12
     fpeak = FP64_PEAK_TFLOPS if args.prec in ("f64", "mixed") else FP32_PEAK_TFLOPS
     traffic = None
-    if (MEASURED_TRAFFIC["workload"] == (nx, ny, args.prec)
+    if (not char and MEASURED_TRAFFIC["workload"] == (nx, ny, args.prec)
             and MEASURED_TRAFFIC["sources_sha256"] == stage_sources_sha256()):
         traffic = MEASURED_TRAFFIC["bytes_per_launch"]
     hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -453,7 +463,7 @@ def main():
     roof["stage_us_per_launch"] = round(launch_s * 1e6, 3)
     roof["launches_timed"] = 3 * K
     roof["algorithmic_bytes_per_launch"] = bytes_launch
-    roof["algorithmic_flops_per_launch"] = FLOPS_PER_CELL_STAGE * n2
+    roof["algorithmic_flops_per_launch"] = flops_cell * n2
     roof["other_bound"] = hbm if roof["bound"] == "alu" else alu
 
     out = {
@@ -461,8 +471,9 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.prec, "data": "synthetic",
         "config": {"workload": f"2D Euler four-quadrant Riemann problem {nx}x{ny} on [0,1]^2, gamma 1.4, "
-                               "seeded +-5% quadrant states, transmissive, WENO5-JS+HLLC, SSP-RK3, CFL 0.5",
-                   "nx": nx, "ny": ny, "prec": args.prec, "graph": bool(args.graph)},
+                               "seeded +-5% quadrant states, transmissive, "
+                               + ("characteristic-wise " if char else "") + "WENO5-JS+HLLC, SSP-RK3, CFL 0.5",
+                   "nx": nx, "ny": ny, "prec": args.prec, "graph": bool(args.graph), "weno": args.weno},
         "hbm_frac_of_peak": round(WORDS_PER_CELL_STEP * esize * n2 * K / el / 1e9 / HBM_PEAK_GBS, 4),
         "hbm_copy_ceiling_GBs": copy_ceiling(),
         "roofline": roof,

@@ -93,6 +93,10 @@ typedef struct {
   int adjoint;         /* 1: reserve adjoint buffers in the workspace          */
   int flux_net;        /* 1: per-face network, 2: convolutional network -- reserve
                           its buffers (ndim 2, SHK_F64, inviscid)            */
+  int weno_char;       /* 1: WENO5 on characteristic variables (projection on
+                          the eigenvectors of the face-normal flux Jacobian at
+                          the Roe average of the two adjacent cells) instead
+                          of on primitives; SHK_F64, no flux_net, no adjoint */
 } shk_grid_desc;
 
 /* Bytes of device workspace a grid with this descriptor needs (0 on a bad

@@ -20,6 +20,7 @@ class GridDesc(ctypes.Structure):
         ("prec", _i), ("gamma", _d), ("cfl", _d), ("weno_eps", _d),
         ("viscous", _i), ("mu", _d), ("prandtl", _d), ("nu_art", _d),
         ("bc", _i * 4), ("inflow_prim", _d * 4), ("ibm", _i), ("adjoint", _i), ("flux_net", _i),
+        ("weno_char", _i),
     ]
 
 

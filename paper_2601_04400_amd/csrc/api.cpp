@@ -87,6 +87,9 @@ bool desc_ok(const shk_grid_desc* d, std::string* why) {
     return bad("flux net needs ndim 2, SHK_F64 and an inviscid grid");
   if (d->flux_net == 2 && (d->nx > 16384 || d->ny > 16384)) return bad("convolutional net: nx, ny <= 16384");
   if (d->nu_art < 0.0) return bad("nu_art must be >= 0");
+  if (d->weno_char != 0 && d->weno_char != 1) return bad("weno_char must be 0 or 1");
+  if (d->weno_char && (d->prec != SHK_F64 || d->flux_net || d->adjoint))
+    return bad("characteristic WENO: SHK_F64, without learned correction or adjoint");
   return true;
 }
 
@@ -306,6 +309,7 @@ shk_status shk_init_grid(const shk_grid_desc* desc, void* workspace, size_t ws_b
   a.gamma = d.gamma; a.eps = d.weno_eps; a.cfl = d.cfl;
   a.viscous = d.viscous; a.mu = d.mu; a.prandtl = d.prandtl > 0 ? d.prandtl : 1.0;
   a.nu_art = d.nu_art;
+  a.weno_char = d.weno_char;
   for (int k = 0; k < 4; ++k) a.bc[k] = d.bc[k];
   set_physics(g->d, a);
   a.cls = nullptr;

@@ -36,6 +36,7 @@ struct GridArgs {
   double x0, y0, dx, dy, inv_dx, inv_dy;
   double gamma, eps, cfl;
   int viscous;
+  int weno_char;               // 1: characteristic-wise WENO5 (FP64 stage kernels)
   double mu, kappa, prandtl;   // kappa = mu gamma / ((gamma-1) Pr), gas constant 1
   double nu_art;
   int bc[4];

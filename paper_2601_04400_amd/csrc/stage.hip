@@ -141,6 +141,60 @@ __device__ __forceinline__ bool finite_val(C x) {
   return isfinite(x);
 }
 
+// Characteristic-wise WENO5 face states (the variant the paper leaves open):
+// the six-cell stencil (face frame, primitive q0..q3 at stride st) in
+// conservative form is projected on the left eigenvectors of the
+// face-normal flux Jacobian at the Roe average of cells 2 and 3, each
+// characteristic field is reconstructed like a primitive one, and the two
+// states are projected back with the right eigenvectors:
+//   R columns (u - c, u, u, u + c): (1, u - c, v, H - u c), (1, u, v, q),
+//   (0, 0, 1, v), (1, u + c, v, H + u c);  L = R^-1 with b1 = (gamma-1)/c^2,
+//   b2 = b1 q: ((b2 + u/c)/2, -(b1 u + 1/c)/2, -b1 v/2, b1/2),
+//   (1 - b2, b1 u, b1 v, -b1), (-v, 0, 1, 0), ((b2 - u/c)/2, -(b1 u - 1/c)/2,
+//   -b1 v/2, b1/2);  q = (u^2 + v^2)/2.
+__device__ __forceinline__ void char_face_states(const double* q0, const double* q1, const double* q2,
+                                                 const double* q3, int st, double eps, double gam,
+                                                 Prim<double>& Lp, Prim<double>& Rp) {
+  const double gm1 = gam - 1.0;
+  const int ia = 2 * st, ib = 3 * st;
+  const double ra = sqrt(q0[ia]), rb = sqrt(q0[ib]);
+  const double Ha = gam / gm1 * q3[ia] / q0[ia] + 0.5 * (q1[ia] * q1[ia] + q2[ia] * q2[ia]);
+  const double Hb = gam / gm1 * q3[ib] / q0[ib] + 0.5 * (q1[ib] * q1[ib] + q2[ib] * q2[ib]);
+  const double iw = 1.0 / (ra + rb);
+  const double u = (ra * q1[ia] + rb * q1[ib]) * iw, v = (ra * q2[ia] + rb * q2[ib]) * iw;
+  const double H = (ra * Ha + rb * Hb) * iw;
+  const double q = 0.5 * (u * u + v * v);
+  const double c = sqrt(gm1 * (H - q));
+  const double ic = 1.0 / c, b1 = gm1 * ic * ic, b2 = b1 * q;
+  const double L[4][4] = {{0.5 * (b2 + u * ic), -0.5 * (b1 * u + ic), -0.5 * b1 * v, 0.5 * b1},
+                          {1.0 - b2, b1 * u, b1 * v, -b1},
+                          {-v, 0.0, 1.0, 0.0},
+                          {0.5 * (b2 - u * ic), -0.5 * (b1 * u - ic), -0.5 * b1 * v, 0.5 * b1}};
+  double wc[4][6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const double r = q0[s * st], un = q1[s * st], ut = q2[s * st], p = q3[s * st];
+    const double U[4] = {r, r * un, r * ut, p / gm1 + 0.5 * r * (un * un + ut * ut)};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) wc[m][s] = ((L[m][0] * U[0] + L[m][1] * U[1]) + L[m][2] * U[2]) + L[m][3] * U[3];
+  }
+  double wl[4], wr[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) weno5_pair(wc[m][0], wc[m][1], wc[m][2], wc[m][3], wc[m][4], wc[m][5], eps, wl[m], wr[m]);
+  auto back = [&](const double w4[4], Prim<double>& P) {
+    const double U0 = (w4[0] + w4[1]) + w4[3];
+    const double U1 = ((u - c) * w4[0] + u * w4[1]) + (u + c) * w4[3];
+    const double U2 = ((v * w4[0] + v * w4[1]) + w4[2]) + v * w4[3];
+    const double U3 = (((H - u * c) * w4[0] + q * w4[1]) + v * w4[2]) + (H + u * c) * w4[3];
+    P.r = U0;
+    P.un = U1 / U0;
+    P.ut = U2 / U0;
+    P.p = gm1 * (U3 - 0.5 * U0 * (P.un * P.un + P.ut * P.ut));
+  };
+  back(wl, Lp);
+  back(wr, Rp);
+}
+
 // ------------------------------------------------------------ stage kernel
 // Modes: MODE_RHS writes L(U); MODE_STAGE1..3 are the three Shu-Osher stages
 // with the step read from dtp[b].  The fused automatic-step sequence is
@@ -157,7 +211,8 @@ __device__ __forceinline__ bool finite_val(C x) {
 //            the primitive halo the tile has already loaded;
 //   NET_EXT: a correction computed beforehand for every face (the
 //            convolutional network), read from a.dFext.
-template <class S, class C, int NDIM, int TX, int TY, bool VISC, int MODE, int NET = NET_NONE>
+// CHAR: characteristic-wise WENO5 instead of the primitive-wise one (FP64).
+template <class S, class C, int NDIM, int TX, int TY, bool VISC, int MODE, int NET = NET_NONE, bool CHAR = false>
 __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restrict__ Us,
                                                     const S* __restrict__ Un, S* __restrict__ Uout,
                                                     const double* __restrict__ dtp,
@@ -373,21 +428,26 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
         gface = (long long)(a.nx + 1) * a.ny + (long long)gf * a.nx + i0 + x;
     }
     Prim<C> L, R;
-    {
-      const C* f = w[0] + s0;
-      weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.r, R.r);
-    }
-    {
-      const C* f = w[cn] + s0;
-      weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.un, R.un);
-    }
-    {
-      const C* f = w[ct] + s0;
-      weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.ut, R.ut);
-    }
-    {
-      const C* f = w[3] + s0;
-      weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.p, R.p);
+    if constexpr (CHAR) {
+      static_assert(sizeof(C) == 8, "characteristic reconstruction: FP64 tiles");
+      char_face_states(w[0] + s0, w[cn] + s0, w[ct] + s0, w[3] + s0, st, a.eps, a.gamma, L, R);
+    } else {
+      {
+        const C* f = w[0] + s0;
+        weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.r, R.r);
+      }
+      {
+        const C* f = w[cn] + s0;
+        weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.un, R.un);
+      }
+      {
+        const C* f = w[ct] + s0;
+        weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.ut, R.ut);
+      }
+      {
+        const C* f = w[3] + s0;
+        weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.p, R.p);
+      }
     }
     if (!(L.r > C(0)) || !(L.p > C(0)) || !(R.r > C(0)) || !(R.p > C(0))) {
       // positivity fallback: first-order states from the two adjacent cells
@@ -704,23 +764,35 @@ hipError_t launch_init_scalars(const GridArgs& a, double t0, double t_end, hipSt
 constexpr int TX2 = SHK_TILE_X, TY2 = SHK_TILE_Y;
 constexpr int TX1 = 256;
 
-template <class S, class C, int MODE>
-static hipError_t launch_mode(const GridArgs& a, const S* Us, const S* Un, S* Uo, const double* dtp,
-                              const S* Lin, hipStream_t st) {
+template <class S, class C, int MODE, bool CHAR>
+static hipError_t launch_mode_r(const GridArgs& a, const S* Us, const S* Un, S* Uo, const double* dtp,
+                                const S* Lin, hipStream_t st) {
   if (a.ndim == 1) {
     dim3 grid((a.nx + TX1 - 1) / TX1, 1, a.nbatch);
-    hipLaunchKernelGGL((stage_kernel<S, C, 1, TX1, 1, false, MODE>), grid, dim3(256), 0, st, a, Us, Un, Uo,
-                       dtp, Lin, NetArgs{});
+    hipLaunchKernelGGL((stage_kernel<S, C, 1, TX1, 1, false, MODE, NET_NONE, CHAR>), grid, dim3(256), 0, st, a,
+                       Us, Un, Uo, dtp, Lin, NetArgs{});
   } else {
     dim3 grid((a.nx + TX2 - 1) / TX2, (a.ny + TY2 - 1) / TY2, a.nbatch);
     if (a.viscous)
-      hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, true, MODE>), grid, dim3(256), 0, st, a, Us, Un,
-                         Uo, dtp, Lin, NetArgs{});
+      hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, true, MODE, NET_NONE, CHAR>), grid, dim3(256), 0, st,
+                         a, Us, Un, Uo, dtp, Lin, NetArgs{});
     else
-      hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, false, MODE>), grid, dim3(256), 0, st, a, Us, Un,
-                         Uo, dtp, Lin, NetArgs{});
+      hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, false, MODE, NET_NONE, CHAR>), grid, dim3(256), 0, st,
+                         a, Us, Un, Uo, dtp, Lin, NetArgs{});
   }
   return hipGetLastError();
+}
+
+// The characteristic reconstruction exists for FP64 storage and arithmetic.
+template <class S, class C, int MODE>
+static hipError_t launch_mode(const GridArgs& a, const S* Us, const S* Un, S* Uo, const double* dtp,
+                              const S* Lin, hipStream_t st) {
+  if (a.weno_char) {
+    if constexpr (sizeof(S) == 8 && sizeof(C) == 8)
+      return launch_mode_r<S, C, MODE, true>(a, Us, Un, Uo, dtp, Lin, st);
+    return hipErrorInvalidValue;
+  }
+  return launch_mode_r<S, C, MODE, false>(a, Us, Un, Uo, dtp, Lin, st);
 }
 
 template <class S, class C>

@@ -27,10 +27,11 @@ class Grid:
     def __init__(self, nx, ny=1, ndim=2, nbatch=1, domain=(0.0, 1.0, 0.0, 1.0), prec="f64", gamma=1.4,
                  cfl=0.5, weno_eps=1e-6, viscous=False, mu=0.0, prandtl=0.72, nu_art=0.0,
                  bc=(TRANSMISSIVE,) * 4, inflow=(1.0, 0.0, 0.0, 1.0), ibm=False, adjoint=False,
-                 flux_net=False, device="cuda"):
+                 flux_net=False, weno_char=False, device="cuda"):
         self._args = dict(nx=nx, ny=ny, ndim=ndim, nbatch=nbatch, domain=domain, prec=prec, gamma=gamma, cfl=cfl,
                           weno_eps=weno_eps, viscous=viscous, mu=mu, prandtl=prandtl, nu_art=nu_art, bc=bc,
-                          inflow=inflow, ibm=ibm, adjoint=adjoint, flux_net=flux_net, device=device)
+                          inflow=inflow, ibm=ibm, adjoint=adjoint, flux_net=flux_net, weno_char=weno_char,
+                          device=device)
         d = GridDesc()
         d.ndim, d.nx, d.ny, d.nbatch = ndim, nx, (1 if ndim == 1 else ny), nbatch
         d.x0, d.x1 = domain[0], domain[1]
@@ -42,6 +43,7 @@ class Grid:
             d.bc[k] = bc[k]
             d.inflow_prim[k] = inflow[k]
         d.ibm, d.adjoint, d.flux_net = int(ibm), int(adjoint), int(flux_net)
+        d.weno_char = int(weno_char)
         self.desc = d
         self.device = torch.device(device)
         self.dtype = torch.float64 if d.prec == F64 else torch.float32

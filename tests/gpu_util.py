@@ -30,12 +30,13 @@ def assert_fields(gpu, ref, tol, what=""):
 
 def make_pair(orc, nx, ny=1, ndim=2, domain=(0.0, 1.0, 0.0, 1.0), prec="f64", bc=(0, 0, 0, 0),
               inflow=(1.0, 0.0, 0.0, 1.0), gamma=1.4, cfl=0.5, viscous=False, mu=0.0, prandtl=0.72,
-              ibm=False, nbatch=1, nu_art=0.0):
+              ibm=False, nbatch=1, nu_art=0.0, weno_char=False):
     """Oracle config and GPU Grid for the same problem."""
     from paper_2601_04400_amd import Grid
     c = orc.config(ndim=ndim, nx=nx, ny=ny, x0=domain[0], x1=domain[1], y0=domain[2], y1=domain[3],
                    gamma=gamma, cfl=cfl, viscous=int(viscous), mu=mu, prandtl=prandtl, bc=bc,
-                   inflow=inflow, nu_art=nu_art)
+                   inflow=inflow, nu_art=nu_art, weno_char=int(weno_char))
     g = Grid(nx, ny, ndim=ndim, nbatch=nbatch, domain=domain, prec=prec, gamma=gamma, cfl=cfl,
-             viscous=viscous, mu=mu, prandtl=prandtl, bc=bc, inflow=inflow, ibm=ibm, nu_art=nu_art)
+             viscous=viscous, mu=mu, prandtl=prandtl, bc=bc, inflow=inflow, ibm=ibm, nu_art=nu_art,
+             weno_char=weno_char)
     return c, g
