@@ -93,18 +93,36 @@ __device__ __forceinline__ long long pixel_face(int img, int R, int C, int nx, i
 
 // One 3x3 layer as an implicit GEMM over 16 x 16 pixel tiles (see the file
 // comment); MT output-channel tiles of 16, KB K-blocks of 16 (k = tap * CIN
-// + channel, taps >= 9 are zero padding).  Workgroups take tiles of every
-// batch member and both images in a fixed order.
+// + channel, taps >= 9 are zero padding).  Each lane keeps its weight
+// fragments in registers for the whole launch; a wave computes its four
+// pixel rows as four independent accumulation chains.  The tile is staged in
+// planes of 16 channels ([plane][pixel][16]), so the 16 pixels x 4 channel
+// groups of one operand read cover the LDS banks evenly.  Workgroups take
+// tiles of every batch member and both images in a fixed order.
 template <int CIN, int MT, int KB, int EPI>
 __global__ void __launch_bounds__(256) cnn_conv_kernel(CnnGeom g, const unsigned short* __restrict__ in,
                                                        const unsigned short* __restrict__ wm,
                                                        const float* __restrict__ bias, ConvOut o) {
   static_assert(CIN % 4 == 0, "channels come in groups of four");
-  __shared__ __attribute__((aligned(16))) unsigned short sw[MT * 16 * KB * 16];
-  __shared__ __attribute__((aligned(16))) unsigned short tile[18 * 18 * CIN];
+  constexpr int CP = CIN >= 16 ? 16 : CIN;  // channels per plane
+  constexpr int NPL = CIN / CP;             // planes
+  __shared__ __attribute__((aligned(16))) unsigned short tile[NPL * 324 * CP];
   __shared__ float red[4][MT * 16];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane >> 4, fl = lane & 15;
-  for (int k = threadIdx.x; k < MT * 16 * KB * 16; k += blockDim.x) sw[k] = wm[k];
+  bf16x4 Aw[MT][KB];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) Aw[mt][kb] = ldA(wm, KB * 16, mt * 16, kb * 16, lane);
+  f32x4 b0[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    b0[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (bias != nullptr) {
+      const float* bp = bias + mt * 16 + 4 * q;
+      b0[mt] = f32x4{bp[0], bp[1], bp[2], bp[3]};
+    }
+  }
   f32x4 bs[MT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) bs[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -112,49 +130,46 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(CnnGeom g, const unsigned
   const long long ntile = (long long)g.tiles * g.nbatch;
   for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
     const TileLoc L = tile_loc(g, t);
-    __syncthreads();  // the previous tile's readers are done (and the weights are in)
-    for (int k = threadIdx.x; k < 18 * 18 * (CIN / 4); k += blockDim.x) {
+    __syncthreads();  // the previous tile's readers are done
+    for (int k = threadIdx.x; k < 324 * (CIN / 4); k += blockDim.x) {
       const int pq = k / (CIN / 4), cq = k - pq * (CIN / 4);
       const int tr = pq / 18, tc = pq - tr * 18;
       const int R = pix_src(L.r0 + tr - 1, L.H, L.wr), C = pix_src(L.c0 + tc - 1, L.W, L.wc);
       bf16x4 v = {0, 0, 0, 0};
       if (R >= 0 && C >= 0) v = *reinterpret_cast<const bf16x4*>(in + (L.pbase + (long long)R * L.W + C) * CIN + 4 * cq);
-      *reinterpret_cast<bf16x4*>(tile + pq * CIN + 4 * cq) = v;
+      const int pl = (4 * cq) / CP, c = 4 * cq - pl * CP;
+      *reinterpret_cast<bf16x4*>(tile + (pl * 324 + pq) * CP + c) = v;
     }
     __syncthreads();
-    for (int rr = 0; rr < 4; ++rr) {
-      const int r = wv * 4 + rr;
-      if (L.r0 + r >= L.H) break;  // uniform over the wave
-      f32x4 acc[MT];
+    // rows beyond the image hold zeros or wrapped pixels: computed, not stored
+    f32x4 acc[4][MT];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        if (bias != nullptr) {
-          const float* bp = bias + mt * 16 + 4 * q;
-          acc[mt] = f32x4{bp[0], bp[1], bp[2], bp[3]};
-        } else {
-          acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        }
-      }
+    for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb) {
-        const int k0 = kb * 16 + 4 * q, tap = k0 / CIN, ci0 = k0 - tap * CIN;
+      for (int mt = 0; mt < MT; ++mt) acc[rr][mt] = b0[mt];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const int k0 = kb * 16 + 4 * q, tap = k0 / CIN, ci0 = k0 - tap * CIN;
+      const int dr = tap / 3, dc = tap - 3 * dr, pl = ci0 / CP, c = ci0 - pl * CP;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
         bf16x4 B = {0, 0, 0, 0};
-        if (tap < 9) {
-          const int dr = tap / 3, dc = tap - 3 * dr;
-          B = *reinterpret_cast<const bf16x4*>(tile + ((r + dr) * 18 + fl + dc) * CIN + ci0);
-        }
+        if (tap < 9) B = *reinterpret_cast<const bf16x4*>(tile + (pl * 324 + (wv * 4 + rr + dr) * 18 + fl + dc) * CP + c);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma(ldA(sw, KB * 16, mt * 16, kb * 16, lane), B, acc[mt]);
+        for (int mt = 0; mt < MT; ++mt) acc[rr][mt] = mfma(Aw[mt][kb], B, acc[rr][mt]);
       }
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
       // lane (pixel fl of the row, q) holds output channels 16 mt + 4q .. + 3
-      const int R = L.r0 + r, C = L.c0 + fl;
-      const bool valid = C < L.W;
+      const int R = L.r0 + wv * 4 + rr, C = L.c0 + fl;
+      const bool valid = R < L.H && C < L.W;
       const long long pix = L.pbase + (long long)R * L.W + C;
       if (EPI == EPI_FWD_HIDDEN) {
         if (valid)
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
-            const f32x4 a = acc[mt];
+            const f32x4 a = acc[rr][mt];
             *reinterpret_cast<bf16x4*>(o.out_bf + pix * (MT * 16) + mt * 16 + 4 * q) =
                 pack4(fmaxf(a[0], 0.f), fmaxf(a[1], 0.f), fmaxf(a[2], 0.f), fmaxf(a[3], 0.f));
           }
@@ -164,7 +179,7 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(CnnGeom g, const unsigned
           bool ok = true;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            th[i] = tanhf(acc[0][i]);
+            th[i] = tanhf(acc[rr][0][i]);
             out[i] = o.out_scale * th[i];
             ok = ok && isfinite(out[i]);
           }
@@ -182,20 +197,19 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(CnnGeom g, const unsigned
           }
         }
       } else if (EPI == EPI_BWD_HIDDEN) {
+        if (valid)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const int c0 = mt * 16 + 4 * q;
-          f32x4 d = acc[mt];
-          if (valid) {
+          for (int mt = 0; mt < MT; ++mt) {
+            const int c0 = mt * 16 + 4 * q;
+            f32x4 d = acc[rr][mt];
             const bf16x4 h = *reinterpret_cast<const bf16x4*>(o.mask_src + pix * (MT * 16) + c0);
 #pragma unroll
             for (int i = 0; i < 4; ++i) d[i] = h[i] > 0 ? d[i] : 0.f;  // bf16 bits: positive iff > 0 as int16
             *reinterpret_cast<bf16x4*>(o.out_bf + pix * (MT * 16) + c0) = pack4(d[0], d[1], d[2], d[3]);
             bs[mt] = bs[mt] + d;
           }
-        }
       } else {  // EPI_BWD_IN
-        if (valid && q == 0) *reinterpret_cast<f32x4*>(o.out_f + pix * 4) = acc[0];
+        if (valid && q == 0) *reinterpret_cast<f32x4*>(o.out_f + pix * 4) = acc[rr][0];
       }
     }
   }
@@ -221,15 +235,25 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(CnnGeom g, const unsigned
 // Weight gradient of one layer: D[out channel][tap, in channel] = sum over
 // pixels of dA[pixel][out] X[pixel + tap][in], a contraction over the 16
 // pixels of a tile row per product.  The operands are staged channel-major
-// (pixels contiguous): dA without halo, X with a one-pixel halo.
+// (pixels contiguous): dA without halo; X with a one-pixel halo of rows and
+// in three copies shifted by the column offset of the tap, so that every
+// operand slice (four pixels of one channel) is one aligned 8-byte LDS read.
+// Channel row strides are 26 (mod 32) dwords (10 for dA): the 16 channels x
+// 4 pixel groups of a read spread evenly over the banks, and the staging
+// writes of channels four apart conflict at most two-way.
 template <int CIN, int COUT, int MT, int NT>
 __global__ void __launch_bounds__(256) cnn_wgrad_kernel(CnnGeom g, const unsigned short* __restrict__ dA,
                                                         const unsigned short* __restrict__ X,
                                                         float* __restrict__ part, int woff) {
   constexpr int K9 = 9 * CIN;
-  __shared__ __attribute__((aligned(16))) unsigned short tA[MT * 16][256];
-  __shared__ unsigned short tX[CIN][18 * 18];
-  __shared__ float red[COUT * K9];
+  constexpr int SA = 276;       // dA channel stride (elements): 256 pixels, padded to 138 dwords
+  constexpr int SX = 308;       // X channel stride: 18 rows x 16 pixels, padded to 154 dwords
+  constexpr int LDS_A = COUT * SA, LDS_X = 3 * CIN * SX;
+  constexpr int LDS_U = (LDS_A + LDS_X) * 2 > COUT * K9 * 4 ? (LDS_A + LDS_X) : COUT * K9 * 2;
+  __shared__ __attribute__((aligned(16))) unsigned short lds[LDS_U];
+  unsigned short* tA = lds;           // [COUT][SA]
+  unsigned short* tX = lds + LDS_A;   // [3][CIN][SX]: copy dc, channel, row * 16 + column
+  float* red = reinterpret_cast<float*>(lds);  // [COUT][K9], after the last tile
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane >> 4, fl = lane & 15;
   f32x4 acc[MT][NT];
 #pragma unroll
@@ -240,36 +264,46 @@ __global__ void __launch_bounds__(256) cnn_wgrad_kernel(CnnGeom g, const unsigne
   for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
     const TileLoc L = tile_loc(g, t);
     __syncthreads();
-    for (int k = threadIdx.x; k < MT * 16 * 256; k += blockDim.x) {
-      const int ch = k >> 8, p = k & 255;
+    for (int k = threadIdx.x; k < 256 * (COUT / 4); k += blockDim.x) {
+      const int p = k / (COUT / 4), cq = k - p * (COUT / 4);
       const int R = L.r0 + (p >> 4), C = L.c0 + (p & 15);
-      unsigned short v = 0;
-      if (ch < COUT && R < L.H && C < L.W) v = dA[(L.pbase + (long long)R * L.W + C) * COUT + ch];
-      tA[ch][p] = v;
+      bf16x4 v = {0, 0, 0, 0};
+      if (R < L.H && C < L.W) v = *reinterpret_cast<const bf16x4*>(dA + (L.pbase + (long long)R * L.W + C) * COUT + 4 * cq);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tA[(4 * cq + i) * SA + p] = (unsigned short)v[i];
     }
-    for (int k = threadIdx.x; k < CIN * 324; k += blockDim.x) {
-      const int pq = k / CIN, ci = k - pq * CIN;
+    for (int k = threadIdx.x; k < 324 * (CIN / 4); k += blockDim.x) {
+      const int pq = k / (CIN / 4), cq = k - pq * (CIN / 4);
       const int tr = pq / 18, tc = pq - tr * 18;
       const int R = pix_src(L.r0 + tr - 1, L.H, L.wr), C = pix_src(L.c0 + tc - 1, L.W, L.wc);
-      unsigned short v = 0;
-      if (R >= 0 && C >= 0) v = X[(L.pbase + (long long)R * L.W + C) * CIN + ci];
-      tX[ci][pq] = v;
+      bf16x4 v = {0, 0, 0, 0};
+      if (R >= 0 && C >= 0) v = *reinterpret_cast<const bf16x4*>(X + (L.pbase + (long long)R * L.W + C) * CIN + 4 * cq);
+      // halo column tc lands at column tc - dc of copy dc
+#pragma unroll
+      for (int dc = 0; dc < 3; ++dc) {
+        const int c = tc - dc;
+        if (c >= 0 && c < 16)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) tX[(dc * CIN + 4 * cq + i) * SX + tr * 16 + c] = (unsigned short)v[i];
+      }
     }
     __syncthreads();
+#pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
-      const int r = wv * 4 + rr;
-      if (L.r0 + r >= L.H) break;  // uniform over the wave
+      const int r = wv * 4 + rr;  // rows beyond the image are zeros in tA
       bf16x4 A[MT];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) A[mt] = *reinterpret_cast<const bf16x4*>(&tA[mt * 16 + fl][r * 16 + 4 * q]);
+      for (int mt = 0; mt < MT; ++mt) {
+        A[mt] = bf16x4{0, 0, 0, 0};
+        if (mt * 16 + fl < COUT) A[mt] = *reinterpret_cast<const bf16x4*>(tA + (mt * 16 + fl) * SA + r * 16 + 4 * q);
+      }
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         const int k = nt * 16 + fl, tap = k / CIN, ci = k - tap * CIN;
         bf16x4 B = {0, 0, 0, 0};
         if (tap < 9) {
           const int dr = tap / 3, dc = tap - 3 * dr;
-          const unsigned short* p = &tX[ci][(r + dr) * 18 + 4 * q + dc];
-          B = bf16x4{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
+          B = *reinterpret_cast<const bf16x4*>(tX + (dc * CIN + ci) * SX + (r + dr) * 16 + 4 * q);
         }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma(A[mt], B, acc[mt][nt]);
@@ -358,33 +392,70 @@ __device__ __forceinline__ PixelLoc pixel_loc(const CnnGeom& g, long long p) {
   return P;
 }
 
+// Primitive states (face frame) of the stencil cells of one 16 x 16 pixel
+// tile: row tr of the tile, index c0 - 3 + tc (tc = 0..20) along the face
+// normal.  Rows beyond the image are left unset (their pixels are skipped).
+__device__ __forceinline__ void stage_tile_prims(const GridArgs& a, const TileLoc& L, const double* __restrict__ U,
+                                                 double (*sp)[16][21]) {
+  const double* __restrict__ Ub = U + (long long)L.b * 4 * a.ncell;
+  for (int k = threadIdx.x; k < 16 * 21; k += blockDim.x) {
+    const int tr = k / 21, tc = k - tr * 21;
+    const int R = L.r0 + tr, nrm = L.c0 - 3 + tc;
+    if (R >= L.H) continue;
+    double w[4];
+    if (L.img == 0) cell_prim_frame(a, Ub, nrm, R, true, w);
+    else cell_prim_frame(a, Ub, R, nrm, false, w);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sp[v][tr][tc] = w[v];
+  }
+}
+
+// The two reconstructed states of the face of pixel (tr, fl) of a staged
+// tile, after the positivity fallback of the stage kernel.
+__device__ __forceinline__ bool tile_face_states(const GridArgs& a, const double (*sp)[16][21], int tr, int fl,
+                                                 double L[4], double R[4]) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double* c = &sp[v][tr][fl];
+    weno5_pair(c[0], c[1], c[2], c[3], c[4], c[5], a.eps, L[v], R[v]);
+  }
+  const bool fallback = !(L[0] > 0.0) || !(L[3] > 0.0) || !(R[0] > 0.0) || !(R[3] > 0.0);
+  if (fallback)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { L[v] = sp[v][tr][fl + 2]; R[v] = sp[v][tr][fl + 3]; }
+  return fallback;
+}
+
 // Normalised network input of every pixel: the conservative mean of the two
 // reconstructed face states (positivity fallback as in the stage kernel),
-// face frame, bfloat16.
+// face frame, bfloat16.  One 16 x 16 pixel tile per workgroup pass: the
+// primitive states of its 16 x 21 stencil cells are converted once into
+// LDS, then each thread reconstructs one face.
 __global__ void __launch_bounds__(256) cnn_inputs_kernel(GridArgs a, CnnGeom g, CnnArgs n,
                                                          const double* __restrict__ U,
                                                          unsigned short* __restrict__ x) {
-  const long long total = (long long)g.npix * g.nbatch;
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < total;
-       p += (long long)gridDim.x * blockDim.x) {
-    const PixelLoc P = pixel_loc(g, p);
-    const double* __restrict__ Ub = U + (long long)P.b * 4 * a.ncell;
-    const long long f = pixel_face(P.img, P.R, P.C, a.nx, a.ny);
-    double w[6][4];
-    for (int s = 0; s < 6; ++s) face_cell_prim(a, Ub, f, s, w[s]);
-    double L[4], R[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) weno5_pair(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], a.eps, L[v], R[v]);
-    if (!(L[0] > 0.0) || !(L[3] > 0.0) || !(R[0] > 0.0) || !(R[3] > 0.0))
-#pragma unroll
-      for (int v = 0; v < 4; ++v) { L[v] = w[2][v]; R[v] = w[3][v]; }
+  __shared__ double sp[4][16][21];
+  const int tr = threadIdx.x >> 4, fl = threadIdx.x & 15;
+  const long long ntile = (long long)g.tiles * g.nbatch;
+  for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const TileLoc L = tile_loc(g, t);
+    __syncthreads();
+    stage_tile_prims(a, L, U, sp);
+    __syncthreads();
+    const int R = L.r0 + tr, C = L.c0 + fl;
+    if (R >= L.H || C >= L.W) continue;
+    double Ls[4], Rs[4];
+    tile_face_states(a, sp, tr, fl, Ls, Rs);
     const double gm1 = a.gamma - 1.0;
-    const double uL[4] = {L[0], L[0] * L[1], L[0] * L[2], L[3] / gm1 + 0.5 * L[0] * (L[1] * L[1] + L[2] * L[2])};
-    const double uR[4] = {R[0], R[0] * R[1], R[0] * R[2], R[3] / gm1 + 0.5 * R[0] * (R[1] * R[1] + R[2] * R[2])};
+    const double uL[4] = {Ls[0], Ls[0] * Ls[1], Ls[0] * Ls[2],
+                          Ls[3] / gm1 + 0.5 * Ls[0] * (Ls[1] * Ls[1] + Ls[2] * Ls[2])};
+    const double uR[4] = {Rs[0], Rs[0] * Rs[1], Rs[0] * Rs[2],
+                          Rs[3] / gm1 + 0.5 * Rs[0] * (Rs[1] * Rs[1] + Rs[2] * Rs[2])};
     float xv[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) xv[v] = float((0.5 * (uL[v] + uR[v]) - n.mean[v]) * n.inv_std[v]);
-    *reinterpret_cast<bf16x4*>(x + p * 4) = pack4(xv[0], xv[1], xv[2], xv[3]);
+    const long long pix = L.pbase + (long long)R * L.W + C;
+    *reinterpret_cast<bf16x4*>(x + pix * 4) = pack4(xv[0], xv[1], xv[2], xv[3]);
   }
 }
 
@@ -435,27 +506,26 @@ __global__ void __launch_bounds__(256) cnn_head_kernel(GridArgs a, CnnGeom g, fl
 // WENO5 reverse (or the fallback's adjacent cells).  The last face of a
 // periodic row is the first one seen from the other side and gets the same
 // stencil gradient (the adjoint kernel takes each of the two copies for the
-// cells on its own side).
+// cells on its own side).  Tiled as the input kernel; the reverse runs one
+// primitive variable at a time from the staged states.
 __global__ void __launch_bounds__(256) cnn_input_grad_kernel(GridArgs a, CnnGeom g, CnnArgs n,
                                                              const double* __restrict__ U,
                                                              const float* __restrict__ dx, float* __restrict__ dX,
                                                              long long nface) {
-  const long long total = (long long)g.npix * g.nbatch;
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < total;
-       p += (long long)gridDim.x * blockDim.x) {
-    const PixelLoc P = pixel_loc(g, p);
-    const double* __restrict__ Ub = U + (long long)P.b * 4 * a.ncell;
-    const long long f = pixel_face(P.img, P.R, P.C, a.nx, a.ny);
-    double w[6][4];
-    for (int s = 0; s < 6; ++s) face_cell_prim(a, Ub, f, s, w[s]);
-    double L[4], R[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) weno5_pair(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], a.eps, L[v], R[v]);
-    const bool fallback = !(L[0] > 0.0) || !(L[3] > 0.0) || !(R[0] > 0.0) || !(R[3] > 0.0);
-    if (fallback)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) { L[v] = w[2][v]; R[v] = w[3][v]; }
-    const f32x4 d = *reinterpret_cast<const f32x4*>(dx + p * 4);
+  __shared__ double sp[4][16][21];
+  const int tr = threadIdx.x >> 4, fl = threadIdx.x & 15;
+  const long long ntile = (long long)g.tiles * g.nbatch;
+  for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const TileLoc L = tile_loc(g, t);
+    __syncthreads();
+    stage_tile_prims(a, L, U, sp);
+    __syncthreads();
+    const int R = L.r0 + tr, C = L.c0 + fl;
+    if (R >= L.H || C >= L.W) continue;
+    double Ls[4], Rs[4];
+    const bool fallback = tile_face_states(a, sp, tr, fl, Ls, Rs);
+    const long long pix = L.pbase + (long long)R * L.W + C;
+    const f32x4 d = *reinterpret_cast<const f32x4*>(dx + pix * 4);
     double du[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) du[v] = 0.5 * double(d[v]) * n.inv_std[v];
@@ -468,36 +538,31 @@ __global__ void __launch_bounds__(256) cnn_input_grad_kernel(GridArgs a, CnnGeom
       o[3] = du[3] * ig;
     };
     double lb[4], rb[4];
-    side(L, lb);
-    side(R, rb);
-    double sl[6][4];
+    side(Ls, lb);
+    side(Rs, rb);
+    float sl[6][4];
 #pragma unroll
-    for (int s = 0; s < 6; ++s)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) sl[s][v] = 0.0;
-    if (fallback) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) { sl[2][v] = lb[v]; sl[3][v] = rb[v]; }
-    } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        weno5_vjp(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], a.eps, lb[v], sl[0][v], sl[1][v], sl[2][v], sl[3][v],
-                  sl[4][v]);
-        weno5_vjp(w[5][v], w[4][v], w[3][v], w[2][v], w[1][v], a.eps, rb[v], sl[5][v], sl[4][v], sl[3][v], sl[2][v],
-                  sl[1][v]);
+    for (int v = 0; v < 4; ++v) {
+      double gs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      if (fallback) {
+        gs[2] = lb[v];
+        gs[3] = rb[v];
+      } else {
+        const double* c = &sp[v][tr][fl];
+        weno5_vjp(c[0], c[1], c[2], c[3], c[4], a.eps, lb[v], gs[0], gs[1], gs[2], gs[3], gs[4]);
+        weno5_vjp(c[5], c[4], c[3], c[2], c[1], a.eps, rb[v], gs[5], gs[4], gs[3], gs[2], gs[1]);
       }
+#pragma unroll
+      for (int s2 = 0; s2 < 6; ++s2) sl[s2][v] = float(gs[s2]);
     }
-    float* o = dX + ((long long)P.b * nface + f) * 24;
+    const long long f = pixel_face(L.img, R, C, a.nx, a.ny);
+    f32x4* o = reinterpret_cast<f32x4*>(dX + ((long long)L.b * nface + f) * 24);
 #pragma unroll
-    for (int s = 0; s < 6; ++s)
+    for (int s2 = 0; s2 < 6; ++s2) o[s2] = f32x4{sl[s2][0], sl[s2][1], sl[s2][2], sl[s2][3]};
+    if (L.wc && C == 0) {
+      f32x4* o2 = reinterpret_cast<f32x4*>(dX + ((long long)L.b * nface + pixel_face(L.img, R, L.W, a.nx, a.ny)) * 24);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) o[s * 4 + v] = float(sl[s][v]);
-    if (P.wc && P.C == 0) {
-      float* o2 = dX + ((long long)P.b * nface + pixel_face(P.img, P.R, P.W, a.nx, a.ny)) * 24;
-#pragma unroll
-      for (int s = 0; s < 6; ++s)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) o2[s * 4 + v] = float(sl[s][v]);
+      for (int s2 = 0; s2 < 6; ++s2) o2[s2] = f32x4{sl[s2][0], sl[s2][1], sl[s2][2], sl[s2][3]};
     }
   }
 }
@@ -566,11 +631,6 @@ __global__ void __launch_bounds__(256) cnn_pack_kernel(const float* __restrict__
   }
 }
 
-unsigned int pixel_blocks(const CnnGeom& g) {
-  const long long n = ((long long)g.npix * g.nbatch + 255) / 256;
-  return (unsigned int)(n < 1 ? 1 : (n > 4096 ? 4096 : n));
-}
-
 unsigned int tile_blocks(const CnnGeom& g) {
   const long long n = (long long)g.tiles * g.nbatch;
   return (unsigned int)(n < 1 ? 1 : (n > 8192 ? 8192 : n));
@@ -635,7 +695,7 @@ hipError_t launch_cnn_pack(const float* theta, unsigned short* w, float* bias, h
 hipError_t launch_cnn_forward(const GridArgs& a, const CnnArgs& n, const double* U, float* dF, const CnnBufs& b,
                               hipStream_t st) {
   const CnnGeom g = cnn_geom(a);
-  hipLaunchKernelGGL(cnn_inputs_kernel, dim3(pixel_blocks(g)), dim3(256), 0, st, a, g, n, U, b.x);
+  hipLaunchKernelGGL(cnn_inputs_kernel, dim3(tile_blocks(g)), dim3(256), 0, st, a, g, n, U, b.x);
   ConvOut o{};
   o.out_bf = b.h1;
   hipLaunchKernelGGL((cnn_conv_kernel<4, 1, 3, EPI_FWD_HIDDEN>), dim3(tile_blocks(g)), dim3(256), 0, st, g, b.x,
@@ -692,7 +752,7 @@ hipError_t launch_cnn_backward(const GridArgs& a, const CnnArgs& n, const double
                      n.w + CNN_B1, nullptr, o1);
   hipLaunchKernelGGL((cnn_wgrad_kernel<4, 16, 1, 3>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.da1, b.x, b.part,
                      CNN_G_W1);
-  hipLaunchKernelGGL(cnn_input_grad_kernel, dim3(pixel_blocks(g)), dim3(256), 0, st, a, g, n, U, b.dx, dX, nface);
+  hipLaunchKernelGGL(cnn_input_grad_kernel, dim3(tile_blocks(g)), dim3(256), 0, st, a, g, n, U, b.dx, dX, nface);
   e = hipGetLastError();
   if (e != hipSuccess || grad == nullptr) return e;
   hipLaunchKernelGGL(cnn_grad_reduce_kernel, dim3((CNN_NP + 63) / 64), dim3(1024), 0, st, b.part, grad);
@@ -702,7 +762,7 @@ hipError_t launch_cnn_backward(const GridArgs& a, const CnnArgs& n, const double
 hipError_t launch_cnn_images(const GridArgs& a, const CnnArgs& n, const double* U, const CnnBufs& b, float* out,
                              hipStream_t st) {
   const CnnGeom g = cnn_geom(a);
-  hipLaunchKernelGGL(cnn_inputs_kernel, dim3(pixel_blocks(g)), dim3(256), 0, st, a, g, n, U, b.x);
+  hipLaunchKernelGGL(cnn_inputs_kernel, dim3(tile_blocks(g)), dim3(256), 0, st, a, g, n, U, b.x);
   const long long cnt = (long long)g.npix * g.nbatch * 4;
   hipLaunchKernelGGL(cnn_unpack_kernel, dim3((unsigned int)((cnt + 255) / 256 > 4096 ? 4096 : (cnt + 255) / 256)),
                      dim3(256), 0, st, b.x, out, cnt);

@@ -23,7 +23,7 @@ constexpr int CNN_G_W1 = 0, CNN_G_B1 = 576, CNN_G_W2 = 592, CNN_G_B2 = 5200, CNN
 constexpr int CNN_F1 = 0, CNN_F2 = 768, CNN_F3 = 5376, CNN_B3 = 9984, CNN_B2 = 11520, CNN_B1 = 16128, CNN_NW = 18432;
 // FP32 biases: b1 [16], b2 [32], b3 [16] (4 used)
 constexpr int CNN_BB1 = 0, CNN_BB2 = 16, CNN_BB3 = 48, CNN_NB = 64;
-constexpr int CNN_BLOCKS = 256;  // workgroups (and parameter partials) of the reverse pass
+constexpr int CNN_BLOCKS = 512;  // workgroups (and parameter partials) of the reverse pass
 
 struct CnnArgs {
   const unsigned short* w;  // [CNN_NW] bf16

@@ -9,25 +9,15 @@
 
 namespace shk {
 
-// Primitive state (rho, u_n, u_t, p) of stencil cell s (0..5) of face f of
-// batch member Ub; x-faces first ((nx+1) per row), then y-faces (nx per row).
-// The faces of one batch member are indexed in 32 bits.
-__device__ __forceinline__ void face_cell_prim(const GridArgs& a, const double* __restrict__ Ub, long long f, int s,
-                                               double w[4]) {
-  const int fi = (int)f, nxf = (a.nx + 1) * a.ny;
-  int gi, gj;
-  bool isx = fi < nxf;
-  if (isx) {
-    gj = fi / (a.nx + 1);
-    gi = fi - gj * (a.nx + 1) - 3 + s;
-  } else {
-    const int g = fi - nxf;
-    const int r = g / a.nx;
-    gi = g - r * a.nx;
-    gj = r - 3 + s;
-  }
+// Primitive state (rho, u_n, u_t, p) of grid cell (gi, gj) of batch member
+// Ub in the frame of an x-face (isx) or a y-face.  Indices outside the
+// domain are ghost cells by the boundary rules of the stage kernel
+// (reflection with the normal velocity negated, inflow state, periodic
+// wrap, zero-gradient outflow), clamped into the domain beyond the ghost
+// layers.
+__device__ __forceinline__ void cell_prim_frame(const GridArgs& a, const double* __restrict__ Ub, int gi, int gj,
+                                                bool isx, double w[4]) {
   double q[4];
-  // boundary rules as in the stage kernel
   int fx = 0, fy = 0;
   auto src = [](int g, int n, int lo, int hi, int& flag) {
     if (g >= 0 && g < n) return g;
@@ -60,6 +50,22 @@ __device__ __forceinline__ void face_cell_prim(const GridArgs& a, const double* 
   w[1] = isx ? p.un : p.ut;
   w[2] = isx ? p.ut : p.un;
   w[3] = p.p;
+}
+
+// Primitive state (rho, u_n, u_t, p) of stencil cell s (0..5) of face f of
+// batch member Ub; x-faces first ((nx+1) per row), then y-faces (nx per row).
+// The faces of one batch member are indexed in 32 bits.
+__device__ __forceinline__ void face_cell_prim(const GridArgs& a, const double* __restrict__ Ub, long long f, int s,
+                                               double w[4]) {
+  const int fi = (int)f, nxf = (a.nx + 1) * a.ny;
+  if (fi < nxf) {
+    const int gj = fi / (a.nx + 1);
+    cell_prim_frame(a, Ub, fi - gj * (a.nx + 1) - 3 + s, gj, true, w);
+  } else {
+    const int g = fi - nxf;
+    const int r = g / a.nx;
+    cell_prim_frame(a, Ub, g - r * a.nx, r - 3 + s, false, w);
+  }
 }
 
 // Reverse of one WENO5-JS reconstruction f(a,b,c,d,e) (the forward value is
