@@ -207,7 +207,8 @@ hipError_t stage_launch(shk_grid* g, const GridArgs& a, int mode, const S* Us, c
     GridArgs ax = a;
     ax.dFext = reinterpret_cast<float*>(g->ws + g->L.cnnDF);
     hipError_t e = launch_cnn_forward(ax, g->cnn, reinterpret_cast<const double*>(Us),
-                                      const_cast<float*>(ax.dFext), cnn_bufs(ax, g->ws + g->L.cnnBufs), g->st);
+                                      const_cast<float*>(ax.dFext), cnn_bufs(ax, g->ws + g->L.cnnBufs), false,
+                                      g->st);
     if (e != hipSuccess) return e;
     return launch_stage_ext(ax, mode, reinterpret_cast<const double*>(Us), reinterpret_cast<const double*>(Un),
                             reinterpret_cast<double*>(Uo), dtp, g->st);
@@ -737,7 +738,7 @@ shk_status shk_flux_cnn_eval(shk_grid* g, const void* U, float* dF) {
   if (!g->cnn_on) return fail(g, SHK_ESTATE, "flux_cnn_eval: no convolutional net set");
   return hip_check(g,
                    launch_cnn_forward(g->a, g->cnn, static_cast<const double*>(U), dF,
-                                      cnn_bufs(g->a, g->ws + g->L.cnnBufs), g->st),
+                                      cnn_bufs(g->a, g->ws + g->L.cnnBufs), false, g->st),
                    "flux_cnn_eval");
 }
 

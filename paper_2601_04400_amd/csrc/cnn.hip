@@ -13,17 +13,19 @@
 // across periodic ones, where the image holds each face once (the last face
 // of a periodic row is its first).
 //
-// Every layer is an implicit GEMM on 16 x 16 pixel tiles staged in LDS with
-// a one-pixel halo: D[out channel][pixel] = W[out channel][tap, in channel]
-// . X[tap, in channel][pixel] with v_mfma_f32_16x16x16_bf16, one pixel row
-// of a tile per product (N = 16), channels last so that an operand slice is
-// one 8-byte LDS read.  The reverse pass runs the same kernel with the
-// mirrored, channel-swapped weights for the input gradients (masked by the
-// forward ReLU) and a second kernel for the weight gradients, a contraction
-// over pixels whose operands are read channel-major from LDS.  Parameter
-// gradients go to one FP32 partial per workgroup (fixed tile order per
-// workgroup, fixed wave order inside it) and are summed in a fixed order:
-// the gradients are reproducible bit for bit.
+// The forward pass is two kernels: the face images (the stencil primitives
+// of a 16 x 16 pixel tile staged once in LDS, FP64 reconstruction, bf16
+// inputs), then the three layers fused over a tile with a three-pixel halo,
+// each an implicit GEMM D[out channel][pixel] = W[out channel][tap, in
+// channel] . X[tap, in channel][pixel] on the matrix cores (16 pixels per
+// product, N = 16), activations channels-last in LDS so that an operand
+// slice is one 8-byte LDS read.  The reverse pass runs a layer kernel with
+// the mirrored, channel-swapped weights for the input gradients (masked by
+// the forward ReLU) and a second kernel for the weight gradients, a
+// contraction over pixels whose operands are read channel-major from LDS.
+// Parameter gradients go to one FP32 partial per workgroup (fixed tile order
+// per workgroup, fixed wave order inside it) and are summed in a fixed
+// order: the gradients are reproducible bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -38,20 +40,15 @@ namespace shk {
 
 namespace {
 
-enum { EPI_FWD_HIDDEN = 0, EPI_FWD_OUT = 1, EPI_BWD_HIDDEN = 2, EPI_BWD_IN = 3 };
+enum { EPI_BWD_HIDDEN = 0, EPI_BWD_IN = 1 };
 
 struct ConvOut {
-  unsigned short* out_bf;            // bf16 image of COUT channels (hidden epilogues)
-  float* out_f;                      // FP32 image of 4 channels (EPI_BWD_IN) or tanh values (EPI_FWD_OUT)
+  unsigned short* out_bf;            // bf16 image of COUT channels (EPI_BWD_HIDDEN)
+  float* out_f;                      // FP32 image of 4 channels (EPI_BWD_IN)
   const unsigned short* mask_src;    // forward activation of the same pixels (EPI_BWD_HIDDEN)
   float* part;                       // [CNN_BLOCKS][CNN_NP] (EPI_BWD_HIDDEN: bias sums)
   int part_off;
   int cout;                          // real output channels
-  float out_scale;
-  float* dF;                         // [nbatch][nface][4] (EPI_FWD_OUT)
-  long long nface;
-  int nx, ny;
-  unsigned int* fault;
 };
 
 // Pixel index along an image axis of n pixels for a 3x3 window position k
@@ -91,9 +88,10 @@ __device__ __forceinline__ long long pixel_face(int img, int R, int C, int nx, i
   return img == 0 ? (long long)R * (nx + 1) + C : (long long)(nx + 1) * ny + (long long)C * nx + R;
 }
 
-// One 3x3 layer as an implicit GEMM over 16 x 16 pixel tiles (see the file
-// comment); MT output-channel tiles of 16, KB K-blocks of 16 (k = tap * CIN
-// + channel, taps >= 9 are zero padding).  Each lane keeps its weight
+// Input gradient of one 3x3 layer (the forward kernel with mirrored,
+// channel-swapped weights) as an implicit GEMM over 16 x 16 pixel tiles;
+// MT output-channel tiles of 16, KB K-blocks of 16 (k = tap * CIN +
+// channel, taps >= 9 are zero padding).  Each lane keeps its weight
 // fragments in registers for the whole launch; a wave computes its four
 // pixel rows as four independent accumulation chains.  The tile is staged in
 // planes of 16 channels ([plane][pixel][16]), so the 16 pixels x 4 channel
@@ -101,8 +99,7 @@ __device__ __forceinline__ long long pixel_face(int img, int R, int C, int nx, i
 // tiles of every batch member and both images in a fixed order.
 template <int CIN, int MT, int KB, int EPI>
 __global__ void __launch_bounds__(256) cnn_conv_kernel(CnnGeom g, const unsigned short* __restrict__ in,
-                                                       const unsigned short* __restrict__ wm,
-                                                       const float* __restrict__ bias, ConvOut o) {
+                                                       const unsigned short* __restrict__ wm, ConvOut o) {
   static_assert(CIN % 4 == 0, "channels come in groups of four");
   constexpr int CP = CIN >= 16 ? 16 : CIN;  // channels per plane
   constexpr int NPL = CIN / CP;             // planes
@@ -114,19 +111,9 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(CnnGeom g, const unsigned
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) Aw[mt][kb] = ldA(wm, KB * 16, mt * 16, kb * 16, lane);
-  f32x4 b0[MT];
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    b0[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (bias != nullptr) {
-      const float* bp = bias + mt * 16 + 4 * q;
-      b0[mt] = f32x4{bp[0], bp[1], bp[2], bp[3]};
-    }
-  }
   f32x4 bs[MT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) bs[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  bool bad = false;
   const long long ntile = (long long)g.tiles * g.nbatch;
   for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
     const TileLoc L = tile_loc(g, t);
@@ -146,7 +133,7 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(CnnGeom g, const unsigned
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) acc[rr][mt] = b0[mt];
+      for (int mt = 0; mt < MT; ++mt) acc[rr][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
       const int k0 = kb * 16 + 4 * q, tap = k0 / CIN, ci0 = k0 - tap * CIN;
@@ -165,38 +152,7 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(CnnGeom g, const unsigned
       const int R = L.r0 + wv * 4 + rr, C = L.c0 + fl;
       const bool valid = R < L.H && C < L.W;
       const long long pix = L.pbase + (long long)R * L.W + C;
-      if (EPI == EPI_FWD_HIDDEN) {
-        if (valid)
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) {
-            const f32x4 a = acc[rr][mt];
-            *reinterpret_cast<bf16x4*>(o.out_bf + pix * (MT * 16) + mt * 16 + 4 * q) =
-                pack4(fmaxf(a[0], 0.f), fmaxf(a[1], 0.f), fmaxf(a[2], 0.f), fmaxf(a[3], 0.f));
-          }
-      } else if (EPI == EPI_FWD_OUT) {
-        if (valid && q == 0) {
-          float th[4], out[4];
-          bool ok = true;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            th[i] = tanhf(acc[rr][0][i]);
-            out[i] = o.out_scale * th[i];
-            ok = ok && isfinite(out[i]);
-          }
-          if (!ok) {  // the uncorrected flux, with zero derivative
-#pragma unroll
-            for (int i = 0; i < 4; ++i) { out[i] = 0.f; th[i] = 1.f; }
-            bad = true;
-          }
-          *reinterpret_cast<f32x4*>(o.out_f + pix * 4) = f32x4{th[0], th[1], th[2], th[3]};
-          float* d = o.dF + ((long long)L.b * o.nface + pixel_face(L.img, R, C, o.nx, o.ny)) * 4;
-          *reinterpret_cast<f32x4*>(d) = f32x4{out[0], out[1], out[2], out[3]};
-          if (L.wc && C == 0) {  // the last face of a periodic row is this one
-            float* d2 = o.dF + ((long long)L.b * o.nface + pixel_face(L.img, R, L.W, o.nx, o.ny)) * 4;
-            *reinterpret_cast<f32x4*>(d2) = f32x4{out[0], out[1], out[2], out[3]};
-          }
-        }
-      } else if (EPI == EPI_BWD_HIDDEN) {
+      if (EPI == EPI_BWD_HIDDEN) {
         if (valid)
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
@@ -213,7 +169,6 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(CnnGeom g, const unsigned
       }
     }
   }
-  if (EPI == EPI_FWD_OUT && bad) atomicOr(o.fault, 8u);
   if (EPI == EPI_BWD_HIDDEN) {
     // this workgroup's bias sums: the 16 pixels of a row group, then the
     // four waves in order
@@ -230,6 +185,189 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(CnnGeom g, const unsigned
       o.part[(long long)blockIdx.x * CNN_NP + o.part_off + threadIdx.x] =
           ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
   }
+}
+
+// Pixel index along an image axis of n pixels for an unwrapped position k
+// of a layer region: k itself inside, the wrapped pixel across a periodic
+// edge, -1 (zero padding) outside otherwise.
+__device__ __forceinline__ int wrap_pix(int k, int n, int wrap) {
+  if (k >= 0 && k < n) return k;
+  if (!wrap) return -1;
+  return ((k % n) + n) % n;
+}
+
+// The forward network on one 16 x 16 output tile in a single pass: the
+// input image with a three-pixel halo is staged in LDS, layer 1 is evaluated
+// on the 20 x 20 pixels around the tile, layer 2 on 18 x 18 and layer 3 on
+// the tile, each layer's activations kept in LDS.  Halo pixels outside the
+// image are zero (the per-layer zero padding) unless they lie across a
+// periodic edge, where they take the wrapped pixel's values.  The pixels of
+// a region are taken 16 at a time in row-major order (one MFMA column
+// each), so a region need not be a multiple of 16 wide.  Layers 2 and 3 use
+// the K = 32 product (two taps of 16 channels, or one tap of 32).  With KEEP
+// the hidden activations and tanh values of the tile's own pixels are
+// written out for the reverse pass.
+template <bool KEEP>
+__global__ void __launch_bounds__(256) cnn_forward_kernel(CnnGeom g, CnnArgs n, const unsigned short* __restrict__ xin,
+                                                          float* __restrict__ dF, long long nface, int nx, int ny,
+                                                          unsigned short* __restrict__ h1g,
+                                                          unsigned short* __restrict__ h2g, float* __restrict__ tg,
+                                                          unsigned int* fault) {
+  __shared__ __attribute__((aligned(16))) unsigned short sX[22 * 22 * 4];
+  __shared__ __attribute__((aligned(16))) unsigned short sH1[20 * 20 * 16];
+  __shared__ __attribute__((aligned(16))) unsigned short sH2[2 * 324 * 16];  // two planes of 16 channels
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane >> 4, fl = lane & 15;
+  const unsigned short* __restrict__ w = n.w;
+  auto bias4 = [&](int off) {
+    const float* bp = n.bias + off + 4 * q;
+    return f32x4{bp[0], bp[1], bp[2], bp[3]};
+  };
+  bool bad = false;
+  const long long ntile = (long long)g.tiles * g.nbatch;
+  for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const TileLoc L = tile_loc(g, t);
+    __syncthreads();  // the previous tile's readers are done
+    for (int k = threadIdx.x; k < 22 * 22; k += blockDim.x) {
+      const int tr = k / 22, tc = k - tr * 22;
+      const int R = wrap_pix(L.r0 - 3 + tr, L.H, L.wr), C = wrap_pix(L.c0 - 3 + tc, L.W, L.wc);
+      bf16x4 v = {0, 0, 0, 0};
+      if (R >= 0 && C >= 0) v = *reinterpret_cast<const bf16x4*>(xin + (L.pbase + (long long)R * L.W + C) * 4);
+      *reinterpret_cast<bf16x4*>(sX + k * 4) = v;
+    }
+    __syncthreads();
+    {  // layer 1 on 20 x 20: 25 groups, K = 3 taps of 4 channels per block of 16
+      bf16x4 A1[3];
+#pragma unroll
+      for (int kb = 0; kb < 3; ++kb) A1[kb] = ldA(w + CNN_F1, 48, 0, kb * 16, lane);
+      const f32x4 b1 = bias4(CNN_BB1);
+      for (int gi = wv; gi < 25; gi += 4) {
+        const int p = gi * 16 + fl, hr = p / 20, hc = p - hr * 20;
+        f32x4 acc = b1;
+#pragma unroll
+        for (int kb = 0; kb < 3; ++kb) {
+          const int tap = 4 * kb + q, dr = tap / 3, dc = tap - 3 * dr;
+          bf16x4 B = {0, 0, 0, 0};
+          if (tap < 9) B = *reinterpret_cast<const bf16x4*>(sX + ((hr + dr) * 22 + hc + dc) * 4);
+          acc = mfma(A1[kb], B, acc);
+        }
+        const int R = L.r0 - 2 + hr, C = L.c0 - 2 + hc;
+        const bool live = wrap_pix(R, L.H, L.wr) >= 0 && wrap_pix(C, L.W, L.wc) >= 0;
+        bf16x4 hv = {0, 0, 0, 0};
+        if (live) hv = pack4(fmaxf(acc[0], 0.f), fmaxf(acc[1], 0.f), fmaxf(acc[2], 0.f), fmaxf(acc[3], 0.f));
+        *reinterpret_cast<bf16x4*>(sH1 + p * 16 + 4 * q) = hv;
+        if (KEEP && R >= L.r0 && R < L.r0 + 16 && C >= L.c0 && C < L.c0 + 16 && R < L.H && C < L.W)
+          *reinterpret_cast<bf16x4*>(h1g + (L.pbase + (long long)R * L.W + C) * 16 + 4 * q) = hv;
+      }
+    }
+    __syncthreads();
+    {  // layer 2 on 18 x 18: 21 groups (the last holds 4 pixels), two at a time
+      s16x8 A2[2][4];
+      bf16x4 A2t[2];  // tap 8
+      f32x4 b2[2];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) A2[mt][kb] = ldA32(w + CNN_F2, 144, mt * 16, kb, lane);
+        A2t[mt] = ldA(w + CNN_F2, 144, mt * 16, 128, lane);
+        b2[mt] = bias4(CNN_BB2 + mt * 16);
+      }
+      for (int g0 = wv; g0 < 21; g0 += 8) {
+        int p[2], hr[2], hc[2];
+        f32x4 acc[2][2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          p[j] = (g0 + 4 * j) * 16 + fl;
+          const int pc = p[j] < 324 ? p[j] : 323;
+          hr[j] = pc / 18;
+          hc[j] = pc - hr[j] * 18;
+          acc[j][0] = b2[0];
+          acc[j][1] = b2[1];
+        }
+        auto ld1 = [&](int j, int tap) {
+          const int dr = tap / 3, dc = tap - 3 * dr;
+          return *reinterpret_cast<const bf16x4*>(sH1 + ((hr[j] + dr) * 20 + hc[j] + dc) * 16 + 4 * q);
+        };
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const s16x8 B = cat8(ld1(j, 2 * kb), ld1(j, 2 * kb + 1));
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) acc[j][mt] = mfma32(A2[mt][kb], B, acc[j][mt]);
+          }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const bf16x4 B = ld1(j, 8);
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) acc[j][mt] = mfma(A2t[mt], B, acc[j][mt]);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (p[j] >= 324) continue;
+          const int R = L.r0 - 1 + hr[j], C = L.c0 - 1 + hc[j];
+          const bool live = wrap_pix(R, L.H, L.wr) >= 0 && wrap_pix(C, L.W, L.wc) >= 0;
+          const bool own = KEEP && R >= L.r0 && R < L.r0 + 16 && C >= L.c0 && C < L.c0 + 16 && R < L.H && C < L.W;
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) {
+            const f32x4 a2 = acc[j][mt];
+            bf16x4 hv = {0, 0, 0, 0};
+            if (live) hv = pack4(fmaxf(a2[0], 0.f), fmaxf(a2[1], 0.f), fmaxf(a2[2], 0.f), fmaxf(a2[3], 0.f));
+            *reinterpret_cast<bf16x4*>(sH2 + (mt * 324 + p[j]) * 16 + 4 * q) = hv;
+            if (own) *reinterpret_cast<bf16x4*>(h2g + (L.pbase + (long long)R * L.W + C) * 32 + mt * 16 + 4 * q) = hv;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    {  // layer 3 on the tile: rows 4 wv .. 4 wv + 3, one tap of 32 channels per K = 32 block
+      s16x8 A3[9];
+#pragma unroll
+      for (int kb = 0; kb < 9; ++kb) A3[kb] = ldA32(w + CNN_F3, 288, 0, kb, lane);
+      const f32x4 b3 = bias4(CNN_BB3);
+      f32x4 acc[4];
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) acc[rr] = b3;
+#pragma unroll
+      for (int kb = 0; kb < 9; ++kb) {
+        const int dr = kb / 3, dc = kb - 3 * dr;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int pix = (wv * 4 + rr + dr) * 18 + fl + dc;
+          const s16x8 B = cat8(*reinterpret_cast<const bf16x4*>(sH2 + pix * 16 + 4 * q),
+                               *reinterpret_cast<const bf16x4*>(sH2 + (324 + pix) * 16 + 4 * q));
+          acc[rr] = mfma32(A3[kb], B, acc[rr]);
+        }
+      }
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        // lane (pixel fl of the row, q = 0) holds the four output channels
+        const int R = L.r0 + wv * 4 + rr, C = L.c0 + fl;
+        if (!(R < L.H && C < L.W && q == 0)) continue;
+        float th[4], out[4];
+        bool ok = true;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          th[i] = tanhf(acc[rr][i]);
+          out[i] = n.out_scale * th[i];
+          ok = ok && isfinite(out[i]);
+        }
+        if (!ok) {  // the uncorrected flux, with zero derivative
+#pragma unroll
+          for (int i = 0; i < 4; ++i) { out[i] = 0.f; th[i] = 1.f; }
+          bad = true;
+        }
+        const long long pix = L.pbase + (long long)R * L.W + C;
+        if (KEEP) *reinterpret_cast<f32x4*>(tg + pix * 4) = f32x4{th[0], th[1], th[2], th[3]};
+        float* d = dF + ((long long)L.b * nface + pixel_face(L.img, R, C, nx, ny)) * 4;
+        *reinterpret_cast<f32x4*>(d) = f32x4{out[0], out[1], out[2], out[3]};
+        if (L.wc && C == 0) {  // the last face of a periodic row is this one
+          float* d2 = dF + ((long long)L.b * nface + pixel_face(L.img, R, L.W, nx, ny)) * 4;
+          *reinterpret_cast<f32x4*>(d2) = f32x4{out[0], out[1], out[2], out[3]};
+        }
+      }
+    }
+  }
+  if (bad) atomicOr(fault, 8u);
 }
 
 // Weight gradient of one layer: D[out channel][tap, in channel] = sum over
@@ -693,33 +831,23 @@ hipError_t launch_cnn_pack(const float* theta, unsigned short* w, float* bias, h
 }
 
 hipError_t launch_cnn_forward(const GridArgs& a, const CnnArgs& n, const double* U, float* dF, const CnnBufs& b,
-                              hipStream_t st) {
+                              bool keep, hipStream_t st) {
   const CnnGeom g = cnn_geom(a);
   hipLaunchKernelGGL(cnn_inputs_kernel, dim3(tile_blocks(g)), dim3(256), 0, st, a, g, n, U, b.x);
-  ConvOut o{};
-  o.out_bf = b.h1;
-  hipLaunchKernelGGL((cnn_conv_kernel<4, 1, 3, EPI_FWD_HIDDEN>), dim3(tile_blocks(g)), dim3(256), 0, st, g, b.x,
-                     n.w + CNN_F1, n.bias + CNN_BB1, o);
-  o.out_bf = b.h2;
-  hipLaunchKernelGGL((cnn_conv_kernel<16, 2, 9, EPI_FWD_HIDDEN>), dim3(tile_blocks(g)), dim3(256), 0, st, g, b.h1,
-                     n.w + CNN_F2, n.bias + CNN_BB2, o);
-  ConvOut o3{};
-  o3.out_f = b.t;
-  o3.out_scale = n.out_scale;
-  o3.dF = dF;
-  o3.nface = (long long)(a.nx + 1) * a.ny + (long long)a.nx * (a.ny + 1);
-  o3.nx = a.nx;
-  o3.ny = a.ny;
-  o3.fault = &a.glob->fault;
-  hipLaunchKernelGGL((cnn_conv_kernel<32, 1, 18, EPI_FWD_OUT>), dim3(tile_blocks(g)), dim3(256), 0, st, g, b.h2,
-                     n.w + CNN_F3, n.bias + CNN_BB3, o3);
+  const long long nface = (long long)(a.nx + 1) * a.ny + (long long)a.nx * (a.ny + 1);
+  if (keep)
+    hipLaunchKernelGGL(cnn_forward_kernel<true>, dim3(tile_blocks(g)), dim3(256), 0, st, g, n, b.x, dF, nface, a.nx,
+                       a.ny, b.h1, b.h2, b.t, &a.glob->fault);
+  else
+    hipLaunchKernelGGL(cnn_forward_kernel<false>, dim3(tile_blocks(g)), dim3(256), 0, st, g, n, b.x, dF, nface, a.nx,
+                       a.ny, b.h1, b.h2, b.t, &a.glob->fault);
   return hipGetLastError();
 }
 
 hipError_t launch_cnn_backward(const GridArgs& a, const CnnArgs& n, const double* U, const double* lam,
                                double clam_f, const double* dtp, float* dX, float* dF, const CnnBufs& b, float* grad,
                                hipStream_t st) {
-  hipError_t e = launch_cnn_forward(a, n, U, dF, b, st);
+  hipError_t e = launch_cnn_forward(a, n, U, dF, b, true, st);
   if (e != hipSuccess) return e;
   const CnnGeom g = cnn_geom(a);
   const long long nface = (long long)(a.nx + 1) * a.ny + (long long)a.nx * (a.ny + 1);
@@ -733,7 +861,7 @@ hipError_t launch_cnn_backward(const GridArgs& a, const CnnArgs& n, const double
   o.part_off = CNN_G_B2;
   o.cout = 32;
   hipLaunchKernelGGL((cnn_conv_kernel<4, 2, 3, EPI_BWD_HIDDEN>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.dz,
-                     n.w + CNN_B3, nullptr, o);
+                     n.w + CNN_B3, o);
   hipLaunchKernelGGL((cnn_wgrad_kernel<32, 4, 1, 18>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.dz, b.h2, b.part,
                      CNN_G_W3);
   // layer 2
@@ -742,14 +870,14 @@ hipError_t launch_cnn_backward(const GridArgs& a, const CnnArgs& n, const double
   o.part_off = CNN_G_B1;
   o.cout = 16;
   hipLaunchKernelGGL((cnn_conv_kernel<32, 1, 18, EPI_BWD_HIDDEN>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.da2,
-                     n.w + CNN_B2, nullptr, o);
+                     n.w + CNN_B2, o);
   hipLaunchKernelGGL((cnn_wgrad_kernel<16, 32, 2, 9>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.da2, b.h1, b.part,
                      CNN_G_W2);
   // layer 1: gradient of the normalised inputs, and weights
   ConvOut o1{};
   o1.out_f = b.dx;
   hipLaunchKernelGGL((cnn_conv_kernel<16, 1, 9, EPI_BWD_IN>), dim3(tile_blocks(g)), dim3(256), 0, st, g, b.da1,
-                     n.w + CNN_B1, nullptr, o1);
+                     n.w + CNN_B1, o1);
   hipLaunchKernelGGL((cnn_wgrad_kernel<4, 16, 1, 3>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.da1, b.x, b.part,
                      CNN_G_W1);
   hipLaunchKernelGGL(cnn_input_grad_kernel, dim3(tile_blocks(g)), dim3(256), 0, st, a, g, n, U, b.dx, dX, nface);

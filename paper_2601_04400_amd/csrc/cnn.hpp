@@ -58,9 +58,9 @@ CnnBufs cnn_bufs(const GridArgs& a, char* base);
 
 hipError_t launch_cnn_pack(const float* theta, unsigned short* w, float* bias, hipStream_t st);
 // forward: correction of every face dF [nbatch][nface][4] (face frame) from
-// the state U; keeps the activations in bufs for the reverse pass
+// the state U; with keep, also the activations in bufs for the reverse pass
 hipError_t launch_cnn_forward(const GridArgs& a, const CnnArgs& n, const double* U, float* dF, const CnnBufs& b,
-                              hipStream_t st);
+                              bool keep, hipStream_t st);
 // reverse: from the right-hand-side adjoint lam (scaled by clam_f * dt[b]),
 // recomputes the forward, writes the stencil gradient of every face
 // dX [nbatch][nface][24] (face frame, w.r.t. the primitive states) and adds
