@@ -204,24 +204,31 @@ __device__ __forceinline__ int wrap_pix(int k, int n, int wrap) {
 // periodic edge, where they take the wrapped pixel's values.  The pixels of
 // a region are taken 16 at a time in row-major order (one MFMA column
 // each), so a region need not be a multiple of 16 wide.  Layers 2 and 3 use
-// the K = 32 product (two taps of 16 channels, or one tap of 32).  With KEEP
-// the hidden activations and tanh values of the tile's own pixels are
-// written out for the reverse pass.
+// the K = 32 product with the eight k-slots of a lane on eight consecutive
+// channels of one tap (two taps of 16 channels, or one tap of 32 per block):
+// an operand is one 16-byte read of the weights or of the channels-last
+// activations, whose pixel strides (48 and 80 bytes) put the 16 pixels of a
+// read on distinct LDS banks.  The output layer's four channels are
+// redistributed through LDS so that every lane evaluates tanh for one pixel.
+// With KEEP the hidden activations and tanh values of the tile's own pixels
+// are written out for the reverse pass.
 template <bool KEEP>
 __global__ void __launch_bounds__(256) cnn_forward_kernel(CnnGeom g, CnnArgs n, const unsigned short* __restrict__ xin,
                                                           float* __restrict__ dF, long long nface, int nx, int ny,
                                                           unsigned short* __restrict__ h1g,
                                                           unsigned short* __restrict__ h2g, float* __restrict__ tg,
                                                           unsigned int* fault) {
+  constexpr int S1 = 24, S2 = 40;  // pixel strides (elements) of the layer-1 and layer-2 activations
   __shared__ __attribute__((aligned(16))) unsigned short sX[22 * 22 * 4];
-  __shared__ __attribute__((aligned(16))) unsigned short sH1[20 * 20 * 16];
-  __shared__ __attribute__((aligned(16))) unsigned short sH2[2 * 324 * 16];  // two planes of 16 channels
+  __shared__ __attribute__((aligned(16))) unsigned short sH1[20 * 20 * S1];
+  __shared__ __attribute__((aligned(16))) unsigned short sH2[18 * 18 * S2];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane >> 4, fl = lane & 15;
   const unsigned short* __restrict__ w = n.w;
   auto bias4 = [&](int off) {
     const float* bp = n.bias + off + 4 * q;
     return f32x4{bp[0], bp[1], bp[2], bp[3]};
   };
+  auto ld16 = [](const unsigned short* p) { return *reinterpret_cast<const s16x8*>(p); };
   bool bad = false;
   const long long ntile = (long long)g.tiles * g.nbatch;
   for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
@@ -235,7 +242,7 @@ __global__ void __launch_bounds__(256) cnn_forward_kernel(CnnGeom g, CnnArgs n, 
       *reinterpret_cast<bf16x4*>(sX + k * 4) = v;
     }
     __syncthreads();
-    {  // layer 1 on 20 x 20: 25 groups, K = 3 taps of 4 channels per block of 16
+    {  // layer 1 on 20 x 20: 25 groups, K = 3 blocks of four taps x 4 channels
       bf16x4 A1[3];
 #pragma unroll
       for (int kb = 0; kb < 3; ++kb) A1[kb] = ldA(w + CNN_F1, 48, 0, kb * 16, lane);
@@ -254,57 +261,62 @@ __global__ void __launch_bounds__(256) cnn_forward_kernel(CnnGeom g, CnnArgs n, 
         const bool live = wrap_pix(R, L.H, L.wr) >= 0 && wrap_pix(C, L.W, L.wc) >= 0;
         bf16x4 hv = {0, 0, 0, 0};
         if (live) hv = pack4(fmaxf(acc[0], 0.f), fmaxf(acc[1], 0.f), fmaxf(acc[2], 0.f), fmaxf(acc[3], 0.f));
-        *reinterpret_cast<bf16x4*>(sH1 + p * 16 + 4 * q) = hv;
+        *reinterpret_cast<bf16x4*>(sH1 + p * S1 + 4 * q) = hv;
         if (KEEP && R >= L.r0 && R < L.r0 + 16 && C >= L.c0 && C < L.c0 + 16 && R < L.H && C < L.W)
           *reinterpret_cast<bf16x4*>(h1g + (L.pbase + (long long)R * L.W + C) * 16 + 4 * q) = hv;
       }
     }
     __syncthreads();
-    {  // layer 2 on 18 x 18: 21 groups (the last holds 4 pixels), two at a time
+    {  // layer 2 on 18 x 18: 21 groups (the last holds 4 pixels), two at a time;
+       // K = 32 block kb holds taps 2 kb (lanes q < 2) and 2 kb + 1 (q >= 2),
+       // channels 8 (q & 1) .. + 7; tap 8 is one K = 16 block
       s16x8 A2[2][4];
-      bf16x4 A2t[2];  // tap 8
+      bf16x4 A2t[2];
       f32x4 b2[2];
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) {
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) A2[mt][kb] = ldA32(w + CNN_F2, 144, mt * 16, kb, lane);
+        for (int kb = 0; kb < 4; ++kb) A2[mt][kb] = ld16(w + CNN_F2 + (mt * 16 + fl) * 144 + 32 * kb + 8 * q);
         A2t[mt] = ldA(w + CNN_F2, 144, mt * 16, 128, lane);
         b2[mt] = bias4(CNN_BB2 + mt * 16);
       }
+      int toff[4];  // this lane's tap offset (elements) in K = 32 block kb
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) {
+        const int tap = 2 * kb + (q >> 1), dr = tap / 3, dc = tap - 3 * dr;
+        toff[kb] = (dr * 20 + dc) * S1 + 8 * (q & 1);
+      }
       for (int g0 = wv; g0 < 21; g0 += 8) {
-        int p[2], hr[2], hc[2];
+        int p[2], base[2];
         f32x4 acc[2][2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           p[j] = (g0 + 4 * j) * 16 + fl;
           const int pc = p[j] < 324 ? p[j] : 323;
-          hr[j] = pc / 18;
-          hc[j] = pc - hr[j] * 18;
+          const int hr = pc / 18, hc = pc - hr * 18;
+          base[j] = (hr * 20 + hc) * S1;
           acc[j][0] = b2[0];
           acc[j][1] = b2[1];
         }
-        auto ld1 = [&](int j, int tap) {
-          const int dr = tap / 3, dc = tap - 3 * dr;
-          return *reinterpret_cast<const bf16x4*>(sH1 + ((hr[j] + dr) * 20 + hc[j] + dc) * 16 + 4 * q);
-        };
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
-            const s16x8 B = cat8(ld1(j, 2 * kb), ld1(j, 2 * kb + 1));
+            const s16x8 B = ld16(sH1 + base[j] + toff[kb]);
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) acc[j][mt] = mfma32(A2[mt][kb], B, acc[j][mt]);
           }
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          const bf16x4 B = ld1(j, 8);
+          const bf16x4 B = *reinterpret_cast<const bf16x4*>(sH1 + base[j] + (2 * 20 + 2) * S1 + 4 * q);
 #pragma unroll
           for (int mt = 0; mt < 2; ++mt) acc[j][mt] = mfma(A2t[mt], B, acc[j][mt]);
         }
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           if (p[j] >= 324) continue;
-          const int R = L.r0 - 1 + hr[j], C = L.c0 - 1 + hc[j];
+          const int hr = p[j] / 18, hc = p[j] - hr * 18;
+          const int R = L.r0 - 1 + hr, C = L.c0 - 1 + hc;
           const bool live = wrap_pix(R, L.H, L.wr) >= 0 && wrap_pix(C, L.W, L.wc) >= 0;
           const bool own = KEEP && R >= L.r0 && R < L.r0 + 16 && C >= L.c0 && C < L.c0 + 16 && R < L.H && C < L.W;
 #pragma unroll
@@ -312,7 +324,7 @@ __global__ void __launch_bounds__(256) cnn_forward_kernel(CnnGeom g, CnnArgs n, 
             const f32x4 a2 = acc[j][mt];
             bf16x4 hv = {0, 0, 0, 0};
             if (live) hv = pack4(fmaxf(a2[0], 0.f), fmaxf(a2[1], 0.f), fmaxf(a2[2], 0.f), fmaxf(a2[3], 0.f));
-            *reinterpret_cast<bf16x4*>(sH2 + (mt * 324 + p[j]) * 16 + 4 * q) = hv;
+            *reinterpret_cast<bf16x4*>(sH2 + p[j] * S2 + mt * 16 + 4 * q) = hv;
             if (own) *reinterpret_cast<bf16x4*>(h2g + (L.pbase + (long long)R * L.W + C) * 32 + mt * 16 + 4 * q) = hv;
           }
         }
@@ -322,7 +334,7 @@ __global__ void __launch_bounds__(256) cnn_forward_kernel(CnnGeom g, CnnArgs n, 
     {  // layer 3 on the tile: rows 4 wv .. 4 wv + 3, one tap of 32 channels per K = 32 block
       s16x8 A3[9];
 #pragma unroll
-      for (int kb = 0; kb < 9; ++kb) A3[kb] = ldA32(w + CNN_F3, 288, 0, kb, lane);
+      for (int kb = 0; kb < 9; ++kb) A3[kb] = ld16(w + CNN_F3 + fl * 288 + 32 * kb + 8 * q);
       const f32x4 b3 = bias4(CNN_BB3);
       f32x4 acc[4];
 #pragma unroll
@@ -331,23 +343,24 @@ __global__ void __launch_bounds__(256) cnn_forward_kernel(CnnGeom g, CnnArgs n, 
       for (int kb = 0; kb < 9; ++kb) {
         const int dr = kb / 3, dc = kb - 3 * dr;
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          const int pix = (wv * 4 + rr + dr) * 18 + fl + dc;
-          const s16x8 B = cat8(*reinterpret_cast<const bf16x4*>(sH2 + pix * 16 + 4 * q),
-                               *reinterpret_cast<const bf16x4*>(sH2 + (324 + pix) * 16 + 4 * q));
-          acc[rr] = mfma32(A3[kb], B, acc[rr]);
-        }
+        for (int rr = 0; rr < 4; ++rr)
+          acc[rr] = mfma32(A3[kb], ld16(sH2 + ((wv * 4 + rr + dr) * 18 + fl + dc) * S2 + 8 * q), acc[rr]);
       }
+      // lanes q = 0 hold the four output channels of rows 4 wv + rr; through
+      // LDS (the layer-1 buffer, free now) lane (fl, q) takes row 4 wv + q
+      float* red = reinterpret_cast<float*>(sH1) + wv * 256;
+      if (q == 0)
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        // lane (pixel fl of the row, q = 0) holds the four output channels
-        const int R = L.r0 + wv * 4 + rr, C = L.c0 + fl;
-        if (!(R < L.H && C < L.W && q == 0)) continue;
+        for (int rr = 0; rr < 4; ++rr) *reinterpret_cast<f32x4*>(red + (rr * 16 + fl) * 4) = acc[rr];
+      __syncthreads();
+      const f32x4 z = *reinterpret_cast<const f32x4*>(red + (q * 16 + fl) * 4);
+      const int R = L.r0 + wv * 4 + q, C = L.c0 + fl;
+      if (R < L.H && C < L.W) {
         float th[4], out[4];
         bool ok = true;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          th[i] = tanhf(acc[rr][i]);
+          th[i] = tanhf(z[i]);
           out[i] = n.out_scale * th[i];
           ok = ok && isfinite(out[i]);
         }
