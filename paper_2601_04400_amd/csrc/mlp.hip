@@ -43,7 +43,7 @@ __device__ __forceinline__ void build_inputs(const GridArgs& a, const NetArgs& n
 // output is replaced by zero (the uncorrected flux) and flagged.
 __global__ void __launch_bounds__(256) net_forward_kernel(GridArgs a, NetArgs n, const double* __restrict__ U,
                                                           float* __restrict__ dF, long long nface) {
-  __shared__ __attribute__((aligned(16))) unsigned short sw[NET_NW];
+  __shared__ __attribute__((aligned(16))) unsigned short sw[NET_LNW];
   __shared__ float sb[NET_NB];
   load_net_lds(n, sw, sb);
   __syncthreads();
@@ -147,8 +147,8 @@ __device__ __forceinline__ void hidden_input_grad(const unsigned short* wT, cons
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    acc = mfma32(ldA32(wT, 64, it * 16, 0, lane), b0, acc);
-    acc = mfma32(ldA32(wT, 64, it * 16, 1, lane), b1, acc);
+    acc = mfma32(ldA32(wT, NET_LD_H, it * 16, 0, lane), b0, acc);
+    acc = mfma32(ldA32(wT, NET_LD_H, it * 16, 1, lane), b1, acc);
     dB[it] = relu_mask(acc, mask, it);
   }
 }
@@ -161,64 +161,79 @@ __device__ __forceinline__ void hidden_input_grad(const unsigned short* wT, cons
 // face (dX[b][face][6][4], face frame, w.r.t. the primitive states) and this
 // block's parameter gradient to part[block][NET_NP].
 //
-// Each wave takes 16-face tiles of all batch members in a fixed order and
-// runs the network forward and backward on one tile at a time.  The weight
-// gradients of all four layers stay in the wave's MFMA accumulators for the
-// whole kernel (176 values per lane); the bias gradients are FP32 running
-// sums of each lane's own pre-activation gradients (52 per lane), summed
-// over the lanes of a row group at the end.  Then the four waves
-// add their sums in wave order: the result is reproducible bit for bit.  The
-// reverse products dH = W^T dA read a transposed copy of the weights.
-__global__ void __launch_bounds__(256) net_backward_kernel(GridArgs a, NetArgs n, const double* __restrict__ U,
+// The four waves of a workgroup take one 16-face tile each per round (tiles
+// of all batch members in a fixed order) and run the network forward and
+// backward on it.  At each layer they exchange their tiles' pre-activation
+// gradients dZ and layer inputs H through LDS (neuron-major, so an operand
+// slice of four faces is one 8-byte read), and each wave accumulates one
+// quarter of the layer's weight gradient dW += dZ . H^T over the four
+// tiles: output rows 16 wv .. 16 wv + 15 of the hidden and first layers,
+// input columns 16 wv .. 16 wv + 15 of the output layer (44 accumulator
+// values per lane instead of the whole 176).  The bias gradients are FP32
+// running sums of each lane's own pre-activation gradients, summed over the
+// lanes of a row group and then over the waves in wave order.  Every
+// parameter's sum runs in a fixed order: the result is reproducible bit for
+// bit.  The reverse products dH = W^T dA read a transposed copy of the
+// weights.
+__global__ void __launch_bounds__(256, 2) net_backward_kernel(GridArgs a, NetArgs n, const double* __restrict__ U,
                                                            const double* __restrict__ lam, double clam_f,
                                                            const double* __restrict__ dtp, float* __restrict__ dX,
                                                            float* __restrict__ part, long long nface) {
-  __shared__ __attribute__((aligned(16))) unsigned short sw[NET_NW];
-  __shared__ __attribute__((aligned(16))) unsigned short swT[NET_NW];  // W0^T [32][64], W1^T, W2^T, W3^T [64][16]
+  __shared__ __attribute__((aligned(16))) unsigned short sw[NET_LNW];
+  __shared__ __attribute__((aligned(16))) unsigned short swT[NET_TNW];  // W0^T [32][64], W1^T, W2^T, W3^T [64][16]
   __shared__ float sb[NET_NB];
-  __shared__ __attribute__((aligned(16))) unsigned short tr[4][8 * 16 * TR_LD];
-  __shared__ float gsum[NET_NP];
+  // per wave: rows 0..63 dZ of the current layer, rows 64..127 its input
+  constexpr int XR = 128;
+  __shared__ __attribute__((aligned(16))) unsigned short xch[4][XR * TR_LD];
+  __shared__ float bred[4][NET_NB];
   load_net_lds(n, sw, sb);
+  // transposed copy: element (o, i) of W_l goes to row i, column o
   for (int k = threadIdx.x; k < NET_NW; k += blockDim.x) {
-    int src;
+    int d;
     if (k < NET_OFF_W1) {
-      const int i = k / 64, o = k % 64;
-      src = NET_OFF_W0 + o * 32 + i;
+      d = NET_T_W0 + (k & 31) * NET_LD_H + (k >> 5);
     } else if (k < NET_OFF_W3) {
-      const int base = k < NET_OFF_W2 ? NET_OFF_W1 : NET_OFF_W2, i = (k - base) / 64, o = (k - base) % 64;
-      src = base + o * 64 + i;
+      const int base = k < NET_OFF_W2 ? NET_OFF_W1 : NET_OFF_W2, kk = k - base;
+      d = (k < NET_OFF_W2 ? NET_T_W1 : NET_T_W2) + (kk & 63) * NET_LD_H + (kk >> 6);
     } else {
-      const int i = (k - NET_OFF_W3) / 16, o = (k - NET_OFF_W3) % 16;
-      src = NET_OFF_W3 + o * 64 + i;
+      const int kk = k - NET_OFF_W3;
+      d = NET_T_W3 + (kk & 63) * NET_LD_O + (kk >> 6);
     }
-    swT[k] = n.w[src];
+    swT[d] = n.w[k];
   }
-  for (int k = threadIdx.x; k < NET_NP; k += blockDim.x) gsum[k] = 0.f;
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane >> 4, fl = lane & 15;
-  unsigned short* trw = tr[wv];
+  unsigned short* xw = xch[wv];
   const int nxf = (a.nx + 1) * a.ny;
   const bool perx = a.bc[0] == BC_PERIODIC, pery = a.bc[2] == BC_PERIODIC;
-  f32x4 g0[4][2], g1[4][4], g2[4][4], g3[4];
+  // this wave's quarter of the weight gradients
+  f32x4 g0[2], g1[4], g2[4], g3;
   f32x4 bs0[4], bs1[4], bs2[4], bs3;  // bias sums of the lane's own faces: [neuron tile] rows 4q..4q+3
-  bs3 = f32x4{0.f, 0.f, 0.f, 0.f};
+  bs3 = g3 = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int ot = 0; ot < 4; ++ot) bs0[ot] = bs1[ot] = bs2[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int ot = 0; ot < 4; ++ot) bs0[ot] = bs1[ot] = bs2[ot] = g1[ot] = g2[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
+  g0[0] = g0[1] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // D-layout tile (lane (face c, q) holds rows r0 + 4q .. + 3) into this
+  // wave's exchange rows, bf16
+  auto put = [&](int r0, bf16x4 v) {
 #pragma unroll
-  for (int ot = 0; ot < 4; ++ot) {
-    g3[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int it = 0; it < 4; ++it) g1[ot][it] = g2[ot][it] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int it = 0; it < 2; ++it) g0[ot][it] = f32x4{0.f, 0.f, 0.f, 0.f};
-  }
+    for (int i = 0; i < 4; ++i) xw[(r0 + 4 * q + i) * TR_LD + fl] = (unsigned short)v[i];
+  };
+  auto putf = [&](int r0, f32x4 v) { put(r0, pack4(v[0], v[1], v[2], v[3])); };
+  // operand slice of wave j's exchange rows: row r0 + (lane & 15), faces 4q .. 4q + 3
+  auto get = [&](int j, int r0) { return *reinterpret_cast<const bf16x4*>(&xch[j][(r0 + fl) * TR_LD + 4 * q]); };
   const long long per_b = (nface + 15) / 16;
   const long long total = per_b * a.nbatch;
-  for (long long t = (long long)blockIdx.x * 4 + wv; t < total; t += (long long)gridDim.x * 4) {
-    const int b = (int)(t / per_b);
-    const long long f = (t % per_b) * 16 + fl;
-    const bool fok = f < nface;
-    const long long fc = fok ? f : nface - 1;
+  // every wave of the workgroup runs the same rounds (a wave past the last
+  // tile computes zeros), so the barriers are uniform
+  for (long long t0 = (long long)blockIdx.x * 4; t0 < total; t0 += (long long)gridDim.x * 4) {
+    const long long t = t0 + wv;
+    const bool tok = t < total;
+    const long long tc = tok ? t : total - 1;
+    const int b = (int)(tc / per_b);
+    const long long f = (tc % per_b) * 16 + fl;
+    const bool fok = tok && f < nface;
+    const long long fc = f < nface ? f : nface - 1;
     const double* __restrict__ Ub = U + (long long)b * 4 * a.ncell;
     const double* __restrict__ Lb = lam + (long long)b * 4 * a.ncell;
     // the adjoint of the two cells beside the face (zero outside the domain
@@ -277,48 +292,70 @@ __global__ void __launch_bounds__(256) net_backward_kernel(GridArgs a, NetArgs n
       }
     const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
     f32x4 dA[4], dB[4];
-    // output layer (16 rows, 4 used): weight and bias gradient, then dH2
-    {
-      const bf16x4 aT = transpose_f(trw, d3, lane);
+    // output layer (16 rows, 4 used): dZ3 and H2 out, dH2 = W3^T dZ3
+    putf(0, d3);
 #pragma unroll
-      for (int it = 0; it < 4; ++it)
-        g3[it] = mfma(aT, transpose_bf(trw + (4 + it) * 16 * TR_LD, A.h[2][it][0], lane), g3[it]);
-      bs3 += d3;
+    for (int it = 0; it < 4; ++it) put(64 + it * 16, A.h[2][it][0]);
+    bs3 += d3;
+    {
       const bf16x4 b3 = pack4(d3[0], d3[1], d3[2], d3[3]);
 #pragma unroll
       for (int it = 0; it < 4; ++it)
-        dA[it] = relu_mask(mfma(ldA(swT + NET_OFF_W3, 16, it * 16, 0, lane), b3, zero), A.mask[2][0], it);
+        dA[it] = relu_mask(mfma(ldA(swT + NET_T_W3, NET_LD_O, it * 16, 0, lane), b3, zero), A.mask[2][0], it);
     }
-    hidden_grad(trw, dA, A.h[1], g2, lane);
+    __syncthreads();
 #pragma unroll
-    for (int ot = 0; ot < 4; ++ot) bs2[ot] += dA[ot];
-    hidden_input_grad(swT + NET_OFF_W2, dA, A.mask[1][0], dB, lane);
-    hidden_grad(trw, dB, A.h[0], g1, lane);
+    for (int j = 0; j < 4; ++j) g3 = mfma(get(j, 0), get(j, 64 + 16 * wv), g3);
+    __syncthreads();
+    // layer 2: dZ2 = dA, input H1
 #pragma unroll
-    for (int ot = 0; ot < 4; ++ot) bs1[ot] += dB[ot];
-    hidden_input_grad(swT + NET_OFF_W1, dB, A.mask[0][0], dA, lane);
+    for (int ot = 0; ot < 4; ++ot) {
+      putf(ot * 16, dA[ot]);
+      put(64 + ot * 16, A.h[1][ot][0]);
+      bs2[ot] += dA[ot];
+    }
+    hidden_input_grad(swT + NET_T_W2, dA, A.mask[1][0], dB, lane);
+    __syncthreads();
 #pragma unroll
-    for (int ot = 0; ot < 4; ++ot) bs0[ot] += dA[ot];
-    // first layer (inputs 0..23; 24..31 are zero padding)
+    for (int j = 0; j < 4; ++j) {
+      const bf16x4 ga = get(j, 16 * wv);
+#pragma unroll
+      for (int it = 0; it < 4; ++it) g2[it] = mfma(ga, get(j, 64 + it * 16), g2[it]);
+    }
+    __syncthreads();
+    // layer 1: dZ1 = dB, input H0
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) {
+      putf(ot * 16, dB[ot]);
+      put(64 + ot * 16, A.h[0][ot][0]);
+      bs1[ot] += dB[ot];
+    }
+    hidden_input_grad(swT + NET_T_W1, dB, A.mask[0][0], dA, lane);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bf16x4 ga = get(j, 16 * wv);
+#pragma unroll
+      for (int it = 0; it < 4; ++it) g1[it] = mfma(ga, get(j, 64 + it * 16), g1[it]);
+    }
+    __syncthreads();
+    // first layer (inputs 0..23; 24..31 are zero padding): dZ0 = dA, input X
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) {
+      putf(ot * 16, dA[ot]);
+      bs0[ot] += dA[ot];
+    }
+    put(64, A.x[0][0]);
+    put(80, A.x[1][0]);
     {
-      bf16x4 aT[4];
-#pragma unroll
-      for (int ot = 0; ot < 4; ++ot) aT[ot] = transpose_f(trw + ot * 16 * TR_LD, dA[ot], lane);
-      const bf16x4 xT0 = transpose_bf(trw + 4 * 16 * TR_LD, A.x[0][0], lane);
-      const bf16x4 xT1 = transpose_bf(trw + 5 * 16 * TR_LD, A.x[1][0], lane);
-#pragma unroll
-      for (int ot = 0; ot < 4; ++ot) {
-        g0[ot][0] = mfma(aT[ot], xT0, g0[ot][0]);
-        g0[ot][1] = mfma(aT[ot], xT1, g0[ot][1]);
-      }
       // stencil gradient dX = W0^T dA (every lane takes part in the products;
       // the stores are masked)
       const s16x8 b0 = pack8(dA[0], dA[1]), b1 = pack8(dA[2], dA[3]);
       f32x4 dx[2];
 #pragma unroll
       for (int it = 0; it < 2; ++it) {
-        dx[it] = mfma32(ldA32(swT + NET_OFF_W0, 64, it * 16, 0, lane), b0, zero);
-        dx[it] = mfma32(ldA32(swT + NET_OFF_W0, 64, it * 16, 1, lane), b1, dx[it]);
+        dx[it] = mfma32(ldA32(swT + NET_T_W0, NET_LD_H, it * 16, 0, lane), b0, zero);
+        dx[it] = mfma32(ldA32(swT + NET_T_W0, NET_LD_H, it * 16, 1, lane), b1, dx[it]);
       }
       if (fok) {
         float* out = dX + ((long long)b * nface + f) * 24;
@@ -332,55 +369,61 @@ __global__ void __launch_bounds__(256) net_backward_kernel(GridArgs a, NetArgs n
         }
       }
     }
-  }
-  // the waves' sums into the block's, in wave order
-  for (int w2 = 0; w2 < 4; ++w2) {
-    if (wv == w2) {
+    __syncthreads();
 #pragma unroll
-      for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int o = ot * 16 + 4 * q + i;
-#pragma unroll
-          for (int it = 0; it < 4; ++it) {
-            const int in = it * 16 + fl;
-            gsum[NET_G_W1 + o * 64 + in] += g1[ot][it][i];
-            gsum[NET_G_W2 + o * 64 + in] += g2[ot][it][i];
-          }
-#pragma unroll
-          for (int it = 0; it < 2; ++it) {
-            const int in = it * 16 + fl;
-            if (in < 24) gsum[NET_G_W0 + o * 24 + in] += g0[ot][it][i];
-          }
-        }
-      if (q == 0)
-#pragma unroll
-        for (int it = 0; it < 4; ++it)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) gsum[NET_G_W3 + i * 64 + it * 16 + fl] += g3[it][i];
-      // bias sums: the 16 faces of a row group, then lanes fl == 0 add
-#pragma unroll
-      for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int o = ot * 16 + 4 * q + i;
-          const float s0 = face_sum16(bs0[ot][i]), s1 = face_sum16(bs1[ot][i]), s2 = face_sum16(bs2[ot][i]);
-          if (fl == 0) {
-            gsum[NET_G_B0 + o] += s0;
-            gsum[NET_G_B1 + o] += s1;
-            gsum[NET_G_B2 + o] += s2;
-          }
-        }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float s3 = face_sum16(bs3[i]);
-        if (q == 0 && fl == 0) gsum[NET_G_B3 + i] += s3;
-      }
+    for (int j = 0; j < 4; ++j) {
+      const bf16x4 ga = get(j, 16 * wv);
+      g0[0] = mfma(ga, get(j, 64), g0[0]);
+      g0[1] = mfma(ga, get(j, 80), g0[1]);
     }
     __syncthreads();
   }
+  // this wave's weight-gradient quarter (lane (in = it * 16 + fl, q) holds
+  // output rows 16 wv + 4q .. + 3)
   float* pb = part + (long long)blockIdx.x * NET_NP;
-  for (int k = threadIdx.x; k < NET_NP; k += blockDim.x) pb[k] = gsum[k];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int o = 16 * wv + 4 * q + i;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int in = it * 16 + fl;
+      pb[NET_G_W1 + o * 64 + in] = g1[it][i];
+      pb[NET_G_W2 + o * 64 + in] = g2[it][i];
+    }
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int in = it * 16 + fl;
+      if (in < 24) pb[NET_G_W0 + o * 24 + in] = g0[it][i];
+    }
+  }
+  if (q == 0)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pb[NET_G_W3 + i * 64 + 16 * wv + fl] = g3[i];
+  // bias sums: the 16 faces of a row group, then the waves in wave order
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int o = ot * 16 + 4 * q + i;
+      const float s0 = face_sum16(bs0[ot][i]), s1 = face_sum16(bs1[ot][i]), s2 = face_sum16(bs2[ot][i]);
+      if (fl == 0) {
+        bred[wv][o] = s0;
+        bred[wv][64 + o] = s1;
+        bred[wv][128 + o] = s2;
+      }
+    }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float s3 = face_sum16(bs3[i]);
+    if (q == 0 && fl == 0) bred[wv][192 + i] = s3;
+  }
+  __syncthreads();
+  if (threadIdx.x < 196) {
+    const int k = threadIdx.x;
+    const float s = ((bred[0][k] + bred[1][k]) + bred[2][k]) + bred[3][k];
+    const int dst = k < 64 ? NET_G_B0 + k : (k < 128 ? NET_G_B1 + k - 64 : (k < 192 ? NET_G_B2 + k - 128 : NET_G_B3 + k - 192));
+    pb[dst] = s;
+  }
 }
 
 // grad[k] += sum over the nblk block partials of part, in a fixed order:

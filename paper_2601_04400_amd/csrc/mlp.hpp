@@ -15,11 +15,21 @@ constexpr int NET_G_W0 = 0, NET_G_B0 = 1536, NET_G_W1 = 1600, NET_G_B1 = 5696, N
 // W3[16][64] (outputs padded); FP32 biases b0[64], b1[64], b2[64], b3[16].
 constexpr int NET_OFF_W0 = 0, NET_OFF_W1 = 2048, NET_OFF_W2 = 6144, NET_OFF_W3 = 10240, NET_NW = 11264;
 constexpr int NET_OFF_B0 = 0, NET_OFF_B1 = 64, NET_OFF_B2 = 128, NET_OFF_B3 = 192, NET_NB = 208;
+// The LDS copies pad each row (bf16 elements: 36 for W0's 32 inputs, 68 for
+// 64, 20 for 16) so that the 16 rows of an operand read, each an 8-byte
+// slice at the same column, fall on distinct LDS bank pairs (a row stride of
+// 32 or 64 elements puts them all on one).
+constexpr int NET_LD_W0 = 36, NET_LD_H = 68, NET_LD_O = 20;
+constexpr int NET_L_W0 = 0, NET_L_W1 = 64 * NET_LD_W0, NET_L_W2 = NET_L_W1 + 64 * NET_LD_H,
+              NET_L_W3 = NET_L_W2 + 64 * NET_LD_H, NET_LNW = NET_L_W3 + 16 * NET_LD_H;
+// transposed copy for the reverse pass: W0^T [32][64], W1^T and W2^T [64][64], W3^T [64][16]
+constexpr int NET_T_W0 = 0, NET_T_W1 = 32 * NET_LD_H, NET_T_W2 = NET_T_W1 + 64 * NET_LD_H,
+              NET_T_W3 = NET_T_W2 + 64 * NET_LD_H, NET_TNW = NET_T_W3 + 64 * NET_LD_O;
 
 
-// workgroups (and parameter partials) of the reverse pass: one per compute
-// unit (its registers and LDS allow one workgroup per unit)
-constexpr int NET_BWD_BLOCKS = 256;
+// workgroups (and parameter partials) of the reverse pass: two per compute
+// unit (its registers and LDS allow two workgroups per unit)
+constexpr int NET_BWD_BLOCKS = 512;
 
 long long net_face_count(const GridArgs& a);
 unsigned int net_backward_blocks(const GridArgs& a);

@@ -87,8 +87,17 @@ __device__ __forceinline__ void net_inputs(const NetArgs& n, int lane, Prim6 pri
   }
 }
 
+// Weights into LDS with the padded row strides (NET_LNW elements; the
+// padding columns are never read), biases as they are.
 __device__ __forceinline__ void load_net_lds(const NetArgs& n, unsigned short* sw, float* sb) {
-  for (int k = threadIdx.x; k < NET_NW; k += blockDim.x) sw[k] = n.w[k];
+  for (int k = threadIdx.x; k < NET_NW; k += blockDim.x) {
+    int d;
+    if (k < NET_OFF_W1) d = NET_L_W0 + (k >> 5) * NET_LD_W0 + (k & 31);
+    else if (k < NET_OFF_W2) d = NET_L_W1 + ((k - NET_OFF_W1) >> 6) * NET_LD_H + (k & 63);
+    else if (k < NET_OFF_W3) d = NET_L_W2 + ((k - NET_OFF_W2) >> 6) * NET_LD_H + (k & 63);
+    else d = NET_L_W3 + ((k - NET_OFF_W3) >> 6) * NET_LD_H + (k & 63);
+    sw[d] = n.w[k];
+  }
   for (int k = threadIdx.x; k < NET_NB; k += blockDim.x) sb[k] = n.bias[k];
 }
 
@@ -118,7 +127,7 @@ __device__ __forceinline__ void net_forward_batch(const unsigned short* sw, cons
       // the accumulator starts at the bias of its four rows
       const float* b0 = sb + NET_OFF_B0 + nt * 16 + 4 * q;
       f32x4 acc = {b0[0], b0[1], b0[2], b0[3]};
-      acc = mfma32(ldA32(sw + NET_OFF_W0, 32, nt * 16, 0, lane), cat8(A.x[0][ft], A.x[1][ft]), acc);
+      acc = mfma32(ldA32(sw + NET_L_W0, NET_LD_W0, nt * 16, 0, lane), cat8(A.x[0][ft], A.x[1][ft]), acc);
       float hv[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -131,7 +140,7 @@ __device__ __forceinline__ void net_forward_batch(const unsigned short* sw, cons
   // layers 2 and 3: 64 x 64
 #pragma unroll
   for (int l = 1; l < 3; ++l) {
-    const unsigned short* W = sw + (l == 1 ? NET_OFF_W1 : NET_OFF_W2);
+    const unsigned short* W = sw + (l == 1 ? NET_L_W1 : NET_L_W2);
     const float* B = sb + (l == 1 ? NET_OFF_B1 : NET_OFF_B2);
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft) A.mask[l][ft] = 0u;
@@ -143,7 +152,7 @@ __device__ __forceinline__ void net_forward_batch(const unsigned short* sw, cons
         f32x4 acc = {bl[0], bl[1], bl[2], bl[3]};
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
-          acc = mfma32(ldA32(W, 64, nt * 16, kb, lane), cat8(A.h[l - 1][2 * kb][ft], A.h[l - 1][2 * kb + 1][ft]), acc);
+          acc = mfma32(ldA32(W, NET_LD_H, nt * 16, kb, lane), cat8(A.h[l - 1][2 * kb][ft], A.h[l - 1][2 * kb + 1][ft]), acc);
         float hv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -161,7 +170,7 @@ __device__ __forceinline__ void net_forward_batch(const unsigned short* sw, cons
     f32x4 acc = {b3[0], b3[1], b3[2], b3[3]};
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb)
-      acc = mfma32(ldA32(sw + NET_OFF_W3, 64, 0, kb, lane), cat8(A.h[2][2 * kb][ft], A.h[2][2 * kb + 1][ft]), acc);
+      acc = mfma32(ldA32(sw + NET_L_W3, NET_LD_H, 0, kb, lane), cat8(A.h[2][2 * kb][ft], A.h[2][2 * kb + 1][ft]), acc);
     z[ft] = acc;
   }
 }

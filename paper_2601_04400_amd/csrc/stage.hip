@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
   __shared__ unsigned int blk_fallback, blk_fault;
   static_assert(NET == NET_NONE || (NDIM == 2 && !VISC), "learned correction: 2D inviscid tiles");
   constexpr bool MLP = NET == NET_MLP;
-  __shared__ __attribute__((aligned(16))) unsigned short net_w[MLP ? NET_NW : 1];
+  __shared__ __attribute__((aligned(16))) unsigned short net_w[MLP ? NET_LNW : 1];
   __shared__ float net_b[MLP ? NET_NB : 1];
   // normalised network inputs of every halo cell, bfloat16, in the x-face
   // frame (rho, u, v, p) and the y-face frame (rho, v, u, p): each cell feeds

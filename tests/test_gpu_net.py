@@ -167,20 +167,23 @@ def test_training_reduces_loss_and_beats_plain_solver():
 def test_sod_learned_flux_trains():
     """The 1D learned flux of section 3, reduced: Sod's tube with 200 cells
     against 400 restricted (as four identical rows), 300 coarse steps to
-    t = 0.25, trained on the first 240 (t <= 0.2) with m = 32 unrolled steps.
+    t = 0.25, trained on the first 240 (t <= 0.2) with m = 64 unrolled steps.
     The training loss falls, the rows stay identical bit for bit with the
-    correction on, and over the training horizon the corrected solver run
-    from t = 0 is closer to the reference than the plain one."""
+    correction on, and the corrected solver run from t = 0 is closer to the
+    reference than the plain one over the training horizon and beyond it.
+    (With m = 32 the outcome depends on the initial weights and on the
+    rounding of the gradient sums; m = 64 gave 0.19-0.34 of the plain error
+    at every checkpoint for three initial seeds.)"""
     import paper_2601_04400_amd.learn as L
     data = L.Dataset(None, nc=200, factor=2, nsnap=300, case="sod", rows=4, t_end=0.25)
     net = L.FluxNet(L.init_theta(0, zero_output=True))
-    before = L.dataset_loss(net, data, m=32, last=240)
-    L.train(net, data, iters=1000, m=32, lr=1e-3, last=240)
-    after = L.dataset_loss(net, data, m=32, last=240)
+    before = L.dataset_loss(net, data, m=64, last=240)
+    L.train(net, data, iters=1000, m=64, lr=1e-3, last=240)
+    after = L.dataset_loss(net, data, m=64, last=240)
     ev = L.evaluate_sod(net, data, [120, 240, 300])
     print("sod training loss", before, after, ev, flush=True)
     assert after < before
-    for s in (120, 240):
+    for s in (120, 240, 300):
         assert ev["learned"]["errors"][s]["mse"] < ev["plain"]["errors"][s]["mse"]
     g = data.grid(flux_net=True)
     g.set_flux_net(net)
