@@ -12,12 +12,12 @@
 // HLLC flux.
 //
 // Each wave evaluates 64 faces as four 16-face tiles.  A layer is computed as
-// D = W . H^T with v_mfma_f32_16x16x16_bf16: the rows of D are the layer's
-// neurons and its columns the faces, which is exactly the B-operand layout
-// of the next layer, so activations stay in registers from layer to layer.
-// The reverse pass chains D = W^T . dA the same way; weight gradients are
-// contractions over faces (K = faces) whose operands are transposed through a
-// small per-wave LDS tile.
+// D = W . H^T on the matrix cores: the rows of D are the layer's neurons and
+// its columns the faces, which is exactly the B-operand layout of the next
+// layer, so activations stay in registers from layer to layer.  The reverse
+// pass chains D = W^T . dA the same way; weight gradients are contractions
+// over faces (K = faces) whose operands the four waves of a workgroup
+// exchange through LDS.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -81,28 +81,10 @@ __global__ void __launch_bounds__(256) net_forward_kernel(GridArgs a, NetArgs n,
 
 namespace {
 
-// Row stride (bf16 elements) of the per-wave transpose tiles: a multiple of 4
-// (8-byte operand reads) that puts rows 4q apart in distinct LDS banks.
+// Row stride (bf16 elements) of the reverse pass's exchange tiles: a
+// multiple of 4 (8-byte operand reads) that puts the 16 rows of a read on
+// distinct LDS bank pairs.
 constexpr int TR_LD = 20;
-
-// 16 x 16 tile in D layout (lane (column c = lane & 15, q = lane >> 4) holds
-// rows 4q..4q+3 of column c) -> MFMA operand layout (lane (row r, q) holds
-// columns 4q..4q+3 of row r of the same tile, i.e. the tile transposed),
-// through a per-wave LDS tile.  Within one wave the LDS operations run in
-// program order, so only the compiler needs a barrier.
-__device__ __forceinline__ bf16x4 transpose_bf(unsigned short* t, bf16x4 v, int lane) {
-  const int q = lane >> 4, c = lane & 15;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) t[(4 * q + i) * TR_LD + c] = (unsigned short)v[i];
-  __builtin_amdgcn_wave_barrier();
-  const bf16x4 r = *reinterpret_cast<const bf16x4*>(t + c * TR_LD + 4 * q);
-  __builtin_amdgcn_wave_barrier();
-  return r;
-}
-
-__device__ __forceinline__ bf16x4 transpose_f(unsigned short* t, f32x4 v, int lane) {
-  return transpose_bf(t, pack4(v[0], v[1], v[2], v[3]), lane);
-}
 
 __device__ __forceinline__ s16x8 pack8(f32x4 lo, f32x4 hi) {
   return cat8(pack4(lo[0], lo[1], lo[2], lo[3]), pack4(hi[0], hi[1], hi[2], hi[3]));
@@ -122,21 +104,6 @@ __device__ __forceinline__ float face_sum16(float v) {
 #pragma unroll
   for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 16);
   return v;
-}
-
-// Weight gradient of a hidden layer (64 outputs x 64 inputs) for one
-// 16-face tile: dW += dA . H^T, a contraction over the faces.
-__device__ __forceinline__ void hidden_grad(unsigned short* tr, const f32x4 (&dA)[4], const bf16x4 (&h)[4][1],
-                                            f32x4 (&g)[4][4], int lane) {
-  bf16x4 aT[4], hT[4];
-#pragma unroll
-  for (int ot = 0; ot < 4; ++ot) aT[ot] = transpose_f(tr + ot * 16 * TR_LD, dA[ot], lane);
-#pragma unroll
-  for (int it = 0; it < 4; ++it) hT[it] = transpose_bf(tr + (4 + it) * 16 * TR_LD, h[it][0], lane);
-#pragma unroll
-  for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-    for (int it = 0; it < 4; ++it) g[ot][it] = mfma(aT[ot], hT[it], g[ot][it]);
 }
 
 // dH = W^T . dA for a 64 x 64 layer (W^T rows in LDS), masked by the ReLU
