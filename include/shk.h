@@ -77,7 +77,8 @@ typedef enum {
 
 typedef struct {
   int ndim;            /* 1 or 2; ndim 1 requires ny == 1                     */
-  int nx, ny;          /* interior cells                                      */
+  int nx, ny;          /* interior cells; >= 3 along each axis of the grid    */
+                       /* (boundary ghost layers are 3 interior cells deep)   */
   int nbatch;          /* independent grids sharing geometry and parameters   */
   double x0, x1, y0, y1; /* domain; cell centres at x0 + (i+1/2) dx           */
   int prec;            /* shk_precision                                       */

@@ -67,6 +67,8 @@ bool desc_ok(const shk_grid_desc* d, std::string* why) {
   if (d->ndim != 1 && d->ndim != 2) return bad("ndim must be 1 or 2");
   if (d->nx < 1 || d->ny < 1 || d->nbatch < 1) return bad("nx, ny, nbatch must be >= 1");
   if (d->ndim == 1 && d->ny != 1) return bad("ndim 1 requires ny == 1");
+  if (d->nx < 3 || (d->ndim == 2 && d->ny < 3))
+    return bad("nx (and ny in 2D) must be >= 3: the boundary ghost layers are three interior cells deep");
   if (d->nx > (1 << 26) || d->ny > (1 << 26)) return bad("grid too large");
   if ((long long)d->nx * d->ny * d->nbatch * 4 > (1LL << 40)) return bad("grid too large");
   if (d->prec < 0 || d->prec > 2) return bad("prec must be SHK_F64, SHK_F32 or SHK_MIXED");

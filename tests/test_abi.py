@@ -54,7 +54,8 @@ def test_workspace_bytes_validates_descriptor(L):
     assert good >= 2 * 4 * 64 * 32 * 8
     assert L.shk_workspace_bytes(ctypes.byref(desc(prec=1))) < good
     assert L.shk_workspace_bytes(ctypes.byref(desc(ibm=1))) > good
-    for bad in (dict(ndim=3), dict(nx=0), dict(gamma=1.0), dict(ndim=1, ny=4), dict(prec=7),
+    for bad in (dict(ndim=3), dict(nx=0), dict(nx=2), dict(ny=2), dict(ndim=1, ny=1, nx=2), dict(gamma=1.0),
+                dict(ndim=1, ny=4), dict(prec=7),
                 dict(bc=(3, 0, 0, 0)), dict(viscous=1, ndim=1, ny=1), dict(x1=-1.0), dict(cfl=0.0)):
         assert L.shk_workspace_bytes(ctypes.byref(desc(**bad))) == 0, bad
     assert L.shk_workspace_bytes(None) == 0
