@@ -89,7 +89,9 @@ __device__ __forceinline__ long long pixel_face(int img, int R, int C, int nx, i
 }
 
 // Input gradient of one 3x3 layer (the forward kernel with mirrored,
-// channel-swapped weights) as an implicit GEMM over 16 x 16 pixel tiles;
+// channel-swapped weights; used for the 4-channel output layer, the wider
+// layers take cnn_conv32_kernel below) as an implicit GEMM over 16 x 16
+// pixel tiles;
 // MT output-channel tiles of 16, KB K-blocks of 16 (k = tap * CIN +
 // channel, taps >= 9 are zero padding).  Each lane keeps its weight
 // fragments in registers for the whole launch; a wave computes its four
@@ -146,6 +148,118 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(CnnGeom g, const unsigned
         for (int mt = 0; mt < MT; ++mt) acc[rr][mt] = mfma(Aw[mt][kb], B, acc[rr][mt]);
       }
     }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      // lane (pixel fl of the row, q) holds output channels 16 mt + 4q .. + 3
+      const int R = L.r0 + wv * 4 + rr, C = L.c0 + fl;
+      const bool valid = R < L.H && C < L.W;
+      const long long pix = L.pbase + (long long)R * L.W + C;
+      if (EPI == EPI_BWD_HIDDEN) {
+        if (valid)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const int c0 = mt * 16 + 4 * q;
+            f32x4 d = acc[rr][mt];
+            const bf16x4 h = *reinterpret_cast<const bf16x4*>(o.mask_src + pix * (MT * 16) + c0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) d[i] = h[i] > 0 ? d[i] : 0.f;  // bf16 bits: positive iff > 0 as int16
+            *reinterpret_cast<bf16x4*>(o.out_bf + pix * (MT * 16) + c0) = pack4(d[0], d[1], d[2], d[3]);
+            bs[mt] = bs[mt] + d;
+          }
+      } else {  // EPI_BWD_IN
+        if (valid && q == 0) *reinterpret_cast<f32x4*>(o.out_f + pix * 4) = acc[rr][0];
+      }
+    }
+  }
+  if (EPI == EPI_BWD_HIDDEN) {
+    // this workgroup's bias sums: the 16 pixels of a row group, then the
+    // four waves in order
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float s = bs[mt][i];
+        for (int m = 8; m >= 1; m >>= 1) s += __shfl_xor(s, m, 16);
+        if (fl == 0) red[wv][mt * 16 + 4 * q + i] = s;
+      }
+    __syncthreads();
+    if ((int)threadIdx.x < o.cout)
+      o.part[(long long)blockIdx.x * CNN_NP + o.part_off + threadIdx.x] =
+          ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+  }
+}
+
+// The same input-gradient layer for CIN = 16 or 32 input channels on
+// v_mfma_f32_16x16x32_bf16: a lane's eight k-slots are eight consecutive
+// channels of one tap (one tap of 32 channels per block, or two taps of 16
+// with the ninth tap as one K = 16 block), so that every operand is one
+// 16-byte read of the weights or of the channels-last tile, whose pixel
+// stride (CIN + 8 elements) puts the 16 pixels of a read on distinct LDS
+// banks.
+template <int CIN, int MT, int EPI>
+__global__ void __launch_bounds__(256) cnn_conv32_kernel(CnnGeom g, const unsigned short* __restrict__ in,
+                                                         const unsigned short* __restrict__ wm, ConvOut o) {
+  static_assert(CIN == 16 || CIN == 32, "16 or 32 input channels");
+  constexpr int PS = CIN + 8;                // pixel stride of the tile (elements)
+  constexpr int K = 9 * CIN;                 // weight row length
+  constexpr int KB = CIN == 32 ? 9 : 4;      // K = 32 blocks
+  __shared__ __attribute__((aligned(16))) unsigned short tile[324 * PS];
+  __shared__ float red[4][MT * 16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane >> 4, fl = lane & 15;
+  auto ld16 = [](const unsigned short* p) { return *reinterpret_cast<const s16x8*>(p); };
+  s16x8 Aw[MT][KB];
+  bf16x4 At[MT];  // tap 8 of the 16-channel layer
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) Aw[mt][kb] = ld16(wm + (mt * 16 + fl) * K + 32 * kb + 8 * q);
+    At[mt] = CIN == 16 ? ldA(wm, K, mt * 16, 128, lane) : bf16x4{0, 0, 0, 0};
+  }
+  // this lane's tap offset (pixels) and channel offset in each K = 32 block
+  int toff[KB], coff[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    const int tap = CIN == 32 ? kb : 2 * kb + (q >> 1), dr = tap / 3, dc = tap - 3 * dr;
+    toff[kb] = dr * 18 + dc;
+    coff[kb] = CIN == 32 ? 8 * q : 8 * (q & 1);
+  }
+  f32x4 bs[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) bs[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const long long ntile = (long long)g.tiles * g.nbatch;
+  for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const TileLoc L = tile_loc(g, t);
+    __syncthreads();  // the previous tile's readers are done
+    for (int k = threadIdx.x; k < 324 * (CIN / 4); k += blockDim.x) {
+      const int pq = k / (CIN / 4), cq = k - pq * (CIN / 4);
+      const int tr = pq / 18, tc = pq - tr * 18;
+      const int R = pix_src(L.r0 + tr - 1, L.H, L.wr), C = pix_src(L.c0 + tc - 1, L.W, L.wc);
+      bf16x4 v = {0, 0, 0, 0};
+      if (R >= 0 && C >= 0) v = *reinterpret_cast<const bf16x4*>(in + (L.pbase + (long long)R * L.W + C) * CIN + 4 * cq);
+      *reinterpret_cast<bf16x4*>(tile + pq * PS + 4 * cq) = v;
+    }
+    __syncthreads();
+    // rows beyond the image hold zeros or wrapped pixels: computed, not stored
+    f32x4 acc[4][MT];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[rr][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const s16x8 B = ld16(tile + ((wv * 4 + rr) * 18 + fl + toff[kb]) * PS + coff[kb]);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[rr][mt] = mfma32(Aw[mt][kb], B, acc[rr][mt]);
+      }
+    if (CIN == 16)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const bf16x4 B = *reinterpret_cast<const bf16x4*>(tile + ((wv * 4 + rr + 2) * 18 + fl + 2) * PS + 4 * q);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[rr][mt] = mfma(At[mt], B, acc[rr][mt]);
+      }
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
       // lane (pixel fl of the row, q) holds output channels 16 mt + 4q .. + 3
@@ -882,14 +996,14 @@ hipError_t launch_cnn_backward(const GridArgs& a, const CnnArgs& n, const double
   o.mask_src = b.h1;
   o.part_off = CNN_G_B1;
   o.cout = 16;
-  hipLaunchKernelGGL((cnn_conv_kernel<32, 1, 18, EPI_BWD_HIDDEN>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.da2,
+  hipLaunchKernelGGL((cnn_conv32_kernel<32, 1, EPI_BWD_HIDDEN>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.da2,
                      n.w + CNN_B2, o);
   hipLaunchKernelGGL((cnn_wgrad_kernel<16, 32, 2, 9>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.da2, b.h1, b.part,
                      CNN_G_W2);
   // layer 1: gradient of the normalised inputs, and weights
   ConvOut o1{};
   o1.out_f = b.dx;
-  hipLaunchKernelGGL((cnn_conv_kernel<16, 1, 9, EPI_BWD_IN>), dim3(tile_blocks(g)), dim3(256), 0, st, g, b.da1,
+  hipLaunchKernelGGL((cnn_conv32_kernel<16, 1, EPI_BWD_IN>), dim3(tile_blocks(g)), dim3(256), 0, st, g, b.da1,
                      n.w + CNN_B1, o1);
   hipLaunchKernelGGL((cnn_wgrad_kernel<4, 16, 1, 3>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.da1, b.x, b.part,
                      CNN_G_W1);
