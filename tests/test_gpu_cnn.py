@@ -39,7 +39,10 @@ def bf16_round(a):
     return f.astype(np.float64)
 
 
-CASES = [((37, 21), (3, 3, 3, 3)), ((37, 21), (0, 0, 0, 0)), ((34, 18), (2, 0, 1, 1)), ((40, 17), (3, 3, 1, 1))]
+# ragged multi-tile grids, and periodic images smaller than the fused forward's
+# 22 x 22 halo region (its windows then wrap around more than once)
+CASES = [((37, 21), (3, 3, 3, 3)), ((37, 21), (0, 0, 0, 0)), ((34, 18), (2, 0, 1, 1)), ((40, 17), (3, 3, 1, 1)),
+         ((5, 4), (3, 3, 3, 3)), ((7, 3), (3, 3, 0, 0))]
 
 
 def setup(orc, shape, bc, seed=6):
@@ -118,7 +121,7 @@ def face_bar(lam, dx, dy, bc):
     return np.array(out)
 
 
-@pytest.mark.parametrize("shape,bc", [((37, 21), (3, 3, 3, 3)), ((34, 18), (0, 0, 0, 0))])
+@pytest.mark.parametrize("shape,bc", [((37, 21), (3, 3, 3, 3)), ((34, 18), (0, 0, 0, 0)), ((5, 4), (3, 3, 3, 3))])
 def test_cnn_parameter_gradient_vs_oracle(orc, shape, bc):
     """Parameter gradient of the network alone (per layer block) for face
     adjoints formed from a random right-hand-side adjoint, against the
