@@ -46,7 +46,7 @@ struct ConvOut {
   unsigned short* out_bf;            // bf16 image of COUT channels (EPI_BWD_HIDDEN)
   float* out_f;                      // FP32 image of 4 channels (EPI_BWD_IN)
   const unsigned short* mask_src;    // forward activation of the same pixels (EPI_BWD_HIDDEN)
-  float* part;                       // [CNN_BLOCKS][CNN_NP] (EPI_BWD_HIDDEN: bias sums)
+  float* part;                       // [workgroup][CNN_BROW] (EPI_BWD_HIDDEN: bias sums)
   int part_off;
   int cout;                          // real output channels
 };
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(CnnGeom g, const unsigned
       }
     __syncthreads();
     if ((int)threadIdx.x < o.cout)
-      o.part[(long long)blockIdx.x * CNN_NP + o.part_off + threadIdx.x] =
+      o.part[(long long)blockIdx.x * CNN_BROW + o.part_off + threadIdx.x] =
           ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
   }
 }
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(256) cnn_conv32_kernel(CnnGeom g, const unsign
       }
     __syncthreads();
     if ((int)threadIdx.x < o.cout)
-      o.part[(long long)blockIdx.x * CNN_NP + o.part_off + threadIdx.x] =
+      o.part[(long long)blockIdx.x * CNN_BROW + o.part_off + threadIdx.x] =
           ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
   }
 }
@@ -840,20 +840,42 @@ __global__ void __launch_bounds__(256) cnn_unpack_kernel(const unsigned short* _
 }
 
 // grad[k] += the CNN_BLOCKS partials of parameter k in block order (16 waves
-// each take every 16th partial, then the wave sums in wave order).
+// each take every 16th partial, then the wave sums in wave order); the
+// hidden-layer biases b1, b2 come from the input-gradient layers' own
+// partials (cnn_bias_reduce_kernel).
 __global__ void __launch_bounds__(1024) cnn_grad_reduce_kernel(const float* __restrict__ part, float* __restrict__ grad) {
   __shared__ double red[16][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int k = blockIdx.x * 64 + lane;
+  const bool mine = k < CNN_NP && !(k >= CNN_G_B1 && k < CNN_G_B1 + 16) && !(k >= CNN_G_B2 && k < CNN_G_B2 + 32);
   double s = 0.0;
-  if (k < CNN_NP)
+  if (mine)
     for (int j = wv; j < CNN_BLOCKS; j += 16) s += part[(long long)j * CNN_NP + k];
   red[wv][lane] = s;
   __syncthreads();
-  if (wv == 0 && k < CNN_NP) {
+  if (wv == 0 && mine) {
     double t = 0.0;
     for (int w = 0; w < 16; ++w) t += red[w][lane];
     grad[k] += float(t);
+  }
+}
+
+// grad[b1, b2] += the nblk rows of bias sums: workgroup i takes bias i,
+// thread t the rows t, t + 256, ..., then a fixed butterfly over each wave
+// and the four waves in order.
+__global__ void __launch_bounds__(256) cnn_bias_reduce_kernel(const float* __restrict__ bpart, int nblk,
+                                                              float* __restrict__ grad) {
+  __shared__ double red[4];
+  const int i = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double s = 0.0;
+#pragma unroll 4
+  for (int j = threadIdx.x; j < nblk; j += 256) s += bpart[(long long)j * CNN_BROW + i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) red[wv] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = ((red[0] + red[1]) + red[2]) + red[3];
+    grad[i < 16 ? CNN_G_B1 + i : CNN_G_B2 + i - 16] += float(t);
   }
 }
 
@@ -898,7 +920,7 @@ __global__ void __launch_bounds__(256) cnn_pack_kernel(const float* __restrict__
 
 unsigned int tile_blocks(const CnnGeom& g) {
   const long long n = (long long)g.tiles * g.nbatch;
-  return (unsigned int)(n < 1 ? 1 : (n > 8192 ? 8192 : n));
+  return (unsigned int)(n < 1 ? 1 : (n > CNN_BMAX ? CNN_BMAX : n));
 }
 
 }  // namespace
@@ -931,7 +953,8 @@ size_t cnn_workspace_bytes(const GridArgs& a) {
   const size_t np = (size_t)g.npix * a.nbatch;
   // bf16 images: 4 + 16 + 32 + 4 + 32 + 16 channels; FP32: tanh and input gradient
   return al256(np * 4 * 2) + al256(np * 16 * 2) + al256(np * 32 * 2) + al256(np * 4 * 2) + al256(np * 32 * 2) +
-         al256(np * 16 * 2) + al256(np * 4 * 4) + al256(np * 4 * 4) + al256((size_t)CNN_BLOCKS * CNN_NP * 4);
+         al256(np * 16 * 2) + al256(np * 4 * 4) + al256(np * 4 * 4) + al256((size_t)CNN_BLOCKS * CNN_NP * 4) +
+         al256((size_t)CNN_BMAX * CNN_BROW * 4);
 }
 
 CnnBufs cnn_bufs(const GridArgs& a, char* base) {
@@ -949,6 +972,7 @@ CnnBufs cnn_bufs(const GridArgs& a, char* base) {
   b.t = reinterpret_cast<float*>(take(np * 4 * 4));
   b.dx = reinterpret_cast<float*>(take(np * 4 * 4));
   b.part = reinterpret_cast<float*>(take((size_t)CNN_BLOCKS * CNN_NP * 4));
+  b.bpart = reinterpret_cast<float*>(take((size_t)CNN_BMAX * CNN_BROW * 4));
   return b;
 }
 
@@ -980,23 +1004,26 @@ hipError_t launch_cnn_backward(const GridArgs& a, const CnnArgs& n, const double
   const long long nface = (long long)(a.nx + 1) * a.ny + (long long)a.nx * (a.ny + 1);
   hipLaunchKernelGGL(cnn_head_kernel, dim3(CNN_BLOCKS), dim3(256), 0, st, a, g, n.out_scale, lam, clam_f, dtp, b.t,
                      b.dz, b.part);
+  // the input-gradient layers take one tile per workgroup and leave their
+  // bias sums (b2, then b1) in one bpart row per workgroup
+  const unsigned int tb = tile_blocks(g);
   ConvOut o{};
-  o.part = b.part;
+  o.part = b.bpart;
   // layer 3: input gradient (32 channels, masked by the layer-2 ReLU) and weights
   o.out_bf = b.da2;
   o.mask_src = b.h2;
-  o.part_off = CNN_G_B2;
+  o.part_off = 16;
   o.cout = 32;
-  hipLaunchKernelGGL((cnn_conv_kernel<4, 2, 3, EPI_BWD_HIDDEN>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.dz,
+  hipLaunchKernelGGL((cnn_conv_kernel<4, 2, 3, EPI_BWD_HIDDEN>), dim3(tb), dim3(256), 0, st, g, b.dz,
                      n.w + CNN_B3, o);
   hipLaunchKernelGGL((cnn_wgrad_kernel<32, 4, 1, 18>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.dz, b.h2, b.part,
                      CNN_G_W3);
   // layer 2
   o.out_bf = b.da1;
   o.mask_src = b.h1;
-  o.part_off = CNN_G_B1;
+  o.part_off = 0;
   o.cout = 16;
-  hipLaunchKernelGGL((cnn_conv32_kernel<32, 1, EPI_BWD_HIDDEN>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.da2,
+  hipLaunchKernelGGL((cnn_conv32_kernel<32, 1, EPI_BWD_HIDDEN>), dim3(tb), dim3(256), 0, st, g, b.da2,
                      n.w + CNN_B2, o);
   hipLaunchKernelGGL((cnn_wgrad_kernel<16, 32, 2, 9>), dim3(CNN_BLOCKS), dim3(256), 0, st, g, b.da2, b.h1, b.part,
                      CNN_G_W2);
@@ -1011,6 +1038,7 @@ hipError_t launch_cnn_backward(const GridArgs& a, const CnnArgs& n, const double
   e = hipGetLastError();
   if (e != hipSuccess || grad == nullptr) return e;
   hipLaunchKernelGGL(cnn_grad_reduce_kernel, dim3((CNN_NP + 63) / 64), dim3(1024), 0, st, b.part, grad);
+  hipLaunchKernelGGL(cnn_bias_reduce_kernel, dim3(CNN_BROW), dim3(256), 0, st, b.bpart, (int)tb, grad);
   return hipGetLastError();
 }
 

@@ -23,7 +23,10 @@ constexpr int CNN_G_W1 = 0, CNN_G_B1 = 576, CNN_G_W2 = 592, CNN_G_B2 = 5200, CNN
 constexpr int CNN_F1 = 0, CNN_F2 = 768, CNN_F3 = 5376, CNN_B3 = 9984, CNN_B2 = 11520, CNN_B1 = 16128, CNN_NW = 18432;
 // FP32 biases: b1 [16], b2 [32], b3 [16] (4 used)
 constexpr int CNN_BB1 = 0, CNN_BB2 = 16, CNN_BB3 = 48, CNN_NB = 64;
-constexpr int CNN_BLOCKS = 512;  // workgroups (and parameter partials) of the reverse pass
+constexpr int CNN_BLOCKS = 512;  // workgroups (and parameter partials) of the weight-gradient kernels
+// hidden-layer bias sums of the input-gradient layers: one row of CNN_BROW
+// per workgroup (b1 at 0..15, b2 at 16..47), at most CNN_BMAX workgroups
+constexpr int CNN_BROW = 48, CNN_BMAX = 8192;
 
 struct CnnArgs {
   const unsigned short* w;  // [CNN_NW] bf16
@@ -53,6 +56,7 @@ struct CnnBufs {
   float *t;                                       // tanh of the output layer [npix][4]
   float *dx;                                      // input gradient [npix][4]
   float *part;                                    // [CNN_BLOCKS][CNN_NP]
+  float *bpart;                                   // [CNN_BMAX][CNN_BROW]
 };
 CnnBufs cnn_bufs(const GridArgs& a, char* base);
 

@@ -45,7 +45,7 @@ def test_prim_to_cons_bitwise(orc):
         np.testing.assert_array_equal(Ug, Uo)
 
 
-@pytest.mark.parametrize("shape", [(37, 29), (64, 64), (70, 17), (33, 9)])
+@pytest.mark.parametrize("shape", [(37, 29), (64, 64), (70, 17), (33, 9), (3, 3), (4, 5)])
 @pytest.mark.parametrize("bc", BCS)
 def test_rhs_f64(orc, shape, bc):
     nx, ny = shape
