@@ -732,8 +732,10 @@ __global__ void __launch_bounds__(256) axpy_kernel(long long n, double alpha, co
 
 // ------------------------------------------------------------------ launchers
 // 32 x 8 tiles with 768 threads: the tile's 712 faces are reversed in one
-// round (three waves per SIMD at <= 168 registers).
-constexpr int ATX = 32, ATY = 8, ANT = 768;
+// round (three waves per SIMD at <= 168 registers).  (32 x 4 tiles with 448
+// threads, two workgroups per compute unit, were 1.6x slower: 22 % more
+// recomputed faces and no better latency.)
+constexpr int ATX = ADJ_TX, ATY = ADJ_TY, ANT = ADJ_NT;
 
 int adjoint_blocks(const GridArgs& a) { return ((a.nx + ATX - 1) / ATX) * ((a.ny + ATY - 1) / ATY); }
 

@@ -126,7 +126,7 @@ WsLayout layout(const shk_grid_desc* d) {
     L.adjC = o; o += st64;
     L.adjP = o; o += st64;
     L.adjQ = o; o += st64;
-    const size_t nblk = size_t((d->nx + 31) / 32) * ((d->ny + 7) / 8);
+    const size_t nblk = size_t((d->nx + ADJ_TX - 1) / ADJ_TX) * ((d->ny + ADJ_TY - 1) / ADJ_TY);
     L.part_stride = 5 * size_t(d->nbatch) * nblk;
     L.adjPart = o; o += al(sizeof(double) * MAX_PART_SLOTS * L.part_stride);
     if (d->ibm) {

@@ -106,6 +106,9 @@ struct PartSlots {
   int nblk[MAX_PART_SLOTS];
   long long stride;
 };
+// tile of the right-hand-side adjoint kernel (cells x, cells y, threads);
+// the workspace sizes its per-block partials with the same tiles
+constexpr int ADJ_TX = 32, ADJ_TY = 8, ADJ_NT = 768;
 int adjoint_blocks(const GridArgs& a);
 // With the immersed boundary (gW != nullptr, a.ghost_of set) the kernel also
 // runs the first half of the refill transpose for the ghost cells it owns:
