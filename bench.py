@@ -357,8 +357,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the path would shard by spatial slabs with halo exchange, see the design notes)",
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the path would shard by spatial slabs with a 3-cell halo exchange per stage)",
               file=sys.stderr)
         sys.exit(2)
 
