@@ -240,3 +240,41 @@ def test_cnn_training_reduces_loss_and_beats_plain_solver():
     ev = L.evaluate(net, list(range(1000, 1008)), nc=64, ny=32, factor=2, nsteps=12)
     print(ev, flush=True)
     assert ev["learned"]["mse"] < ev["plain"]["mse"]
+
+
+def test_graph_replays_with_cnn_equal_eager_steps(orc):
+    """Automatic-step RK3 steps with the convolutional correction captured in
+    a HIP graph (network forward and corrected stage per stage, no memory
+    fills): every replay, with eager work and synchronisations between the
+    replays, gives the eager steps' state bit for bit."""
+    from paper_2601_04400_amd import Grid
+    n, k = 48, 4
+    net, _, _ = make_cnn(orc, 5)
+    g = Grid(n, n, flux_net=2)
+    g.set_flux_cnn(net)
+    U0 = g.prim_to_cons(torch.from_numpy(inputs.riemann2d_prim(n, n)))
+    Ue = U0.clone()
+    g.set_time(0.0, 1e30)
+    for _ in range(k):
+        g.step(Ue)
+    want = to_np(Ue)
+    U = U0.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        g.set_time(0.0, 1e30)
+        g.step(U)  # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(k):
+            g.step(U)
+    for rep in range(3):
+        U.copy_(U0)
+        g.set_time(0.0, 1e30)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(to_np(U), want, err_msg=f"replay {rep}")
+        Ue.mul_(1.0)  # eager work between replays

@@ -256,3 +256,40 @@ def test_corrected_step_vs_oracle(orc):
     g.step(Ug, dt)
     got = to_np(Ug)[0]
     assert np.max(np.abs(got - want)) <= 4e-3 * effect + 1e-11 * np.max(np.abs(want))
+
+
+def test_graph_replays_with_net_equal_eager_steps(orc):
+    """Automatic-step RK3 steps with the in-tile network captured in a HIP
+    graph: every replay, with eager work and synchronisations between the
+    replays, gives the eager steps' state bit for bit."""
+    from paper_2601_04400_amd import Grid
+    n, k = 64, 4
+    net, _, _ = make_net(orc, 5)
+    g = Grid(n, n, flux_net=True)
+    g.set_flux_net(net)
+    U0 = g.prim_to_cons(torch.from_numpy(inputs.riemann2d_prim(n, n)))
+    Ue = U0.clone()
+    g.set_time(0.0, 1e30)
+    for _ in range(k):
+        g.step(Ue)
+    want = to_np(Ue)
+    U = U0.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        g.set_time(0.0, 1e30)
+        g.step(U)  # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(k):
+            g.step(U)
+    for rep in range(3):
+        U.copy_(U0)
+        g.set_time(0.0, 1e30)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(to_np(U), want, err_msg=f"replay {rep}")
+        Ue.mul_(1.0)  # eager work between replays
