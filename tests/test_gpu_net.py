@@ -293,3 +293,27 @@ def test_graph_replays_with_net_equal_eager_steps(orc):
         torch.cuda.synchronize()
         np.testing.assert_array_equal(to_np(U), want, err_msg=f"replay {rep}")
         Ue.mul_(1.0)  # eager work between replays
+
+
+def test_corrected_rhs_full_size_training_batch(orc):
+    """The learned-correction workload at full size: 64 random four-quadrant
+    problems at 128^2 (the training batch) through the stage kernel with the
+    in-tile network in one launch; members 0 and 63 against the oracle's
+    corrected right-hand side (bfloat16-emulating network), to one bfloat16
+    unit of the correction's effect plus FP64 rounding."""
+    import paper_2601_04400_amd.learn as L
+    from paper_2601_04400_amd import Grid
+    n, nb = 128, 64
+    W = L.riemann_batch(list(range(nb)), n, "cpu").numpy()
+    g = Grid(n, n, nbatch=nb, flux_net=True)
+    net, ref, _ = make_net(orc, 9)
+    g.set_flux_net(net)
+    c = orc.config(nx=n, ny=n)
+    U = np.stack([orc.prim_to_cons(c, W[b]) for b in range(nb)])
+    Lg = to_np(g.rhs(torch.from_numpy(U).cuda().reshape(g.shape)))
+    for b in (0, nb - 1):
+        want = orc.rhs(c, U[b], net=ref)[0]
+        plain = orc.rhs(c, U[b])[0]
+        effect = np.max(np.abs(want - plain))
+        assert effect > 1e-6 * np.max(np.abs(want))
+        assert np.max(np.abs(Lg[b] - want)) <= 4e-3 * effect + 1e-11 * np.max(np.abs(want)), b
