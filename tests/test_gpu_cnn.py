@@ -278,3 +278,29 @@ def test_graph_replays_with_cnn_equal_eager_steps(orc):
         torch.cuda.synchronize()
         np.testing.assert_array_equal(to_np(U), want, err_msg=f"replay {rep}")
         Ue.mul_(1.0)  # eager work between replays
+
+
+def test_cnn_forward_full_size_training_batch(orc):
+    """The convolutional workload at full size: 64 random four-quadrant
+    problems at 128 x 64 (the training batch) in one launch; the per-face
+    corrections of members 0 and 63 against the oracle network on the
+    oracle's images."""
+    import paper_2601_04400_amd.learn as L
+    from paper_2601_04400_amd import Grid
+    nx, ny, nb = 128, 64, 64
+    dom = (0.0, 1.0, 0.0, ny / nx)
+    W = L.riemann_batch(list(range(nb)), nx, "cpu", ny=ny).numpy()
+    c = orc.config(nx=nx, ny=ny, y1=dom[3])
+    g = Grid(nx, ny, nbatch=nb, domain=dom, flux_net=2)
+    net, ref, _ = make_cnn(orc, 3)
+    g.set_flux_cnn(net)
+    U = np.stack([orc.prim_to_cons(c, W[b]) for b in range(nb)])
+    dF = to_np(g.flux_cnn_eval(torch.from_numpy(U).cuda().reshape(g.shape))).astype(np.float64)
+    for b in (0, nb - 1):
+        Ox, Oy = orc.cnn_images(c, U[b], ref)
+        fx = ref.forward(Ox, wrap=(False, False))
+        fy = ref.forward(Oy, wrap=(False, False))
+        want = np.concatenate([fx.reshape(-1, 4), np.transpose(fy, (1, 0, 2)).reshape(-1, 4)])
+        scale = np.max(np.abs(want))
+        assert scale > 1e-3
+        assert np.max(np.abs(dF[b] - want)) <= 4e-3 * scale, b
