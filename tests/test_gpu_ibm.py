@@ -138,3 +138,28 @@ def test_paper_shock_cylinder_line_profile_self_converges():
     d1 = np.mean(np.abs(down(profiles[512]) - profiles[256]))
     d2 = np.mean(np.abs(down(profiles[1024]) - profiles[512]))
     assert d2 < d1, (d1, d2)
+
+
+def test_paper_shock_cylinder_full_size(orc):
+    """The section 3 Mach-5 shock-cylinder at its full 4096 x 2048 size
+    (slip wall, inflow / outflow / reflective walls): cell classes and ghost
+    count bit-exact, one right-hand side and one automatic step from the
+    initial condition against the oracle."""
+    nx, ny = 4096, 2048
+    sc = inputs.paper_shock_cylinder(nx, ny)
+    c, g = make_pair(orc, nx, ny, domain=sc["domain"], bc=sc["bc"], inflow=sc["inflow"], ibm=True)
+    ng = g.set_levelset(torch.from_numpy(sc["phi"]), wall=0)
+    cls_o, ng_o = orc.ibm_classify(c, sc["phi"])
+    np.testing.assert_array_equal(g.classes().cpu().numpy(), cls_o)
+    assert ng == ng_o > 0
+    Uo = orc.prim_to_cons(c, sc["W"])
+    Ug = g.prim_to_cons(torch.from_numpy(sc["W"]))
+    Lo, _, _ = orc.rhs(c, Uo, phi=sc["phi"], wall=0)
+    assert_fields(to_np(g.rhs(Ug.clone()))[0], Lo, 1e-13, "4096x2048 rhs")
+    dto = orc.cfl_dt(c, Uo, phi=sc["phi"])
+    U1o, _ = orc.rk3_step(c, Uo, dto, phi=sc["phi"], wall=0)
+    dts = torch.zeros(1, dtype=torch.float64, device=g.device)
+    g.set_time(0.0, 1.2)
+    g.step(Ug, dt_out=dts)
+    assert float(dts.cpu()[0]) == dto
+    assert_fields(to_np(Ug)[0], U1o, 1e-13, "4096x2048 step")
