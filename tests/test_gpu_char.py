@@ -90,3 +90,22 @@ def test_char_rejects_what_it_does_not_support():
     for kw in (dict(prec="f32"), dict(adjoint=True), dict(flux_net=True)):
         with pytest.raises(Exception):
             Grid(32, 16, weno_char=True, **kw)
+
+
+def test_char_full_size_step(orc):
+    """512^2 four-quadrant problem (the size `bench.py --weno char` times):
+    one right-hand side and one automatic step against the oracle."""
+    n = 512
+    c, g = make_pair(orc, n, n, weno_char=True)
+    W = inputs.riemann2d_prim(n, n)
+    Uo = orc.prim_to_cons(c, W)
+    Ug = g.prim_to_cons(torch.from_numpy(W))
+    Lo, _, _ = orc.rhs(c, Uo)
+    assert_fields(to_np(g.rhs(Ug.clone()))[0], Lo, 1e-12, "512^2 char rhs")
+    dto = orc.cfl_dt(c, Uo)
+    U1o, _ = orc.rk3_step(c, Uo, dto)
+    dts = torch.zeros(1, dtype=torch.float64, device=g.device)
+    g.set_time(0.0, 1.0)
+    g.step(Ug, dt_out=dts)
+    assert float(dts.cpu()[0]) == dto
+    assert_fields(to_np(Ug)[0], U1o, 1e-12, "512^2 char step")
