@@ -193,7 +193,16 @@ __global__ void __launch_bounds__(256, 2) net_backward_kernel(GridArgs a, NetArg
   const long long total = per_b * a.nbatch;
   // every wave of the workgroup runs the same rounds (a wave past the last
   // tile computes zeros), so the barriers are uniform
-  for (long long t0 = (long long)blockIdx.x * 4; t0 < total; t0 += (long long)gridDim.x * 4) {
+  // XCD-aware order: workgroups are dealt to the eight XCDs round-robin, so
+  // the k-th workgroup an XCD receives takes block slot start + k of a
+  // contiguous run; in each round an XCD then covers one contiguous run of
+  // face tiles, whose stencil cells mostly stay in its own L2
+  int blk;
+  {
+    const int n = gridDim.x, x = blockIdx.x & 7, k = blockIdx.x >> 3, qn = n >> 3, rn = n & 7;
+    blk = x * qn + (x < rn ? x : rn) + k;
+  }
+  for (long long t0 = (long long)blk * 4; t0 < total; t0 += (long long)gridDim.x * 4) {
     const long long t = t0 + wv;
     const bool tok = t < total;
     const long long tc = tok ? t : total - 1;
@@ -347,7 +356,7 @@ __global__ void __launch_bounds__(256, 2) net_backward_kernel(GridArgs a, NetArg
   }
   // this wave's weight-gradient quarter (lane (in = it * 16 + fl, q) holds
   // output rows 16 wv + 4q .. + 3)
-  float* pb = part + (long long)blockIdx.x * NET_NP;
+  float* pb = part + (long long)blk * NET_NP;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int o = 16 * wv + 4 * q + i;
