@@ -361,3 +361,40 @@ def char_basis(Wa, Wb, gamma=1.4):
     L, R = np.empty((4, 4)), np.empty((4, 4))
     lib().orc_char_basis(_d(gamma), _ptr(Wa), _ptr(Wb), _ptr(L), _ptr(R))
     return L, R
+
+
+# ------------------------------------------------------------- training
+def restrict(fine, factor):
+    """Restriction d(U) of section 2: block mean of factor x factor fine
+    cells.  fine [..., ny_f, nx_f] -> [..., ny_f/factor, nx_f/factor]."""
+    fine = np.ascontiguousarray(fine, dtype=np.float64)
+    *lead, nyf, nxf = fine.shape
+    lead = tuple(lead)
+    npl = int(np.prod(lead)) if lead else 1
+    out = np.empty(lead + (nyf // factor, nxf // factor))
+    assert lib().orc_restrict(_ptr(fine), _i(nxf), _i(nyf), _i(factor), _i(npl), _i(1), _ptr(out)) == 0
+    return out
+
+
+def mse(U, T, scale=1.0, nbatch=1, grad=True):
+    """Unrolled-loss term of section 2 per batch member: (loss [nbatch],
+    gradient scale * 2 (U - T) / N or None), N = entries per member."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    assert U.shape == T.shape and U.size % nbatch == 0
+    loss = np.zeros(nbatch)
+    G = np.zeros_like(U) if grad else None
+    lib().orc_mse.argtypes = [_p, _p, ctypes.c_longlong, _i, _d, _p, _p]
+    assert lib().orc_mse(_ptr(U), _ptr(T), U.size // nbatch, nbatch, float(scale), _ptr(loss), _ptr(G)) == 0
+    return loss, G
+
+
+def adam(theta, g, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step on copies: returns (theta, m, v) after the update."""
+    th = np.array(theta, dtype=np.float64)
+    mm = np.array(m, dtype=np.float64)
+    vv = np.array(v, dtype=np.float64)
+    gg = np.ascontiguousarray(g, dtype=np.float64)
+    assert lib().orc_adam(_ptr(th), _ptr(gg), _ptr(mm), _ptr(vv), _i(th.size), _d(lr), _d(b1), _d(b2),
+                          _d(eps), _i(step)) == 0
+    return th, mm, vv

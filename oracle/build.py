@@ -9,7 +9,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SOURCES = ["capi.cpp"]
-HEADERS = ["solver.hpp", "dual.hpp", "exact_riemann.hpp", "mlp.hpp", "cnn.hpp", "correction.hpp"]
+HEADERS = ["solver.hpp", "dual.hpp", "exact_riemann.hpp", "mlp.hpp", "cnn.hpp", "correction.hpp", "training.hpp"]
 FLAGS = ["-std=c++17", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-Wall"]
 
 

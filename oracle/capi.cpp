@@ -11,6 +11,7 @@
 #include "exact_riemann.hpp"
 #include "mlp.hpp"
 #include "solver.hpp"
+#include "training.hpp"
 
 using namespace orc;
 
@@ -452,6 +453,28 @@ void orc_cnn_backward(const void* net, int H, int W, int wrap_r, int wrap_c, con
   const bool wrap[2] = {wrap_r != 0, wrap_c != 0};
   cnn_backward(*as_cnn(net), xv, H, W, wrap, dv, g, d);
   if (dx) std::copy(d.begin(), d.end(), dx);
+}
+
+// ------------------------------------------------------------ training
+// Restriction d(U), unrolled-loss term and Adam step (training.hpp).
+int orc_restrict(const double* fine, int nx_f, int ny_f, int factor, int nvar, int nbatch, double* coarse) {
+  if (!fine || !coarse || factor < 1 || nx_f % factor || ny_f % factor || nvar < 1 || nbatch < 1) return 1;
+  restrict_blocks(fine, nx_f, ny_f, factor, nvar, nbatch, coarse);
+  return 0;
+}
+
+int orc_mse(const double* U, const double* T, long long per_batch, int nbatch, double scale, double* loss,
+            double* G) {
+  if (!U || !T || !loss || per_batch < 1 || nbatch < 1) return 1;
+  mse_term(U, T, per_batch, nbatch, scale, loss, G);
+  return 0;
+}
+
+int orc_adam(double* theta, const double* g, double* m, double* v, int n, double lr, double b1, double b2,
+             double eps, int step) {
+  if (!theta || !g || !m || !v || n < 1 || step < 1) return 1;
+  adam_step(theta, g, m, v, n, lr, b1, b2, eps, step);
+  return 0;
 }
 
 }  // extern "C"
