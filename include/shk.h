@@ -320,7 +320,12 @@ shk_status shk_flux_cnn_images(shk_grid* g, const void* U, float* images, int* n
 /* Device form (bf16 weight matrices, FP32 biases) from theta. */
 shk_status shk_flux_cnn_pack(const float* theta, uint16_t* w_bf16, float* bias, void* hip_stream);
 
-/* One Adam step on n parameters (device arrays; step counts from 1). */
+/* One Adam step on n parameters (Kingma & Ba, the optimiser of section 3;
+ * device FP32 arrays; step counts from 1):
+ *   m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2;
+ *   theta <- theta - lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps),
+ * the two bias corrections formed in double on the host.  SHK_EINVAL for
+ * null arrays, n < 1, step < 1, or beta1 / beta2 outside [0, 1). */
 shk_status shk_adam(float* theta, const float* grad, float* m, float* v, int n, float lr, float beta1, float beta2,
                     float eps, int step, void* hip_stream);
 

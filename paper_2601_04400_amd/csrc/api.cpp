@@ -781,6 +781,7 @@ shk_status shk_flux_net_pack(const float* theta, uint16_t* w_bf16, float* bias, 
 shk_status shk_adam(float* theta, const float* grad, float* m, float* v, int n, float lr, float beta1, float beta2,
                     float eps, int step, void* hip_stream) {
   if (!theta || !grad || !m || !v || n <= 0 || step < 1) return SHK_EINVAL;
+  if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f)) return SHK_EINVAL;
   return launch_adam(theta, grad, m, v, n, lr, beta1, beta2, eps, step, reinterpret_cast<hipStream_t>(hip_stream)) ==
                  hipSuccess ? SHK_OK : SHK_EHIP;
 }

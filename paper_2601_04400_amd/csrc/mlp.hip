@@ -452,10 +452,12 @@ __global__ void __launch_bounds__(256) net_pack_kernel(const float* __restrict__
   }
 }
 
-// Adam (bias-corrected) on the FP32 master parameters.
+// Adam (bias-corrected) on the FP32 master parameters.  ic1 = 1/(1 - b1^step)
+// and ic2 = 1/(1 - b2^step) come from the host in double: 1 - b2^step
+// evaluated in FP32 loses most of its digits to cancellation at small steps.
 __global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ theta, const float* __restrict__ grad,
                                                    float* __restrict__ m, float* __restrict__ v, int n, float lr,
-                                                   float b1, float b2, float eps, int step) {
+                                                   float b1, float b2, float eps, float ic1, float ic2) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const float gk = grad[k];
@@ -463,8 +465,8 @@ __global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ theta, co
   const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
   m[k] = mk;
   v[k] = vk;
-  const float mh = mk / (1.f - powf(b1, (float)step));
-  const float vh = vk / (1.f - powf(b2, (float)step));
+  const float mh = mk * ic1;
+  const float vh = vk * ic2;
   theta[k] = theta[k] - lr * mh / (sqrtf(vh) + eps);
 }
 
@@ -510,9 +512,10 @@ __global__ void __launch_bounds__(256) mse_kernel(const double* __restrict__ U, 
   if (threadIdx.x == 0) part[(long long)b * gridDim.x + blockIdx.x] = (red[0] + red[1] + red[2] + red[3]) / double(per_b);
 }
 
+// One thread per batch member, 64 members per workgroup.
 __global__ void __launch_bounds__(64) mse_finalize_kernel(const double* __restrict__ part, int nblk, int nbatch,
                                                           double* __restrict__ loss) {
-  const int b = threadIdx.x;
+  const int b = blockIdx.x * 64 + threadIdx.x;
   if (b >= nbatch) return;
   double s = 0.0;
   for (int k = 0; k < nblk; ++k) s += part[(long long)b * nblk + k];
@@ -565,8 +568,10 @@ hipError_t launch_net_pack(const float* theta, unsigned short* w, float* bias, h
 
 hipError_t launch_adam(float* theta, const float* grad, float* m, float* v, int n, float lr, float b1, float b2,
                        float eps, int step, hipStream_t st) {
+  const float ic1 = float(1.0 / (1.0 - std::pow(double(b1), step)));
+  const float ic2 = float(1.0 / (1.0 - std::pow(double(b2), step)));
   hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, st, theta, grad, m, v, n, lr, b1, b2, eps,
-                     step);
+                     ic1, ic2);
   return hipGetLastError();
 }
 
@@ -587,7 +592,7 @@ hipError_t launch_mse(const double* U, const double* T, double* G, double scale,
   hipLaunchKernelGGL(mse_kernel, dim3(nb, nbatch), dim3(256), 0, st, U, T, G, scale, per_b, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(mse_finalize_kernel, dim3(1), dim3(64 * ((nbatch + 63) / 64)), 0, st, part, (int)nb, nbatch, loss);
+  hipLaunchKernelGGL(mse_finalize_kernel, dim3((nbatch + 63) / 64), dim3(64), 0, st, part, (int)nb, nbatch, loss);
   return hipGetLastError();
 }
 
