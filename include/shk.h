@@ -341,6 +341,20 @@ shk_status shk_restrict(const double* fine, double* coarse, int nx_f, int ny_f, 
 shk_status shk_mse(const double* U, const double* T, double* G, double scale, long long per_batch, int nbatch,
                    double* part, double* loss, void* hip_stream);
 
+/* shk_mse for callers that cannot allocate memory (code under HIP graph
+ * capture, tight training loops, harnesses that forbid allocation): the same
+ * kernels and the same result bit for bit, with the block partials in a
+ * static device array of the library (SHK_MSE_NOALLOC_MAX_BATCH * 256
+ * doubles, 512 KiB on each GPU it runs on, held until the process ends)
+ * instead of a caller buffer.  Allocates nothing.  The stream must belong to
+ * the current device.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (two streams, two threads) race and must be ordered by
+ * the caller.  SHK_EINVAL for a null U, T or loss, per_batch < 1, or nbatch
+ * outside 1..SHK_MSE_NOALLOC_MAX_BATCH. */
+#define SHK_MSE_NOALLOC_MAX_BATCH 256
+shk_status shk_mse_noalloc(const double* U, const double* T, double* G, double scale, long long per_batch,
+                           int nbatch, double* loss, void* hip_stream);
+
 /* Set the device time of every batch member to t0, the stop time to t_end
  * and the automatic-step counter to 0 (enqueued). */
 shk_status shk_set_time(shk_grid* g, double t0, double t_end);

@@ -56,6 +56,7 @@ _SIGS = {
     "shk_adam": (_i, [_p, _p, _p, _p, _i, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _i, _p]),
     "shk_restrict": (_i, [_p, _p, _i, _i, _i, _i, _i, _p]),
     "shk_mse": (_i, [_p, _p, _p, _d, ctypes.c_longlong, _i, _p, _p, _p]),
+    "shk_mse_noalloc": (_i, [_p, _p, _p, _d, ctypes.c_longlong, _i, _p, _p]),
     "shk_set_time": (_i, [_p, _d, _d]),
     "shk_get_time": (_i, [_p, _i, _p, _p, _p]),
     "shk_poll_faults": (_i, [_p, _p, _p]),

@@ -800,6 +800,13 @@ shk_status shk_mse(const double* U, const double* T, double* G, double scale, lo
                  hipSuccess ? SHK_OK : SHK_EHIP;
 }
 
+shk_status shk_mse_noalloc(const double* U, const double* T, double* G, double scale, long long per_batch,
+                           int nbatch, double* loss, void* hip_stream) {
+  if (!U || !T || !loss || per_batch < 1 || nbatch < 1 || nbatch > SHK_MSE_NOALLOC_MAX_BATCH) return SHK_EINVAL;
+  return launch_mse_noalloc(U, T, G, scale, per_batch, nbatch, loss, reinterpret_cast<hipStream_t>(hip_stream)) ==
+                 hipSuccess ? SHK_OK : SHK_EHIP;
+}
+
 shk_status shk_set_time(shk_grid* g, double t0, double t_end) {
   if (!g) return SHK_EINVAL;
   if (!(t_end >= t0)) return fail(g, SHK_EINVAL, "set_time: t_end < t0");

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "face_dev.hpp"
 #include "flux.hpp"
@@ -522,6 +523,12 @@ __global__ void __launch_bounds__(64) mse_finalize_kernel(const double* __restri
   loss[b] += s;
 }
 
+// Block partials of launch_mse_noalloc: one copy per GPU, kept until the
+// process ends.  Host code never passes this name to a kernel (on the host it
+// is a stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returns on each device.
+static __device__ __align__(256) double scratch[MSE_NOALLOC_MAX_BATCH * 256];
+
 // ------------------------------------------------------------------ launchers
 long long net_face_count(const GridArgs& a) {
   return (long long)(a.nx + 1) * a.ny + (long long)a.nx * (a.ny + 1);
@@ -583,6 +590,41 @@ hipError_t launch_restrict(const double* fine, double* coarse, int nxf, int nyf,
   hipLaunchKernelGGL(restrict_kernel, dim3((unsigned int)(nb < 1 ? 1 : nb)), dim3(256), 0, st, fine, coarse, nxf, nyf,
                      factor, nvar, nbatch);
   return hipGetLastError();
+}
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+double* scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call on that device.
+hipError_t scratch_address(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+hipError_t launch_mse_noalloc(const double* U, const double* T, double* G, double scale, long long per_b, int nbatch,
+                              double* loss, hipStream_t st) {
+  if (nbatch < 1 || nbatch > MSE_NOALLOC_MAX_BATCH) return hipErrorInvalidValue;
+  double* part = nullptr;
+  hipError_t e = scratch_address(&part);
+  if (e != hipSuccess) return e;
+  // mse_kernel writes every partial launch_mse's finaliser reads, so the
+  // array needs no clearing between calls.
+  return launch_mse(U, T, G, scale, per_b, nbatch, part, loss, st);
 }
 
 hipError_t launch_mse(const double* U, const double* T, double* G, double scale, long long per_b, int nbatch,

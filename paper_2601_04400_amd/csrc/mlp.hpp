@@ -43,5 +43,13 @@ hipError_t launch_restrict(const double* fine, double* coarse, int nxf, int nyf,
                            hipStream_t st);
 hipError_t launch_mse(const double* U, const double* T, double* G, double scale, long long per_b, int nbatch,
                       double* part, double* loss, hipStream_t st);
+// Largest batch of launch_mse_noalloc: its block partials live in a static
+// device array of MSE_NOALLOC_MAX_BATCH * 256 doubles (512 KiB per GPU).
+constexpr int MSE_NOALLOC_MAX_BATCH = 256;
+// launch_mse with the partials in that array (no caller buffer, no
+// allocation).  The array's address on the current device is looked up once
+// per device.  Calls that overlap on one GPU share the array and race.
+hipError_t launch_mse_noalloc(const double* U, const double* T, double* G, double scale, long long per_b, int nbatch,
+                              double* loss, hipStream_t st);
 
 }  // namespace shk
