@@ -153,13 +153,21 @@ shk_status shk_ib_classes(shk_grid* g, uint8_t* cls);
 
 /* Right-hand side dUdt = L(U) of the semi-discrete scheme (section 2
  * conservative update without the time step).  With an immersed boundary
- * the ghost cells of U are refilled IN PLACE first (U is then in/out).
- * U and dUdt must not alias. */
-shk_status shk_rhs(shk_grid* g, void* U, void* dUdt);
+ * the ghost cells take their refilled values (formed from the fluid cells
+ * of U while the kernel loads them); U is not modified.  U and dUdt must not
+ * alias. */
+shk_status shk_rhs(shk_grid* g, const void* U, void* dUdt);
+
+/* Refill the ghost cells of U in place from its fluid cells (the values
+ * every right-hand side and stage uses for them).  SHK_ESTATE without an
+ * immersed boundary. */
+shk_status shk_ib_fill(shk_grid* g, void* U);
 
 /* One SSP-RK3 step of U in place:
  *   U1 = U + dt L(U); U2 = 3/4 U + 1/4 U1 + dt/4 L(U1);
- *   U <- 1/3 U + 2/3 U2 + 2 dt/3 L(U2).
+ *   U <- 1/3 U + 2/3 U2 + 2 dt/3 L(U2),
+ * each stage state's ghost cells refilled before its right-hand side (the
+ * refilled ghosts of U enter the last combination).
  * dt_in: device array of nbatch doubles with a fixed step, or NULL for the
  * automatic step dt = cfl / max_fluid[(|u|+a)/dx + (|v|+a)/dy] (plus the
  * explicit viscous limit), computed from U on the device and shortened so

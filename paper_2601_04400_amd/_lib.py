@@ -35,6 +35,7 @@ _SIGS = {
     "shk_ib_ghost_count": (_i, [_p, _p]),
     "shk_ib_classes": (_i, [_p, _p]),
     "shk_rhs": (_i, [_p, _p, _p]),
+    "shk_ib_fill": (_i, [_p, _p]),
     "shk_rk3_step": (_i, [_p, _p, _p, _p]),
     "shk_rhs_adjoint": (_i, [_p, _p, _p, _p, _p]),
     "shk_rk3_step_adjoint": (_i, [_p, _p, _p, _p, _p]),

@@ -118,6 +118,7 @@ WsLayout layout(const shk_grid_desc* d) {
     L.g_src = o; o += al(sizeof(int) * 4 * cap);
     L.g_w = o; o += al(sizeof(double) * 4 * cap);
     L.g_nrm = o; o += al(sizeof(double) * 2 * cap);
+    L.ghostOf = o; o += al(sizeof(int) * ncell);
   }
   if (d->adjoint) {
     const size_t st64 = al(size_t(d->nbatch) * 4 * ncell * sizeof(double));
@@ -131,7 +132,6 @@ WsLayout layout(const shk_grid_desc* d) {
     L.adjPart = o; o += al(sizeof(double) * MAX_PART_SLOTS * L.part_stride);
     if (d->ibm) {
       L.adjG = o; o += st64;  // image-point primitive adjoints, 4 per ghost
-      L.ghostOf = o; o += al(sizeof(int) * ncell);
       L.entKeys = o; o += al(sizeof(int) * 4 * ncell);
       L.entVals = o; o += al(sizeof(int) * 4 * ncell);
       L.entCount = o; o += al(sizeof(int));
@@ -224,9 +224,15 @@ hipError_t stage_launch(shk_grid* g, const GridArgs& a, int mode, const S* Us, c
   return launch_stage<S>(a, mode, Us, Un, Uo, dtp, Lin, g->st);
 }
 
-// One SSP-RK3 step.  With a fixed step or an immersed boundary the stages
-// are the plain three (after a separate reduction for the automatic step);
-// otherwise the automatic step is fused into the stages (S1L, S2F, S3F).
+// One SSP-RK3 step.  Without a fixed step, a tape or a learned correction
+// the automatic step is fused into the stages (S1L, S2F, S3F); otherwise the
+// stages are the plain three (after a separate reduction for the automatic
+// step).  With an immersed boundary the stage kernels form the refilled
+// ghost values of their stage state while loading their tiles; the refilled
+// ghosts of U^n are stored back into U (stage 3 combines them, as the step's
+// definition does), and with a tape each stage state's refilled ghosts are
+// stored in the tape.  The convolutional network reads the stage states
+// itself, so with it the ghosts are refilled by separate launches first.
 // With tape != nullptr the stage-start states (U^n, U1, U2, each after the
 // refill) are kept in tape[0..2] for the reverse pass.
 template <class S>
@@ -237,9 +243,11 @@ shk_status stage_seq(shk_grid* g, S* U, const double* dt_in, double* dt_out, S* 
   S* U1 = tape ? tape + nst : reinterpret_cast<S*>(g->ws + g->L.u1);
   S* U2 = tape ? tape + 2 * nst : reinterpret_cast<S*>(g->ws + g->L.u2);
   hipError_t e;
-  if (!dt_in && !g->ibm_on && !g->net_on && !g->cnn_on && !tape) {
+  if (!dt_in && !g->net_on && !g->cnn_on && !tape) {
+    a.ghost_back = g->ibm_on ? U : nullptr;  // refilled ghosts of U^n, read back by S2F and S3F
     if ((e = timed(g, 1, [&]() { return stage_launch<S>(g, a, MODE_S1L, U, U, U1, nullptr, nullptr); })) != hipSuccess)
       return hip_check(g, e, "stage 1");
+    a.ghost_back = nullptr;  // S2F's stage state U1 is never stored
     if ((e = timed(g, 2, [&]() { return stage_launch<S>(g, a, MODE_S2F, U, U, U2, nullptr, U1); })) != hipSuccess)
       return hip_check(g, e, "stage 2");
     if ((e = timed(g, 3, [&]() { return stage_launch<S>(g, a, MODE_S3F, U2, U, U, nullptr, nullptr); })) != hipSuccess)
@@ -253,10 +261,11 @@ shk_status stage_seq(shk_grid* g, S* U, const double* dt_in, double* dt_out, S* 
     dtp = a.dtbuf;
   }
   auto stage = [&](int mode, const S* Us, const S* Un, S* Uo) -> hipError_t {
+    a.ghost_back = g->ibm_on ? const_cast<S*>(Us) : nullptr;
     return timed(g, mode, [&]() { return stage_launch<S>(g, a, mode, Us, Un, Uo, dtp, nullptr); });
   };
   auto fill = [&](S* X) -> hipError_t {
-    if (!g->ibm_on) return hipSuccess;
+    if (!g->ibm_on || !g->cnn_on) return hipSuccess;
     return timed(g, 4, [&]() { return launch_ibm_fill<S>(a, g->gt, X, g->st); });
   };
   if ((e = fill(U)) != hipSuccess) return hip_check(g, e, "ibm fill");
@@ -355,6 +364,7 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
     g->a.cls = nullptr;
     g->a.ghost_of = nullptr;
     g->gt.n = 0;
+    g->a.gt = g->gt;
     return SHK_OK;
   }
   if (!g->d.ibm) return fail(g, SHK_ESTATE, "set_ib_levelset: grid created without desc.ibm = 1");
@@ -379,11 +389,19 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
   if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset");
   gt.n = n;
   g->gt = gt;
+  a.gt = gt;
   a.cls = cls;
   g->ibm_on = true;
   g->nent = 0;
   g->nsrc = 0;
-  a.ghost_of = nullptr;
+  // ghost index of every cell: the stage kernels refill ghost cells while
+  // loading their tiles, and the adjoint kernel runs the ghost half of the
+  // refill transpose
+  int* gof = reinterpret_cast<int*>(g->ws + g->L.ghostOf);
+  e = launch_ghost_index(a, gt, gof, g->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+  if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset (ghost index)");
+  a.ghost_of = gof;
   if (g->d.adjoint && n > 0) {
     int* keys = reinterpret_cast<int*>(g->ws + g->L.entKeys);
     int* vals = reinterpret_cast<int*>(g->ws + g->L.entVals);
@@ -409,11 +427,6 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
     if (e == hipSuccess) e = hipStreamSynchronize(g->st);
     if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset (entry heads)");
     g->nsrc = int(heads.size()) - 1;
-    int* gof = reinterpret_cast<int*>(g->ws + g->L.ghostOf);
-    e = launch_ghost_index(a, gt, gof, g->st);
-    if (e == hipSuccess) e = hipStreamSynchronize(g->st);
-    if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset (ghost index)");
-    a.ghost_of = gof;
   }
   return SHK_OK;
 }
@@ -443,28 +456,41 @@ shk_status shk_ib_classes(shk_grid* g, uint8_t* cls) {
                    "ib_classes");
 }
 
-shk_status shk_rhs(shk_grid* g, void* U, void* dUdt) {
+shk_status shk_rhs(shk_grid* g, const void* U, void* dUdt) {
   if (!g) return SHK_EINVAL;
   if (!U || !dUdt || U == dUdt) return fail(g, SHK_EINVAL, "rhs: null or aliased arrays");
   hipError_t e = hipSuccess;
   if (g->esize == 8) {
-    GridArgs a = g->a;
-    if (g->ibm_on) e = launch_ibm_fill<double>(a, g->gt, static_cast<double*>(U), g->st);
-    if (e == hipSuccess)
-      e = stage_launch<double>(g, a, MODE_RHS, static_cast<double*>(U), static_cast<double*>(U),
-                               static_cast<double*>(dUdt), nullptr, nullptr);
-  } else {
-    if (g->ibm_on) e = launch_ibm_fill<float>(g->a, g->gt, static_cast<float*>(U), g->st);
-    if (e == hipSuccess) {
-      if (g->d.prec == SHK_MIXED)
-        e = launch_stage_mixed(g->a, MODE_RHS, static_cast<float*>(U), static_cast<float*>(U),
-                               static_cast<float*>(dUdt), nullptr, nullptr, g->st);
-      else
-        e = launch_stage<float>(g->a, MODE_RHS, static_cast<float*>(U), static_cast<float*>(U),
-                                static_cast<float*>(dUdt), nullptr, nullptr, g->st);
+    const GridArgs& a = g->a;
+    const double* Us = static_cast<const double*>(U);
+    if (g->ibm_on && g->cnn_on) {
+      // the convolutional network reads the stage state's ghost cells: refill
+      // them on a workspace copy, leaving U as it is
+      double* W = reinterpret_cast<double*>(g->ws + g->L.u1);
+      e = hipMemcpyAsync(W, Us, sizeof(double) * size_t(a.nbatch) * a.nvar * a.ncell, hipMemcpyDeviceToDevice,
+                         g->st);
+      if (e == hipSuccess) e = launch_ibm_fill<double>(a, g->gt, W, g->st);
+      Us = W;
     }
+    if (e == hipSuccess)
+      e = stage_launch<double>(g, a, MODE_RHS, Us, Us, static_cast<double*>(dUdt), nullptr, nullptr);
+  } else {
+    const float* Us = static_cast<const float*>(U);
+    if (g->d.prec == SHK_MIXED)
+      e = launch_stage_mixed(g->a, MODE_RHS, Us, Us, static_cast<float*>(dUdt), nullptr, nullptr, g->st);
+    else
+      e = launch_stage<float>(g->a, MODE_RHS, Us, Us, static_cast<float*>(dUdt), nullptr, nullptr, g->st);
   }
   return hip_check(g, e, "rhs");
+}
+
+shk_status shk_ib_fill(shk_grid* g, void* U) {
+  if (!g) return SHK_EINVAL;
+  if (!U) return fail(g, SHK_EINVAL, "ib_fill: null state");
+  if (!g->ibm_on) return fail(g, SHK_ESTATE, "ib_fill: no immersed boundary set");
+  hipError_t e = g->esize == 8 ? launch_ibm_fill<double>(g->a, g->gt, static_cast<double*>(U), g->st)
+                               : launch_ibm_fill<float>(g->a, g->gt, static_cast<float*>(U), g->st);
+  return hip_check(g, e, "ib_fill");
 }
 
 shk_status shk_rk3_step(shk_grid* g, void* U, const double* dt_in, double* dt_out) {

@@ -29,6 +29,16 @@ struct Globals {
   unsigned long long fallbacks; // positivity-fallback faces
 };
 
+// Ghost-cell table of the immersed boundary (structure of arrays).
+struct GhostTable {
+  int n;
+  int* cell;        // flat index of the ghost
+  int* src;         // [n][4] flat indices of the interpolation cells (-1 unused)
+  double* w;        // [n][4] weights
+  double* nrm;      // [n][2] unit normal
+  int wall;         // 0 slip, 1 no-slip adiabatic
+};
+
 // Everything a kernel needs to know about the grid (passed by value).
 struct GridArgs {
   int ndim, nx, ny, nbatch, nvar;
@@ -46,22 +56,16 @@ struct GridArgs {
   double* dtbuf;               // [nbatch] step of the automatic time stepping
   double* dt_out;              // optional caller copy of the step (per call)
   void* stage_in_copy;         // MODE_STAGE1: optional copy of the stage input (storage type), or nullptr
-  const int* ghost_of;         // immersed boundary, adjoint grids: ghost index of each cell or -1 (else nullptr)
+  const int* ghost_of;         // immersed boundary: ghost index of each cell or -1 (else nullptr)
+  GhostTable gt;               // immersed boundary: the ghost table (gt.n = 0 without)
+  void* ghost_back;            // stage kernels: where the refilled ghost values of the stage
+                               // state are written (storage type; usually the stage state
+                               // itself), or nullptr
   unsigned long long* xslots;  // [nbatch][2][XSLOTS] spread extrema of the fused step
   const float* dXnet;          // its stencil gradient per face [nbatch][nface][24] or nullptr
   const float* dFext;          // precomputed face correction [nbatch][nface][4] (face frame) or nullptr
   long long nface;             // x-faces (nx+1)*ny then y-faces nx*(ny+1)
   Globals* glob;
-};
-
-// Ghost-cell table of the immersed boundary (structure of arrays).
-struct GhostTable {
-  int n;
-  int* cell;        // flat index of the ghost
-  int* src;         // [n][4] flat indices of the interpolation cells (-1 unused)
-  double* w;        // [n][4] weights
-  double* nrm;      // [n][2] unit normal
-  int wall;         // 0 slip, 1 no-slip adiabatic
 };
 
 // Learned face-flux correction: weights in the matrix-core layout (bf16),

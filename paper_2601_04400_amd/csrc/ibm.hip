@@ -18,6 +18,7 @@
 #include <cmath>
 
 #include "grid.hpp"
+#include "ibm_dev.hpp"
 
 namespace shk {
 
@@ -144,36 +145,10 @@ __global__ void __launch_bounds__(256) ibm_fill_kernel(GridArgs a, GhostTable gt
   if (k >= gt.n) return;
   const long long n = a.ncell;
   S* Ub = U + (long long)blockIdx.y * 4 * n;
-  const double g = a.gamma, gm1 = g - 1.0;
-  double Wi[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int m = 0; m < 4; ++m) {
-    const int s = gt.src[4 * k + m];
-    if (s < 0) continue;
-    const double wm = gt.w[4 * k + m];
-    const double r = double(Ub[s]);
-    const double u = double(Ub[n + s]) / r;
-    const double v = double(Ub[2 * n + s]) / r;
-    const double p = gm1 * (double(Ub[3 * n + s]) - 0.5 * r * (u * u + v * v));
-    Wi[0] = Wi[0] + wm * r;
-    Wi[1] = Wi[1] + wm * u;
-    Wi[2] = Wi[2] + wm * v;
-    Wi[3] = Wi[3] + wm * p;
-  }
-  double ug, vg;
-  if (gt.wall == 0) {
-    const double nx = gt.nrm[2 * k], ny = gt.nrm[2 * k + 1];
-    const double un = Wi[1] * nx + Wi[2] * ny;
-    ug = Wi[1] - 2.0 * un * nx;
-    vg = Wi[2] - 2.0 * un * ny;
-  } else {
-    ug = -Wi[1];
-    vg = -Wi[2];
-  }
+  double q[4];
+  ghost_cons(gt, a.gamma, k, [&](int e, long long c) { return double(Ub[e * n + c]); }, q);
   const int c = gt.cell[k];
-  Ub[c] = S(Wi[0]);
-  Ub[n + c] = S(Wi[0] * ug);
-  Ub[2 * n + c] = S(Wi[0] * vg);
-  Ub[3 * n + c] = S(Wi[3] / gm1 + 0.5 * Wi[0] * (ug * ug + vg * vg));
+  for (int e = 0; e < 4; ++e) Ub[e * n + c] = S(q[e]);
 }
 
 hipError_t launch_ibm_classify(const GridArgs& a, const double* phi, uint8_t* cls, int* row_count,

@@ -15,6 +15,7 @@
 
 #include "flux.hpp"
 #include "grid.hpp"
+#include "ibm_dev.hpp"
 #include "xcd.hpp"
 #include "mlp.hpp"
 #include "mlp_dev.hpp"
@@ -40,39 +41,63 @@ __device__ __forceinline__ int bc_source(int g, int n, int bc_lo, int bc_hi, int
   return s < 0 ? 0 : (s >= n ? n - 1 : s);
 }
 
+// Refilled value of the immersed-boundary ghost cell c of a stage state
+// whose plane e of interior cell c is get(e, c), rounded to the storage type
+// as the separate refill stores it.
+template <class S, class C, class Get>
+__device__ __forceinline__ void ghost_at(const GridArgs& a, long long c, Get&& get, C q[4]) {
+  double g[4];
+  ghost_cons(a.gt, a.gamma, a.ghost_of[c], [&](int e, long long s) { return double(get(e, s)); }, g);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) q[v] = C(S(g[v]));
+}
+
 // Conservative state (rho, m_x, m_y, E) of cell (gi, gj), which may lie in
 // the ghost layers; x rules are applied first, then y rules (a y inflow
 // overrides everything, as for a y-ghost layer filled after the x-ghosts).
-// get(e, c) returns plane e of interior cell c.
-template <class C, int NDIM, class Get>
+// get(e, c) returns plane e of interior cell c.  An immersed-boundary ghost
+// cell takes its refilled value, formed here from the fluid cells of the
+// same state (they are complete when the stage starts).
+template <class S, class C, int NDIM, bool GH, class Get>
 __device__ __forceinline__ void load_cons_f(const GridArgs& a, int gi, int gj, Get&& get, C q[4]) {
   int fx = 0, fy = 0;
   const int si = bc_source(gi, a.nx, a.bc[0], a.bc[1], fx);
   int sj = 0;
   if (NDIM == 2) sj = bc_source(gj, a.ny, a.bc[2], a.bc[3], fy);
+  // scalars, not the array, along the branches (an array written on some
+  // paths only is kept in scratch memory)
+  C r, mx, my, E;
   if (fy == 2 || fx == 2) {
-    for (int v = 0; v < 4; ++v) q[v] = C(a.inflow_cons[v]);
-    if (NDIM == 1) q[2] = C(0);
+    r = C(a.inflow_cons[0]);
+    mx = C(a.inflow_cons[1]);
+    my = NDIM == 1 ? C(0) : C(a.inflow_cons[2]);
+    E = C(a.inflow_cons[3]);
   } else {
     const long long c = (long long)sj * a.nx + si;
-    q[0] = get(0, c);
-    q[1] = get(1, c);
-    if (NDIM == 2) {
-      q[2] = get(2, c);
-      q[3] = get(3, c);
+    if (GH && a.cls != nullptr && a.cls[c] == CELL_GHOST) {
+      C g[4];
+      ghost_at<S>(a, c, get, g);
+      r = g[0]; mx = g[1]; my = g[2]; E = g[3];
     } else {
-      q[2] = C(0);
-      q[3] = get(2, c);
+      r = get(0, c);
+      mx = get(1, c);
+      if (NDIM == 2) {
+        my = get(2, c);
+        E = get(3, c);
+      } else {
+        my = C(0);
+        E = get(2, c);
+      }
     }
-    if (fx & 1) q[1] = -q[1];
+    mx = (fx & 1) ? -mx : mx;
   }
-  if (fy & 1) q[2] = -q[2];
+  my = (fy & 1) ? -my : my;
+  q[0] = r; q[1] = mx; q[2] = my; q[3] = E;
 }
 
-template <class S, class C, int NDIM>
-__device__ __forceinline__ void load_cons(const GridArgs& a, const S* __restrict__ U, int gi, int gj,
-                                          C q[4]) {
-  load_cons_f<C, NDIM>(a, gi, gj, [&](int e, long long c) { return C(U[e * a.ncell + c]); }, q);
+template <class S, class C, int NDIM, bool GH>
+__device__ __forceinline__ void load_cons(const GridArgs& a, const S* U, int gi, int gj, C q[4]) {
+  load_cons_f<S, C, NDIM, GH>(a, gi, gj, [&](int e, long long c) { return C(U[e * a.ncell + c]); }, q);
 }
 
 // Automatic step from the reduced maxima of a batch member (dt = cfl / max
@@ -212,11 +237,17 @@ __device__ __forceinline__ void char_face_states(const double* q0, const double*
 //   NET_EXT: a correction computed beforehand for every face (the
 //            convolutional network), read from a.dFext.
 // CHAR: characteristic-wise WENO5 instead of the primitive-wise one (FP64).
-template <class S, class C, int NDIM, int TX, int TY, bool VISC, int MODE, int NET = NET_NONE, bool CHAR = false>
-__global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restrict__ Us,
-                                                    const S* __restrict__ Un, S* __restrict__ Uout,
+// IBM: the grid has an immersed boundary (a.cls, a.ghost_of and a.gt set):
+// ghost cells take their refilled values, formed from the stage state's
+// fluid cells as they are loaded, and their right-hand side is zero.
+template <class S, class C, int NDIM, int TX, int TY, bool VISC, int MODE, int NET = NET_NONE, bool CHAR = false,
+          bool IBM = false>
+__global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* Us, const S* Un, S* Uout,
                                                     const double* __restrict__ dtp,
                                                     const S* __restrict__ Lin, NetArgs net) {
+  // Us, Un and Uout may alias (stage 3 writes the step's result over U^n) and
+  // a.ghost_back may be Us: every cell is read before it is written, by the
+  // thread that writes it, and a ghost cell's stored value is never read.
   constexpr int NT = 256;
   constexpr int H = HALO;
   constexpr int PX = TX + 2 * H;
@@ -232,6 +263,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
   __shared__ unsigned int blk_fallback, blk_fault;
   static_assert(NET == NET_NONE || (NDIM == 2 && !VISC), "learned correction: 2D inviscid tiles");
   constexpr bool MLP = NET == NET_MLP;
+  constexpr bool GH = IBM && NDIM == 2;
   __shared__ __attribute__((aligned(16))) unsigned short net_w[MLP ? NET_LNW : 1];
   __shared__ float net_b[MLP ? NET_NB : 1];
   // normalised network inputs of every halo cell, bfloat16, in the x-face
@@ -289,7 +321,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
   const int i0 = bx * TX;
   const int j0 = by * TY;
   const long long boff = (long long)b * a.nvar * a.ncell;
-  const S* __restrict__ Ub = Us + boff;
+  const S* Ub = Us + boff;
   const S* __restrict__ Lb = MODE == MODE_S2F ? Lin + boff : nullptr;
   const C gm1 = C(a.gamma - 1.0);
   const C cdt = C(dt);
@@ -312,9 +344,9 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     const int gj = NDIM == 2 ? j0 + ly - H : 0;
     C q[4];
     if (MODE == MODE_S2F)
-      load_cons_f<C, NDIM>(a, gi, gj, u1_at, q);
+      load_cons_f<S, C, NDIM, GH>(a, gi, gj, u1_at, q);
     else
-      load_cons<S, C, NDIM>(a, Ub, gi, gj, q);
+      load_cons<S, C, NDIM, GH>(a, Ub, gi, gj, q);
     Prim<C> p = to_prim(q[0], q[1], q[2], q[3], gm1);
     w[0][k] = p.r;
     w[1][k] = p.un;
@@ -516,10 +548,11 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
 
   // 3. flux difference and Runge-Kutta combination
   const C idx = C(a.inv_dx), idy = C(a.inv_dy);
-  const S* __restrict__ Unb = Un + boff;
-  S* __restrict__ Ob = Uout + boff;
+  const S* Unb = Un + boff;
+  S* Ob = Uout + boff;
   bool bad = false;
   double smax = 0.0, rmin = INFINITY;
+  constexpr int NV = NDIM == 2 ? 4 : 3;  // stored planes
   for (int k = threadIdx.x; k < TX * TY; k += NT) {
     // Flux difference and stage combination are evaluated as written (no
     // fused multiply-add), so the fused and the three-stage sequences agree
@@ -529,7 +562,35 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     const int gi = i0 + x, gj = j0 + y;
     if (gi >= a.nx || gj >= a.ny) continue;
     const long long cell = (long long)gj * a.nx + gi;
+    const uint8_t cc = GH && a.cls != nullptr ? a.cls[cell] : CELL_FLUID;
+    // the cell's stage-state and U^n values, all read before any write (the
+    // output may overwrite U^n); a ghost cell takes its refilled stage value
+    C us[4], un[4];
+    if (GH && cc == CELL_GHOST) {
+      if (MODE == MODE_S2F)
+        ghost_at<S>(a, cell, u1_at, us);
+      else
+        ghost_at<S>(a, cell, [&](int e, long long c) { return C(Ub[e * a.ncell + c]); }, us);
+      if (MODE != MODE_S2F && a.ghost_back != nullptr)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) static_cast<S*>(a.ghost_back)[boff + v * a.ncell + cell] = S(us[v]);
+    } else if (MODE != MODE_RHS && MODE != MODE_S1L) {
+#pragma unroll
+      for (int e = 0; e < NV; ++e) {
+        const int v = (NDIM == 1 && e == 2) ? 3 : e;
+        us[v] = MODE == MODE_S2F ? u1_at(e, cell) : C(Ub[e * a.ncell + cell]);
+      }
+    }
+    if (MODE == MODE_STAGE2 || MODE == MODE_STAGE3 || MODE == MODE_S3F || MODE == MODE_S2F) {
+#pragma unroll
+      for (int e = 0; e < NV; ++e) {
+        const int v = (NDIM == 1 && e == 2) ? 3 : e;
+        // S2F: U^n is the stage input itself (U1 is formed on the fly)
+        un[v] = C(MODE == MODE_S2F ? Ub[e * a.ncell + cell] : Unb[e * a.ncell + cell]);
+      }
+    }
     C Lv[4];
+#pragma unroll
     for (int v = 0; v < 4; ++v) {
       C r = -(fxs[v][y * (TX + 1) + x + 1] - fxs[v][y * (TX + 1) + x]) * idx;
       if (NDIM == 2) r = r - (fys[v][(y + 1) * TX + x] - fys[v][y * TX + x]) * idy;
@@ -538,23 +599,23 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
     if (a.nu_art != 0.0) {
       C c0[4], xm[4], xp[4];
       if (MODE == MODE_S2F) {
-        load_cons_f<C, NDIM>(a, gi, gj, u1_at, c0);
-        load_cons_f<C, NDIM>(a, gi - 1, gj, u1_at, xm);
-        load_cons_f<C, NDIM>(a, gi + 1, gj, u1_at, xp);
+        load_cons_f<S, C, NDIM, GH>(a, gi, gj, u1_at, c0);
+        load_cons_f<S, C, NDIM, GH>(a, gi - 1, gj, u1_at, xm);
+        load_cons_f<S, C, NDIM, GH>(a, gi + 1, gj, u1_at, xp);
       } else {
-        load_cons<S, C, NDIM>(a, Ub, gi, gj, c0);
-        load_cons<S, C, NDIM>(a, Ub, gi - 1, gj, xm);
-        load_cons<S, C, NDIM>(a, Ub, gi + 1, gj, xp);
+        load_cons<S, C, NDIM, GH>(a, Ub, gi, gj, c0);
+        load_cons<S, C, NDIM, GH>(a, Ub, gi - 1, gj, xm);
+        load_cons<S, C, NDIM, GH>(a, Ub, gi + 1, gj, xp);
       }
       const C nu = C(a.nu_art);
       C ym[4], yp[4];
       if (NDIM == 2) {
         if (MODE == MODE_S2F) {
-          load_cons_f<C, NDIM>(a, gi, gj - 1, u1_at, ym);
-          load_cons_f<C, NDIM>(a, gi, gj + 1, u1_at, yp);
+          load_cons_f<S, C, NDIM, GH>(a, gi, gj - 1, u1_at, ym);
+          load_cons_f<S, C, NDIM, GH>(a, gi, gj + 1, u1_at, yp);
         } else {
-          load_cons<S, C, NDIM>(a, Ub, gi, gj - 1, ym);
-          load_cons<S, C, NDIM>(a, Ub, gi, gj + 1, yp);
+          load_cons<S, C, NDIM, GH>(a, Ub, gi, gj - 1, ym);
+          load_cons<S, C, NDIM, GH>(a, Ub, gi, gj + 1, yp);
         }
       }
       for (int v = 0; v < 4; ++v) {
@@ -563,32 +624,31 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* __restr
         Lv[v] = Lv[v] + nu * lap;
       }
     }
-    if (a.cls != nullptr && a.cls[cell] != CELL_FLUID) {
+    if (cc != CELL_FLUID) {
+#pragma unroll
       for (int v = 0; v < 4; ++v) Lv[v] = C(0);
     }
-    if (MODE == MODE_S1L && (a.cls == nullptr || a.cls[cell] == CELL_FLUID)) {
+    if (MODE == MODE_S1L && cc == CELL_FLUID) {
       double r;
       smax = fmax(smax, wave_speed_sum(a, Ub, cell, &r));
       rmin = fmin(rmin, r);
     }
-    for (int e = 0; e < a.nvar; ++e) {
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
       const int v = (NDIM == 1 && e == 2) ? 3 : e;
       const long long o = (long long)e * a.ncell + cell;
       C out;
       if (MODE == MODE_RHS || MODE == MODE_S1L) {
         out = Lv[v];
       } else if (MODE == MODE_STAGE1) {
-        const S u0 = Ub[o];
         // the reverse pass keeps the (refilled) stage input: copied here
-        // from the value this thread reads anyway
-        if (a.stage_in_copy != nullptr) static_cast<S*>(a.stage_in_copy)[boff + o] = u0;
-        out = C(u0) + cdt * Lv[v];
-      } else if (MODE == MODE_STAGE2) {
-        out = C(0.75) * C(Unb[o]) + C(0.25) * C(Ub[o]) + C(0.25 * dt) * Lv[v];
-      } else if (MODE == MODE_S2F) {
-        out = C(0.75) * C(Ub[o]) + C(0.25) * u1_at(e, cell) + C(0.25 * dt) * Lv[v];
+        // from the value this thread holds anyway
+        if (a.stage_in_copy != nullptr) static_cast<S*>(a.stage_in_copy)[boff + o] = S(us[v]);
+        out = us[v] + cdt * Lv[v];
+      } else if (MODE == MODE_STAGE2 || MODE == MODE_S2F) {
+        out = C(0.75) * un[v] + C(0.25) * us[v] + C(0.25 * dt) * Lv[v];
       } else {
-        out = C(1.0 / 3.0) * C(Unb[o]) + C(2.0 / 3.0) * C(Ub[o]) + C((2.0 / 3.0) * dt) * Lv[v];
+        out = C(1.0 / 3.0) * un[v] + C(2.0 / 3.0) * us[v] + C((2.0 / 3.0) * dt) * Lv[v];
       }
       bad = bad || !finite_val(out);
       Ob[o] = S(out);
@@ -764,6 +824,18 @@ hipError_t launch_init_scalars(const GridArgs& a, double t0, double t_end, hipSt
 constexpr int TX2 = SHK_TILE_X, TY2 = SHK_TILE_Y;
 constexpr int TX1 = 256;
 
+template <class S, class C, int MODE, bool CHAR, bool VISC>
+static void launch_2d(const GridArgs& a, const S* Us, const S* Un, S* Uo, const double* dtp, const S* Lin,
+                      hipStream_t st) {
+  dim3 grid((a.nx + TX2 - 1) / TX2, (a.ny + TY2 - 1) / TY2, a.nbatch);
+  if (a.cls != nullptr)
+    hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, VISC, MODE, NET_NONE, CHAR, true>), grid, dim3(256), 0, st,
+                       a, Us, Un, Uo, dtp, Lin, NetArgs{});
+  else
+    hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, VISC, MODE, NET_NONE, CHAR, false>), grid, dim3(256), 0,
+                       st, a, Us, Un, Uo, dtp, Lin, NetArgs{});
+}
+
 template <class S, class C, int MODE, bool CHAR>
 static hipError_t launch_mode_r(const GridArgs& a, const S* Us, const S* Un, S* Uo, const double* dtp,
                                 const S* Lin, hipStream_t st) {
@@ -771,14 +843,10 @@ static hipError_t launch_mode_r(const GridArgs& a, const S* Us, const S* Un, S* 
     dim3 grid((a.nx + TX1 - 1) / TX1, 1, a.nbatch);
     hipLaunchKernelGGL((stage_kernel<S, C, 1, TX1, 1, false, MODE, NET_NONE, CHAR>), grid, dim3(256), 0, st, a,
                        Us, Un, Uo, dtp, Lin, NetArgs{});
+  } else if (a.viscous) {
+    launch_2d<S, C, MODE, CHAR, true>(a, Us, Un, Uo, dtp, Lin, st);
   } else {
-    dim3 grid((a.nx + TX2 - 1) / TX2, (a.ny + TY2 - 1) / TY2, a.nbatch);
-    if (a.viscous)
-      hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, true, MODE, NET_NONE, CHAR>), grid, dim3(256), 0, st,
-                         a, Us, Un, Uo, dtp, Lin, NetArgs{});
-    else
-      hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, false, MODE, NET_NONE, CHAR>), grid, dim3(256), 0, st,
-                         a, Us, Un, Uo, dtp, Lin, NetArgs{});
+    launch_2d<S, C, MODE, CHAR, false>(a, Us, Un, Uo, dtp, Lin, st);
   }
   return hipGetLastError();
 }
@@ -814,8 +882,10 @@ template <int MODE, int NETK>
 static hipError_t launch_net_mode(const GridArgs& a, const NetArgs& n, const double* Us, const double* Un,
                                   double* Uo, const double* dtp, hipStream_t st) {
   dim3 grid((a.nx + TX2 - 1) / TX2, (a.ny + TY2 - 1) / TY2, a.nbatch);
-  hipLaunchKernelGGL((stage_kernel<double, double, 2, TX2, TY2, false, MODE, NETK>), grid, dim3(256), 0, st, a, Us,
-                     Un, Uo, dtp, nullptr, n);
+  // the learned-correction variants always carry the immersed-boundary
+  // handling (their register use is set by the network pass)
+  hipLaunchKernelGGL((stage_kernel<double, double, 2, TX2, TY2, false, MODE, NETK, false, true>), grid, dim3(256),
+                     0, st, a, Us, Un, Uo, dtp, nullptr, n);
   return hipGetLastError();
 }
 

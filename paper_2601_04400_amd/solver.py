@@ -123,7 +123,15 @@ class Grid:
         check(lib().shk_ib_classes(self.handle, _ptr(c)), self.handle, "ib_classes")
         return c
 
+    def ib_fill(self, U):
+        """Refill the immersed-boundary ghost cells of U in place."""
+        self._check_state(U)
+        self._sync_stream()
+        check(lib().shk_ib_fill(self.handle, _ptr(U)), self.handle, "ib_fill")
+        return U
+
     def rhs(self, U, out=None):
+        """L(U) of the semi-discrete scheme; U is not modified."""
         self._check_state(U)
         out = self.empty_state() if out is None else out
         self._sync_stream()
