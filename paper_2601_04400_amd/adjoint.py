@@ -22,7 +22,7 @@ import torch
 
 class _Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, U0, params, grid, nsteps, dt, every, overlap):
+    def forward(ctx, U0, params, grid, nsteps, dt, every, overlap, trace):
         U = U0.detach().clone()
         if not torch.is_tensor(dt):
             dt = torch.full((grid.shape[0],), float(dt), dtype=torch.float64, device=U.device)
@@ -31,7 +31,7 @@ class _Rollout(torch.autograd.Function):
             grid.step(U, dt)
             if (s + 1) % every == 0 and s + 1 < nsteps:
                 ckpts.append(U.clone())
-        ctx.grid, ctx.nsteps, ctx.dt, ctx.every, ctx.overlap = grid, nsteps, dt, every, overlap
+        ctx.grid, ctx.nsteps, ctx.dt, ctx.every, ctx.overlap, ctx.trace = grid, nsteps, dt, every, overlap, trace
         ctx.ckpts = ckpts
         return U
 
@@ -51,11 +51,19 @@ class _Rollout(torch.autograd.Function):
                 g.steps_record(U, tapes, count, dt)
                 g.steps_adjoint_tape(tapes, count, dt, Ub, pb)
         else:
-            _reverse_overlapped(g, ctx.ckpts, nsteps, every, dt, Ub, pb)
-        return Ub, pb, None, None, None, None, None
+            _reverse_overlapped(g, ctx.ckpts, nsteps, every, dt, Ub, pb, ctx.trace)
+        return Ub, pb, None, None, None, None, None, None
 
 
-def _reverse_overlapped(g, ckpts, nsteps, every, dt, Ub, pb):
+def _mark(trace, stream, label):
+    """Timing event on `stream` appended to trace (a list) as (label, event)."""
+    if trace is not None:
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        trace.append((label, e))
+
+
+def _reverse_overlapped(g, ckpts, nsteps, every, dt, Ub, pb, trace=None):
     main = torch.cuda.current_stream(Ub.device)
     rep, side = g.replica()
     tapes, work = g.replay_buffers(min(every, nsteps))
@@ -70,8 +78,10 @@ def _reverse_overlapped(g, ckpts, nsteps, every, dt, Ub, pb):
         if freed[k] is not None:
             side.wait_event(freed[k])
         with torch.cuda.stream(side):
+            _mark(trace, side, f"replay {c} start")
             work.copy_(ckpts[c])
             rep.steps_record(work, tapes[k], min(every, nsteps - c * every), dt)
+            _mark(trace, side, f"replay {c} end")
             ready[c] = torch.cuda.Event()
             ready[c].record(side)
 
@@ -80,17 +90,22 @@ def _reverse_overlapped(g, ckpts, nsteps, every, dt, Ub, pb):
     for c in range(nseg - 1, -1, -1):
         if c > 0:
             replay(c - 1)
+        _mark(trace, main, f"reverse {c} issued")
         main.wait_event(ready.pop(c))
         k = c % 2
+        _mark(trace, main, f"reverse {c} start")
         g.steps_adjoint_tape(tapes[k], min(every, nsteps - c * every), dt, Ub, pb)
+        _mark(trace, main, f"reverse {c} end")
         freed[k] = torch.cuda.Event()
         freed[k].record(main)
 
 
-def rollout(grid, U0, params, nsteps, dt, every=20, overlap=True):
+def rollout(grid, U0, params, nsteps, dt, every=20, overlap=True, trace=None):
     """U after `nsteps` fixed-dt RK3 steps from U0, differentiable with
     respect to U0 and `params` = tensor [nbatch, 5] of (gamma, inflow rho, u,
     v, p).  `params` carries no values into the solver: it must equal the
     grid's own description and only receives the gradient.  overlap: replay
-    segments on a replica grid concurrently with the reverse pass."""
-    return _Rollout.apply(U0, params, grid, nsteps, dt, every, overlap)
+    segments on a replica grid concurrently with the reverse pass.  trace: a
+    list that, in the overlapped backward pass, receives (label, timing
+    event) pairs at the start and end of every replay and reverse segment."""
+    return _Rollout.apply(U0, params, grid, nsteps, dt, every, overlap, trace)
