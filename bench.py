@@ -69,12 +69,16 @@ MEASURED = {
 
 
 def stage_sources_sha256():
+    """SHA-256 of the stage-kernel sources, or None where they are absent."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2601_04400_amd", "csrc")
     for f in STAGE_SOURCES:
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(fh.read())
+        try:
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+        except OSError:
+            return None
     return h.hexdigest()
 
 

@@ -31,6 +31,24 @@ __device__ __forceinline__ float qrcp(float b) { return __builtin_amdgcn_rcpf(b)
 // Square root: IEEE sequence in double, the hardware estimate in float.
 __device__ __forceinline__ double qsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float qsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// 1/sqrt(x) for finite x > 0.  double: the hardware estimate refined by two
+// Newton steps y <- y + y (1 - x y^2) / 2 (each squares the relative error),
+// which leaves a few units in the last place; float: the hardware estimate.
+__device__ __forceinline__ double qrsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-(x * y), y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-(x * y), y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+__device__ __forceinline__ float qrsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+// Speed of sound sqrt(gamma p / rho), formed as gamma p / sqrt(gamma p rho):
+// one reciprocal square root instead of a quotient and a square root.
+template <class C>
+__device__ __forceinline__ C sound_speed(C gamma, C p, C rho) {
+  const C gp = gamma * p;
+  return gp * qrsqrt(gp * rho);
+}
 
 template <class C>
 struct Prim {
@@ -85,6 +103,58 @@ __device__ __forceinline__ void weno5_pair(C a, C b, C c, C d, C e, C f, C eps, 
   right = qdiv(v0 * r0 + v1 * qp + v2 * qm, C(6) * (v0 + v1 + v2));
 }
 
+// WENO5-JS states of three consecutive faces from the eight cells c0..c7 (the
+// stride st apart from f): face k (k = 0, 1, 2) lies between cells k+2 and
+// k+3, its left state comes from cells k..k+4 and its right state from the
+// mirrored k+5..k+1 -- as weno5_pair on cells k..k+5.  The indicators of a
+// face's right state are those of the next face's left state (the same three
+// triples of cells, with the ideal weights in reverse order), so three faces
+// need four indicator sets instead of six, and the six triples' curvature
+// terms are formed once.  Set j (cells j..j+4) holds the products P0 = G1
+// G2, P1 = G0 G2, P2 = G0 G1 of G_m = (eps + beta_m)^2 of the triples starting
+// at j, j+1, j+2 (Jiang-Shu indicators in the left-state orientation); the
+// left state of face j has the weights (0.1 P0, 0.6 P1, 0.3 P2) on the
+// candidates (q0, q1, q2) of cells j..j+4, and the right state of face j-1
+// the weights (0.1 P2, 0.6 P1, 0.3 P0) on its candidates (r0, q2, q1).
+template <class C>
+__device__ __forceinline__ void weno5_triple(const C* f, int st, C eps, C L[3], C R[3]) {
+  const C k13 = C(13) / C(12);
+  C c[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) c[m] = f[m * st];
+  C kc[6];  // 13/12 (curvature)^2 of the triple starting at cell t
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    const C sc = c[t] - C(2) * c[t + 1] + c[t + 2];
+    kc[t] = k13 * sc * sc;
+  }
+  C P[4][3];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const C t0 = c[j] - C(4) * c[j + 1] + C(3) * c[j + 2];
+    const C t1 = c[j + 1] - c[j + 3];
+    const C t2 = C(3) * c[j + 2] - C(4) * c[j + 3] + c[j + 4];
+    C g0 = eps + (kc[j] + C(0.25) * t0 * t0);
+    C g1 = eps + (kc[j + 1] + C(0.25) * t1 * t1);
+    C g2 = eps + (kc[j + 2] + C(0.25) * t2 * t2);
+    g0 = g0 * g0; g1 = g1 * g1; g2 = g2 * g2;
+    P[j][0] = g1 * g2;
+    P[j][1] = g0 * g2;
+    P[j][2] = g0 * g1;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const C q0 = C(2) * c[k] - C(7) * c[k + 1] + C(11) * c[k + 2];
+    const C q1 = C(5) * c[k + 2] - c[k + 1] + C(2) * c[k + 3];
+    const C q2 = C(2) * c[k + 2] + C(5) * c[k + 3] - c[k + 4];
+    const C r0 = C(2) * c[k + 5] - C(7) * c[k + 4] + C(11) * c[k + 3];
+    const C w0 = C(0.1) * P[k][0], w1 = C(0.6) * P[k][1], w2 = C(0.3) * P[k][2];
+    const C v0 = C(0.1) * P[k + 1][2], v1 = C(0.6) * P[k + 1][1], v2 = C(0.3) * P[k + 1][0];
+    L[k] = qdiv(w0 * q0 + w1 * q1 + w2 * q2, C(6) * (w0 + w1 + w2));
+    R[k] = qdiv(v0 * r0 + v1 * q2 + v2 * q1, C(6) * (v0 + v1 + v2));
+  }
+}
+
 // HLLC flux (section 2) in the face-normal frame, components
 // (mass, normal momentum, tangential momentum, energy).
 //   wave speeds (Davis): sL = min(uL-aL, uR-aR), sR = max(uL+aL, uR+aR)
@@ -100,7 +170,10 @@ struct Flux4 {
 
 // One bracket, evaluated without branches: the star correction is always
 // formed and selected away on a supersonic side (its value there is never
-// used, whatever it is), so lanes of a wavefront never diverge here.
+// used, whatever it is), so lanes of a wavefront never diverge here.  With
+// su = s - u and chi = su / (s - s*), the star energy chi (E + (s* - u)(rho s*
+// + p / su)) is (su (E + (s* - u) rho s*) + (s* - u) p) / (s - s*): su
+// cancels, so one reciprocal serves the whole bracket.
 template <class C>
 __device__ __forceinline__ Flux4<C> hllc_side(const Prim<C>& w, C E, C s, C ss, bool supersonic) {
   // physical flux of this side
@@ -111,12 +184,14 @@ __device__ __forceinline__ Flux4<C> hllc_side(const Prim<C>& w, C E, C s, C ss, 
   F.f2 = mn * w.ut;
   F.f3 = w.un * (E + w.p);
   C su = s - w.un;
-  C chi = qdiv(su, s - ss);
+  C id = qrcp(s - ss);
+  C chi = su * id;
   C rs = chi * w.r;
   C d0 = rs - w.r;
   C d1 = rs * ss - mn;
-  C d2 = rs * w.ut - w.r * w.ut;
-  C d3 = chi * (E + (ss - w.un) * (w.r * ss + qdiv(w.p, su))) - E;
+  C d2 = d0 * w.ut;
+  C du = ss - w.un;
+  C d3 = (su * (E + du * (w.r * ss)) + du * w.p) * id - E;
   Flux4<C> G;
   G.f0 = supersonic ? F.f0 : F.f0 + s * d0;
   G.f1 = supersonic ? F.f1 : F.f1 + s * d1;
@@ -126,28 +201,31 @@ __device__ __forceinline__ Flux4<C> hllc_side(const Prim<C>& w, C E, C s, C ss, 
 }
 
 template <class C>
+__device__ __forceinline__ C total_energy(const Prim<C>& w, C igm1) {
+  return w.p * igm1 + C(0.5) * w.r * (w.un * w.un + w.ut * w.ut);
+}
+
+template <class C>
 __device__ __forceinline__ Flux4<C> hllc(const Prim<C>& L, const Prim<C>& R, C gamma, C igm1) {
-  C aL = qsqrt(qdiv(gamma * L.p, L.r));
-  C aR = qsqrt(qdiv(gamma * R.p, R.r));
+  C aL = sound_speed(gamma, L.p, L.r);
+  C aR = sound_speed(gamma, R.p, R.r);
   C sL = fmin(L.un - aL, R.un - aR);
   C sR = fmax(L.un + aL, R.un + aR);
   C dL = sL - L.un, dR = sR - R.un;
   C ss = qdiv(R.p - L.p + L.r * L.un * dL - R.r * R.un * dR, L.r * dL - R.r * dR);
-  C EL = L.p * igm1 + C(0.5) * L.r * (L.un * L.un + L.ut * L.ut);
-  C ER = R.p * igm1 + C(0.5) * R.r * (R.un * R.un + R.ut * R.ut);
   if (ss == C(0)) {
     // contact exactly at rest: the mean of the two brackets (rare)
-    Flux4<C> A = hllc_side(L, EL, sL, ss, sL >= C(0));
-    Flux4<C> B = hllc_side(R, ER, sR, ss, sR <= C(0));
+    Flux4<C> A = hllc_side(L, total_energy(L, igm1), sL, ss, sL >= C(0));
+    Flux4<C> B = hllc_side(R, total_energy(R, igm1), sR, ss, sR <= C(0));
     return Flux4<C>{C(0.5) * (A.f0 + B.f0), C(0.5) * (A.f1 + B.f1), C(0.5) * (A.f2 + B.f2),
                     C(0.5) * (A.f3 + B.f3)};
   }
   // s* > 0: left bracket; s* < 0 (or not a number): right bracket.  The side
-  // is chosen first so only one bracket is evaluated per face.
+  // is chosen first so only one bracket (and one energy) is evaluated per face.
   const bool left = ss > C(0);
   const Prim<C> W{left ? L.r : R.r, left ? L.un : R.un, left ? L.ut : R.ut, left ? L.p : R.p};
   const C s = left ? sL : sR;
-  return hllc_side(W, left ? EL : ER, s, ss, left ? sL >= C(0) : sR <= C(0));
+  return hllc_side(W, total_energy(W, igm1), s, ss, left ? sL >= C(0) : sR <= C(0));
 }
 
 }  // namespace shk

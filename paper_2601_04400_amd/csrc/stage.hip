@@ -58,12 +58,16 @@ __device__ __forceinline__ void ghost_at(const GridArgs& a, long long c, Get&& g
 // get(e, c) returns plane e of interior cell c.  An immersed-boundary ghost
 // cell takes its refilled value, formed here from the fluid cells of the
 // same state (they are complete when the stage starts).
+// inside: (gi, gj) is known to be an interior cell (no boundary rule).
 template <class S, class C, int NDIM, bool GH, class Get>
-__device__ __forceinline__ void load_cons_f(const GridArgs& a, int gi, int gj, Get&& get, C q[4]) {
+__device__ __forceinline__ void load_cons_f(const GridArgs& a, int gi, int gj, Get&& get, C q[4],
+                                            bool inside = false) {
   int fx = 0, fy = 0;
-  const int si = bc_source(gi, a.nx, a.bc[0], a.bc[1], fx);
-  int sj = 0;
-  if (NDIM == 2) sj = bc_source(gj, a.ny, a.bc[2], a.bc[3], fy);
+  int si = gi, sj = NDIM == 2 ? gj : 0;
+  if (!inside) {
+    si = bc_source(gi, a.nx, a.bc[0], a.bc[1], fx);
+    if (NDIM == 2) sj = bc_source(gj, a.ny, a.bc[2], a.bc[3], fy);
+  }
   // scalars, not the array, along the branches (an array written on some
   // paths only is kept in scratch memory)
   C r, mx, my, E;
@@ -96,8 +100,9 @@ __device__ __forceinline__ void load_cons_f(const GridArgs& a, int gi, int gj, G
 }
 
 template <class S, class C, int NDIM, bool GH>
-__device__ __forceinline__ void load_cons(const GridArgs& a, const S* U, int gi, int gj, C q[4]) {
-  load_cons_f<S, C, NDIM, GH>(a, gi, gj, [&](int e, long long c) { return C(U[e * a.ncell + c]); }, q);
+__device__ __forceinline__ void load_cons(const GridArgs& a, const S* U, int gi, int gj, C q[4],
+                                          bool inside = false) {
+  load_cons_f<S, C, NDIM, GH>(a, gi, gj, [&](int e, long long c) { return C(U[e * a.ncell + c]); }, q, inside);
 }
 
 // Automatic step from the reduced maxima of a batch member (dt = cfl / max
@@ -334,7 +339,9 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* Us, con
 
   if (MLP) load_net_lds(net, net_w, net_b);
 
-  // 1. halo tile of primitives
+  // 1. halo tile of primitives; a tile whose halo lies inside the domain
+  // (the same for the whole workgroup) skips the boundary rules
+  const bool inside = i0 >= H && i0 + TX + H <= a.nx && (NDIM == 1 || (j0 >= H && j0 + TY + H <= a.ny));
   for (int k = threadIdx.x; k < PY * PX; k += NT) {
     const int lx = k % PX, ly = k / PX;
     const bool inx = lx >= H && lx < TX + H;
@@ -344,9 +351,9 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* Us, con
     const int gj = NDIM == 2 ? j0 + ly - H : 0;
     C q[4];
     if (MODE == MODE_S2F)
-      load_cons_f<S, C, NDIM, GH>(a, gi, gj, u1_at, q);
+      load_cons_f<S, C, NDIM, GH>(a, gi, gj, u1_at, q, inside);
     else
-      load_cons<S, C, NDIM, GH>(a, Ub, gi, gj, q);
+      load_cons<S, C, NDIM, GH>(a, Ub, gi, gj, q, inside);
     Prim<C> p = to_prim(q[0], q[1], q[2], q[3], gm1);
     w[0][k] = p.r;
     w[1][k] = p.un;
@@ -435,51 +442,25 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* Us, con
   const C igm1 = C(1.0 / (a.gamma - 1.0));
   unsigned int my_fallback = 0;
   bool net_bad = false;
-  for (int k = threadIdx.x; k < NFX + NFY; k += NT) {
-    const bool isx = k < NFX;
-    int s0, st, cn, ct, oidx;
+  // Everything after the reconstruction for the face whose stencil starts at
+  // LDS cell s0 (stride st; cn, ct: normal and tangential velocity arrays):
+  // position fi along the normal and line (row of an x-face, column of a
+  // y-face) in the tile; L, R its reconstructed states.
+  auto face_flux = [&](bool isx, int s0, int st, int cn, int ct, int fi, int line, Prim<C> L, Prim<C> R) {
+    int oidx;
     bool owned;  // this tile is the one that reports the face (fallback count)
     long long gface = -1;  // NET_EXT: the face's index, -1 outside the domain
     if (isx) {
-      const int fi = k % (TX + 1), y = k / (TX + 1);
-      s0 = (NDIM == 2 ? (y + H) * PX : 0) + fi;
-      st = 1; cn = 1; ct = 2;
-      oidx = y * (TX + 1) + fi;
+      oidx = line * (TX + 1) + fi;
       const int gf = i0 + fi;
-      owned = j0 + y < a.ny && gf <= a.nx && (fi < TX || gf == a.nx);
-      if (NET == NET_EXT && j0 + y < a.ny && gf <= a.nx) gface = (long long)(j0 + y) * (a.nx + 1) + gf;
+      owned = j0 + line < a.ny && gf <= a.nx && (fi < TX || gf == a.nx);
+      if (NET == NET_EXT && j0 + line < a.ny && gf <= a.nx) gface = (long long)(j0 + line) * (a.nx + 1) + gf;
     } else {
-      const int kk = k - NFX;
-      const int x = kk % TX, fj = kk / TX;
-      s0 = fj * PX + x + H;
-      st = PX; cn = 2; ct = 1;
-      oidx = fj * TX + x;
-      const int gf = j0 + fj;
-      owned = i0 + x < a.nx && gf <= a.ny && (fj < TY || gf == a.ny);
-      if (NET == NET_EXT && i0 + x < a.nx && gf <= a.ny)
-        gface = (long long)(a.nx + 1) * a.ny + (long long)gf * a.nx + i0 + x;
-    }
-    Prim<C> L, R;
-    if constexpr (CHAR) {
-      static_assert(sizeof(C) == 8, "characteristic reconstruction: FP64 tiles");
-      char_face_states(w[0] + s0, w[cn] + s0, w[ct] + s0, w[3] + s0, st, a.eps, a.gamma, L, R);
-    } else {
-      {
-        const C* f = w[0] + s0;
-        weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.r, R.r);
-      }
-      {
-        const C* f = w[cn] + s0;
-        weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.un, R.un);
-      }
-      {
-        const C* f = w[ct] + s0;
-        weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.ut, R.ut);
-      }
-      {
-        const C* f = w[3] + s0;
-        weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.p, R.p);
-      }
+      oidx = fi * TX + line;
+      const int gf = j0 + fi;
+      owned = i0 + line < a.nx && gf <= a.ny && (fi < TY || gf == a.ny);
+      if (NET == NET_EXT && i0 + line < a.nx && gf <= a.ny)
+        gface = (long long)(a.nx + 1) * a.ny + (long long)gf * a.nx + i0 + line;
     }
     if (!(L.r > C(0)) || !(L.p > C(0)) || !(R.r > C(0)) || !(R.p > C(0))) {
       // positivity fallback: first-order states from the two adjacent cells
@@ -540,6 +521,87 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* Us, con
       fxs[0][oidx] = F.f0; fxs[1][oidx] = F.f1; fxs[2][oidx] = F.f2; fxs[3][oidx] = F.f3;
     } else {
       fys[0][oidx] = F.f0; fys[1][oidx] = F.f2; fys[2][oidx] = F.f1; fys[3][oidx] = F.f3;
+    }
+  };
+  if constexpr (NDIM == 2 && !CHAR && sizeof(C) == 4) {
+    // FP32 arithmetic: three consecutive faces per thread along a row
+    // (x-faces) or a column (y-faces), sharing indicator sets and curvature
+    // terms (weno5_triple): TX + 1 and TY + 1 are multiples of 3, so the
+    // tile's faces split into NTX + NTY triples, one round of the workgroup.
+    // Lanes of a y-triple wave take neighbouring columns (consecutive LDS
+    // words).  In FP64 the 24 face values held through three flux
+    // evaluations need about 165 registers, which costs a quarter of the
+    // resident waves and more time than the shared work saves; FP64 tiles
+    // take one face per thread.
+    static_assert((TX + 1) % 3 == 0 && (TY + 1) % 3 == 0, "face triples need TX + 1 and TY + 1 divisible by 3");
+    constexpr int TPR = (TX + 1) / 3;  // triples per row of x-faces
+    constexpr int NTX = TPR * TY, NTY = (TY + 1) / 3 * TX;
+    static_assert(NTX + NTY <= NT, "one round of face triples");
+    const int t = threadIdx.x;
+    if (t < NTX + NTY) {
+      const bool isx = t < NTX;
+      int s0, st, cn, ct, fa, line;
+      if (isx) {
+        line = t / TPR;
+        fa = 3 * (t - line * TPR);
+        s0 = (line + H) * PX + fa;
+        st = 1; cn = 1; ct = 2;
+      } else {
+        const int u = t - NTX;
+        fa = 3 * (u / TX);
+        line = u - (fa / 3) * TX;
+        s0 = fa * PX + line + H;
+        st = PX; cn = 2; ct = 1;
+      }
+      C lr[3], rr[3], lu[3], ru[3], lt[3], rt[3], lp[3], rp[3];
+      weno5_triple(w[0] + s0, st, eps, lr, rr);
+      weno5_triple(w[cn] + s0, st, eps, lu, ru);
+      weno5_triple(w[ct] + s0, st, eps, lt, rt);
+      weno5_triple(w[3] + s0, st, eps, lp, rp);
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        face_flux(isx, s0 + q * st, st, cn, ct, fa + q, line, Prim<C>{lr[q], lu[q], lt[q], lp[q]},
+                  Prim<C>{rr[q], ru[q], rt[q], rp[q]});
+    }
+  } else {
+    for (int k = threadIdx.x; k < NFX + NFY; k += NT) {
+      const bool isx = k < NFX;
+      int s0, st, cn, ct, fi, line;
+      if (isx) {
+        fi = k % (TX + 1);
+        line = k / (TX + 1);
+        s0 = (NDIM == 2 ? (line + H) * PX : 0) + fi;
+        st = 1; cn = 1; ct = 2;
+      } else {
+        const int kk = k - NFX;
+        line = kk % TX;
+        fi = kk / TX;
+        s0 = fi * PX + line + H;
+        st = PX; cn = 2; ct = 1;
+      }
+      Prim<C> L, R;
+      if constexpr (CHAR) {
+        static_assert(sizeof(C) == 8, "characteristic reconstruction: FP64 tiles");
+        char_face_states(w[0] + s0, w[cn] + s0, w[ct] + s0, w[3] + s0, st, a.eps, a.gamma, L, R);
+      } else {
+        {
+          const C* f = w[0] + s0;
+          weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.r, R.r);
+        }
+        {
+          const C* f = w[cn] + s0;
+          weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.un, R.un);
+        }
+        {
+          const C* f = w[ct] + s0;
+          weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.ut, R.ut);
+        }
+        {
+          const C* f = w[3] + s0;
+          weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.p, R.p);
+        }
+      }
+      face_flux(isx, s0, st, cn, ct, fi, line, L, R);
     }
   }
   if (my_fallback) atomicAdd(&blk_fallback, my_fallback);
