@@ -52,7 +52,14 @@ def lib():
         _lib.orc_cnn_backward.argtypes = [_p, _i, _i, _i, _i, _p, _p, _p, _p]
         _lib.orc_cnn_images.argtypes = [_p, _p, _p, _i, _p, _p, _p]
         _lib.orc_char_basis.argtypes = [_d, _p, _p, _p, _p]
+        _lib.orc_threads.argtypes = [_i]
+        _lib.orc_threads.restype = _i
     return _lib
+
+
+def threads(n=0):
+    """Set (n >= 1) and return the oracle's OpenMP thread count."""
+    return lib().orc_threads(int(n))
 
 
 def config(ndim=2, nx=64, ny=64, x0=0.0, x1=1.0, y0=0.0, y1=1.0, gamma=1.4, cfl=0.5,

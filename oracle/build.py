@@ -2,6 +2,8 @@
 
 The oracle is compiled with strict IEEE semantics: no fast-math and no
 floating-point contraction, so every sum and product is rounded as written.
+Its row loops are shared over OpenMP threads; every value is computed as in
+a serial run, so the results do not depend on the thread count.
 """
 import os
 import subprocess
@@ -10,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SOURCES = ["capi.cpp"]
 HEADERS = ["solver.hpp", "dual.hpp", "exact_riemann.hpp", "mlp.hpp", "cnn.hpp", "correction.hpp", "training.hpp"]
-FLAGS = ["-std=c++17", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-Wall"]
+FLAGS = ["-std=c++17", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-Wall"]
 
 
 def build(verbose=False):

@@ -1,6 +1,7 @@
 // Oracle C entry points (TEST INFRASTRUCTURE ONLY): thin extern "C" wrappers
 // over the templated serial solver so the Python test suite can call it
 // through ctypes.  Nothing here is used by the GPU library.
+#include <omp.h>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -47,6 +48,13 @@ void run_rhs(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f, Fi
 extern "C" {
 
 int orc_abi_version() { return 1; }
+
+// Threads of the oracle's OpenMP loops (n >= 1 sets it; 0 only reads it).
+// Results do not depend on it: every value is computed as in a serial run.
+int orc_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+}
 
 // Primitive planes (1D: rho,u,p; 2D: rho,u,v,p) -> conservative planes.
 int orc_prim_to_cons(const Config* c, const double* W, double* U) {

@@ -447,7 +447,10 @@ inline Ibm build_ibm(const Config& c, const double* phi, int wall) {
 template <class T>
 void ibm_fill(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f) {
   if (!ib.active) return;
-  for (const auto& g : ib.ghosts) {
+  // each ghost reads fluid cells only, so the ghosts are independent
+#pragma omp parallel for schedule(static)
+  for (size_t gk = 0; gk < ib.ghosts.size(); ++gk) {
+    const auto& g = ib.ghosts[gk];
     T Wi[4] = {T(0.0), T(0.0), T(0.0), T(0.0)};
     for (int k = 0; k < 4; ++k) {
       if (g.src[k] < 0) continue;
@@ -565,6 +568,12 @@ void rhs(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f, Field<
   // primitives everywhere (interior and ghost layers)
   Field<T> w(nx, ny);
   const int jlo = c.ndim == 2 ? -NG : 0, jhi = c.ndim == 2 ? ny + NG : ny;
+  // Rows are independent: with OpenMP the loops below are shared out over
+  // threads (each value is computed exactly as in a serial run; the learned
+  // corrections stay serial).
+  const bool par = !net && !cnn;
+  long fbl = 0;  // positivity fallbacks of this call
+#pragma omp parallel for schedule(static)
   for (int j = jlo; j < jhi; ++j)
     for (int i = -NG; i < nx + NG; ++i) {
       T U[4] = {f.at(0, i, j), f.at(1, i, j), f.at(2, i, j), f.at(3, i, j)};
@@ -589,12 +598,13 @@ void rhs(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f, Field<
     prim_to_cons(WR, P.gamma, UR);
     for (int v = 0; v < 4; ++v) x[v] = cnn_norm(cnn, v, T(0.5) * (UL[v] + UR[v]));
   };
+#pragma omp parallel for schedule(static) if (par) reduction(+ : fbl)
   for (int j = 0; j < ny; ++j)
     for (int fi = 0; fi <= nx; ++fi) {
       T st[6][4];
       for (int s = 0; s < 6; ++s) Wat(fi - 3 + s, j, st[s]);
       T F[4], WL[4], WR[4];
-      face_flux(c, P, st, net, F, fallback_count, WL, WR);
+      face_flux(c, P, st, net, F, &fbl, WL, WR);
       if (cnn && fi < wx) cnn_input(WL, WR, &Xx[(size_t(j) * wx + fi) * 4]);
       if (c.viscous) {
         T a[4], b[4], ap[4], am[4], bp[4], bm[4], Fv[4];
@@ -610,6 +620,7 @@ void rhs(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f, Field<
   if (c.ndim == 2) {
     Fy.resize(size_t(4) * nx * (ny + 1));
     if (cnn) Xy.resize(size_t(4) * nx * wy);
+#pragma omp parallel for schedule(static) if (par) reduction(+ : fbl)
     for (int fj = 0; fj <= ny; ++fj)
       for (int i = 0; i < nx; ++i) {
         T st[6][4];
@@ -619,7 +630,7 @@ void rhs(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f, Field<
           st[s][0] = W[0]; st[s][1] = W[2]; st[s][2] = W[1]; st[s][3] = W[3];
         }
         T G[4], WL[4], WR[4];
-        face_flux(c, P, st, net, G, fallback_count, WL, WR);
+        face_flux(c, P, st, net, G, &fbl, WL, WR);
         if (cnn && fj < wy) cnn_input(WL, WR, &Xy[(size_t(i) * wy + fj) * 4]);  // transposed image
         if (c.viscous) {
           T a[4], b[4], ap[4], am[4], bp[4], bm[4], Fv[4], t[4];
@@ -634,6 +645,7 @@ void rhs(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f, Field<
         for (int v = 0; v < 4; ++v) Fy[(size_t(v) * (ny + 1) + fj) * nx + i] = Gs[v];
       }
   }
+  if (fallback_count) *fallback_count += fbl;
   if (cnn && images) {  // the network's input images (x-faces, transposed y-faces)
     images[0] = Xx;
     images[1] = Xy;
@@ -659,6 +671,7 @@ void rhs(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& f, Field<
           }
     }
   }
+#pragma omp parallel for collapse(2) schedule(static)
   for (int v = 0; v < 4; ++v)
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
@@ -687,12 +700,14 @@ void rk3_step(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& un, 
   Field<T> L(c.nx, c.ny), u1(c.nx, c.ny), u2(c.nx, c.ny);
   ibm_fill(c, P, ib, un);
   rhs(c, P, ib, un, L, net, fb);
+#pragma omp parallel for collapse(2) schedule(static)
   for (int v = 0; v < 4; ++v)
     for (int j = 0; j < c.ny; ++j)
       for (int i = 0; i < c.nx; ++i) u1.at(v, i, j) = un.at(v, i, j) + dt * L.at(v, i, j);
   ibm_fill(c, P, ib, u1);
   rhs(c, P, ib, u1, L, net, fb);
   const T dt2 = 0.25 * dt;
+#pragma omp parallel for collapse(2) schedule(static)
   for (int v = 0; v < 4; ++v)
     for (int j = 0; j < c.ny; ++j)
       for (int i = 0; i < c.nx; ++i)
@@ -700,6 +715,7 @@ void rk3_step(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& un, 
   ibm_fill(c, P, ib, u2);
   rhs(c, P, ib, u2, L, net, fb);
   const T dt3 = (2.0 / 3.0) * dt;
+#pragma omp parallel for collapse(2) schedule(static)
   for (int v = 0; v < 4; ++v)
     for (int j = 0; j < c.ny; ++j)
       for (int i = 0; i < c.nx; ++i)
@@ -713,6 +729,8 @@ void rk3_step(const Config& c, const Params<T>& P, const Ibm& ib, Field<T>& un, 
 inline double cfl_dt(const Config& c, const Ibm& ib, const Field<double>& f) {
   const double dx = dx_of(c), dy = dy_of(c);
   double smax = 0.0, rmin = 1e300;
+  // max and min are exact, so the reduction order does not matter
+#pragma omp parallel for schedule(static) reduction(max : smax) reduction(min : rmin)
   for (int j = 0; j < c.ny; ++j)
     for (int i = 0; i < c.nx; ++i) {
       if (ib.active && ib.cls[size_t(j) * c.nx + i] != FLUID) continue;
