@@ -135,6 +135,7 @@ def cpu_baseline(nx, ny, budget_s):
     """The oracle (serial FP64 C++), timed on a bounded number of RK3 steps of
     the same problem from the same initial state."""
     import oracle
+    oracle.threads(1)  # the serial oracle
     from paper_2601_04400_amd import inputs
     c = oracle.config(nx=nx, ny=ny)
     U = oracle.prim_to_cons(c, inputs.riemann2d_prim(nx, ny))
@@ -337,6 +338,7 @@ def cylinder_cpu_baseline(budget_s):
     planar shock placed at x = 0.25, inside the cylinder's leading part), for
     about budget_s seconds of automatic steps."""
     import oracle
+    oracle.threads(1)  # the serial oracle
     nx, ny = CYL_NX, CYL_NY
     sc, inflow, mu = cylinder_problem(xs=0.25)
     c = oracle.config(nx=nx, ny=ny, x0=0.0, x1=2.0, y0=0.0, y1=1.0, viscous=1, mu=mu, prandtl=0.72, bc=sc["bc"],
@@ -440,6 +442,7 @@ def learned_costs(iters=400):
 def sod_cpu_baseline():
     """The oracle on the whole Sod run (200 cells to t = 0.2)."""
     import oracle
+    oracle.threads(1)  # the serial oracle
     from paper_2601_04400_amd import inputs
     c = oracle.config(ndim=1, nx=200)
     U = oracle.prim_to_cons(c, inputs.sod_prim(200))

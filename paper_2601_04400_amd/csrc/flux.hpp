@@ -68,14 +68,30 @@ __device__ __forceinline__ Prim<C> to_prim(C rho, C mn, C mt, C E, C gm1) {
   return w;
 }
 
+// Unnormalised nonlinear weights of a stencil set from G_m = (eps + beta_m)^2:
+// the product form (G1 G2, G0 G2, G0 G1) in double, which needs no division
+// (every weight is d_m/G_m times the same factor G0 G1 G2); the reciprocals
+// (1/G0, 1/G1, 1/G2) in float, where the products, of the order of the
+// eighth power of the jump across the stencil, would overflow for jumps
+// above about 1e4 (a float reciprocal is one instruction).
+__device__ __forceinline__ void weno_products(double g0, double g1, double g2, double P[3]) {
+  P[0] = g1 * g2;
+  P[1] = g0 * g2;
+  P[2] = g0 * g1;
+}
+__device__ __forceinline__ void weno_products(float g0, float g1, float g2, float P[3]) {
+  P[0] = qrcp(g0);
+  P[1] = qrcp(g1);
+  P[2] = qrcp(g2);
+}
+
 // Both WENO5-JS values at the face between c and d of the six cells
 // a b c d e f (Jiang-Shu indicators, ideal weights 1/10, 6/10, 3/10, eps):
 // the left-biased one from a..e and the right-biased one from the mirrored
 // stencil f..b.  The two share the curvature terms of the triples (b,c,d)
 // and (c,d,e) and two of the six candidate polynomials, which are formed
-// once.  The nonlinear weights d_k/(eps+beta_k)^2 are normalised by
-// multiplying through with the product of the three squared denominators,
-// which leaves a single division per value.
+// once.  The nonlinear weights d_k/(eps+beta_k)^2 are normalised as
+// weno_products describes, which leaves a single division per value.
 template <class C>
 __device__ __forceinline__ void weno5_pair(C a, C b, C c, C d, C e, C f, C eps, C& left, C& right) {
   const C k13 = C(13) / C(12);
@@ -97,8 +113,11 @@ __device__ __forceinline__ void weno5_pair(C a, C b, C c, C d, C e, C f, C eps, 
   const C r0 = C(2) * f - C(7) * e + C(11) * d;
   g0 = g0 * g0; g1 = g1 * g1; g2 = g2 * g2;
   h0 = h0 * h0; h1 = h1 * h1; h2 = h2 * h2;
-  const C w0 = C(0.1) * (g1 * g2), w1 = C(0.6) * (g0 * g2), w2 = C(0.3) * (g0 * g1);
-  const C v0 = C(0.1) * (h1 * h2), v1 = C(0.6) * (h0 * h2), v2 = C(0.3) * (h0 * h1);
+  C Pg[3], Ph[3];
+  weno_products(g0, g1, g2, Pg);
+  weno_products(h0, h1, h2, Ph);
+  const C w0 = C(0.1) * Pg[0], w1 = C(0.6) * Pg[1], w2 = C(0.3) * Pg[2];
+  const C v0 = C(0.1) * Ph[0], v1 = C(0.6) * Ph[1], v2 = C(0.3) * Ph[2];
   left = qdiv(w0 * q0 + w1 * qm + w2 * qp, C(6) * (w0 + w1 + w2));
   right = qdiv(v0 * r0 + v1 * qp + v2 * qm, C(6) * (v0 + v1 + v2));
 }
@@ -110,10 +129,11 @@ __device__ __forceinline__ void weno5_pair(C a, C b, C c, C d, C e, C f, C eps, 
 // face's right state are those of the next face's left state (the same three
 // triples of cells, with the ideal weights in reverse order), so three faces
 // need four indicator sets instead of six, and the six triples' curvature
-// terms are formed once.  Set j (cells j..j+4) holds the products P0 = G1
-// G2, P1 = G0 G2, P2 = G0 G1 of G_m = (eps + beta_m)^2 of the triples starting
-// at j, j+1, j+2 (Jiang-Shu indicators in the left-state orientation); the
-// left state of face j has the weights (0.1 P0, 0.6 P1, 0.3 P2) on the
+// terms are formed once.  Set j (cells j..j+4) holds the weight factors
+// P0, P1, P2 (proportional to 1/G0, 1/G1, 1/G2; weno_products) of G_m =
+// (eps + beta_m)^2 of the triples starting at j, j+1, j+2 (Jiang-Shu
+// indicators in the left-state orientation); the left state of face j has
+// the weights (0.1 P0, 0.6 P1, 0.3 P2) on the
 // candidates (q0, q1, q2) of cells j..j+4, and the right state of face j-1
 // the weights (0.1 P2, 0.6 P1, 0.3 P0) on its candidates (r0, q2, q1).
 template <class C>
@@ -138,9 +158,7 @@ __device__ __forceinline__ void weno5_triple(const C* f, int st, C eps, C L[3], 
     C g1 = eps + (kc[j + 1] + C(0.25) * t1 * t1);
     C g2 = eps + (kc[j + 2] + C(0.25) * t2 * t2);
     g0 = g0 * g0; g1 = g1 * g1; g2 = g2 * g2;
-    P[j][0] = g1 * g2;
-    P[j][1] = g0 * g2;
-    P[j][2] = g0 * g1;
+    weno_products(g0, g1, g2, P[j]);
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {

@@ -342,6 +342,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* Us, con
   // 1. halo tile of primitives; a tile whose halo lies inside the domain
   // (the same for the whole workgroup) skips the boundary rules
   const bool inside = i0 >= H && i0 + TX + H <= a.nx && (NDIM == 1 || (j0 >= H && j0 + TY + H <= a.ny));
+  bool nonphys = false;  // a loaded cell with rho <= 0 or p <= 0 (or not a number)
   for (int k = threadIdx.x; k < PY * PX; k += NT) {
     const int lx = k % PX, ly = k / PX;
     const bool inx = lx >= H && lx < TX + H;
@@ -355,6 +356,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* Us, con
     else
       load_cons<S, C, NDIM, GH>(a, Ub, gi, gj, q, inside);
     Prim<C> p = to_prim(q[0], q[1], q[2], q[3], gm1);
+    nonphys = nonphys || !(p.r > C(0)) || !(p.p > C(0));
     w[0][k] = p.r;
     w[1][k] = p.un;
     w[2][k] = p.ut;
@@ -722,6 +724,7 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* Us, con
     if ((threadIdx.x & 63) == 0) { red_s[threadIdx.x >> 6] = smax; red_r[threadIdx.x >> 6] = rmin; }
   }
   if (bad) atomicOr(&blk_fault, 1u);
+  if (nonphys) atomicOr(&blk_fault, 4u);
   __syncthreads();
   if (threadIdx.x == 0) {
     if (MODE == MODE_S1L) {

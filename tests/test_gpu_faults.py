@@ -1,0 +1,79 @@
+"""Failure handling, forced from the host (no kernel is made to fault).
+
+  - The learned correction's fallback: a NaN written into one output-layer
+    weight of the per-face network or of the convolutional network (host
+    parameters, packed on the device as usual) makes every face's network
+    output non-finite; each face must then take the uncorrected flux, so the
+    corrected right-hand side and step equal the plain oracle's to 1e-13, and
+    the network fault bit is set.
+  - The non-physical-cell flag: a cell whose energy is below its kinetic
+    energy (p < 0) sets SHK_FAULT_NONPHYS; a valid state sets no flag.
+"""
+import numpy as np
+import pytest
+
+from paper_2601_04400_amd import inputs
+from gpu_util import assert_fields
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+FAULT_NONFINITE, FAULT_FALLBACK, FAULT_NONPHYS, FAULT_NET = 1, 2, 4, 8
+
+
+def to_np(U):
+    torch.cuda.synchronize()
+    return U.detach().to("cpu", torch.float64).numpy()
+
+
+def _nan_net(kind):
+    import paper_2601_04400_amd.learn as L
+    if kind == "mlp":
+        theta = L.init_theta(3)
+        theta[9920] = np.nan  # W3[0][0]: the first output's weight on hidden neuron 0
+        return L.FluxNet(theta), 1
+    theta = L.init_cnn_theta(3)
+    theta[L.CNN_NP - 4 - 1152] = np.nan  # W3[0][0][0][0] of the output layer
+    return L.FluxCnn(theta), 2
+
+
+@pytest.mark.parametrize("kind", ["mlp", "cnn"])
+@pytest.mark.parametrize("bc", [(3, 3, 3, 3), (2, 0, 1, 1)])
+def test_nan_network_weight_falls_back_to_uncorrected_flux(orc, kind, bc):
+    from paper_2601_04400_amd import Grid
+    nx, ny = 45, 27
+    dom = (0.0, 1.0, 0.0, ny / nx)
+    inflow = (1.3, 0.7, -0.2, 1.1)
+    net, fn = _nan_net(kind)
+    g = Grid(nx, ny, domain=dom, bc=bc, inflow=inflow, flux_net=fn)
+    (g.set_flux_net if kind == "mlp" else g.set_flux_cnn)(net)
+    c = orc.config(nx=nx, ny=ny, y1=dom[3], bc=bc, inflow=inflow)
+    U = orc.prim_to_cons(c, inputs.smooth_prim(nx, ny, seed=11, amp=0.3, domain=dom))
+    Ug = torch.from_numpy(U).cuda().reshape(g.shape)
+    Lo, _, _ = orc.rhs(c, U)
+    assert_fields(to_np(g.rhs(Ug))[0], Lo, 1e-13, f"{kind} NaN weight: right-hand side")
+    flags, _ = g.poll_faults()
+    assert flags & FAULT_NET and not flags & FAULT_NONFINITE, flags
+    dt = 0.4 * orc.cfl_dt(c, U)
+    U1o, _ = orc.rk3_step(c, U, dt)
+    g.step(Ug, dt)
+    assert_fields(to_np(Ug)[0], U1o, 1e-13, f"{kind} NaN weight: step")
+    flags, _ = g.poll_faults()
+    assert flags & FAULT_NET and not flags & FAULT_NONFINITE, flags
+
+
+def test_nonphysical_cell_sets_flag(orc):
+    from paper_2601_04400_amd import Grid
+    n = 40
+    g = Grid(n, n)
+    c = orc.config(nx=n, ny=n)
+    U = orc.prim_to_cons(c, inputs.smooth_prim(n, n, seed=2, amp=0.3))
+    g.rhs(torch.from_numpy(U).cuda().reshape(g.shape))
+    flags, _ = g.poll_faults()
+    assert flags == 0
+    r, mx, my = U[0, 17, 23], U[1, 17, 23], U[2, 17, 23]
+    U[3, 17, 23] = 0.25 * (mx * mx + my * my) / r  # half the kinetic energy: p < 0
+    g.rhs(torch.from_numpy(U).cuda().reshape(g.shape))
+    flags, _ = g.poll_faults()
+    assert flags & FAULT_NONPHYS, flags
+    assert g.poll_faults()[0] == 0  # polling clears
