@@ -123,6 +123,19 @@ shk_status shk_set_stream(shk_grid* g, void* hip_stream);
  * W and U are device arrays of the grid's element type; they may not alias. */
 shk_status shk_prim_to_cons(shk_grid* g, const void* W, void* U);
 
+/* Reverse mode of shk_prim_to_cons, to carry the gradient of a loss with
+ * respect to a conservative state (the initial state of a differentiated
+ * run, section 2 and the reverse learning of section 3) back to the
+ * primitive variables it was built from and to gamma.  With U = (rho, rho u,
+ * rho v, E), E = p/(gamma-1) + rho (u^2+v^2)/2 (1D: (rho, rho u, E), W =
+ * (rho, u, p)):  W_bar += (dU/dW)^T U_bar cell by cell, and
+ * param_bar[b][0] += sum over the cells of member b of (dU/dgamma) . U_bar,
+ * summed in a fixed order.  W, U_bar, W_bar: device doubles in the state
+ * layout (W_bar may alias neither); param_bar: device [nbatch][5] as for
+ * shk_rhs_adjoint; W_bar or param_bar may be NULL.  SHK_F64 grids
+ * (SHK_EUNSUPPORTED otherwise). */
+shk_status shk_prim_to_cons_vjp(shk_grid* g, const void* W, const void* U_bar, void* W_bar, double* param_bar);
+
 /* Immersed boundary on the signed-distance level set phi (device, double,
  * [ny][nx], phi < 0 inside the solid; shared by all batch members).
  * Classifies cells (fluid phi >= 0, solid, ghost = solid within 3 cells of a
@@ -133,7 +146,12 @@ shk_status shk_prim_to_cons(shk_grid* g, const void* W, void* U);
  * From then on ghost cells are refilled before every right-hand side and the
  * right-hand side is zero at solid and ghost cells.  Requires desc.ibm = 1
  * and ndim = 2.  Synchronises the stream once (to size the ghost list).
- * phi = NULL removes the immersed boundary. */
+ * phi = NULL removes the immersed boundary.  SHK_EINVAL (and no immersed
+ * boundary) when some ghost has no image point: the central-difference
+ * gradient of phi there is far from unit length (|grad phi| < 1/2, where the
+ * difference straddles the solid's medial axis: a solid thinner than about
+ * two cells, a body a few cells across), or no fluid cell is found around
+ * the image point or along the normal. */
 shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall);
 
 /* Change the ratio of specific heats gamma and, unless inflow_prim is NULL,

@@ -210,6 +210,12 @@ def ibm_ghosts(c, phi):
     return dict(ij=ij[:n], normal=nrm[:n], src=src[:n], w=w[:n])
 
 
+def ibm_degenerate(c, phi):
+    """Number of ghosts whose image point is undefined (vanishing grad phi or
+    no fluid cell to interpolate from)."""
+    return lib().orc_ibm_degenerate(ctypes.byref(c), _ptr(_phi(c, phi)))
+
+
 def ibm_fill(c, U, phi, wall=0):
     U = _arr(U, _shape(c)).copy()
     assert lib().orc_ibm_fill(ctypes.byref(c), _ptr(U), _ptr(_phi(c, phi)), _i(wall)) == 0

@@ -184,6 +184,12 @@ int orc_ibm_classify(const Config* c, const double* phi, uint8_t* cls) {
 
 // Ghost table in row-major ghost order: (i, j), unit normal, 4 source cells
 // (flat index or -1) and their weights.  Returns the number of ghosts.
+// Ghosts of the level set whose image point is undefined (see Ibm::degenerate).
+int orc_ibm_degenerate(const Config* c, const double* phi) {
+  if (!config_ok(c) || !phi) return -1;
+  return build_ibm(*c, phi, 0).degenerate;
+}
+
 int orc_ibm_ghosts(const Config* c, const double* phi, int cap, int* ij, double* normal, int* src,
                    double* w) {
   if (!config_ok(c) || !phi) return -1;

@@ -370,6 +370,12 @@ struct Ibm {
     double w[4];                // renormalised fluid-only weights
   };
   std::vector<GhostPt> ghosts;
+  // ghosts whose image point is undefined: the central-difference gradient
+  // of the signed distance is far from unit length (|grad phi| < 1/2: the
+  // difference straddles the solid's medial axis -- a solid thinner than
+  // about two cells, a body a few cells across), or no fluid cell is found
+  // around the image point or along the normal
+  int degenerate = 0;
 };
 
 inline Ibm build_ibm(const Config& c, const double* phi, int wall) {
@@ -438,6 +444,9 @@ inline Ibm build_ibm(const Config& c, const double* phi, int wall) {
           if (is_fluid(is, js)) { g.src[0] = js * nx + is; g.w[0] = 1.0; break; }
         }
       }
+      bool resolved = false;
+      for (int k = 0; k < 4; ++k) resolved = resolved || g.src[k] >= 0;
+      if (!(gn >= 0.5) || !resolved) ++ib.degenerate;
       ib.ghosts.push_back(g);
     }
   return ib;

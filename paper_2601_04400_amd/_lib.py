@@ -31,6 +31,7 @@ _SIGS = {
     "shk_destroy": (None, [_p]),
     "shk_set_stream": (_i, [_p, _p]),
     "shk_prim_to_cons": (_i, [_p, _p, _p]),
+    "shk_prim_to_cons_vjp": (_i, [_p, _p, _p, _p, _p]),
     "shk_set_ib_levelset": (_i, [_p, _p, _i]),
     "shk_ib_ghost_count": (_i, [_p, _p]),
     "shk_ib_classes": (_i, [_p, _p]),

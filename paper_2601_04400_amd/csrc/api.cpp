@@ -24,7 +24,7 @@ using namespace shk;
 struct WsLayout {
   size_t scalars, globals, dtbuf, xslots, u1, u2, cls, row_count, row_off, g_cell, g_src, g_w, g_nrm;
   size_t adjA, adjB, adjC, adjP, adjQ, adjPart, part_stride, adjG, ghostOf, entKeys, entVals, entCount, entHeads;
-  size_t netX, netPart, cnnDF, cnnBufs;
+  size_t netX, netPart, cnnDF, cnnBufs, vjpPart;
   size_t total;
 };
 
@@ -109,6 +109,7 @@ WsLayout layout(const shk_grid_desc* d) {
   L.xslots = o; o += al(sizeof(unsigned long long) * 2 * XSLOTS * d->nbatch);
   L.u1 = o; o += al(state);
   L.u2 = o; o += al(state);
+  L.vjpPart = o; o += al(sizeof(double) * VJP_BLOCKS * d->nbatch);
   if (d->ibm) {
     const size_t cap = ncell;
     L.cls = o; o += al(ncell);
@@ -357,6 +358,17 @@ shk_status shk_prim_to_cons(shk_grid* g, const void* W, void* U) {
   return hip_check(g, e, "prim_to_cons");
 }
 
+shk_status shk_prim_to_cons_vjp(shk_grid* g, const void* W, const void* U_bar, void* W_bar, double* param_bar) {
+  if (!g) return SHK_EINVAL;
+  if (g->d.prec != SHK_F64) return fail(g, SHK_EUNSUPPORTED, "prim_to_cons_vjp: SHK_F64 grids only");
+  if (!W || !U_bar) return fail(g, SHK_EINVAL, "prim_to_cons_vjp: null array");
+  if (!W_bar && !param_bar) return SHK_OK;
+  double* part = reinterpret_cast<double*>(g->ws + g->L.vjpPart);
+  return hip_check(g, launch_prim_to_cons_vjp(g->a, static_cast<const double*>(W), static_cast<const double*>(U_bar),
+                                              static_cast<double*>(W_bar), param_bar, part, g->st),
+                   "prim_to_cons_vjp");
+}
+
 shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
   if (!g) return SHK_EINVAL;
   if (!phi) {
@@ -380,13 +392,25 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
   gt.nrm = reinterpret_cast<double*>(g->ws + g->L.g_nrm);
   gt.wall = wall;
   gt.n = 0;
+  // rc[0..ny-1]: ghosts per row; rc[ny]: ghosts whose image point is undefined
   hipError_t e = hipMemsetAsync(rc, 0, sizeof(int) * (a.ny + 1), g->st);
   if (e == hipSuccess) e = launch_ibm_classify(a, phi, cls, rc, g->st);
-  if (e == hipSuccess) e = launch_ibm_table(a, phi, cls, rc, ro, gt, g->st);
-  int n = 0;
+  if (e == hipSuccess) e = launch_ibm_table(a, phi, cls, rc, ro, gt, rc + a.ny, g->st);
+  int n = 0, nbad = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&n, ro + a.ny, sizeof(int), hipMemcpyDeviceToHost, g->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&nbad, rc + a.ny, sizeof(int), hipMemcpyDeviceToHost, g->st);
   if (e == hipSuccess) e = hipStreamSynchronize(g->st);
   if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset");
+  if (nbad > 0) {
+    g->ibm_on = false;
+    g->a.cls = nullptr;
+    g->a.ghost_of = nullptr;
+    g->gt.n = 0;
+    g->a.gt = g->gt;
+    return fail(g, SHK_EINVAL, "set_ib_levelset: " + std::to_string(nbad) +
+                                   " ghost cells have no image point (|grad phi| < 1/2 there, or no fluid cell is "
+                                   "found from them); the immersed boundary is off");
+  }
   gt.n = n;
   g->gt = gt;
   a.gt = gt;

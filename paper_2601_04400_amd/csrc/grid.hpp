@@ -82,6 +82,11 @@ template <class S>
 hipError_t launch_prim_to_cons(const GridArgs& a, const S* W, S* U, hipStream_t st);
 template <class S>
 hipError_t launch_cfl(const GridArgs& a, const S* U, double* dt_out, hipStream_t st);
+// reverse mode of the primitive-to-conservative conversion (FP64); part:
+// VJP_BLOCKS doubles per batch member
+constexpr int VJP_BLOCKS = 256;
+hipError_t launch_prim_to_cons_vjp(const GridArgs& a, const double* W, const double* Ubar, double* Wbar,
+                                   double* param_bar, double* part, hipStream_t st);
 template <class S>
 hipError_t launch_stage(const GridArgs& a, int mode, const S* Us, const S* Un, S* Uout,
                         const double* dtp, const S* Lin, hipStream_t st);
@@ -91,7 +96,7 @@ hipError_t launch_ibm_fill(const GridArgs& a, const GhostTable& gt, S* U, hipStr
 hipError_t launch_ibm_classify(const GridArgs& a, const double* phi, uint8_t* cls, int* row_count,
                                hipStream_t st);
 hipError_t launch_ibm_table(const GridArgs& a, const double* phi, const uint8_t* cls, const int* row_count,
-                            int* row_off, GhostTable gt, hipStream_t st);
+                            int* row_off, GhostTable gt, int* nbad, hipStream_t st);
 // Stage kernel with the learned correction evaluated inside the tile (2D,
 // FP64, inviscid; modes MODE_RHS .. MODE_STAGE3).
 hipError_t launch_stage_net(const GridArgs& a, const NetArgs& n, int mode, const double* Us, const double* Un,

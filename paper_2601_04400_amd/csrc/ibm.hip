@@ -72,9 +72,15 @@ __global__ void __launch_bounds__(1024) ibm_scan_kernel(const int* __restrict__ 
 
 // One workgroup (one wave) per row: ghosts get consecutive slots in
 // increasing x, then each fills its table entry.
+// A ghost whose image point is undefined -- the central-difference gradient
+// of the signed distance is far from unit length (|grad phi| < 1/2: the
+// difference straddles the solid's medial axis, as in a solid thinner than
+// about two cells or a body a few cells across), or no fluid cell is found
+// around the image point or along the normal -- is counted in *nbad.
 __global__ void __launch_bounds__(64) ibm_table_kernel(GridArgs a, const double* __restrict__ phi,
                                                        const uint8_t* __restrict__ cls,
-                                                       const int* __restrict__ row_off, GhostTable gt) {
+                                                       const int* __restrict__ row_off, GhostTable gt,
+                                                       int* __restrict__ nbad) {
 #pragma clang fp contract(off)
   const int j = blockIdx.x;
   const int nx = a.nx, ny = a.ny;
@@ -128,6 +134,9 @@ __global__ void __launch_bounds__(64) ibm_table_kernel(GridArgs a, const double*
           if (P(is, js) >= 0.0) { src[0] = js * nx + is; w[0] = 1.0; break; }
         }
       }
+      bool resolved = false;
+      for (int k = 0; k < 4; ++k) resolved = resolved || src[k] >= 0;
+      if (!(gn >= 0.5) || !resolved) atomicAdd(nbad, 1);
       gt.cell[slot] = j * nx + i;
       for (int k = 0; k < 4; ++k) { gt.src[4 * slot + k] = src[k]; gt.w[4 * slot + k] = w[k]; }
       gt.nrm[2 * slot] = nxv;
@@ -159,9 +168,9 @@ hipError_t launch_ibm_classify(const GridArgs& a, const double* phi, uint8_t* cl
 }
 
 hipError_t launch_ibm_table(const GridArgs& a, const double* phi, const uint8_t* cls, const int* row_count,
-                            int* row_off, GhostTable gt, hipStream_t st) {
+                            int* row_off, GhostTable gt, int* nbad, hipStream_t st) {
   hipLaunchKernelGGL(ibm_scan_kernel, dim3(1), dim3(1024), 0, st, row_count, row_off, a.ny);
-  hipLaunchKernelGGL(ibm_table_kernel, dim3(a.ny), dim3(64), 0, st, a, phi, cls, row_off, gt);
+  hipLaunchKernelGGL(ibm_table_kernel, dim3(a.ny), dim3(64), 0, st, a, phi, cls, row_off, gt, nbad);
   return hipGetLastError();
 }
 

@@ -853,6 +853,52 @@ __global__ void __launch_bounds__(256) prim_to_cons_kernel(GridArgs a, const S* 
   }
 }
 
+// Reverse mode of prim_to_cons_kernel (FP64 states): per cell, with U = (rho,
+// rho u, rho v, E), E = p/(gamma-1) + rho (u^2 + v^2)/2,
+//   W_bar += (dU/dW)^T U_bar:  rho: Ub0 + u Ub1 + v Ub2 + (u^2+v^2)/2 Ub3,
+//   u: rho (Ub1 + u Ub3), v: rho (Ub2 + v Ub3), p: Ub3/(gamma-1);
+// and the block partial of dU/dgamma . U_bar = -p/(gamma-1)^2 Ub3 summed over
+// the block's cells (a fixed order: each thread's cells, then a fixed tree).
+__global__ void __launch_bounds__(256) prim_to_cons_vjp_kernel(GridArgs a, const double* __restrict__ W,
+                                                               const double* __restrict__ Ubar,
+                                                               double* __restrict__ Wbar,
+                                                               double* __restrict__ part) {
+  __shared__ double red[4];
+  const long long n = a.ncell;
+  const int b = blockIdx.y;
+  const double* Wb = W + (long long)b * a.nvar * n;
+  const double* Ub = Ubar + (long long)b * a.nvar * n;
+  double* Wo = Wbar ? Wbar + (long long)b * a.nvar * n : nullptr;
+  const double gm1 = a.gamma - 1.0, igm = 1.0 / gm1;
+  const int pv = a.nvar - 1;  // pressure / energy plane
+  double s = 0.0;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+    const double r = Wb[c], u = Wb[n + c], v = a.ndim == 2 ? Wb[2 * n + c] : 0.0, p = Wb[pv * n + c];
+    const double u0 = Ub[c], u1 = Ub[n + c], u2 = a.ndim == 2 ? Ub[2 * n + c] : 0.0, u3 = Ub[pv * n + c];
+    if (Wo) {
+      Wo[c] += u0 + u * u1 + v * u2 + 0.5 * (u * u + v * v) * u3;
+      Wo[n + c] += r * (u1 + u * u3);
+      if (a.ndim == 2) Wo[2 * n + c] += r * (u2 + v * u3);
+      Wo[pv * n + c] += u3 * igm;
+    }
+    s += -p * igm * igm * u3;
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(long long)b * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// param_bar[b][0] += the block partials of member b in block order.
+__global__ void vjp_gamma_finalize_kernel(const double* __restrict__ part, int nblk, int nbatch,
+                                          double* __restrict__ param_bar) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbatch) return;
+  double s = 0.0;
+  for (int k = 0; k < nblk; ++k) s += part[(long long)b * nblk + k];
+  param_bar[(long long)b * 5] += s;
+}
+
 // --------------------------------------------------------------- launchers
 static inline unsigned int blocks_for(long long n, int per) {
   long long b = (n + per - 1) / per;
@@ -864,6 +910,18 @@ template <class S>
 hipError_t launch_prim_to_cons(const GridArgs& a, const S* W, S* U, hipStream_t st) {
   hipLaunchKernelGGL(prim_to_cons_kernel<S>, dim3(blocks_for(a.ncell * a.nbatch, 256)), dim3(256), 0, st,
                      a, W, U);
+  return hipGetLastError();
+}
+
+hipError_t launch_prim_to_cons_vjp(const GridArgs& a, const double* W, const double* Ubar, double* Wbar,
+                                   double* param_bar, double* part, hipStream_t st) {
+  unsigned int nb = blocks_for(a.ncell, 256 * 4);
+  if (nb > VJP_BLOCKS) nb = VJP_BLOCKS;
+  hipLaunchKernelGGL(prim_to_cons_vjp_kernel, dim3(nb, a.nbatch), dim3(256), 0, st, a, W, Ubar, Wbar, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !param_bar) return e;
+  hipLaunchKernelGGL(vjp_gamma_finalize_kernel, dim3((a.nbatch + 63) / 64), dim3(64), 0, st, part, (int)nb,
+                     a.nbatch, param_bar);
   return hipGetLastError();
 }
 

@@ -167,8 +167,11 @@ class GammaFit(ReverseFit):
         return self.g.prim_to_cons(self.W0)
 
     def chain(self, gamma, U0_bar, pb):
-        dE = -self.W0[3] / (gamma - 1.0) ** 2
-        return float(pb[0]) + float((U0_bar[3] * dE).sum())
+        # the initial state's dependence on gamma (through its energy), by the
+        # library's reverse mode of the primitive-to-conservative conversion
+        g_bar = self.g.param_bar()
+        self.g.prim_to_cons_vjp(self.W0, U0_bar, None, g_bar)
+        return float(pb[0]) + float(g_bar[0, 0])
 
 
 class MachFit(ReverseFit):
@@ -198,14 +201,19 @@ class MachFit(ReverseFit):
         W = self.W0.clone()
         for k in range(4):
             W[k][:, self.x_post] = post[k]
+        self.W = W
         return self.g.prim_to_cons(W)
 
     def chain(self, mach, U0_bar, pb):
-        (r, u, _, p), (dr, du, dp) = self.post(mach)
-        gm1 = self.gamma - 1.0
-        dU = (dr, dr * u + r * du, 0.0, dp / gm1 + 0.5 * dr * u * u + r * u * du)
-        g = sum(float(U0_bar[k][:, self.x_post].sum()) * dU[k] for k in range(4))
-        return g + float(pb[1]) * dr + float(pb[2]) * du + float(pb[4]) * dp
+        # primitive adjoint of the initial state (the library's reverse mode
+        # of the conversion), summed over the post-shock cells, and the
+        # inflow partials: both times d(post-shock state)/dMach
+        _, (dr, du, dp) = self.post(mach)
+        W_bar = torch.zeros_like(self.W)
+        self.g.prim_to_cons_vjp(self.W, U0_bar, W_bar, None)
+        post_bar = [float(W_bar[k][:, self.x_post].sum()) for k in range(4)]
+        return ((post_bar[0] + float(pb[1])) * dr + (post_bar[1] + float(pb[2])) * du
+                + (post_bar[3] + float(pb[4])) * dp)
 
 
 def main():

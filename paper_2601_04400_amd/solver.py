@@ -100,6 +100,17 @@ class Grid:
         check(lib().shk_prim_to_cons(self.handle, _ptr(W), _ptr(U)), self.handle, "prim_to_cons")
         return U
 
+    def prim_to_cons_vjp(self, W, U_bar, W_bar=None, param_bar=None):
+        """Reverse mode of prim_to_cons: W_bar += (dU/dW)^T U_bar and
+        param_bar[:, 0] += (dU/dgamma) . U_bar (each may be None).  Returns
+        (W_bar, param_bar)."""
+        W = W.to(device=self.device, dtype=torch.float64).contiguous().reshape(self.shape)
+        U_bar = U_bar.to(device=self.device, dtype=torch.float64).contiguous().reshape(self.shape)
+        self._sync_stream()
+        check(lib().shk_prim_to_cons_vjp(self.handle, _ptr(W), _ptr(U_bar), _ptr(W_bar), _ptr(param_bar)),
+              self.handle, "prim_to_cons_vjp")
+        return W_bar, param_bar
+
     def set_levelset(self, phi, wall=0):
         self.version += 1
         if phi is None:

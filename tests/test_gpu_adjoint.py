@@ -246,22 +246,18 @@ def gpu_c3_loss_and_grad(nx, ny, mach, gamma, steps, dt, target, every, grad=Tru
         return float(J), U.detach()
     J.backward()
     Ub, pb = U0.grad[0].double(), params.grad[0].double()
-    # d U0 / d(M, gamma): post-shock cells depend on M and gamma, all cells on
-    # gamma through E = p/(gamma-1) + rho |u|^2/2
-    post_mask = torch.from_numpy((inputs.centres(nx, 0, 1) < 0.1)[None, :].repeat(ny, 0)).cuda().double()
-    r2, u2, p2 = post
-    gm1 = gamma - 1.0
-
-    def dcons(dr, du, dp, dgam_direct):
-        return [dr, dr * u2 + r2 * du, 0.0, dp / gm1 + 0.5 * dr * u2 * u2 + r2 * u2 * du + dgam_direct]
-    dUdM = dcons(dM[0], dM[1], dM[2], 0.0)
-    dUdg_post = dcons(dg[0], dg[1], dg[2], -p2 / gm1 ** 2)
-    dUdg_pre = -1.0 / gm1 ** 2
-    dJdM = sum(float((Ub[k] * post_mask).sum()) * dUdM[k] for k in range(4))
-    dJdg = sum(float((Ub[k] * post_mask).sum()) * dUdg_post[k] for k in range(4))
-    dJdg += float((Ub[3] * (1 - post_mask)).sum()) * dUdg_pre
-    dJdM += float(pb[1]) * dM[0] + float(pb[2]) * dM[1] + float(pb[4]) * dM[2]
-    dJdg += float(pb[0]) + float(pb[1]) * dg[0] + float(pb[2]) * dg[1] + float(pb[4]) * dg[2]
+    # the initial state's adjoint in primitive variables and gamma (the
+    # library's reverse mode of the conversion); the post-shock cells and the
+    # inflow carry d(post-shock state)/d(M, gamma)
+    Wt = torch.from_numpy(W).cuda()
+    W_bar, g_bar = torch.zeros_like(Wt), g.param_bar()
+    g.prim_to_cons_vjp(Wt, Ub, W_bar, g_bar)
+    post_cols = torch.from_numpy(inputs.centres(nx, 0, 1) < 0.1).cuda()
+    post_bar = [float(W_bar[k][:, post_cols].sum()) for k in range(4)]
+    inflow_bar = [float(pb[1 + k]) for k in range(4)]
+    prim = (0, 1, 3)  # (rho, u, p) of the post-shock state
+    dJdM = sum((post_bar[k] + inflow_bar[k]) * dM[i] for i, k in enumerate(prim))
+    dJdg = float(g_bar[0, 0]) + float(pb[0]) + sum((post_bar[k] + inflow_bar[k]) * dg[i] for i, k in enumerate(prim))
     return float(J), (dJdM, dJdg)
 
 
@@ -455,3 +451,125 @@ def test_mach_fit_gradient_and_recovery():
     print("mach", m_end, "loss", hist[0][2], "->", loss_end, flush=True)
     assert abs(m_end - 5.0) < 0.02
     assert loss_end < 1e-3 * hist[0][2]
+
+
+def _oracle_gamma_fit(orc, c, W, phi, nsteps, dt, target):
+    """The oracle's loss and dLoss/dgamma of a gamma fit: forward-mode tangent
+    with d gamma = 1 through the initial state's energy (the primitive state
+    W is fixed) and every step; loss = mean over fluid cells of
+    (rho - target)^2."""
+    U = orc.prim_to_cons(c, W)
+    Udot = np.zeros_like(U)
+    Udot[3] = -W[3] / (c.gamma - 1.0) ** 2
+    for _ in range(nsteps):
+        U, Udot = orc.rk3_step_jvp(c, U, Udot, dt, gdot=1.0, phi=phi)
+    fl = np.ones(W.shape[1:], dtype=bool) if phi is None else phi >= 0.0
+    e = (U[0] - target)[fl]
+    return float(np.mean(e * e)), float(2.0 * np.mean(e * Udot[0][fl]))
+
+
+def _oracle_run(orc, c, W, phi, nsteps, dt):
+    U = orc.prim_to_cons(c, W)
+    for _ in range(nsteps):
+        U, _ = orc.rk3_step(c, U, dt, phi=phi)
+    return U
+
+
+@pytest.mark.parametrize("case", ["cylinder", "sod"])
+def test_gamma_fit_loss_and_gradient_vs_oracle(orc, case):
+    """Reverse learning of gamma (section 3): the GPU fit's loss and gradient
+    (adjoint through the run plus the initial state's dependence on gamma,
+    via shk_prim_to_cons_vjp) against the oracle's forward-mode tangent at
+    two values of gamma, 1e-9 relative.  Restricted Mach-5 shock-cylinder at
+    64 x 32 (30 steps) and Sod's tube as 200 x 4 rows (250 steps to t = 0.2);
+    each side makes its own target run at the target gamma."""
+    from paper_2601_04400_amd.infer import GammaFit
+    if case == "cylinder":
+        fit = GammaFit(nx=64, ny=32, gamma_target=2.0, nsteps=30, every=10)
+    else:
+        fit = GammaFit(nx=200, ny=4, gamma_target=1.4, nsteps=250, every=25, case="sod")
+    sc = fit.sc
+    W = sc["W"]
+    ny, nx = W.shape[1:]
+    cfg = dict(nx=nx, ny=ny, x0=sc["domain"][0], x1=sc["domain"][1], y0=sc["domain"][2], y1=sc["domain"][3],
+               bc=sc["bc"], inflow=sc["inflow"])
+    phi = sc["phi"]
+    dt = float(fit.dt.cpu()[0])
+    if case == "cylinder":
+        cu = orc.config(gamma=fit.upper, **cfg)
+        assert dt == 0.6 * orc.cfl_dt(cu, orc.prim_to_cons(cu, W), phi=phi)  # the same fixed step
+    target = _oracle_run(orc, orc.config(gamma=2.0 if case == "cylinder" else 1.4, **cfg), W, phi, fit.nsteps,
+                         dt)[0]
+    for gamma in ((1.7, 2.3) if case == "cylinder" else (1.25, 1.55)):
+        Jg, dg = fit.loss_and_grad(gamma)
+        Jo, do = _oracle_gamma_fit(orc, orc.config(gamma=gamma, **cfg), W, phi, fit.nsteps, dt, target)
+        print(f"gamma fit {case} at {gamma}: loss {Jg:.12e} / {Jo:.12e}, gradient {dg:.12e} / {do:.12e}",
+              flush=True)
+        assert abs(Jg - Jo) <= 1e-10 * abs(Jo)
+        assert abs(dg - do) <= 1e-9 * abs(do), (dg, do)
+
+
+def test_mach_fit_loss_and_gradient_vs_oracle(orc):
+    """Reverse learning of the shock Mach number on the restricted
+    shock-cylinder (64 x 32, 30 steps): the GPU fit's loss and dLoss/dMach
+    (adjoint, plus the initial state's and inflow's dependence on Mach through
+    the normal-shock relations, via shk_prim_to_cons_vjp) against the oracle's
+    forward-mode tangent (its own normal-shock relations), 1e-9 relative, at
+    Mach 4 and 5.5; each side makes its own Mach-5 target run."""
+    from paper_2601_04400_amd.infer import MachFit
+    fit = MachFit(nx=64, ny=32, mach_target=5.0, nsteps=30, every=10)
+    sc = fit.sc
+    ny, nx = sc["W"].shape[1:]
+    phi = sc["phi"]
+    dt = float(fit.dt.cpu()[0])
+
+    def cfg(mach):
+        post = orc.rh_post_shock(mach)
+        inflow = (post[0], post[1], 0.0, post[2])
+        c = orc.config(nx=nx, ny=ny, x0=0.0, x1=1.5, y0=0.0, y1=1.0, bc=(2, 0, 1, 1), inflow=inflow)
+        return c, inputs.shock_prim(nx, ny, sc["domain"], 0.3, inflow, (1.4, 0.0, 0.0, 1.0))
+
+    cu, Wu = cfg(6.0)
+    assert dt == 0.6 * orc.cfl_dt(cu, orc.prim_to_cons(cu, Wu), phi=phi)  # the same fixed step
+    ct, Wt = cfg(5.0)
+    target = _oracle_run(orc, ct, Wt, phi, fit.nsteps, dt)[0]
+    for mach in (4.0, 5.5):
+        Jg, dg = fit.loss_and_grad(mach)
+        c, _ = cfg(mach)
+        Jo, dMo, _, _ = orc.shock_tangent(c, phi, mach, 0.3, fit.nsteps, dt, target)
+        print(f"Mach fit at {mach}: loss {Jg:.12e} / {Jo:.12e}, gradient {dg:.12e} / {dMo:.12e}", flush=True)
+        assert abs(Jg - Jo) <= 1e-10 * abs(Jo)
+        assert abs(dg - dMo) <= 1e-9 * abs(dMo), (dg, dMo)
+
+
+def test_prim_to_cons_vjp_vs_oracle_jacobian(orc):
+    """shk_prim_to_cons_vjp on two random states: <U_bar, (dU/dW) dW> from
+    central differences of the oracle's conversion (h = 1e-6) equals
+    <W_bar, dW> for random directions dW, and the gamma partial equals the
+    difference quotient in gamma, both to 1e-7 relative (the truncation error
+    of the quadratic energy row)."""
+    from paper_2601_04400_amd import Grid
+    nx, ny, gamma = 23, 17, 1.37
+    g = Grid(nx, ny, gamma=gamma, nbatch=2)
+    rng = np.random.default_rng(5)
+    W = np.stack([inputs.random_prim(nx, ny, seed=s) for s in (1, 2)])
+    Ub = rng.normal(size=W.shape)
+    Wt, Ubt = torch.from_numpy(W).cuda(), torch.from_numpy(Ub).cuda()
+    W_bar = torch.zeros_like(Wt)
+    pb = g.param_bar()
+    g.prim_to_cons_vjp(Wt, Ubt, W_bar, pb)
+    W_bar, pb = to_np(W_bar), to_np(pb)
+    c = orc.config(nx=nx, ny=ny, gamma=gamma)
+    h = 1e-6
+    for b in range(2):
+        # directional derivatives of the oracle's conversion against <W_bar, dW>
+        for trial in range(3):
+            dW = rng.normal(size=W[b].shape)
+            fd = (orc.prim_to_cons(c, W[b] + h * dW) - orc.prim_to_cons(c, W[b] - h * dW)) / (2 * h)
+            lhs, rhs = float(np.sum(Ub[b] * fd)), float(np.sum(W_bar[b] * dW))
+            assert abs(lhs - rhs) <= 1e-7 * abs(lhs), (lhs, rhs)
+        cp = orc.config(nx=nx, ny=ny, gamma=gamma + h)
+        cm = orc.config(nx=nx, ny=ny, gamma=gamma - h)
+        fdg = float(np.sum(Ub[b] * (orc.prim_to_cons(cp, W[b]) - orc.prim_to_cons(cm, W[b])) / (2 * h)))
+        assert abs(pb[b, 0] - fdg) <= 1e-7 * abs(fdg), (pb[b, 0], fdg)
+        assert np.all(pb[b, 1:] == 0.0)

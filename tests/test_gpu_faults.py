@@ -77,3 +77,25 @@ def test_nonphysical_cell_sets_flag(orc):
     flags, _ = g.poll_faults()
     assert flags & FAULT_NONPHYS, flags
     assert g.poll_faults()[0] == 0  # polling clears
+
+
+def test_degenerate_level_set_rejected(orc):
+    """A solid plate one cell thick has ghosts without an image point: the
+    library rejects the level set (SHK_EINVAL, the same count of degenerate
+    ghosts as the oracle's check) and the grid runs on without a body."""
+    from paper_2601_04400_amd import Grid
+    from paper_2601_04400_amd._lib import ShkError
+    n = 40
+    y = inputs.centres(n, 0.0, 1.0)[:, None]
+    phi = np.broadcast_to(np.abs(y - y[n // 2, 0]) - 0.4 / n, (n, n)).copy()
+    c = orc.config(nx=n, ny=n)
+    assert orc.ibm_degenerate(c, phi) == n
+    g = Grid(n, n, ibm=True)
+    with pytest.raises(ShkError, match=f"{n} ghost cells have no image point"):
+        g.set_levelset(torch.from_numpy(phi))
+    U = orc.prim_to_cons(c, inputs.smooth_prim(n, n, seed=4, amp=0.3))
+    Lo, _, _ = orc.rhs(c, U)
+    assert_fields(to_np(g.rhs(torch.from_numpy(U).cuda().reshape(g.shape)))[0], Lo, 1e-13, "after the rejection")
+    # a resolved body is accepted afterwards
+    phi_c = inputs.circle_phi(n, n, (0.0, 1.0, 0.0, 1.0), (0.5, 0.5), 0.25)
+    assert g.set_levelset(torch.from_numpy(phi_c)) > 0

@@ -405,3 +405,22 @@ def test_adam_constant_gradient_closed_form(orc):
     # first moment is (1 - b1^t) g, second (1 - b2^t) g^2
     np.testing.assert_allclose(m, (1 - 0.9 ** 7) * g, rtol=1e-13)
     np.testing.assert_allclose(v, (1 - 0.999 ** 7) * g * g, rtol=1e-12)
+
+
+def test_degenerate_ghosts_counted(orc):
+    """A solid plate one cell thick (signed distance |y - yc| - t/2, t < dy):
+    at its cells the central difference of phi straddles the plate's middle
+    and vanishes (up to rounding), so the ghosts have no normal and no image
+    point -- every one is counted as degenerate; a cylinder many cells across
+    has none."""
+    from paper_2601_04400_amd import inputs
+    n = 40
+    dom = (0.0, 1.0, 0.0, 1.0)
+    y = inputs.centres(n, 0.0, 1.0)[:, None]
+    yc = y[n // 2, 0]
+    phi = np.broadcast_to(np.abs(y - yc) - 0.4 / n, (n, n)).copy()
+    c = orc.config(nx=n, ny=n)
+    cls, ng = orc.ibm_classify(c, phi)
+    assert ng == n and orc.ibm_degenerate(c, phi) == n
+    phi_c = inputs.circle_phi(n, n, dom, (0.5, 0.5), 0.25)
+    assert orc.ibm_degenerate(c, phi_c) == 0
