@@ -473,15 +473,17 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* Us, con
     }
     Flux4<C> F = hllc(L, R, gam, igm1);
     if (VISC) {
+      // derivatives as products with the reciprocal spacings, the
+      // temperature T = p / rho by the fast quotient (no IEEE division)
       const int ia = s0 + 2 * st, ib = s0 + 3 * st;
       const int tt = isx ? PX : 1;  // tangential LDS stride
-      const C dn = C(isx ? a.dx : a.dy), dtn = C(isx ? a.dy : a.dx);
+      const C idn = C(isx ? a.inv_dx : a.inv_dy), idt4 = C(0.25 * (isx ? a.inv_dy : a.inv_dx));
       const C mu = C(a.mu), kap = C(a.kappa);
-      const C un_n = (w[cn][ib] - w[cn][ia]) / dn;
-      const C ut_n = (w[ct][ib] - w[ct][ia]) / dn;
-      const C T_n = (w[3][ib] / w[0][ib] - w[3][ia] / w[0][ia]) / dn;
-      const C un_t = (w[cn][ia + tt] - w[cn][ia - tt] + w[cn][ib + tt] - w[cn][ib - tt]) / (C(4) * dtn);
-      const C ut_t = (w[ct][ia + tt] - w[ct][ia - tt] + w[ct][ib + tt] - w[ct][ib - tt]) / (C(4) * dtn);
+      const C un_n = (w[cn][ib] - w[cn][ia]) * idn;
+      const C ut_n = (w[ct][ib] - w[ct][ia]) * idn;
+      const C T_n = (qdiv(w[3][ib], w[0][ib]) - qdiv(w[3][ia], w[0][ia])) * idn;
+      const C un_t = (w[cn][ia + tt] - w[cn][ia - tt] + w[cn][ib + tt] - w[cn][ib - tt]) * idt4;
+      const C ut_t = (w[ct][ia + tt] - w[ct][ia - tt] + w[ct][ib + tt] - w[ct][ib - tt]) * idt4;
       const C tnn = mu * (C(4.0 / 3.0) * un_n - C(2.0 / 3.0) * ut_t);
       const C tnt = mu * (un_t + ut_n);
       const C qn = -kap * T_n;
