@@ -58,12 +58,12 @@ STAGE_SOURCES = ("stage.hip", "flux.hpp", "xcd.hpp", "ibm_dev.hpp")
 # reports them as null.
 MEASURED = {
     ("cylinder", 1024, 512, "f64"): {
-        "sources_sha256": "7334b64c3db52a451d3f2c315d0455a27122cba45a19a4c446ed21e7485a5e77",
-        "bytes_per_launch": 48414669, "valu_wave_instr_per_launch": 17110975,
+        "sources_sha256": "11b0cec5ddcb6af68e12c60ada8e2deccdd6f7b2a439d934a4623852566012ec",
+        "bytes_per_launch": 48336725, "valu_wave_instr_per_launch": 15464348,
         "profile": "profiles/stage_kernel_cylinder1024x512_ns_f64.md"},
     ("quadrant", 4096, 2048, "f64"): {
-        "sources_sha256": "7334b64c3db52a451d3f2c315d0455a27122cba45a19a4c446ed21e7485a5e77",
-        "bytes_per_launch": 815910280, "valu_wave_instr_per_launch": 222620581,
+        "sources_sha256": "11b0cec5ddcb6af68e12c60ada8e2deccdd6f7b2a439d934a4623852566012ec",
+        "bytes_per_launch": 805663437, "valu_wave_instr_per_launch": 214069745,
         "profile": "profiles/stage_kernel_quadrant4096x2048_f64.md"},
 }
 
@@ -176,9 +176,7 @@ def adjoint_ratio(n=256, steps=200, every=20):
     params = torch.tensor([[1.4, *inflow]], dtype=torch.float64, device="cuda", requires_grad=True)
 
     def measure(overlap):
-        # Python's cyclic garbage collector can stop the host for tens of
-        # milliseconds (a full collection in a process holding torch): the
-        # timed repetitions run with it paused after one explicit collection
+        # the timed repetitions run with Python's garbage collector paused
         gc.collect()
         gc.disable()
         try:
@@ -189,7 +187,12 @@ def adjoint_ratio(n=256, steps=200, every=20):
     def _measure(overlap):
         runs = []
         for rep in range(6):  # the first is a warm-up; the median and the maximum of the other five are reported
+            # both gradients start empty in every repetition: accumulating into
+            # an existing params.grad would run torch's own add kernel, whose
+            # first (lazy) load stalled one repetition's backward call by
+            # ~65 ms after the library's work had been issued
             U0.grad = None
+            params.grad = None
             U0.requires_grad_(True)
             trace = [] if overlap else None
             torch.cuda.synchronize()
