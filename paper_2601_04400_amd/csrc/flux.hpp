@@ -85,6 +85,28 @@ __device__ __forceinline__ void weno_products(float g0, float g1, float g2, floa
   P[2] = qrcp(g2);
 }
 
+// Indicator terms.  In double the Jiang-Shu indicators are formed four
+// times over, beta' = 4 beta = (13/3) s^2 + t^2 (s the curvature of the
+// triple, t its one-sided slope term), with eps' = 4 eps: every nonlinear
+// weight d_m / (eps + beta_m)^2 then carries the same factor 16, which the
+// normalisation removes, and the 1/4 of the slope term and the separate eps
+// addition disappear (eps' is added once to each triple's curvature term,
+// which the two biased values of a face share).  Float keeps the unscaled
+// form eps + ((13/12) s^2 + t^2 / 4), whose rounding near strong shocks is
+// the one the single-precision path was validated with.
+// weno_kterm: the curvature term of the triple (x, y, z); weno_gterm: eps +
+// beta from it and the slope term t.
+__device__ __forceinline__ double weno_kterm(double x, double y, double z, double eps) {
+  const double s = x - 2.0 * y + z;
+  return fma((13.0 / 3.0) * s, s, 4.0 * eps);
+}
+__device__ __forceinline__ double weno_gterm(double t, double k, double) { return fma(t, t, k); }
+__device__ __forceinline__ float weno_kterm(float x, float y, float z, float) {
+  const float s = x - 2.f * y + z;
+  return (13.f / 12.f) * s * s;
+}
+__device__ __forceinline__ float weno_gterm(float t, float k, float eps) { return eps + (k + 0.25f * t * t); }
+
 // Both WENO5-JS values at the face between c and d of the six cells
 // a b c d e f (Jiang-Shu indicators, ideal weights 1/10, 6/10, 3/10, eps):
 // the left-biased one from a..e and the right-biased one from the mirrored
@@ -94,18 +116,17 @@ __device__ __forceinline__ void weno_products(float g0, float g1, float g2, floa
 // weno_products describes, which leaves a single division per value.
 template <class C>
 __device__ __forceinline__ void weno5_pair(C a, C b, C c, C d, C e, C f, C eps, C& left, C& right) {
-  const C k13 = C(13) / C(12);
-  // curvature (second difference) of each triple, symmetric under mirroring
-  const C sA = a - C(2) * b + c, sB = b - C(2) * c + d, sC = c - C(2) * d + e, sD = d - C(2) * e + f;
-  const C kB = k13 * sB * sB, kC = k13 * sC * sC;
+  // curvature terms of the four triples, symmetric under mirroring
+  const C kA = weno_kterm(a, b, c, eps), kB = weno_kterm(b, c, d, eps);
+  const C kC = weno_kterm(c, d, e, eps), kD = weno_kterm(d, e, f, eps);
   // left: triples A, B, C
-  C g0 = eps + (k13 * sA * sA + C(0.25) * (a - C(4) * b + C(3) * c) * (a - C(4) * b + C(3) * c));
-  C g1 = eps + (kB + C(0.25) * (b - d) * (b - d));
-  C g2 = eps + (kC + C(0.25) * (C(3) * c - C(4) * d + e) * (C(3) * c - C(4) * d + e));
+  C g0 = weno_gterm(a - C(4) * b + C(3) * c, kA, eps);
+  C g1 = weno_gterm(b - d, kB, eps);
+  C g2 = weno_gterm(C(3) * c - C(4) * d + e, kC, eps);
   // right (mirrored): triples D, C, B
-  C h0 = eps + (k13 * sD * sD + C(0.25) * (f - C(4) * e + C(3) * d) * (f - C(4) * e + C(3) * d));
-  C h1 = eps + (kC + C(0.25) * (e - c) * (e - c));
-  C h2 = eps + (kB + C(0.25) * (C(3) * d - C(4) * c + b) * (C(3) * d - C(4) * c + b));
+  C h0 = weno_gterm(f - C(4) * e + C(3) * d, kD, eps);
+  C h1 = weno_gterm(e - c, kC, eps);
+  C h2 = weno_gterm(C(3) * d - C(4) * c + b, kB, eps);
   // candidate polynomials (x6); the centred ones coincide across the pair
   const C qm = C(5) * c - b + C(2) * d;  // left q1 = right q2
   const C qp = C(2) * c + C(5) * d - e;  // left q2 = right q1
@@ -122,46 +143,39 @@ __device__ __forceinline__ void weno5_pair(C a, C b, C c, C d, C e, C f, C eps, 
   right = qdiv(v0 * r0 + v1 * qp + v2 * qm, C(6) * (v0 + v1 + v2));
 }
 
-// WENO5-JS states of three consecutive faces from the eight cells c0..c7 (the
-// stride st apart from f): face k (k = 0, 1, 2) lies between cells k+2 and
-// k+3, its left state comes from cells k..k+4 and its right state from the
-// mirrored k+5..k+1 -- as weno5_pair on cells k..k+5.  The indicators of a
-// face's right state are those of the next face's left state (the same three
-// triples of cells, with the ideal weights in reverse order), so three faces
-// need four indicator sets instead of six, and the six triples' curvature
-// terms are formed once.  Set j (cells j..j+4) holds the weight factors
-// P0, P1, P2 (proportional to 1/G0, 1/G1, 1/G2; weno_products) of G_m =
-// (eps + beta_m)^2 of the triples starting at j, j+1, j+2 (Jiang-Shu
-// indicators in the left-state orientation); the left state of face j has
-// the weights (0.1 P0, 0.6 P1, 0.3 P2) on the
+// WENO5-JS states of NF consecutive faces from the NF + 5 cells c0.. (the
+// stride st apart from f): face k lies between cells k+2 and k+3, its left
+// state comes from cells k..k+4 and its right state from the mirrored
+// k+5..k+1 -- as weno5_pair on cells k..k+5.  The indicators of a face's
+// right state are those of the next face's left state (the same three
+// triples of cells, with the ideal weights in reverse order), so NF faces
+// need NF + 1 indicator sets instead of 2 NF, and the NF + 3 triples'
+// curvature terms are formed once.  Set j (cells j..j+4) holds the weight
+// factors P0, P1, P2 (proportional to 1/G0, 1/G1, 1/G2; weno_products) of
+// G_m = (eps + beta_m)^2 of the triples starting at j, j+1, j+2 (indicators
+// in the left-state orientation, formed by weno_kterm and weno_gterm); the
+// left state of face j has the weights (0.1 P0, 0.6 P1, 0.3 P2) on the
 // candidates (q0, q1, q2) of cells j..j+4, and the right state of face j-1
 // the weights (0.1 P2, 0.6 P1, 0.3 P0) on its candidates (r0, q2, q1).
-template <class C>
-__device__ __forceinline__ void weno5_triple(const C* f, int st, C eps, C L[3], C R[3]) {
-  const C k13 = C(13) / C(12);
-  C c[8];
+template <int NF, class C>
+__device__ __forceinline__ void weno5_run(const C* f, int st, C eps, C L[NF], C R[NF]) {
+  C c[NF + 5];
 #pragma unroll
-  for (int m = 0; m < 8; ++m) c[m] = f[m * st];
-  C kc[6];  // 13/12 (curvature)^2 of the triple starting at cell t
+  for (int m = 0; m < NF + 5; ++m) c[m] = f[m * st];
+  C kc[NF + 3];  // curvature term of the triple starting at cell t
 #pragma unroll
-  for (int t = 0; t < 6; ++t) {
-    const C sc = c[t] - C(2) * c[t + 1] + c[t + 2];
-    kc[t] = k13 * sc * sc;
-  }
-  C P[4][3];
+  for (int t = 0; t < NF + 3; ++t) kc[t] = weno_kterm(c[t], c[t + 1], c[t + 2], eps);
+  C P[NF + 1][3];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const C t0 = c[j] - C(4) * c[j + 1] + C(3) * c[j + 2];
-    const C t1 = c[j + 1] - c[j + 3];
-    const C t2 = C(3) * c[j + 2] - C(4) * c[j + 3] + c[j + 4];
-    C g0 = eps + (kc[j] + C(0.25) * t0 * t0);
-    C g1 = eps + (kc[j + 1] + C(0.25) * t1 * t1);
-    C g2 = eps + (kc[j + 2] + C(0.25) * t2 * t2);
+  for (int j = 0; j < NF + 1; ++j) {
+    C g0 = weno_gterm(c[j] - C(4) * c[j + 1] + C(3) * c[j + 2], kc[j], eps);
+    C g1 = weno_gterm(c[j + 1] - c[j + 3], kc[j + 1], eps);
+    C g2 = weno_gterm(C(3) * c[j + 2] - C(4) * c[j + 3] + c[j + 4], kc[j + 2], eps);
     g0 = g0 * g0; g1 = g1 * g1; g2 = g2 * g2;
     weno_products(g0, g1, g2, P[j]);
   }
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < NF; ++k) {
     const C q0 = C(2) * c[k] - C(7) * c[k + 1] + C(11) * c[k + 2];
     const C q1 = C(5) * c[k + 2] - c[k + 1] + C(2) * c[k + 3];
     const C q2 = C(2) * c[k + 2] + C(5) * c[k + 3] - c[k + 4];
@@ -186,12 +200,13 @@ struct Flux4 {
   C f0, f1, f2, f3;
 };
 
-// One bracket, evaluated without branches: the star correction is always
-// formed and selected away on a supersonic side (its value there is never
-// used, whatever it is), so lanes of a wavefront never diverge here.  With
-// su = s - u and chi = su / (s - s*), the star energy chi (E + (s* - u)(rho s*
-// + p / su)) is (su (E + (s* - u) rho s*) + (s* - u) p) / (s - s*): su
-// cancels, so one reciprocal serves the whole bracket.
+// One bracket, evaluated without branches.  With su = s - u and chi = su /
+// (s - s*), the star energy chi (E + (s* - u)(rho s* + p / su)) is (su (E +
+// (s* - u) rho s*) + (s* - u) p) / (s - s*): su cancels, so one reciprocal
+// serves the whole bracket.  On a supersonic side the bracket is the
+// physical flux alone: the wave speed and the reciprocal are set to zero
+// there, which keeps the star differences finite (whatever s - s* is) and
+// adds exactly zero, so lanes of a wavefront never diverge here.
 template <class C>
 __device__ __forceinline__ Flux4<C> hllc_side(const Prim<C>& w, C E, C s, C ss, bool supersonic) {
   // physical flux of this side
@@ -202,7 +217,8 @@ __device__ __forceinline__ Flux4<C> hllc_side(const Prim<C>& w, C E, C s, C ss, 
   F.f2 = mn * w.ut;
   F.f3 = w.un * (E + w.p);
   C su = s - w.un;
-  C id = qrcp(s - ss);
+  const C id = supersonic ? C(0) : qrcp(s - ss);
+  const C se = supersonic ? C(0) : s;
   C chi = su * id;
   C rs = chi * w.r;
   C d0 = rs - w.r;
@@ -210,12 +226,7 @@ __device__ __forceinline__ Flux4<C> hllc_side(const Prim<C>& w, C E, C s, C ss, 
   C d2 = d0 * w.ut;
   C du = ss - w.un;
   C d3 = (su * (E + du * (w.r * ss)) + du * w.p) * id - E;
-  Flux4<C> G;
-  G.f0 = supersonic ? F.f0 : F.f0 + s * d0;
-  G.f1 = supersonic ? F.f1 : F.f1 + s * d1;
-  G.f2 = supersonic ? F.f2 : F.f2 + s * d2;
-  G.f3 = supersonic ? F.f3 : F.f3 + s * d3;
-  return G;
+  return Flux4<C>{F.f0 + se * d0, F.f1 + se * d1, F.f2 + se * d2, F.f3 + se * d3};
 }
 
 template <class C>

@@ -225,6 +225,12 @@ __device__ __forceinline__ void char_face_states(const double* q0, const double*
   back(wr, Rp);
 }
 
+// Compile-time integer passed to a generic lambda.
+template <int V>
+struct IntC {
+  static constexpr int value = V;
+};
+
 // ------------------------------------------------------------ stage kernel
 // Modes: MODE_RHS writes L(U); MODE_STAGE1..3 are the three Shu-Osher stages
 // with the step read from dtp[b].  The fused automatic-step sequence is
@@ -247,13 +253,14 @@ __device__ __forceinline__ void char_face_states(const double* q0, const double*
 // fluid cells as they are loaded, and their right-hand side is zero.
 template <class S, class C, int NDIM, int TX, int TY, bool VISC, int MODE, int NET = NET_NONE, bool CHAR = false,
           bool IBM = false>
-__global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* Us, const S* Un, S* Uout,
+__global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArgs a, const S* Us, const S* Un, S* Uout,
                                                     const double* __restrict__ dtp,
                                                     const S* __restrict__ Lin, NetArgs net) {
   // Us, Un and Uout may alias (stage 3 writes the step's result over U^n) and
   // a.ghost_back may be Us: every cell is read before it is written, by the
   // thread that writes it, and a ghost cell's stored value is never read.
-  constexpr int NT = 256;
+  constexpr int NT = NDIM == 2 ? TX * TY : TX;  // one thread per cell of the tile
+  static_assert(NT % 64 == 0 && NT <= 1024, "whole waves");
   constexpr int H = HALO;
   constexpr int PX = TX + 2 * H;
   constexpr int PY = NDIM == 2 ? TY + 2 * H : 1;
@@ -527,85 +534,114 @@ __global__ void __launch_bounds__(256) stage_kernel(GridArgs a, const S* Us, con
       fys[0][oidx] = F.f0; fys[1][oidx] = F.f2; fys[2][oidx] = F.f1; fys[3][oidx] = F.f3;
     }
   };
+  // One face per thread, k = x-faces first, then y-faces.  DIR 1 (x-faces)
+  // and 2 (y-faces) fix the LDS stride and the velocity planes at compile
+  // time, so the stencil reads take immediate offsets; DIR 0 decides per
+  // lane.
+  auto face_task = [&](int k, auto dirc) {
+    constexpr int DIR = decltype(dirc)::value;
+    const bool isx = DIR == 1 ? true : (DIR == 2 ? false : k < NFX);
+    int s0, fi, line;
+    if (isx) {
+      fi = k % (TX + 1);
+      line = k / (TX + 1);
+      s0 = (NDIM == 2 ? (line + H) * PX : 0) + fi;
+    } else {
+      const int kk = k - NFX;
+      line = kk % TX;
+      fi = kk / TX;
+      s0 = fi * PX + line + H;
+    }
+    const int st = isx ? 1 : PX;
+    const int cn = isx ? 1 : 2, ct = isx ? 2 : 1;
+    Prim<C> L, R;
+    if constexpr (CHAR) {
+      static_assert(sizeof(C) == 8, "characteristic reconstruction: FP64 tiles");
+      char_face_states(w[0] + s0, w[cn] + s0, w[ct] + s0, w[3] + s0, st, a.eps, a.gamma, L, R);
+    } else {
+      {
+        const C* f = w[0] + s0;
+        weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.r, R.r);
+      }
+      {
+        const C* f = w[cn] + s0;
+        weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.un, R.un);
+      }
+      {
+        const C* f = w[ct] + s0;
+        weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.ut, R.ut);
+      }
+      {
+        const C* f = w[3] + s0;
+        weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.p, R.p);
+      }
+    }
+    face_flux(isx, s0, st, cn, ct, fi, line, L, R);
+  };
   if constexpr (NDIM == 2 && !CHAR && sizeof(C) == 4) {
     // FP32 arithmetic: three consecutive faces per thread along a row
     // (x-faces) or a column (y-faces), sharing indicator sets and curvature
-    // terms (weno5_triple): TX + 1 and TY + 1 are multiples of 3, so the
-    // tile's faces split into NTX + NTY triples, one round of the workgroup.
-    // Lanes of a y-triple wave take neighbouring columns (consecutive LDS
-    // words).  In FP64 the 24 face values held through three flux
-    // evaluations need about 165 registers, which costs a quarter of the
-    // resident waves and more time than the shared work saves; FP64 tiles
-    // take one face per thread.
+    // terms (weno5_run); TX + 1 and TY + 1 are multiples of 3, so the tile's
+    // faces split into NTX + NTY triples, one round of the workgroup.  Lanes
+    // of a y-triple wave take neighbouring columns (consecutive LDS words).
+    // DIR as for face_task, per wave.  FP64 tiles take one face per thread:
+    // runs of three faces hold 24 face values through three flux evaluations
+    // (about 165 registers), and even pairs (144 registers, three resident
+    // waves per SIMD instead of four) were 4-6 % slower than single faces on
+    // 512^2 and 4096 x 2048 grids; forced into 128 registers they spill.
     static_assert((TX + 1) % 3 == 0 && (TY + 1) % 3 == 0, "face triples need TX + 1 and TY + 1 divisible by 3");
     constexpr int TPR = (TX + 1) / 3;  // triples per row of x-faces
     constexpr int NTX = TPR * TY, NTY = (TY + 1) / 3 * TX;
     static_assert(NTX + NTY <= NT, "one round of face triples");
-    const int t = threadIdx.x;
-    if (t < NTX + NTY) {
-      const bool isx = t < NTX;
-      int s0, st, cn, ct, fa, line;
+    auto triple_task = [&](int t, auto dirc) {
+      constexpr int DIR = decltype(dirc)::value;
+      const bool isx = DIR == 1 ? true : (DIR == 2 ? false : t < NTX);
+      int s0, fa, line;
       if (isx) {
         line = t / TPR;
         fa = 3 * (t - line * TPR);
         s0 = (line + H) * PX + fa;
-        st = 1; cn = 1; ct = 2;
       } else {
         const int u = t - NTX;
         fa = 3 * (u / TX);
         line = u - (fa / 3) * TX;
         s0 = fa * PX + line + H;
-        st = PX; cn = 2; ct = 1;
       }
+      const int st = isx ? 1 : PX;
+      const int cn = isx ? 1 : 2, ct = isx ? 2 : 1;
       C lr[3], rr[3], lu[3], ru[3], lt[3], rt[3], lp[3], rp[3];
-      weno5_triple(w[0] + s0, st, eps, lr, rr);
-      weno5_triple(w[cn] + s0, st, eps, lu, ru);
-      weno5_triple(w[ct] + s0, st, eps, lt, rt);
-      weno5_triple(w[3] + s0, st, eps, lp, rp);
+      weno5_run<3>(w[0] + s0, st, eps, lr, rr);
+      weno5_run<3>(w[cn] + s0, st, eps, lu, ru);
+      weno5_run<3>(w[ct] + s0, st, eps, lt, rt);
+      weno5_run<3>(w[3] + s0, st, eps, lp, rp);
 #pragma unroll
       for (int q = 0; q < 3; ++q)
         face_flux(isx, s0 + q * st, st, cn, ct, fa + q, line, Prim<C>{lr[q], lu[q], lt[q], lp[q]},
                   Prim<C>{rr[q], ru[q], rt[q], rp[q]});
+    };
+    const int t = threadIdx.x;
+    if (t < NTX + NTY) {
+      const int tw = t - (t & 63);  // first thread of this wave (wave-uniform)
+      const int tl = min(tw + 63, NTX + NTY - 1);
+      if (tl < NTX)
+        triple_task(t, IntC<1>{});
+      else if (tw >= NTX)
+        triple_task(t, IntC<2>{});
+      else
+        triple_task(t, IntC<0>{});
     }
   } else {
+    // A wave takes DIR 1 or 2 when all its faces lie in one direction, else
+    // DIR 0 (at most one wave of a round straddles the x/y boundary).
     for (int k = threadIdx.x; k < NFX + NFY; k += NT) {
-      const bool isx = k < NFX;
-      int s0, st, cn, ct, fi, line;
-      if (isx) {
-        fi = k % (TX + 1);
-        line = k / (TX + 1);
-        s0 = (NDIM == 2 ? (line + H) * PX : 0) + fi;
-        st = 1; cn = 1; ct = 2;
-      } else {
-        const int kk = k - NFX;
-        line = kk % TX;
-        fi = kk / TX;
-        s0 = fi * PX + line + H;
-        st = PX; cn = 2; ct = 1;
-      }
-      Prim<C> L, R;
-      if constexpr (CHAR) {
-        static_assert(sizeof(C) == 8, "characteristic reconstruction: FP64 tiles");
-        char_face_states(w[0] + s0, w[cn] + s0, w[ct] + s0, w[3] + s0, st, a.eps, a.gamma, L, R);
-      } else {
-        {
-          const C* f = w[0] + s0;
-          weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.r, R.r);
-        }
-        {
-          const C* f = w[cn] + s0;
-          weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.un, R.un);
-        }
-        {
-          const C* f = w[ct] + s0;
-          weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.ut, R.ut);
-        }
-        {
-          const C* f = w[3] + s0;
-          weno5_pair(f[0], f[st], f[2 * st], f[3 * st], f[4 * st], f[5 * st], eps, L.p, R.p);
-        }
-      }
-      face_flux(isx, s0, st, cn, ct, fi, line, L, R);
+      const int kw = k - (threadIdx.x & 63);  // first face of this wave's block (wave-uniform)
+      const int kl = min(kw + 63, NFX + NFY - 1);
+      if (kl < NFX)
+        face_task(k, IntC<1>{});
+      else if (kw >= NFX)
+        face_task(k, IntC<2>{});
+      else
+        face_task(k, IntC<0>{});
     }
   }
   if (my_fallback) atomicAdd(&blk_fallback, my_fallback);
@@ -941,12 +977,12 @@ hipError_t launch_init_scalars(const GridArgs& a, double t0, double t_end, hipSt
   return hipGetLastError();
 }
 
-// 2D tile shape (cells); chosen for 256 threads and a halo overhead near 2x.
-#ifndef SHK_TILE_X
-#define SHK_TILE_X 32
-#define SHK_TILE_Y 8
-#endif
-constexpr int TX2 = SHK_TILE_X, TY2 = SHK_TILE_Y;
+// 2D tile shape (cells; one thread per cell): 32 x 8, 256 threads.  A
+// 32 x 16 tile (512 threads, two workgroups per CU within the LDS) evaluates
+// 2.09 faces and loads 1.56 halo cells per cell instead of 2.16 and 1.94; in
+// FP64 it was 5 % faster on a 512^2 grid but 10 % slower on 4096 x 2048 and
+// 1 % slower on the 1024 x 512 cylinder.
+constexpr int TX2 = 32, TY2 = 8;
 constexpr int TX1 = 256;
 
 template <class S, class C, int MODE, bool CHAR, bool VISC>
@@ -954,11 +990,11 @@ static void launch_2d(const GridArgs& a, const S* Us, const S* Un, S* Uo, const 
                       hipStream_t st) {
   dim3 grid((a.nx + TX2 - 1) / TX2, (a.ny + TY2 - 1) / TY2, a.nbatch);
   if (a.cls != nullptr)
-    hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, VISC, MODE, NET_NONE, CHAR, true>), grid, dim3(256), 0, st,
-                       a, Us, Un, Uo, dtp, Lin, NetArgs{});
+    hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, VISC, MODE, NET_NONE, CHAR, true>), grid, dim3(TX2 * TY2),
+                       0, st, a, Us, Un, Uo, dtp, Lin, NetArgs{});
   else
-    hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, VISC, MODE, NET_NONE, CHAR, false>), grid, dim3(256), 0,
-                       st, a, Us, Un, Uo, dtp, Lin, NetArgs{});
+    hipLaunchKernelGGL((stage_kernel<S, C, 2, TX2, TY2, VISC, MODE, NET_NONE, CHAR, false>), grid, dim3(TX2 * TY2),
+                       0, st, a, Us, Un, Uo, dtp, Lin, NetArgs{});
 }
 
 template <class S, class C, int MODE, bool CHAR>
@@ -966,7 +1002,7 @@ static hipError_t launch_mode_r(const GridArgs& a, const S* Us, const S* Un, S* 
                                 const S* Lin, hipStream_t st) {
   if (a.ndim == 1) {
     dim3 grid((a.nx + TX1 - 1) / TX1, 1, a.nbatch);
-    hipLaunchKernelGGL((stage_kernel<S, C, 1, TX1, 1, false, MODE, NET_NONE, CHAR>), grid, dim3(256), 0, st, a,
+    hipLaunchKernelGGL((stage_kernel<S, C, 1, TX1, 1, false, MODE, NET_NONE, CHAR>), grid, dim3(TX1), 0, st, a,
                        Us, Un, Uo, dtp, Lin, NetArgs{});
   } else if (a.viscous) {
     launch_2d<S, C, MODE, CHAR, true>(a, Us, Un, Uo, dtp, Lin, st);
@@ -1009,8 +1045,8 @@ static hipError_t launch_net_mode(const GridArgs& a, const NetArgs& n, const dou
   dim3 grid((a.nx + TX2 - 1) / TX2, (a.ny + TY2 - 1) / TY2, a.nbatch);
   // the learned-correction variants always carry the immersed-boundary
   // handling (their register use is set by the network pass)
-  hipLaunchKernelGGL((stage_kernel<double, double, 2, TX2, TY2, false, MODE, NETK, false, true>), grid, dim3(256),
-                     0, st, a, Us, Un, Uo, dtp, nullptr, n);
+  hipLaunchKernelGGL((stage_kernel<double, double, 2, TX2, TY2, false, MODE, NETK, false, true>), grid,
+                     dim3(TX2 * TY2), 0, st, a, Us, Un, Uo, dtp, nullptr, n);
   return hipGetLastError();
 }
 
