@@ -16,8 +16,11 @@ LIB = os.path.join(HERE, "libshk.so")
 SOURCES = ["api.cpp", "stage.hip", "ibm.hip", "adjoint.hip", "mlp.hip", "cnn.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
+# -amdgpu-mfma-vgpr-form: matrix-core accumulators in ordinary VGPRs (the
+# activation code reads every accumulator element; from AGPRs each read is
+# an extra instruction).
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=on",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form=1",
          "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 OBJDIR = os.path.join(HERE, "_build")
 

@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(256) cnn_forward_kernel(CnnGeom g, CnnArgs n, 
         const int R = L.r0 - 2 + hr, C = L.c0 - 2 + hc;
         const bool live = wrap_pix(R, L.H, L.wr) >= 0 && wrap_pix(C, L.W, L.wc) >= 0;
         bf16x4 hv = {0, 0, 0, 0};
-        if (live) hv = pack4(fmaxf(acc[0], 0.f), fmaxf(acc[1], 0.f), fmaxf(acc[2], 0.f), fmaxf(acc[3], 0.f));
+        if (live) hv = pack4(relu0(acc[0]), relu0(acc[1]), relu0(acc[2]), relu0(acc[3]));
         *reinterpret_cast<bf16x4*>(sH1 + p * S1 + 4 * q) = hv;
         if (KEEP && R >= L.r0 && R < L.r0 + 16 && C >= L.c0 && C < L.c0 + 16 && R < L.H && C < L.W)
           *reinterpret_cast<bf16x4*>(h1g + (L.pbase + (long long)R * L.W + C) * 16 + 4 * q) = hv;
@@ -437,7 +437,7 @@ __global__ void __launch_bounds__(256) cnn_forward_kernel(CnnGeom g, CnnArgs n, 
           for (int mt = 0; mt < 2; ++mt) {
             const f32x4 a2 = acc[j][mt];
             bf16x4 hv = {0, 0, 0, 0};
-            if (live) hv = pack4(fmaxf(a2[0], 0.f), fmaxf(a2[1], 0.f), fmaxf(a2[2], 0.f), fmaxf(a2[3], 0.f));
+            if (live) hv = pack4(relu0(a2[0]), relu0(a2[1]), relu0(a2[2]), relu0(a2[3]));
             *reinterpret_cast<bf16x4*>(sH2 + p[j] * S2 + mt * 16 + 4 * q) = hv;
             if (own) *reinterpret_cast<bf16x4*>(h2g + (L.pbase + (long long)R * L.W + C) * 32 + mt * 16 + 4 * q) = hv;
           }

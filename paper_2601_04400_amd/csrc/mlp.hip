@@ -87,15 +87,16 @@ namespace {
 // distinct LDS bank pairs.
 constexpr int TR_LD = 20;
 
-__device__ __forceinline__ s16x8 pack8(f32x4 lo, f32x4 hi) {
-  return cat8(pack4(lo[0], lo[1], lo[2], lo[3]), pack4(hi[0], hi[1], hi[2], hi[3]));
-}
-
-// ReLU mask of the layer below: bit (tile * 4 + i) of m.
+// ReLU mask of the layer below: bit 15 - (tile * 4 + i) of m (relu_tile's
+// order), sign-extended to a whole word (all ones or zero) and applied to
+// the value's bits.
 __device__ __forceinline__ f32x4 relu_mask(f32x4 v, unsigned int m, int tile) {
   f32x4 r;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) r[i] = ((m >> (tile * 4 + i)) & 1u) ? v[i] : 0.f;
+  for (int i = 0; i < 4; ++i) {
+    const unsigned int keep = (unsigned int)((int)(m << (16 + tile * 4 + i)) >> 31);
+    r[i] = __uint_as_float(__float_as_uint(v[i]) & keep);
+  }
   return r;
 }
 
@@ -107,11 +108,11 @@ __device__ __forceinline__ float face_sum16(float v) {
   return v;
 }
 
-// dH = W^T . dA for a 64 x 64 layer (W^T rows in LDS), masked by the ReLU
-// of the layer below.
-__device__ __forceinline__ void hidden_input_grad(const unsigned short* wT, const f32x4 (&dA)[4], unsigned int mask,
+// dH = W^T . dA for a 64 x 64 layer (W^T rows in LDS; dA as bf16 tiles),
+// masked by the ReLU of the layer below.
+__device__ __forceinline__ void hidden_input_grad(const unsigned short* wT, const bf16x4 (&dA)[4], unsigned int mask,
                                                   f32x4 (&dB)[4], int lane) {
-  const s16x8 b0 = pack8(dA[0], dA[1]), b1 = pack8(dA[2], dA[3]);
+  const s16x8 b0 = cat8(dA[0], dA[1]), b1 = cat8(dA[2], dA[3]);
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -187,7 +188,6 @@ __global__ void __launch_bounds__(256, 2) net_backward_kernel(GridArgs a, NetArg
 #pragma unroll
     for (int i = 0; i < 4; ++i) xw[(r0 + 4 * q + i) * TR_LD + fl] = (unsigned short)v[i];
   };
-  auto putf = [&](int r0, f32x4 v) { put(r0, pack4(v[0], v[1], v[2], v[3])); };
   // operand slice of wave j's exchange rows: row r0 + (lane & 15), faces 4q .. 4q + 3
   auto get = [&](int j, int r0) { return *reinterpret_cast<const bf16x4*>(&xch[j][(r0 + fl) * TR_LD + 4 * q]); };
   const long long per_b = (nface + 15) / 16;
@@ -213,9 +213,9 @@ __global__ void __launch_bounds__(256, 2) net_backward_kernel(GridArgs a, NetArg
     const long long fc = f < nface ? f : nface - 1;
     const double* __restrict__ Ub = U + (long long)b * 4 * a.ncell;
     const double* __restrict__ Lb = lam + (long long)b * 4 * a.ncell;
-    // the adjoint of the two cells beside the face (zero outside the domain
-    // unless periodic, and in solid cells)
-    auto lam_cell = [&](int gi, int gj, double l[4]) {
+    // component v of the adjoint of a cell beside the face (zero outside the
+    // domain unless periodic, and in solid cells)
+    auto lam_cell = [&](int gi, int gj, int v) {
       bool ok = true;
       if (gi < 0 || gi >= a.nx) {
         ok = perx;
@@ -227,55 +227,54 @@ __global__ void __launch_bounds__(256, 2) net_backward_kernel(GridArgs a, NetArg
       }
       const int c = gj * a.nx + gi;
       if (ok && a.cls != nullptr) ok = a.cls[c] == CELL_FLUID;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) l[v] = ok ? Lb[(long long)v * a.ncell + c] : 0.0;
+      return ok ? Lb[(long long)v * a.ncell + c] : 0.0;
     };
-    // upstream gradient of the face flux (face frame), lanes q == 0; loaded
-    // before the forward so the loads overlap it
-    double fb[4] = {0.0, 0.0, 0.0, 0.0};
-    if (q == 0 && fok) {
+    // upstream gradient of the face flux (face frame): lane (face fl, q)
+    // forms component q; loaded before the forward so the loads overlap it
+    double fbq = 0.0;
+    if (fok) {
       const double clam = clam_f * (dtp ? dtp[b] : 1.0);
       const int fi = (int)f;
-      double lo[4], hi[4];
       if (fi < nxf) {
         const int gj = fi / (a.nx + 1), gf = fi - gj * (a.nx + 1);
-        lam_cell(gf - 1, gj, lo);
-        lam_cell(gf, gj, hi);
         const double sc = clam * a.inv_dx;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) fb[v] = sc * (hi[v] - lo[v]);
+        fbq = sc * (lam_cell(gf, gj, q) - lam_cell(gf - 1, gj, q));
       } else {
         const int g = fi - nxf, gf = g / a.nx, gi = g - gf * a.nx;
-        lam_cell(gi, gf - 1, lo);
-        lam_cell(gi, gf, hi);
+        const int vy = q == 1 ? 2 : (q == 2 ? 1 : q);
         const double sc = clam * a.inv_dy;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int vy = v == 1 ? 2 : (v == 2 ? 1 : v);
-          fb[v] = sc * (hi[vy] - lo[vy]);
-        }
+        fbq = sc * (lam_cell(gi, gf, vy) - lam_cell(gi, gf - 1, vy));
       }
     }
     ActsT<1> A;
     f32x4 z[1];
     build_inputs(a, n, Ub, fc, lane, A.x[0][0], A.x[1][0]);
-    net_forward_batch<1>(sw, sb, lane, A, z);
+    net_forward_batch<1, true>(sw, sb, lane, A, z);
+    // d3 = gradient of the pre-tanh outputs.  Lanes q == 0 hold the outputs
+    // z[0][0..3] of face fl; lane (fl, q) takes output q through this wave's
+    // exchange rows (nothing reads them before this wave's first barrier of
+    // the round), forms its component there, and lanes q == 0 gather the
+    // four back.  One wave's LDS operations complete in order.
     f32x4 d3 = {0.f, 0.f, 0.f, 0.f};
-    if (q == 0)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float th = tanhf(z[0][i]);
-        d3[i] = float(fb[i]) * n.out_scale * (1.f - th * th);
-      }
+    {
+      float* zx = reinterpret_cast<float*>(xw);  // [face][4]
+      if (q == 0) *reinterpret_cast<f32x4*>(zx + 4 * fl) = z[0];
+      const float th = tanhf(zx[4 * fl + q]);
+      zx[4 * fl + q] = float(fbq) * n.out_scale * (1.f - th * th);
+      if (q == 0) d3 = *reinterpret_cast<const f32x4*>(zx + 4 * fl);
+    }
     const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
     f32x4 dA[4], dB[4];
+    // every gradient tile is rounded to bf16 once, for the exchange and for
+    // the next product
+    bf16x4 pk[4];
     // output layer (16 rows, 4 used): dZ3 and H2 out, dH2 = W3^T dZ3
-    putf(0, d3);
-#pragma unroll
-    for (int it = 0; it < 4; ++it) put(64 + it * 16, A.h[2][it][0]);
-    bs3 += d3;
     {
       const bf16x4 b3 = pack4(d3[0], d3[1], d3[2], d3[3]);
+      put(0, b3);
+#pragma unroll
+      for (int it = 0; it < 4; ++it) put(64 + it * 16, A.h[2][it][0]);
+      bs3 += d3;
 #pragma unroll
       for (int it = 0; it < 4; ++it)
         dA[it] = relu_mask(mfma(ldA(swT + NET_T_W3, NET_LD_O, it * 16, 0, lane), b3, zero), A.mask[2][0], it);
@@ -287,11 +286,12 @@ __global__ void __launch_bounds__(256, 2) net_backward_kernel(GridArgs a, NetArg
     // layer 2: dZ2 = dA, input H1
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot) {
-      putf(ot * 16, dA[ot]);
+      pk[ot] = pack4(dA[ot][0], dA[ot][1], dA[ot][2], dA[ot][3]);
+      put(ot * 16, pk[ot]);
       put(64 + ot * 16, A.h[1][ot][0]);
       bs2[ot] += dA[ot];
     }
-    hidden_input_grad(swT + NET_T_W2, dA, A.mask[1][0], dB, lane);
+    hidden_input_grad(swT + NET_T_W2, pk, A.mask[1][0], dB, lane);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -303,11 +303,12 @@ __global__ void __launch_bounds__(256, 2) net_backward_kernel(GridArgs a, NetArg
     // layer 1: dZ1 = dB, input H0
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot) {
-      putf(ot * 16, dB[ot]);
+      pk[ot] = pack4(dB[ot][0], dB[ot][1], dB[ot][2], dB[ot][3]);
+      put(ot * 16, pk[ot]);
       put(64 + ot * 16, A.h[0][ot][0]);
       bs1[ot] += dB[ot];
     }
-    hidden_input_grad(swT + NET_T_W1, dB, A.mask[0][0], dA, lane);
+    hidden_input_grad(swT + NET_T_W1, pk, A.mask[0][0], dA, lane);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -319,7 +320,8 @@ __global__ void __launch_bounds__(256, 2) net_backward_kernel(GridArgs a, NetArg
     // first layer (inputs 0..23; 24..31 are zero padding): dZ0 = dA, input X
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot) {
-      putf(ot * 16, dA[ot]);
+      pk[ot] = pack4(dA[ot][0], dA[ot][1], dA[ot][2], dA[ot][3]);
+      put(ot * 16, pk[ot]);
       bs0[ot] += dA[ot];
     }
     put(64, A.x[0][0]);
@@ -327,7 +329,7 @@ __global__ void __launch_bounds__(256, 2) net_backward_kernel(GridArgs a, NetArg
     {
       // stencil gradient dX = W0^T dA (every lane takes part in the products;
       // the stores are masked)
-      const s16x8 b0 = pack8(dA[0], dA[1]), b1 = pack8(dA[2], dA[3]);
+      const s16x8 b0 = cat8(pk[0], pk[1]), b1 = cat8(pk[2], pk[3]);
       f32x4 dx[2];
 #pragma unroll
       for (int it = 0; it < 2; ++it) {

@@ -59,8 +59,12 @@ __device__ __forceinline__ bf16x4 ldAT(const unsigned short* m, int ld, int r0, 
                 (short)m[(k + 3) * ld + r]};
 }
 
+// Four floats to bfloat16 (round to nearest even) as two packed conversions
+// (v_cvt_pk_bf16_f32 takes a pair).
 __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
-  return bf16x4{(short)f2bf(a), (short)f2bf(b), (short)f2bf(c), (short)f2bf(d)};
+  typedef float f32x4v __attribute__((ext_vector_type(4)));
+  typedef __bf16 bf16x4v __attribute__((ext_vector_type(4)));
+  return __builtin_bit_cast(bf16x4, __builtin_convertvector(f32x4v{a, b, c, d}, bf16x4v));
 }
 
 // Network input of one 16-face tile from the face's six stencil cells:
@@ -108,12 +112,39 @@ template <int FT = 4>
 struct ActsT {
   bf16x4 x[2][FT];
   bf16x4 h[3][4][FT];        // layer, neuron tile, face tile
-  unsigned int mask[3][FT];  // bit (nt*4 + i) of face tile ft: pre-activation > 0
+  unsigned int mask[3][FT];  // bit 15 - (nt*4 + i) of face tile ft: pre-activation > 0
 };
 typedef ActsT<4> Acts;
 
-// FT face tiles of 16 faces per call (FT = 4: 64 faces per wave).
-template <int FT = 4>
+// max(x, 0) as one integer maximum of the bit pattern: every non-negative
+// float orders like its bits taken as a signed integer and every negative
+// one (-0 included) is below zero, so the result is max(x, 0) with -0 giving
+// +0 for every number (a floating-point maximum first quiets a NaN operand,
+// a second instruction); a NaN of positive sign passes through, which
+// carries it to the network output and its non-finite check.
+__device__ __forceinline__ float relu0(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+// ReLU of one accumulator tile.  MASK (the reverse pass): the activations
+// and the mask bits shifted into m (the tile's four rows in order, each
+// appended at bit 0; set where the pre-activation is positive), a select on
+// the comparison.  Otherwise the activations alone (relu0).
+template <bool MASK>
+__device__ __forceinline__ void relu_tile(f32x4 acc, float hv[4], unsigned int& m) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if constexpr (MASK) {
+      const bool pos = acc[i] > 0.f;
+      hv[i] = pos ? acc[i] : 0.f;
+      m = m * 2u + (pos ? 1u : 0u);
+    } else {
+      hv[i] = relu0(acc[i]);
+    }
+  }
+}
+
+// FT face tiles of 16 faces per call (FT = 4: 64 faces per wave); MASK:
+// keep the ReLU masks (the reverse pass).
+template <int FT = 4, bool MASK = false>
 __device__ __forceinline__ void net_forward_batch(const unsigned short* sw, const float* sb, int lane, ActsT<FT>& A,
                                                   f32x4 z[FT]) {
   const int q = lane >> 4;
@@ -129,12 +160,7 @@ __device__ __forceinline__ void net_forward_batch(const unsigned short* sw, cons
       f32x4 acc = {b0[0], b0[1], b0[2], b0[3]};
       acc = mfma32(ldA32(sw + NET_L_W0, NET_LD_W0, nt * 16, 0, lane), cat8(A.x[0][ft], A.x[1][ft]), acc);
       float hv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float pre = acc[i];
-        hv[i] = pre > 0.f ? pre : 0.f;
-        if (pre > 0.f) A.mask[0][ft] |= 1u << (nt * 4 + i);
-      }
+      relu_tile<MASK>(acc, hv, A.mask[0][ft]);
       A.h[0][nt][ft] = pack4(hv[0], hv[1], hv[2], hv[3]);
     }
   // layers 2 and 3: 64 x 64
@@ -154,12 +180,7 @@ __device__ __forceinline__ void net_forward_batch(const unsigned short* sw, cons
         for (int kb = 0; kb < 2; ++kb)
           acc = mfma32(ldA32(W, NET_LD_H, nt * 16, kb, lane), cat8(A.h[l - 1][2 * kb][ft], A.h[l - 1][2 * kb + 1][ft]), acc);
         float hv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float pre = acc[i];
-          hv[i] = pre > 0.f ? pre : 0.f;
-          if (pre > 0.f) A.mask[l][ft] |= 1u << (nt * 4 + i);
-        }
+        relu_tile<MASK>(acc, hv, A.mask[l][ft]);
         A.h[l][nt][ft] = pack4(hv[0], hv[1], hv[2], hv[3]);
       }
   }
