@@ -24,7 +24,7 @@ using namespace shk;
 struct WsLayout {
   size_t scalars, globals, dtbuf, xslots, u1, u2, cls, row_count, row_off, g_cell, g_src, g_w, g_nrm;
   size_t adjA, adjB, adjC, adjP, adjQ, adjPart, part_stride, adjG, ghostOf, entKeys, entVals, entCount, entHeads;
-  size_t netX, netPart, cnnDF, cnnBufs, vjpPart;
+  size_t netX, netPart, cnnDF, cnnBufs, vjpPart, tileBody, tileOrder;
   size_t total;
 };
 
@@ -120,6 +120,8 @@ WsLayout layout(const shk_grid_desc* d) {
     L.g_w = o; o += al(sizeof(double) * 4 * cap);
     L.g_nrm = o; o += al(sizeof(double) * 2 * cap);
     L.ghostOf = o; o += al(sizeof(int) * ncell);
+    L.tileBody = o; o += al(size_t(stage_tiles(d->nx, d->ny)));
+    L.tileOrder = o; o += al(sizeof(int) * size_t(stage_tiles(d->nx, d->ny)));
   }
   if (d->adjoint) {
     const size_t st64 = al(size_t(d->nbatch) * 4 * ncell * sizeof(double));
@@ -369,12 +371,40 @@ shk_status shk_prim_to_cons_vjp(shk_grid* g, const void* W, const void* U_bar, v
                    "prim_to_cons_vjp");
 }
 
+// Dispatch order of the 2D stage tiles of a grid with a body: workgroup w
+// goes to XCD w % 8 (round robin), so XCD x takes the tiles of queue x in
+// order.  The tiles near the body (their ghost cells chain four dependent
+// loads and take longest) come first, dealt round robin, so that none of
+// them is left for the launch's last round; each XCD then takes one
+// contiguous run of the other tiles in row-major order, whose shared halo
+// rows stay in that XCD's L2.
+static std::vector<int> body_first_order(int gx, int gy, const std::vector<uint8_t>& body) {
+  const int n = gx * gy;
+  std::vector<std::vector<int>> q(8);
+  int nb = 0;
+  for (int t = 0; t < n; ++t)
+    if (body[t]) q[nb++ % 8].push_back(t);
+  int t = 0;
+  for (int x = 0; x < 8; ++x) {
+    const int cnt = n > x ? (n - x + 7) / 8 : 0;  // workgroups x, x + 8, ... below n
+    while (int(q[x].size()) < cnt) {
+      while (body[t]) ++t;
+      q[x].push_back(t++);
+    }
+  }
+  std::vector<int> order(n);
+  for (int w = 0; w < n; ++w) order[w] = q[w % 8][w / 8];
+  return order;
+}
+
 shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
   if (!g) return SHK_EINVAL;
   if (!phi) {
     g->ibm_on = false;
     g->a.cls = nullptr;
     g->a.ghost_of = nullptr;
+    g->a.tile_body = nullptr;
+    g->a.tile_order = nullptr;
     g->gt.n = 0;
     g->a.gt = g->gt;
     return SHK_OK;
@@ -405,6 +435,8 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
     g->ibm_on = false;
     g->a.cls = nullptr;
     g->a.ghost_of = nullptr;
+    g->a.tile_body = nullptr;
+    g->a.tile_order = nullptr;
     g->gt.n = 0;
     g->a.gt = g->gt;
     return fail(g, SHK_EINVAL, "set_ib_levelset: " + std::to_string(nbad) +
@@ -426,6 +458,26 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
   if (e == hipSuccess) e = hipStreamSynchronize(g->st);
   if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset (ghost index)");
   a.ghost_of = gof;
+  // tiles whose cells and halo sources are all fluid skip the immersed-boundary
+  // handling in the stage kernels
+  uint8_t* tb = reinterpret_cast<uint8_t*>(g->ws + g->L.tileBody);
+  int* to = reinterpret_cast<int*>(g->ws + g->L.tileOrder);
+  a.tile_body = nullptr;
+  a.tile_order = nullptr;
+  const int tgx = (a.nx + STAGE_TX - 1) / STAGE_TX, tgy = (a.ny + STAGE_TY - 1) / STAGE_TY;
+  std::vector<uint8_t> body(size_t(tgx) * tgy);
+  std::vector<int> order;
+  e = launch_tile_body(a, tb, g->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(body.data(), tb, body.size(), hipMemcpyDeviceToHost, g->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+  if (e == hipSuccess) {
+    order = body_first_order(tgx, tgy, body);
+    e = hipMemcpyAsync(to, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice, g->st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+  if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset (tile flags)");
+  a.tile_body = tb;
+  a.tile_order = to;
   if (g->d.adjoint && n > 0) {
     int* keys = reinterpret_cast<int*>(g->ws + g->L.entKeys);
     int* vals = reinterpret_cast<int*>(g->ws + g->L.entVals);

@@ -9,6 +9,7 @@ namespace shk {
 enum : int { BC_TRANS = 0, BC_REFL = 1, BC_INFLOW = 2, BC_PERIODIC = 3 };
 enum : uint8_t { CELL_FLUID = 0, CELL_SOLID = 1, CELL_GHOST = 2 };
 constexpr int HALO = 3;
+constexpr int STAGE_TX = 32, STAGE_TY = 8;  // cells of a 2D stage-kernel tile
 constexpr int XSLOTS = 64;  // atomic targets the blocks of one reduction spread over
 
 // Per-batch-member device scalars of the time loop.
@@ -57,6 +58,12 @@ struct GridArgs {
   double* dt_out;              // optional caller copy of the step (per call)
   void* stage_in_copy;         // MODE_STAGE1: optional copy of the stage input (storage type), or nullptr
   const int* ghost_of;         // immersed boundary: ghost index of each cell or -1 (else nullptr)
+  const uint8_t* tile_body;    // immersed boundary: per 2D stage tile (STAGE_TX x STAGE_TY cells, row-major
+                               // over the tile grid), 1 if a cell of the tile or of any source cell its halo
+                               // loads is not fluid (else nullptr: every tile checks its cells)
+  const int* tile_order;       // immersed boundary: the stage tile (row-major index) each workgroup of a
+                               // 2D stage launch takes, by workgroup index within a batch member (else
+                               // nullptr: the XCD-aware order of xcd_tile)
   GhostTable gt;               // immersed boundary: the ghost table (gt.n = 0 without)
   void* ghost_back;            // stage kernels: where the refilled ghost values of the stage
                                // state are written (storage type; usually the stage state
@@ -95,6 +102,11 @@ template <class S>
 hipError_t launch_ibm_fill(const GridArgs& a, const GhostTable& gt, S* U, hipStream_t st);
 hipError_t launch_ibm_classify(const GridArgs& a, const double* phi, uint8_t* cls, int* row_count,
                                hipStream_t st);
+// per-tile flags of the stage kernel's immersed-boundary handling (a.cls set)
+hipError_t launch_tile_body(const GridArgs& a, uint8_t* flags, hipStream_t st);
+inline long long stage_tiles(int nx, int ny) {
+  return (long long)((nx + STAGE_TX - 1) / STAGE_TX) * ((ny + STAGE_TY - 1) / STAGE_TY);
+}
 hipError_t launch_ibm_table(const GridArgs& a, const double* phi, const uint8_t* cls, const int* row_count,
                             int* row_off, GhostTable gt, int* nbad, hipStream_t st);
 // Stage kernel with the learned correction evaluated inside the tile (2D,

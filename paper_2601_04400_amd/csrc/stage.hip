@@ -41,13 +41,13 @@ __device__ __forceinline__ int bc_source(int g, int n, int bc_lo, int bc_hi, int
   return s < 0 ? 0 : (s >= n ? n - 1 : s);
 }
 
-// Refilled value of the immersed-boundary ghost cell c of a stage state
+// Refilled value of the immersed-boundary ghost cell of ghost index k of a stage state
 // whose plane e of interior cell c is get(e, c), rounded to the storage type
 // as the separate refill stores it.
 template <class S, class C, class Get>
-__device__ __forceinline__ void ghost_at(const GridArgs& a, long long c, Get&& get, C q[4]) {
+__device__ __forceinline__ void ghost_at(const GridArgs& a, int k, Get&& get, C q[4]) {
   double g[4];
-  ghost_cons(a.gt, a.gamma, a.ghost_of[c], [&](int e, long long s) { return double(get(e, s)); }, g);
+  ghost_cons(a.gt, a.gamma, k, [&](int e, long long s) { return double(get(e, s)); }, g);
 #pragma unroll
   for (int v = 0; v < 4; ++v) q[v] = C(S(g[v]));
 }
@@ -78,9 +78,12 @@ __device__ __forceinline__ void load_cons_f(const GridArgs& a, int gi, int gj, G
     E = C(a.inflow_cons[3]);
   } else {
     const long long c = (long long)sj * a.nx + si;
-    if (GH && a.cls != nullptr && a.cls[c] == CELL_GHOST) {
+    // the ghost index itself marks a ghost cell (one load fewer ahead of the
+    // refill's dependent loads than testing the cell class first)
+    const int gk = GH && a.ghost_of != nullptr ? a.ghost_of[c] : -1;
+    if (gk >= 0) {
       C g[4];
-      ghost_at<S>(a, c, get, g);
+      ghost_at<S>(a, gk, get, g);
       r = g[0]; mx = g[1]; my = g[2]; E = g[3];
     } else {
       r = get(0, c);
@@ -250,7 +253,8 @@ struct IntC {
 // CHAR: characteristic-wise WENO5 instead of the primitive-wise one (FP64).
 // IBM: the grid has an immersed boundary (a.cls, a.ghost_of and a.gt set):
 // ghost cells take their refilled values, formed from the stage state's
-// fluid cells as they are loaded, and their right-hand side is zero.
+// fluid cells as they are loaded, and their right-hand side is zero.  Tiles
+// that a.tile_body marks all fluid skip this handling.
 template <class S, class C, int NDIM, int TX, int TY, bool VISC, int MODE, int NET = NET_NONE, bool CHAR = false,
           bool IBM = false>
 __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArgs a, const S* Us, const S* Un, S* Uout,
@@ -285,7 +289,15 @@ __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArg
   __shared__ double red_s[NT / 64], red_r[NT / 64];
 
   int bx, by, b;
-  xcd_tile(bx, by, b);
+  if (GH && TX == STAGE_TX && TY == STAGE_TY && a.tile_order != nullptr) {
+    // grid with a body: the tiles near it first (host-built order)
+    const int t = a.tile_order[blockIdx.x + gridDim.x * blockIdx.y];
+    bx = t % gridDim.x;
+    by = t / gridDim.x;
+    b = blockIdx.z;
+  } else {
+    xcd_tile(bx, by, b);
+  }
   StepScalars* sc = a.sc + b;
   const bool lead = bx == 0 && by == 0 && threadIdx.x == 0;
   double dt = 0.0;
@@ -332,6 +344,15 @@ __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArg
   if (threadIdx.x == 0) { blk_fallback = 0; blk_fault = 0; }
   const int i0 = bx * TX;
   const int j0 = by * TY;
+  // immersed boundary: a tile whose cells and halo sources are all fluid
+  // (the same for the whole workgroup) takes the plain path, reading no
+  // cell classes
+  bool body = false;
+  if constexpr (GH) {
+    body = a.cls != nullptr;
+    if constexpr (TX == STAGE_TX && TY == STAGE_TY)
+      if (body && a.tile_body != nullptr) body = a.tile_body[by * gridDim.x + bx] != 0;
+  }
   const long long boff = (long long)b * a.nvar * a.ncell;
   const S* Ub = Us + boff;
   const S* __restrict__ Lb = MODE == MODE_S2F ? Lin + boff : nullptr;
@@ -358,10 +379,17 @@ __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArg
     const int gi = i0 + lx - H;
     const int gj = NDIM == 2 ? j0 + ly - H : 0;
     C q[4];
-    if (MODE == MODE_S2F)
-      load_cons_f<S, C, NDIM, GH>(a, gi, gj, u1_at, q, inside);
-    else
-      load_cons<S, C, NDIM, GH>(a, Ub, gi, gj, q, inside);
+    if (MODE == MODE_S2F) {
+      if (body)
+        load_cons_f<S, C, NDIM, GH>(a, gi, gj, u1_at, q, inside);
+      else
+        load_cons_f<S, C, NDIM, false>(a, gi, gj, u1_at, q, inside);
+    } else {
+      if (body)
+        load_cons<S, C, NDIM, GH>(a, Ub, gi, gj, q, inside);
+      else
+        load_cons<S, C, NDIM, false>(a, Ub, gi, gj, q, inside);
+    }
     Prim<C> p = to_prim(q[0], q[1], q[2], q[3], gm1);
     nonphys = nonphys || !(p.r > C(0)) || !(p.p > C(0));
     w[0][k] = p.r;
@@ -664,15 +692,18 @@ __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArg
     const int gi = i0 + x, gj = j0 + y;
     if (gi >= a.nx || gj >= a.ny) continue;
     const long long cell = (long long)gj * a.nx + gi;
-    const uint8_t cc = GH && a.cls != nullptr ? a.cls[cell] : CELL_FLUID;
+    // the class (solid cells keep a zero right-hand side) and the ghost index
+    // are independent loads, issued together
+    const uint8_t cc = GH && body ? a.cls[cell] : CELL_FLUID;
+    const int gk = GH && body ? a.ghost_of[cell] : -1;
     // the cell's stage-state and U^n values, all read before any write (the
     // output may overwrite U^n); a ghost cell takes its refilled stage value
     C us[4], un[4];
-    if (GH && cc == CELL_GHOST) {
+    if (GH && gk >= 0) {
       if (MODE == MODE_S2F)
-        ghost_at<S>(a, cell, u1_at, us);
+        ghost_at<S>(a, gk, u1_at, us);
       else
-        ghost_at<S>(a, cell, [&](int e, long long c) { return C(Ub[e * a.ncell + c]); }, us);
+        ghost_at<S>(a, gk, [&](int e, long long c) { return C(Ub[e * a.ncell + c]); }, us);
       if (MODE != MODE_S2F && a.ghost_back != nullptr)
 #pragma unroll
         for (int v = 0; v < 4; ++v) static_cast<S*>(a.ghost_back)[boff + v * a.ncell + cell] = S(us[v]);
@@ -779,6 +810,31 @@ __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArg
     }
     if (blk_fault) atomicOr(&a.glob->fault, blk_fault);
   }
+}
+
+// ------------------------------------------------- immersed-boundary tiles
+// Flag of one 2D stage tile: 1 if any cell of the tile or any source cell
+// its halo loads (the tile and three layers around it, corners included,
+// mapped by the boundary rules) is not fluid.  One workgroup per tile.
+__global__ void __launch_bounds__(256) tile_body_kernel(GridArgs a, uint8_t* __restrict__ flags) {
+  constexpr int PX = STAGE_TX + 2 * HALO, PY = STAGE_TY + 2 * HALO;
+  const int i0 = blockIdx.x * STAGE_TX, j0 = blockIdx.y * STAGE_TY;
+  int any = 0;
+  for (int k = threadIdx.x; k < PX * PY; k += blockDim.x) {
+    int fx = 0, fy = 0;
+    const int si = bc_source(i0 - HALO + k % PX, a.nx, a.bc[0], a.bc[1], fx);
+    const int sj = bc_source(j0 - HALO + k / PX, a.ny, a.bc[2], a.bc[3], fy);
+    if (a.cls[(long long)sj * a.nx + si] != CELL_FLUID) any = 1;
+  }
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) flags[blockIdx.y * gridDim.x + blockIdx.x] = any ? 1 : 0;
+}
+
+hipError_t launch_tile_body(const GridArgs& a, uint8_t* flags, hipStream_t st) {
+  if (a.ndim != 2 || a.cls == nullptr) return hipErrorInvalidValue;
+  const dim3 grid((a.nx + STAGE_TX - 1) / STAGE_TX, (a.ny + STAGE_TY - 1) / STAGE_TY);
+  hipLaunchKernelGGL(tile_body_kernel, grid, dim3(256), 0, st, a, flags);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------ CFL kernel
@@ -982,7 +1038,7 @@ hipError_t launch_init_scalars(const GridArgs& a, double t0, double t_end, hipSt
 // 2.09 faces and loads 1.56 halo cells per cell instead of 2.16 and 1.94; in
 // FP64 it was 5 % faster on a 512^2 grid but 10 % slower on 4096 x 2048 and
 // 1 % slower on the 1024 x 512 cylinder.
-constexpr int TX2 = 32, TY2 = 8;
+constexpr int TX2 = STAGE_TX, TY2 = STAGE_TY;
 constexpr int TX1 = 256;
 
 template <class S, class C, int MODE, bool CHAR, bool VISC>
