@@ -387,8 +387,8 @@ static std::vector<int> body_first_order(int gx, int gy, const std::vector<uint8
   int t = 0;
   for (int x = 0; x < 8; ++x) {
     const int cnt = n > x ? (n - x + 7) / 8 : 0;  // workgroups x, x + 8, ... below n
-    while (int(q[x].size()) < cnt) {
-      while (body[t]) ++t;
+    while (int(q[x].size()) < cnt) {  // the counts add up to the n - nb other tiles
+      while (t < n - 1 && body[t]) ++t;
       q[x].push_back(t++);
     }
   }
