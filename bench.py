@@ -50,7 +50,7 @@ FLOPS_PER_CELL_STAGE_CHAR = FLOPS_PER_CELL_STAGE + 660
 # (12 words each).  With an immersed boundary each stage also reads the
 # one-byte cell class.
 WORDS_PER_CELL_STEP = 32
-STAGE_SOURCES = ("stage.hip", "flux.hpp", "xcd.hpp", "ibm_dev.hpp")
+STAGE_SOURCES = ("stage.hip", "flux.hpp", "grid.hpp", "ibm_dev.hpp", "xcd.hpp", "mlp.hpp", "mlp_dev.hpp")
 # Measured counters of the stage kernels (per dispatch, mean of the three
 # stage modes): HBM bytes from FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the
 # copy-kernel calibration) and SQ_INSTS_VALU (wave instructions), for the
@@ -58,11 +58,11 @@ STAGE_SOURCES = ("stage.hip", "flux.hpp", "xcd.hpp", "ibm_dev.hpp")
 # reports them as null.
 MEASURED = {
     ("cylinder", 1024, 512, "f64"): {
-        "sources_sha256": "2f9df58c094e01a808c8702c02176151f74f1b13f1aeee0e2e0105325fd3494e",
+        "sources_sha256": "fa48f3903100d4f691182b1a541a56778a5052b0f1fa356aa6bfa437f1e78e1a",
         "bytes_per_launch": 49919356, "valu_wave_instr_per_launch": 13297597,
         "profile": "profiles/stage_kernel_cylinder1024x512_ns_f64.md"},
     ("quadrant", 4096, 2048, "f64"): {
-        "sources_sha256": "2f9df58c094e01a808c8702c02176151f74f1b13f1aeee0e2e0105325fd3494e",
+        "sources_sha256": "fa48f3903100d4f691182b1a541a56778a5052b0f1fa356aa6bfa437f1e78e1a",
         "bytes_per_launch": 803330013, "valu_wave_instr_per_launch": 186249713,
         "profile": "profiles/stage_kernel_quadrant4096x2048_f64.md"},
 }
@@ -534,11 +534,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "quadrant", "sod", "paper-cylinder"],
+    ap.add_argument("--workload", default="cylinder",
+                    choices=["cylinder", "quadrant", "sod", "paper-cylinder", "adjoint"],
                     help="cylinder: the viscous shock-cylinder case at 1024x512 (default, with the extra keys); "
                          "quadrant: the four-quadrant Riemann problem (--nx, --ny, --prec, --weno, --graph); "
-                         "sod: the 200-cell shock tube; paper-cylinder: the section 3 run at 4096x2048 "
-                         "(each prints its own line)")
+                         "sod: the 200-cell shock tube; paper-cylinder: the section 3 run at 4096x2048; "
+                         "adjoint: the adjoint:forward measurement alone (each prints its own line)")
     ap.add_argument("--nx", type=int, default=512, help="quadrant: cells along x")
     ap.add_argument("--ny", type=int, default=512, help="quadrant: cells along y")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "mixed"], help="quadrant: precision")
@@ -584,6 +585,13 @@ def main():
         return
     if args.workload == "paper-cylinder":
         print(json.dumps(paper_cylinder_workload(args)), flush=True)
+        return
+    if args.workload == "adjoint":
+        # the adjoint:forward measurement of the default line on its own
+        res = adjoint_ratio()
+        print(json.dumps({"metric": "adjoint:forward cost ratio", "value": res["ratio"], "unit": "ratio",
+                          "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": res["workload"]}, "adjoint": res}), flush=True)
         return
     if args.workload == "quadrant":
         q = quadrant_run(args.nx, args.ny, args.prec, args.steps, args.warmup, args.weno == "char", args.graph)
