@@ -1,7 +1,7 @@
 // Oracle: plain serial CPU solver for the compressible Euler / Navier-Stokes
 // right-hand side, the SSP-RK3 step and the ghost-cell immersed boundary.
 //
-// TEST INFRASTRUCTURE ONLY.  This code exists to judge the GPU library: it is
+// TEST INFRASTRUCTURE ONLY.  This code exists to check the GPU library: it is
 // loaded by the test suite, by the package's smoke check and by the CPU
 // baseline leg of the benchmark, and by nothing else.  It shares no code,
 // header, table or constant with the GPU path.
