@@ -78,23 +78,23 @@ __device__ __forceinline__ void load_cons_f(const GridArgs& a, int gi, int gj, G
     E = C(a.inflow_cons[3]);
   } else {
     const long long c = (long long)sj * a.nx + si;
-    // the ghost index itself marks a ghost cell (one load fewer ahead of the
-    // refill's dependent loads than testing the cell class first)
+    // the state loads do not wait for the ghost test: they are issued beside
+    // the ghost-index load (which itself marks a ghost cell), and a ghost
+    // cell's values are then replaced by its refilled ones
+    r = get(0, c);
+    mx = get(1, c);
+    if (NDIM == 2) {
+      my = get(2, c);
+      E = get(3, c);
+    } else {
+      my = C(0);
+      E = get(2, c);
+    }
     const int gk = GH && a.ghost_of != nullptr ? a.ghost_of[c] : -1;
     if (gk >= 0) {
       C g[4];
       ghost_at<S>(a, gk, get, g);
       r = g[0]; mx = g[1]; my = g[2]; E = g[3];
-    } else {
-      r = get(0, c);
-      mx = get(1, c);
-      if (NDIM == 2) {
-        my = get(2, c);
-        E = get(3, c);
-      } else {
-        my = C(0);
-        E = get(2, c);
-      }
     }
     mx = (fx & 1) ? -mx : mx;
   }
@@ -698,7 +698,15 @@ __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArg
     const int gk = GH && body ? a.ghost_of[cell] : -1;
     // the cell's stage-state and U^n values, all read before any write (the
     // output may overwrite U^n); a ghost cell takes its refilled stage value
+    // (its stored one is loaded anyway, beside the ghost index, and replaced)
     C us[4], un[4];
+    if (MODE != MODE_RHS && MODE != MODE_S1L) {
+#pragma unroll
+      for (int e = 0; e < NV; ++e) {
+        const int v = (NDIM == 1 && e == 2) ? 3 : e;
+        us[v] = MODE == MODE_S2F ? u1_at(e, cell) : C(Ub[e * a.ncell + cell]);
+      }
+    }
     if (GH && gk >= 0) {
       if (MODE == MODE_S2F)
         ghost_at<S>(a, gk, u1_at, us);
@@ -707,12 +715,6 @@ __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArg
       if (MODE != MODE_S2F && a.ghost_back != nullptr)
 #pragma unroll
         for (int v = 0; v < 4; ++v) static_cast<S*>(a.ghost_back)[boff + v * a.ncell + cell] = S(us[v]);
-    } else if (MODE != MODE_RHS && MODE != MODE_S1L) {
-#pragma unroll
-      for (int e = 0; e < NV; ++e) {
-        const int v = (NDIM == 1 && e == 2) ? 3 : e;
-        us[v] = MODE == MODE_S2F ? u1_at(e, cell) : C(Ub[e * a.ncell + cell]);
-      }
     }
     if (MODE == MODE_STAGE2 || MODE == MODE_STAGE3 || MODE == MODE_S3F || MODE == MODE_S2F) {
 #pragma unroll
