@@ -82,6 +82,40 @@ def test_ibm_bodies_across_periodic_edges(orc, viscous, wall):
     assert_fields(to_np(Ug)[0], U1o, 1e-13, f"periodic-edge bodies step viscous={viscous}")
 
 
+@pytest.mark.parametrize("viscous,wall", [(True, 1), (False, 0)])
+def test_ibm_batch_members_step_independently(orc, viscous, wall):
+    """Two batch members share one body: the Mach-3 shock already at the
+    cylinder, and a smooth periodic-mode state.  Ten automatic steps of the
+    batched grid (each member its own step size, every member covering all of
+    the body-first tile order) against the oracle per member, and member 1
+    bit for bit against the same state stepped on a one-member grid."""
+    nx, ny = 160, 80
+    post_o = orc.rh_post_shock(3.0)
+    sc = inputs.shock_cylinder(nx, ny, (post_o[0], post_o[1], 0.0, post_o[2]), xs=0.25)
+    mu = inputs.cylinder_viscosity(3.0) if viscous else 0.0
+    kw = dict(domain=sc["domain"], bc=sc["bc"], inflow=sc["inflow"], viscous=viscous, mu=mu, ibm=True)
+    c, g = make_pair(orc, nx, ny, nbatch=2, **kw)
+    _, g1 = make_pair(orc, nx, ny, **kw)
+    for gg in (g, g1):
+        gg.set_levelset(torch.from_numpy(sc["phi"]), wall=wall)
+    W1 = inputs.smooth_prim(nx, ny, seed=21, amp=0.3, domain=sc["domain"])
+    Ug = g.prim_to_cons(torch.from_numpy(np.stack([sc["W"], W1])))
+    U1 = g1.prim_to_cons(torch.from_numpy(W1))
+    g.set_time(0.0, 1.0)
+    g1.set_time(0.0, 1.0)
+    for _ in range(10):
+        g.step(Ug)
+        g1.step(U1)
+    assert torch.equal(Ug[1], U1[0]), "batch member 1 differs from the one-member grid"
+    for b, W in enumerate((sc["W"], W1)):
+        Ue, te, steps_o, fbo = orc.run(c, orc.prim_to_cons(c, W), 1.0, max_steps=10, phi=sc["phi"], wall=wall)
+        t, _, steps = g.get_time(b)
+        assert steps == steps_o == 10 and abs(t - te) <= 1e-14 * te and fbo == 0
+        errs = assert_fields(to_np(Ug)[b], Ue, 1e-11, f"batch member {b}, 10 steps")
+        print(f"ibm batch member {b} viscous={viscous}: per-field errors {errs}", flush=True)
+    assert g.poll_faults() == (0, 0)
+
+
 def test_shock_cylinder_ns_trajectory_small(orc):
     """Mach-3 shock on the cylinder, Navier-Stokes, no-slip adiabatic wall, at
     160x80, 40 automatic steps (the shock reaches the cylinder)."""
