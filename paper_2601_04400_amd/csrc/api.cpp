@@ -121,7 +121,7 @@ WsLayout layout(const shk_grid_desc* d) {
     L.g_nrm = o; o += al(sizeof(double) * 2 * cap);
     L.ghostOf = o; o += al(sizeof(int) * ncell);
     L.tileBody = o; o += al(size_t(stage_tiles(d->nx, d->ny)));
-    L.tileOrder = o; o += al(sizeof(int) * size_t(stage_tiles(d->nx, d->ny)));
+    L.tileOrder = o; o += al(sizeof(unsigned) * size_t(stage_tiles(d->nx, d->ny)));
   }
   if (d->adjoint) {
     const size_t st64 = al(size_t(d->nbatch) * 4 * ncell * sizeof(double));
@@ -377,8 +377,9 @@ shk_status shk_prim_to_cons_vjp(shk_grid* g, const void* W, const void* U_bar, v
 // loads and take longest) come first, dealt round robin, so that none of
 // them is left for the launch's last round; each XCD then takes one
 // contiguous run of the other tiles in row-major order, whose shared halo
-// rows stay in that XCD's L2.
-static std::vector<int> body_first_order(int gx, int gy, const std::vector<uint8_t>& body) {
+// rows stay in that XCD's L2.  Each entry carries the tile's body flag in
+// bit 31 (the tile count is below 2^30: at most 2^38 cells).
+static std::vector<unsigned> body_first_order(int gx, int gy, const std::vector<uint8_t>& body) {
   const int n = gx * gy;
   std::vector<std::vector<int>> q(8);
   int nb = 0;
@@ -392,8 +393,11 @@ static std::vector<int> body_first_order(int gx, int gy, const std::vector<uint8
       q[x].push_back(t++);
     }
   }
-  std::vector<int> order(n);
-  for (int w = 0; w < n; ++w) order[w] = q[w % 8][w / 8];
+  std::vector<unsigned> order(n);
+  for (int w = 0; w < n; ++w) {
+    const int tile = q[w % 8][w / 8];
+    order[w] = unsigned(tile) | (body[tile] ? 0x80000000u : 0u);
+  }
   return order;
 }
 
@@ -403,7 +407,6 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
     g->ibm_on = false;
     g->a.cls = nullptr;
     g->a.ghost_of = nullptr;
-    g->a.tile_body = nullptr;
     g->a.tile_order = nullptr;
     g->gt.n = 0;
     g->a.gt = g->gt;
@@ -435,7 +438,6 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
     g->ibm_on = false;
     g->a.cls = nullptr;
     g->a.ghost_of = nullptr;
-    g->a.tile_body = nullptr;
     g->a.tile_order = nullptr;
     g->gt.n = 0;
     g->a.gt = g->gt;
@@ -461,22 +463,20 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
   // tiles whose cells and halo sources are all fluid skip the immersed-boundary
   // handling in the stage kernels
   uint8_t* tb = reinterpret_cast<uint8_t*>(g->ws + g->L.tileBody);
-  int* to = reinterpret_cast<int*>(g->ws + g->L.tileOrder);
-  a.tile_body = nullptr;
+  unsigned* to = reinterpret_cast<unsigned*>(g->ws + g->L.tileOrder);
   a.tile_order = nullptr;
   const int tgx = (a.nx + STAGE_TX - 1) / STAGE_TX, tgy = (a.ny + STAGE_TY - 1) / STAGE_TY;
   std::vector<uint8_t> body(size_t(tgx) * tgy);
-  std::vector<int> order;
+  std::vector<unsigned> order;
   e = launch_tile_body(a, tb, g->st);
   if (e == hipSuccess) e = hipMemcpyAsync(body.data(), tb, body.size(), hipMemcpyDeviceToHost, g->st);
   if (e == hipSuccess) e = hipStreamSynchronize(g->st);
   if (e == hipSuccess) {
     order = body_first_order(tgx, tgy, body);
-    e = hipMemcpyAsync(to, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice, g->st);
+    e = hipMemcpyAsync(to, order.data(), sizeof(unsigned) * order.size(), hipMemcpyHostToDevice, g->st);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(g->st);
   if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset (tile flags)");
-  a.tile_body = tb;
   a.tile_order = to;
   if (g->d.adjoint && n > 0) {
     int* keys = reinterpret_cast<int*>(g->ws + g->L.entKeys);

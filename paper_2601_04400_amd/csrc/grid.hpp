@@ -58,12 +58,12 @@ struct GridArgs {
   double* dt_out;              // optional caller copy of the step (per call)
   void* stage_in_copy;         // MODE_STAGE1: optional copy of the stage input (storage type), or nullptr
   const int* ghost_of;         // immersed boundary: ghost index of each cell or -1 (else nullptr)
-  const uint8_t* tile_body;    // immersed boundary: per 2D stage tile (STAGE_TX x STAGE_TY cells, row-major
-                               // over the tile grid), 1 if a cell of the tile or of any source cell its halo
-                               // loads is not fluid (else nullptr: every tile checks its cells)
-  const int* tile_order;       // immersed boundary: the stage tile (row-major index) each workgroup of a
-                               // 2D stage launch takes, by workgroup index within a batch member (else
-                               // nullptr: the XCD-aware order of xcd_tile)
+  const unsigned* tile_order;  // immersed boundary: the 2D stage tile (STAGE_TX x STAGE_TY cells; row-major
+                               // index over the tile grid, bits 0..30) each workgroup of a stage launch
+                               // takes, by workgroup index within a batch member, and in bit 31 the tile's
+                               // body flag: set if a cell of the tile or a source cell its halo loads is not
+                               // fluid (nullptr: the XCD-aware order of xcd_tile, and every tile checks its
+                               // cells)
   GhostTable gt;               // immersed boundary: the ghost table (gt.n = 0 without)
   void* ghost_back;            // stage kernels: where the refilled ghost values of the stage
                                // state are written (storage type; usually the stage state

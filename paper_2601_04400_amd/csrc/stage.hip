@@ -254,7 +254,7 @@ struct IntC {
 // IBM: the grid has an immersed boundary (a.cls, a.ghost_of and a.gt set):
 // ghost cells take their refilled values, formed from the stage state's
 // fluid cells as they are loaded, and their right-hand side is zero.  Tiles
-// that a.tile_body marks all fluid skip this handling.
+// that a.tile_order marks all fluid skip this handling.
 template <class S, class C, int NDIM, int TX, int TY, bool VISC, int MODE, int NET = NET_NONE, bool CHAR = false,
           bool IBM = false>
 __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArgs a, const S* Us, const S* Un, S* Uout,
@@ -289,9 +289,13 @@ __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArg
   __shared__ double red_s[NT / 64], red_r[NT / 64];
 
   int bx, by, b;
+  bool near_body = true;
   if (GH && TX == STAGE_TX && TY == STAGE_TY && a.tile_order != nullptr) {
-    // grid with a body: the tiles near it first (host-built order)
-    const int t = a.tile_order[blockIdx.x + gridDim.x * blockIdx.y];
+    // grid with a body: the tiles near it first (host-built order); the
+    // entry's top bit is the tile's body flag, so one load gives both
+    const unsigned e = a.tile_order[blockIdx.x + gridDim.x * blockIdx.y];
+    const int t = int(e & 0x7fffffffu);
+    near_body = (e >> 31) != 0;
     bx = t % gridDim.x;
     by = t / gridDim.x;
     b = blockIdx.z;
@@ -347,12 +351,7 @@ __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArg
   // immersed boundary: a tile whose cells and halo sources are all fluid
   // (the same for the whole workgroup) takes the plain path, reading no
   // cell classes
-  bool body = false;
-  if constexpr (GH) {
-    body = a.cls != nullptr;
-    if constexpr (TX == STAGE_TX && TY == STAGE_TY)
-      if (body && a.tile_body != nullptr) body = a.tile_body[by * gridDim.x + bx] != 0;
-  }
+  const bool body = GH && a.cls != nullptr && near_body;
   const long long boff = (long long)b * a.nvar * a.ncell;
   const S* Ub = Us + boff;
   const S* __restrict__ Lb = MODE == MODE_S2F ? Lin + boff : nullptr;
