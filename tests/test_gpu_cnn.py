@@ -223,6 +223,86 @@ def test_step_adjoint_with_cnn_vs_oracle_jacobian(orc, bc):
     assert np.max(np.abs(got - want)) <= 4e-3 * np.max(np.abs(net_part)) + 1e-10 * np.max(np.abs(want))
 
 
+def cylinder_case(orc, nx, ny):
+    """The restricted shock-cylinder set-up of section 3 (a Mach-5 shock,
+    the cylinder centred on the top symmetry edge, slip wall) at nx x ny,
+    the shock moved to x = 0.5, into the body's front, so every ghost cell
+    sees a moving, shocked gas."""
+    from paper_2601_04400_amd import Grid, infer
+    sc = infer.restricted_cylinder(nx, ny)
+    sc["W"] = inputs.shock_prim(nx, ny, sc["domain"], 0.5, sc["inflow"], infer.PRE)
+    dom = sc["domain"]
+    c = orc.config(nx=nx, ny=ny, x0=dom[0], x1=dom[1], y0=dom[2], y1=dom[3], bc=sc["bc"], inflow=sc["inflow"])
+    g = Grid(nx, ny, domain=dom, bc=sc["bc"], inflow=sc["inflow"], flux_net=2, adjoint=True, ibm=True)
+    assert g.set_levelset(torch.from_numpy(sc["phi"]), wall=0) == orc.ibm_classify(c, sc["phi"])[1] > 0
+    return c, g, sc, orc.prim_to_cons(c, sc["W"])
+
+
+def test_rhs_with_cnn_and_body_vs_oracle(orc):
+    """The convolutional correction on a grid with a body (its input images
+    read the refilled ghost cells; solid and ghost cells keep a zero
+    right-hand side) against the oracle's, to one bfloat16 unit of what the
+    network changes."""
+    c, g, sc, U = cylinder_case(orc, 48, 32)
+    net, ref, _ = make_cnn(orc, 3)
+    g.set_flux_cnn(net)
+    Ug = torch.from_numpy(U).cuda().reshape(g.shape).contiguous()
+    got = to_np(g.rhs(Ug))[0]
+    assert np.array_equal(to_np(Ug)[0], U)  # the state is left as it was
+    want = orc.rhs(c, U, phi=sc["phi"], wall=0, net=ref)[0]
+    plain = orc.rhs(c, U, phi=sc["phi"], wall=0)[0]
+    effect = np.max(np.abs(want - plain))
+    assert effect > 1e-4 * np.max(np.abs(want))  # the shock's own terms reach 2e4
+    err = np.max(np.abs(got - want))
+    print(f"cnn + body rhs: error {err:.3e}, network effect {effect:.3e}", flush=True)
+    assert err <= 4e-3 * effect + 1e-11 * np.max(np.abs(want))
+
+
+def test_step_adjoint_with_cnn_and_body_vs_oracle_tangent(orc):
+    """Vector-Jacobian product of one RK3 step with the convolutional
+    correction on a grid with a body (the refill transpose and the network's
+    reverse pass together) against the oracle, entry by entry on a sample:
+    entry i of J^T lam is <lam, J e_i>, one forward-mode oracle step.  The
+    sample takes every variable of ghost cells, of fluid cells next to them
+    (the refill's sources) and of cells away from the body; the bar is one
+    bfloat16 unit of the network's share."""
+    nx, ny = 24, 16
+    c, g, sc, U = cylinder_case(orc, nx, ny)
+    net, ref, _ = make_cnn(orc, 5)
+    g.set_flux_cnn(net)
+    dt = 0.4 * orc.cfl_dt(c, U, phi=sc["phi"])
+    lam = np.random.default_rng(4).normal(size=U.shape)
+    Ub = torch.from_numpy(lam).cuda().reshape(g.shape).clone()
+    g.step_adjoint(torch.from_numpy(U).cuda().reshape(g.shape), dt, Ub, g.param_bar())
+    got = to_np(Ub)[0]
+    cls = orc.ibm_classify(c, sc["phi"])[0]
+    rng = np.random.default_rng(9)
+    ghosts = np.argwhere(cls == 2)
+    near = np.zeros_like(cls, dtype=bool)
+    for j, i in ghosts:
+        near[max(j - 2, 0):j + 3, max(i - 2, 0):i + 3] = True
+    near &= cls == 0
+    pick = [tuple(x) for x in ghosts[rng.choice(len(ghosts), 12, replace=False)]]
+    pick += [tuple(x) for x in rng.permutation(np.argwhere(near))[:12]]
+    pick += [tuple(x) for x in rng.permutation(np.argwhere(~near & (cls == 0)))[:4]]
+    want, share, gv = [], [], []
+    for (j, i) in pick:
+        for v in range(4):
+            e = np.zeros_like(U)
+            e[v, j, i] = 1.0
+            w = float(np.sum(lam * orc.rk3_step_jvp(c, U, e, dt, phi=sc["phi"], wall=0, net=ref)[1]))
+            w0 = float(np.sum(lam * orc.rk3_step_jvp(c, U, e, dt, phi=sc["phi"], wall=0)[1]))
+            want.append(w)
+            share.append(w - w0)
+            gv.append(got[v, j, i])
+    want, share, gv = np.array(want), np.array(share), np.array(gv)
+    assert np.max(np.abs(share)) > 1e-3 * np.max(np.abs(want))
+    err = np.max(np.abs(gv - want))
+    print(f"cnn + body step adjoint: {len(want)} entries, error {err:.3e}, "
+          f"network share {np.max(np.abs(share)):.3e}", flush=True)
+    assert err <= 4e-3 * np.max(np.abs(share)) + 1e-10 * np.max(np.abs(want))
+
+
 def test_cnn_training_reduces_loss_and_beats_plain_solver():
     """Reduced convolutional training run: 16 random Riemann problems on
     64 x 32 against 128 x 64 restricted 2 x 2, m = 8 unrolled steps, the
