@@ -193,11 +193,21 @@ class Dataset:
     (transmissive boundaries make every y-face of a column see one stencil,
     so the y-flux differences -- with or without the correction -- vanish
     exactly and each row evolves as the 1D problem); coarse step t_end / nsnap.
+    case "cylinder" (section 3's learned flux for the moving shock and the
+    cylinder; seeds ignored): the restricted shock-cylinder set-up (Mach-5
+    shock, slip wall) on nc x ny coarse cells (ny = nc / 2 unless given)
+    against factor times finer, both with the immersed boundary, to t_end;
+    the coarse step is t_end / nsnap with nsnap the least count whose step
+    is at most cfl_frac x the CFL step of the initial coarse state (the
+    nsnap argument is not used).
     """
 
     def __init__(self, seeds, nc=128, factor=4, nsnap=24, cfl_frac=0.5, device="cuda", keep_fine_ic=False,
                  case="riemann", rows=4, t_end=0.25, ny=None):
         self.case = case
+        self.grid_kw = {}
+        self.phi = None
+        phi_f = None
         if case == "riemann":
             nb = len(seeds)
             nxc, nyc = nc, ny or nc
@@ -207,10 +217,21 @@ class Dataset:
             nb, nxc, nyc = 1, nc, rows
             W = torch.from_numpy(sod_rows_prim(nc * factor, rows * factor)).to(device)
             self.domain = (0.0, 1.0, 0.0, rows / nc)
+        elif case == "cylinder":
+            from .infer import restricted_cylinder
+            nb, nxc, nyc = 1, nc, ny or nc // 2
+            fine = restricted_cylinder(nxc * factor, nyc * factor)
+            W = torch.from_numpy(fine["W"]).to(device)
+            self.domain = fine["domain"]
+            self.grid_kw = dict(bc=fine["bc"], inflow=fine["inflow"], ibm=True)
+            self.phi = torch.from_numpy(restricted_cylinder(nxc, nyc)["phi"])
+            phi_f = torch.from_numpy(fine["phi"])
         else:
-            raise ValueError("case must be 'riemann' or 'sod'")
+            raise ValueError("case must be 'riemann', 'sod' or 'cylinder'")
         self.nx, self.ny = nxc, nyc
-        gf = Grid(nxc * factor, nyc * factor, nbatch=nb, domain=self.domain, device=device)
+        gf = Grid(nxc * factor, nyc * factor, nbatch=nb, domain=self.domain, device=device, **self.grid_kw)
+        if phi_f is not None:
+            gf.set_levelset(phi_f, wall=0)
         Uf = gf.prim_to_cons(W)
         self.fine_ic = Uf.clone() if keep_fine_ic else None
         self.factor = factor
@@ -222,6 +243,12 @@ class Dataset:
             gc.set_time(0.0, 1e30)
             gc.step(U0c.clone(), dt_out=d)
             self.dt_c = (cfl_frac * d).contiguous()
+        elif case == "cylinder":
+            d = torch.zeros(1, dtype=torch.float64, device=device)
+            gc.set_time(0.0, 1e30)
+            gc.step(U0c.clone(), dt_out=d)
+            nsnap = int(math.ceil(t_end / (cfl_frac * float(d[0]))))
+            self.dt_c = torch.full((1,), t_end / nsnap, dtype=torch.float64, device=device)
         else:
             self.dt_c = torch.full((1,), t_end / nsnap, dtype=torch.float64, device=device)
         dt_f = (self.dt_c / factor).contiguous()
@@ -239,8 +266,12 @@ class Dataset:
         torch.cuda.synchronize()
 
     def grid(self, nb=None, **kw):
-        """A coarse grid of this data set's geometry (transmissive)."""
-        return Grid(self.nx, self.ny, nbatch=nb or self.nb, domain=self.domain, **kw)
+        """A coarse grid of this data set's geometry (boundaries, and the body
+        of the cylinder case)."""
+        g = Grid(self.nx, self.ny, nbatch=nb or self.nb, domain=self.domain, **self.grid_kw, **kw)
+        if self.phi is not None:
+            g.set_levelset(self.phi, wall=0)
+        return g
 
 
 def train(net, data, iters=400, m=4, lr=1e-3, lr_late=1e-4, switch=None, log_every=50, log=None, last=None):
@@ -256,6 +287,7 @@ def train(net, data, iters=400, m=4, lr=1e-3, lr_late=1e-4, switch=None, log_eve
     part = torch.empty(nb * 256, dtype=torch.float64, device=data.snaps.device)
     tapes = torch.empty((m, 3) + tuple(g.shape), dtype=torch.float64, device=data.snaps.device)
     history = []
+    skipped = 0
     switch = switch if switch is not None else int(0.875 * iters)
     for it in range(iters):
         k = it % (last - m + 1)
@@ -270,12 +302,18 @@ def train(net, data, iters=400, m=4, lr=1e-3, lr_late=1e-4, switch=None, log_eve
         for s in range(m, 0, -1):
             mse_accumulate(states[s], data.snaps[k + s], Ub, 1.0 / m, loss, part)
             g.step_adjoint_tape(tapes[s - 1], data.dt_c, Ub, None)
-        net.adam(lr if it < switch else lr_late)
+        if bool(torch.isfinite(net.grad).all()):
+            net.adam(lr if it < switch else lr_late)
+        else:
+            skipped += 1  # a rollout left the physical states: no update from it
         L = float(loss.sum()) / m if (log is not None and (it % log_every == 0 or it == iters - 1)) else None
         if L is not None:
             history.append((it, k, L))
             log(f"iter {it} start {k} loss {L:.6e}")
     g.set_flux_net_grad(None)
+    if skipped and log is not None:
+        log(f"{skipped} of {iters} iterations skipped (non-finite gradient)")
+    train.skipped = skipped
     return history
 
 
@@ -371,6 +409,105 @@ def evaluate_sod(net, data, marks):
     return out
 
 
+def cnn_norm_from(data, centre=None):
+    """Input normalisation of the convolutional correction from a data set's
+    coarse snapshots: inverse standard deviation of rho and E, and of the two
+    momenta taken together (the normal and tangential channels of x- and
+    y-faces share the statistics, as the faces share the network); centred
+    on the snapshots' mean, or on `centre` (conservative rho, m_n, m_t, E)
+    if given.  The zero padding of the 3x3 layers at non-periodic edges
+    stands for the centre state."""
+    S = data.snaps[:, :, :, :, :]
+    r, E = S[:, :, 0], S[:, :, 3]
+    m = torch.cat([S[:, :, 1].flatten(), S[:, :, 2].flatten()])
+    mean = (float(r.mean()), float(m.mean()), float(m.mean()), float(E.mean()))
+    if centre is not None:
+        mean = tuple(float(x) for x in centre)
+    std = (float(r.std()), float(m.std()), float(m.std()), float(E.std()))
+    return mean, [1.0 / x for x in std]
+
+
+def evaluate_cylinder(net, data, times=(0.18, 0.2), x_line=0.29, gamma=1.4):
+    """Error of the coarse cylinder run with and without the correction
+    against the restricted fine solution at the given times: mean squared
+    error over the coarse fluid cells, and the density, velocity and pressure
+    profiles along the column through x = x_line (mean absolute error over
+    its fluid cells, relative to the reference profile's largest magnitude),
+    with the time per coarse step."""
+    dt = float(data.dt_c[0])
+    marks = {t: min(data.nsnap, int(round(t / dt))) for t in times}
+    g0 = data.grid(device=data.snaps.device)
+    fluid = g0.classes() == 0
+    x0, x1 = data.domain[0], data.domain[1]
+    col = min(data.nx - 1, int((x_line - x0) / ((x1 - x0) / data.nx)))
+    cf = fluid[:, col]
+
+    def prim(U):
+        r = U[0]
+        u, v = U[1] / r, U[2] / r
+        return {"rho": r, "u": u, "v": v, "p": (gamma - 1.0) * (U[3] - 0.5 * r * (u * u + v * v))}
+    out = {"line_x": x0 + (col + 0.5) * (x1 - x0) / data.nx, "steps": marks, "dt": dt}
+    for name, use in (("plain", False), ("learned", True)):
+        g = data.grid(flux_net=net_kind(net), device=data.snaps.device)
+        attach(g, net if use else None)
+        U = data.snaps[0].clone()
+        res = {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(1, max(marks.values()) + 1):
+            g.step(U, data.dt_c)
+            for t, k in marks.items():
+                if s == k:
+                    T = data.snaps[k][0]
+                    d = U[0] - T
+                    pu, pt = prim(U[0][:, :, col]), prim(T[:, :, col])
+                    line = {}
+                    for q in pu:
+                        ref = pt[q][cf]
+                        line[q] = float((pu[q][cf] - ref).abs().mean() / ref.abs().max())
+                    res[str(t)] = {"mse_fluid": float((d[:, fluid] ** 2).mean()), "line_rel_l1": line}
+        torch.cuda.synchronize()
+        out[name] = {"errors": res, "ms_per_step": (time.perf_counter() - t0) * 1e3 / max(marks.values())}
+    return out
+
+
+def main_cylinder(a):
+    """Section 3's learned flux for the moving shock and the cylinder: the
+    convolutional correction on 128 x 64 against 256 x 128 restricted 2 x 2,
+    trained up to t = 0.2 with the paper's rates (1e-4, then 1e-5), and the
+    density, velocity and pressure along x = 0.29 at t = 0.18 and 0.2."""
+    import json
+    t0 = time.perf_counter()
+    data = Dataset(None, nc=a.nc_cyl, factor=2, case="cylinder", t_end=0.2, cfl_frac=a.cfl_frac_cyl)
+    print(f"data: cylinder {data.nx}x{data.ny} vs {2 * data.nx}x{2 * data.ny}, {data.nsnap} coarse steps "
+          f"to t = 0.2, {time.perf_counter() - t0:.1f} s", flush=True)
+    centre = None
+    if a.norm_cyl == "ambient":
+        from .infer import PRE
+        r, u, v, p = PRE
+        centre = (r, r * u, r * v, p / 0.4 + 0.5 * r * (u * u + v * v))
+    mean, inv = cnn_norm_from(data, centre)
+    net = FluxCnn(init_cnn_theta(0, zero_output=True), mean, inv, out_scale=a.out_scale_cyl)
+    before = dataset_loss(net, data, m=a.m_cyl)
+    t1 = time.perf_counter()
+    hist = train(net, data, iters=a.iters_cyl, m=a.m_cyl, lr=a.lr_cyl, lr_late=a.lr_late_cyl,
+                 switch=a.switch_cyl, log_every=250, log=lambda s: print(s, flush=True))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    after = dataset_loss(net, data, m=a.m_cyl)
+    ev = evaluate_cylinder(net, data)
+    res = {"case": "cylinder", "coarse": [data.nx, data.ny], "fine": [2 * data.nx, 2 * data.ny],
+           "coarse_steps": data.nsnap, "unroll_m": a.m_cyl, "iters": a.iters_cyl, "lr": [a.lr_cyl, a.lr_late_cyl],
+           "lr_switch": a.switch_cyl, "norm": a.norm_cyl, "norm_mean": mean, "norm_inv_std": inv, "out_scale": a.out_scale_cyl,
+           "train_seconds": round(train_s, 2), "train_ms_per_iter": round(train_s * 1e3 / a.iters_cyl, 3),
+           "iters_skipped": train.skipped, "training_loss_before": before, "training_loss_after": after,
+           "eval": ev, "history": hist}
+    print(json.dumps({k: v for k, v in res.items() if k != "history"}), flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+
+
 def main_sod(a):
     """Section 3's 1D learned flux: Sod's shock tube with N = 500 cells
     against N = 1000 restricted, trained on t <= 0.2 and evaluated to 0.25."""
@@ -414,16 +551,28 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--lr-late", type=float, default=1e-4)
     ap.add_argument("--out", default=None)
-    ap.add_argument("--case", choices=("riemann", "sod"), default="riemann")
+    ap.add_argument("--case", choices=("riemann", "sod", "cylinder"), default="riemann")
     ap.add_argument("--net", choices=("mlp", "cnn"), default="mlp")
     ap.add_argument("--ny", type=int, default=None, help="coarse rows (default: nc)")
     ap.add_argument("--nc-sod", type=int, default=500)
     ap.add_argument("--nsnap-sod", type=int, default=625)
     ap.add_argument("--m-sod", type=int, default=64)
     ap.add_argument("--iters-sod", type=int, default=1000)
+    ap.add_argument("--nc-cyl", type=int, default=128)
+    ap.add_argument("--cfl-frac-cyl", type=float, default=0.5)
+    ap.add_argument("--m-cyl", type=int, default=32)
+    ap.add_argument("--iters-cyl", type=int, default=5000)
+    ap.add_argument("--switch-cyl", type=int, default=3500)
+    ap.add_argument("--lr-cyl", type=float, default=1e-4)
+    ap.add_argument("--lr-late-cyl", type=float, default=1e-5)
+    ap.add_argument("--out-scale-cyl", type=float, default=0.1)
+    ap.add_argument("--norm-cyl", choices=("data", "ambient"), default="ambient",
+                    help="centre of the input normalisation: the data mean or the gas at rest ahead of the shock")
     a = ap.parse_args()
     if a.case == "sod":
         return main_sod(a)
+    if a.case == "cylinder":
+        return main_cylinder(a)
     t0 = time.perf_counter()
     data = Dataset(list(range(a.train_seeds)), nc=a.nc, factor=a.factor, nsnap=a.nsnap, ny=a.ny)
     print(f"data: {a.train_seeds} problems, {a.nsnap} coarse snapshots, {time.perf_counter() - t0:.1f} s", flush=True)
