@@ -59,9 +59,12 @@ __device__ __forceinline__ void ghost_at(const GridArgs& a, int k, Get&& get, C 
 // cell takes its refilled value, formed here from the fluid cells of the
 // same state (they are complete when the stage starts).
 // inside: (gi, gj) is known to be an interior cell (no boundary rule).
-template <class S, class C, int NDIM, bool GH, class Get>
+// DEFER: an immersed-boundary ghost cell is not refilled here; its ghost
+// index goes to *ghost (else -1) and q holds its stored values.
+template <class S, class C, int NDIM, bool GH, bool DEFER = false, class Get>
 __device__ __forceinline__ void load_cons_f(const GridArgs& a, int gi, int gj, Get&& get, C q[4],
-                                            bool inside = false) {
+                                            bool inside = false, int* ghost = nullptr) {
+  if (DEFER) *ghost = -1;
   int fx = 0, fy = 0;
   int si = gi, sj = NDIM == 2 ? gj : 0;
   if (!inside) {
@@ -91,7 +94,9 @@ __device__ __forceinline__ void load_cons_f(const GridArgs& a, int gi, int gj, G
       E = get(2, c);
     }
     const int gk = GH && a.ghost_of != nullptr ? a.ghost_of[c] : -1;
-    if (gk >= 0) {
+    if (DEFER) {
+      *ghost = gk;
+    } else if (gk >= 0) {
       C g[4];
       ghost_at<S>(a, gk, get, g);
       r = g[0]; mx = g[1]; my = g[2]; E = g[3];
@@ -102,10 +107,11 @@ __device__ __forceinline__ void load_cons_f(const GridArgs& a, int gi, int gj, G
   q[0] = r; q[1] = mx; q[2] = my; q[3] = E;
 }
 
-template <class S, class C, int NDIM, bool GH>
+template <class S, class C, int NDIM, bool GH, bool DEFER = false>
 __device__ __forceinline__ void load_cons(const GridArgs& a, const S* U, int gi, int gj, C q[4],
-                                          bool inside = false) {
-  load_cons_f<S, C, NDIM, GH>(a, gi, gj, [&](int e, long long c) { return C(U[e * a.ncell + c]); }, q, inside);
+                                          bool inside = false, int* ghost = nullptr) {
+  load_cons_f<S, C, NDIM, GH, DEFER>(a, gi, gj, [&](int e, long long c) { return C(U[e * a.ncell + c]); }, q,
+                                     inside, ghost);
 }
 
 // Automatic step from the reduced maxima of a batch member (dt = cfl / max
@@ -253,8 +259,9 @@ struct IntC {
 // CHAR: characteristic-wise WENO5 instead of the primitive-wise one (FP64).
 // IBM: the grid has an immersed boundary (a.cls, a.ghost_of and a.gt set):
 // ghost cells take their refilled values, formed from the stage state's
-// fluid cells as they are loaded, and their right-hand side is zero.  Tiles
-// that a.tile_order marks all fluid skip this handling.
+// fluid cells (in one pass over the tile's ghost slots after its plain
+// loads), and their right-hand side is zero.  Tiles that a.tile_order marks
+// all fluid skip this handling.
 template <class S, class C, int NDIM, int TX, int TY, bool VISC, int MODE, int NET = NET_NONE, bool CHAR = false,
           bool IBM = false>
 __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArgs a, const S* Us, const S* Un, S* Uout,
@@ -287,6 +294,10 @@ __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArg
   // twelve faces, so it is converted once here
   __shared__ bf16x4 net_in[MLP ? 2 : 1][MLP ? PY * PX : 1];
   __shared__ double red_s[NT / 64], red_r[NT / 64];
+  // immersed boundary: the halo slots whose source is a ghost cell, with
+  // its ghost index, refilled together after the plain loads
+  __shared__ int gl_slot[GH ? PY * PX : 1], gl_idx[GH ? PY * PX : 1];
+  __shared__ unsigned int gl_n;
 
   int bx, by, b;
   bool near_body = true;
@@ -370,25 +381,8 @@ __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArg
   // (the same for the whole workgroup) skips the boundary rules
   const bool inside = i0 >= H && i0 + TX + H <= a.nx && (NDIM == 1 || (j0 >= H && j0 + TY + H <= a.ny));
   bool nonphys = false;  // a loaded cell with rho <= 0 or p <= 0 (or not a number)
-  for (int k = threadIdx.x; k < PY * PX; k += NT) {
-    const int lx = k % PX, ly = k / PX;
-    const bool inx = lx >= H && lx < TX + H;
-    const bool iny = NDIM == 1 || (ly >= H && ly < TY + H);
-    if (!VISC && !inx && !iny) continue;  // corner block: read only by viscous stencils
-    const int gi = i0 + lx - H;
-    const int gj = NDIM == 2 ? j0 + ly - H : 0;
-    C q[4];
-    if (MODE == MODE_S2F) {
-      if (body)
-        load_cons_f<S, C, NDIM, GH>(a, gi, gj, u1_at, q, inside);
-      else
-        load_cons_f<S, C, NDIM, false>(a, gi, gj, u1_at, q, inside);
-    } else {
-      if (body)
-        load_cons<S, C, NDIM, GH>(a, Ub, gi, gj, q, inside);
-      else
-        load_cons<S, C, NDIM, false>(a, Ub, gi, gj, q, inside);
-    }
+  // primitives of halo slot k into the tile (and the network's inputs)
+  auto put = [&](int k, const C q[4]) {
     Prim<C> p = to_prim(q[0], q[1], q[2], q[3], gm1);
     nonphys = nonphys || !(p.r > C(0)) || !(p.p > C(0));
     w[0][k] = p.r;
@@ -406,6 +400,63 @@ __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArg
       }
       net_in[0][k] = pack4(xn[0], xn[1], xn[2], xn[3]);
       net_in[1][k] = pack4(yn[0], yn[1], yn[2], yn[3]);
+    }
+  };
+  if (GH && body) {
+    if (threadIdx.x == 0) gl_n = 0;
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < PY * PX; k += NT) {
+    const int lx = k % PX, ly = k / PX;
+    const bool inx = lx >= H && lx < TX + H;
+    const bool iny = NDIM == 1 || (ly >= H && ly < TY + H);
+    if (!VISC && !inx && !iny) continue;  // corner block: read only by viscous stencils
+    const int gi = i0 + lx - H;
+    const int gj = NDIM == 2 ? j0 + ly - H : 0;
+    C q[4];
+    int gk = -1;
+    if (MODE == MODE_S2F) {
+      if (body)
+        load_cons_f<S, C, NDIM, GH, true>(a, gi, gj, u1_at, q, inside, &gk);
+      else
+        load_cons_f<S, C, NDIM, false>(a, gi, gj, u1_at, q, inside);
+    } else {
+      if (body)
+        load_cons<S, C, NDIM, GH, true>(a, Ub, gi, gj, q, inside, &gk);
+      else
+        load_cons<S, C, NDIM, false>(a, Ub, gi, gj, q, inside);
+    }
+    if (GH && gk >= 0) {
+      // a ghost cell's source: listed, and refilled in the pass below
+      const unsigned int at = atomicAdd(&gl_n, 1u);
+      gl_slot[at] = k;
+      gl_idx[at] = gk;
+      continue;
+    }
+    put(k, q);
+  }
+  if (GH && body) {
+    // 1b. the listed ghost slots, all at once: each takes its ghost's
+    // refilled value (from the stage state's fluid cells, complete when the
+    // stage starts) and the boundary rule of its halo position
+    __syncthreads();
+    const int n = int(gl_n);
+    for (int t = threadIdx.x; t < n; t += NT) {
+      const int k = gl_slot[t];
+      const int gi = i0 + k % PX - H, gj = j0 + k / PX - H;
+      int fx = 0, fy = 0;
+      if (!inside) {
+        bc_source(gi, a.nx, a.bc[0], a.bc[1], fx);
+        bc_source(gj, a.ny, a.bc[2], a.bc[3], fy);
+      }
+      C q[4];
+      if (MODE == MODE_S2F)
+        ghost_at<S>(a, gl_idx[t], u1_at, q);
+      else
+        ghost_at<S>(a, gl_idx[t], [&](int e, long long c) { return C(Ub[e * a.ncell + c]); }, q);
+      q[1] = (fx & 1) ? -q[1] : q[1];
+      q[2] = (fy & 1) ? -q[2] : q[2];
+      put(k, q);
     }
   }
   __syncthreads();

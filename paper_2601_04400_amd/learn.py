@@ -274,11 +274,14 @@ class Dataset:
         return g
 
 
-def train(net, data, iters=400, m=4, lr=1e-3, lr_late=1e-4, switch=None, log_every=50, log=None, last=None):
+def train(net, data, iters=400, m=4, lr=1e-3, lr_late=1e-4, switch=None, log_every=50, log=None, last=None,
+          stats=None):
     """Unrolled m-step training: loss = 1/m sum_s ||U^{n+s} - T^{n+s}||^2
     (mean over entries, summed over the batch), gradient by the adjoint.
     Windows cycle over the start snapshots 0 .. last - m (last: the final
-    snapshot used, default the data set's last)."""
+    snapshot used, default the data set's last).  An iteration whose
+    gradient is not finite (a rollout that left the physical states) makes
+    no update; stats, if a dict, receives their count as "skipped"."""
     nb = data.nb
     last = data.nsnap if last is None else last
     g = data.grid(adjoint=True, flux_net=net_kind(net), device=data.snaps.device)
@@ -313,7 +316,8 @@ def train(net, data, iters=400, m=4, lr=1e-3, lr_late=1e-4, switch=None, log_eve
     g.set_flux_net_grad(None)
     if skipped and log is not None:
         log(f"{skipped} of {iters} iterations skipped (non-finite gradient)")
-    train.skipped = skipped
+    if stats is not None:
+        stats["skipped"] = skipped
     return history
 
 
@@ -490,8 +494,9 @@ def main_cylinder(a):
     net = FluxCnn(init_cnn_theta(0, zero_output=True), mean, inv, out_scale=a.out_scale_cyl)
     before = dataset_loss(net, data, m=a.m_cyl)
     t1 = time.perf_counter()
+    stats = {}
     hist = train(net, data, iters=a.iters_cyl, m=a.m_cyl, lr=a.lr_cyl, lr_late=a.lr_late_cyl,
-                 switch=a.switch_cyl, log_every=250, log=lambda s: print(s, flush=True))
+                 switch=a.switch_cyl, log_every=250, log=lambda s: print(s, flush=True), stats=stats)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
     after = dataset_loss(net, data, m=a.m_cyl)
@@ -500,7 +505,7 @@ def main_cylinder(a):
            "coarse_steps": data.nsnap, "unroll_m": a.m_cyl, "iters": a.iters_cyl, "lr": [a.lr_cyl, a.lr_late_cyl],
            "lr_switch": a.switch_cyl, "norm": a.norm_cyl, "norm_mean": mean, "norm_inv_std": inv, "out_scale": a.out_scale_cyl,
            "train_seconds": round(train_s, 2), "train_ms_per_iter": round(train_s * 1e3 / a.iters_cyl, 3),
-           "iters_skipped": train.skipped, "training_loss_before": before, "training_loss_after": after,
+           "iters_skipped": stats["skipped"], "training_loss_before": before, "training_loss_after": after,
            "eval": ev, "history": hist}
     print(json.dumps({k: v for k, v in res.items() if k != "history"}), flush=True)
     if a.out:
