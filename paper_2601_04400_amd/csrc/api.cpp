@@ -253,6 +253,7 @@ shk_status stage_seq(shk_grid* g, S* U, const double* dt_in, double* dt_out, S* 
     a.ghost_back = nullptr;  // S2F's stage state U1 is never stored
     if ((e = timed(g, 2, [&]() { return stage_launch<S>(g, a, MODE_S2F, U, U, U2, nullptr, U1); })) != hipSuccess)
       return hip_check(g, e, "stage 2");
+    a.ghost_back = g->ibm_on ? U2 : nullptr;  // refilled ghosts of U2 (a work array), read back by S3F's update
     if ((e = timed(g, 3, [&]() { return stage_launch<S>(g, a, MODE_S3F, U2, U, U, nullptr, nullptr); })) != hipSuccess)
       return hip_check(g, e, "stage 3");
     return SHK_OK;

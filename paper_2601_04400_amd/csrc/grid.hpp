@@ -66,8 +66,8 @@ struct GridArgs {
                                // cells)
   GhostTable gt;               // immersed boundary: the ghost table (gt.n = 0 without)
   void* ghost_back;            // stage kernels: where the refilled ghost values of the stage
-                               // state are written (storage type; usually the stage state
-                               // itself), or nullptr
+                               // state are written (storage type), or nullptr; when it is the
+                               // stage state itself, the update reads them back from there
   unsigned long long* xslots;  // [nbatch][2][XSLOTS] spread extrema of the fused step
   const float* dXnet;          // its stencil gradient per face [nbatch][nface][24] or nullptr
   const float* dFext;          // precomputed face correction [nbatch][nface][4] (face frame) or nullptr

@@ -267,9 +267,12 @@ template <class S, class C, int NDIM, int TX, int TY, bool VISC, int MODE, int N
 __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArgs a, const S* Us, const S* Un, S* Uout,
                                                     const double* __restrict__ dtp,
                                                     const S* __restrict__ Lin, NetArgs net) {
-  // Us, Un and Uout may alias (stage 3 writes the step's result over U^n) and
-  // a.ghost_back may be Us: every cell is read before it is written, by the
-  // thread that writes it, and a ghost cell's stored value is never read.
+  // Us, Un and Uout may alias (stage 3 writes the step's result over U^n):
+  // every cell is read before it is written, by the thread that writes it.
+  // a.ghost_back may be Us: a ghost cell's refilled value is written there
+  // by the workgroup whose tile holds the cell, in its ghost pass, and read
+  // back only by that workgroup's update, after a barrier; any other read of
+  // a ghost cell's stored value replaces it by the refilled one.
   constexpr int NT = NDIM == 2 ? TX * TY : TX;  // one thread per cell of the tile
   static_assert(NT % 64 == 0 && NT <= 1024, "whole waves");
   constexpr int H = HALO;
@@ -454,6 +457,16 @@ __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArg
         ghost_at<S>(a, gl_idx[t], u1_at, q);
       else
         ghost_at<S>(a, gl_idx[t], [&](int e, long long c) { return C(Ub[e * a.ncell + c]); }, q);
+      const int lx = k % PX, ly = k / PX;
+      if (MODE != MODE_S2F && a.ghost_back != nullptr && lx >= H && lx < TX + H && ly >= H && ly < TY + H &&
+          gi < a.nx && gj < a.ny) {
+        // a ghost cell of this tile (no boundary rule): its refilled value
+        // is stored here; where that is the stage state, the update below
+        // reads it back instead of forming it again
+        const long long cell = (long long)gj * a.nx + gi;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) static_cast<S*>(a.ghost_back)[boff + v * a.ncell + cell] = S(q[v]);
+      }
       q[1] = (fx & 1) ? -q[1] : q[1];
       q[2] = (fy & 1) ? -q[2] : q[2];
       put(k, q);
@@ -747,8 +760,10 @@ __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArg
     const uint8_t cc = GH && body ? a.cls[cell] : CELL_FLUID;
     const int gk = GH && body ? a.ghost_of[cell] : -1;
     // the cell's stage-state and U^n values, all read before any write (the
-    // output may overwrite U^n); a ghost cell takes its refilled stage value
-    // (its stored one is loaded anyway, beside the ghost index, and replaced)
+    // output may overwrite U^n); a ghost cell takes its refilled stage value:
+    // the one the ghost pass stored, where it stored it in the stage state,
+    // else formed again (its stored one is loaded anyway, beside the ghost
+    // index, and replaced)
     C us[4], un[4];
     if (MODE != MODE_RHS && MODE != MODE_S1L) {
 #pragma unroll
@@ -756,15 +771,12 @@ __global__ void __launch_bounds__(NDIM == 2 ? TX * TY : TX) stage_kernel(GridArg
         const int v = (NDIM == 1 && e == 2) ? 3 : e;
         us[v] = MODE == MODE_S2F ? u1_at(e, cell) : C(Ub[e * a.ncell + cell]);
       }
-    }
-    if (GH && gk >= 0) {
-      if (MODE == MODE_S2F)
-        ghost_at<S>(a, gk, u1_at, us);
-      else
-        ghost_at<S>(a, gk, [&](int e, long long c) { return C(Ub[e * a.ncell + c]); }, us);
-      if (MODE != MODE_S2F && a.ghost_back != nullptr)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) static_cast<S*>(a.ghost_back)[boff + v * a.ncell + cell] = S(us[v]);
+      if (GH && gk >= 0) {
+        if (MODE == MODE_S2F)
+          ghost_at<S>(a, gk, u1_at, us);
+        else if (a.ghost_back != static_cast<const void*>(Us))
+          ghost_at<S>(a, gk, [&](int e, long long c) { return C(Ub[e * a.ncell + c]); }, us);
+      }
     }
     if (MODE == MODE_STAGE2 || MODE == MODE_STAGE3 || MODE == MODE_S3F || MODE == MODE_S2F) {
 #pragma unroll
