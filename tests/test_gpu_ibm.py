@@ -116,6 +116,32 @@ def test_ibm_batch_members_step_independently(orc, viscous, wall):
     assert g.poll_faults() == (0, 0)
 
 
+@pytest.mark.parametrize("viscous,wall", [(False, 0), (True, 1), (True, 0)])
+def test_ibm_body_cut_by_reflective_wall(orc, viscous, wall):
+    """The restricted shock-cylinder geometry (the cylinder centred on the
+    reflecting top edge): halo slots above that edge reach ghost cells
+    through the wall's mirror rule, so their refilled values take its sign
+    flip.  Right-hand side on a rough state and one step with the shock
+    inside the body, against the oracle."""
+    from paper_2601_04400_amd import infer
+    nx, ny = 120, 80
+    sc = infer.restricted_cylinder(nx, ny)
+    dom = sc["domain"]
+    mu = 2e-3 if viscous else 0.0
+    c, g = make_pair(orc, nx, ny, domain=dom, bc=sc["bc"], inflow=sc["inflow"], viscous=viscous, mu=mu, ibm=True)
+    assert g.set_levelset(torch.from_numpy(sc["phi"]), wall=wall) == orc.ibm_classify(c, sc["phi"])[1] > 0
+    Uo = orc.prim_to_cons(c, inputs.random_prim(nx, ny, seed=23))
+    Lo, _, _ = orc.rhs(c, Uo, phi=sc["phi"], wall=wall)
+    Ug = torch.from_numpy(Uo).to(g.device).reshape(g.shape).contiguous()
+    assert_fields(to_np(g.rhs(Ug))[0], Lo, 1e-13, f"wall-cut body rhs viscous={viscous} wall={wall}")
+    Uo = orc.prim_to_cons(c, inputs.shock_prim(nx, ny, dom, 0.5, sc["inflow"], infer.PRE))
+    dt = 0.4 * orc.cfl_dt(c, Uo, phi=sc["phi"])
+    U1o, _ = orc.rk3_step(c, Uo, dt, phi=sc["phi"], wall=wall)
+    Ug = torch.from_numpy(Uo).to(g.device).reshape(g.shape).contiguous()
+    g.step(Ug, dt)
+    assert_fields(to_np(Ug)[0], U1o, 1e-13, f"wall-cut body step viscous={viscous} wall={wall}")
+
+
 def test_shock_cylinder_ns_trajectory_small(orc):
     """Mach-3 shock on the cylinder, Navier-Stokes, no-slip adiabatic wall, at
     160x80, 40 automatic steps (the shock reaches the cylinder)."""
