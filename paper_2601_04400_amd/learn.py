@@ -454,6 +454,7 @@ def evaluate_cylinder(net, data, times=(0.18, 0.2), x_line=0.29, gamma=1.4):
     for name, use in (("plain", False), ("learned", True)):
         g = data.grid(flux_net=net_kind(net), device=data.snaps.device)
         attach(g, net if use else None)
+        g.step(data.snaps[0].clone(), data.dt_c)  # untimed: first-use costs
         U = data.snaps[0].clone()
         res = {}
         torch.cuda.synchronize()

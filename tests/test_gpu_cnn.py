@@ -322,6 +322,26 @@ def test_cnn_training_reduces_loss_and_beats_plain_solver():
     assert ev["learned"]["mse"] < ev["plain"]["mse"]
 
 
+def test_cylinder_learned_flux_case_runs_and_zero_output_is_plain():
+    """The shock-cylinder learned-flux data set (coarse 32 x 16 against
+    64 x 32 restricted 2 x 2, both with the body, fixed steps to t = 0.2):
+    the step count lands on t = 0.2 within the CFL bound, the snapshots
+    stay finite, and a network whose output layer is zero (a zero correction)
+    reproduces the uncorrected coarse run exactly in the evaluation."""
+    import paper_2601_04400_amd.learn as L
+    data = L.Dataset(None, nc=32, factor=2, case="cylinder", t_end=0.2, cfl_frac=0.5)
+    assert (data.nx, data.ny) == (32, 16)
+    assert abs(float(data.dt_c[0]) * data.nsnap - 0.2) < 1e-12
+    assert bool(torch.isfinite(data.snaps).all())
+    mean, inv = L.cnn_norm_from(data)
+    net = L.FluxCnn(L.init_cnn_theta(0, zero_output=True), mean, inv, out_scale=0.1)
+    ev = L.evaluate_cylinder(net, data)
+    print(ev, flush=True)
+    for t in ev["plain"]["errors"]:
+        assert ev["learned"]["errors"][t] == ev["plain"]["errors"][t]
+        assert np.isfinite(ev["plain"]["errors"][t]["mse_fluid"])
+
+
 def test_graph_replays_with_cnn_equal_eager_steps(orc):
     """Automatic-step RK3 steps with the convolutional correction captured in
     a HIP graph (network forward and corrected stage per stage, no memory
