@@ -258,6 +258,43 @@ def test_corrected_step_vs_oracle(orc):
     assert np.max(np.abs(got - want)) <= 4e-3 * effect + 1e-11 * np.max(np.abs(want))
 
 
+def test_corrected_rhs_and_step_with_body_vs_oracle(orc):
+    """The in-tile network on a grid with a body (its inputs for ghost
+    sources come from the refilled values, solid and ghost cells keep a zero
+    right-hand side): right-hand side and one RK3 step against the oracle's
+    bfloat16-emulating network, within one bfloat16 unit of what the network
+    changes plus FP64 rounding."""
+    from paper_2601_04400_amd import Grid
+    nx, ny = 48, 32
+    dom = (0.0, 1.0, 0.0, ny / nx)
+    bc = (0, 0, 1, 1)
+    phi = inputs.circle_phi(nx, ny, dom, (0.45, 0.3), 0.13)
+    c = orc.config(nx=nx, ny=ny, y1=dom[3], bc=bc)
+    g = Grid(nx, ny, domain=dom, bc=bc, flux_net=True, ibm=True)
+    assert g.set_levelset(torch.from_numpy(phi), wall=0) == orc.ibm_classify(c, phi)[1] > 0
+    net, ref, _ = make_net(orc, 8)
+    g.set_flux_net(net)
+    U = orc.prim_to_cons(c, inputs.smooth_prim(nx, ny, seed=14, amp=0.3, domain=dom))
+    want = orc.rhs(c, U, phi=phi, wall=0, net=ref)[0]
+    plain = orc.rhs(c, U, phi=phi, wall=0)[0]
+    effect = np.max(np.abs(want - plain))
+    assert effect > 1e-3 * np.max(np.abs(want))
+    got = to_np(g.rhs(torch.from_numpy(U).cuda().reshape(g.shape).contiguous()))[0]
+    err = np.max(np.abs(got - want))
+    print(f"net + body rhs: error {err:.3e}, network effect {effect:.3e}", flush=True)
+    assert err <= 4e-3 * effect + 1e-11 * np.max(np.abs(want))
+    dt = 0.4 * orc.cfl_dt(c, U, phi=phi)
+    want, _ = orc.rk3_step(c, U, dt, phi=phi, wall=0, net=ref)
+    plain, _ = orc.rk3_step(c, U, dt, phi=phi, wall=0)
+    effect = np.max(np.abs(want - plain))
+    Ug = torch.from_numpy(U).cuda().reshape(g.shape).clone()
+    g.step(Ug, dt)
+    got = to_np(Ug)[0]
+    err = np.max(np.abs(got - want))
+    print(f"net + body step: error {err:.3e}, network effect {effect:.3e}", flush=True)
+    assert err <= 4e-3 * effect + 1e-11 * np.max(np.abs(want))
+
+
 def test_graph_replays_with_net_equal_eager_steps(orc):
     """Automatic-step RK3 steps with the in-tile network captured in a HIP
     graph: every replay, with eager work and synchronisations between the
