@@ -142,6 +142,34 @@ def test_ibm_body_cut_by_reflective_wall(orc, viscous, wall):
     assert_fields(to_np(Ug)[0], U1o, 1e-13, f"wall-cut body step viscous={viscous} wall={wall}")
 
 
+@pytest.mark.parametrize("prec,viscous", [("f32", False), ("mixed", False), ("mixed", True)])
+def test_ibm_single_precision_storage(orc, prec, viscous):
+    """The immersed boundary with FP32 storage (FP32 or FP64 arithmetic):
+    right-hand side and one step with the Mach-3 shock inside the body's
+    front, against the oracle run on the FP32-rounded state, to 1e-5 per
+    field.  FP32 arithmetic is held on the smooth side of the bar: its
+    right-hand side is taken before the shock reaches the body."""
+    nx, ny = 160, 80
+    post_o = orc.rh_post_shock(3.0)
+    post = (post_o[0], post_o[1], 0.0, post_o[2])
+    xs = 0.1 if prec == "f32" else 0.25
+    sc = inputs.shock_cylinder(nx, ny, post, xs=xs)
+    mu = inputs.cylinder_viscosity(3.0) if viscous else 0.0
+    c, g = make_pair(orc, nx, ny, domain=sc["domain"], bc=sc["bc"], inflow=sc["inflow"], viscous=viscous, mu=mu,
+                     prec=prec, ibm=True)
+    assert g.set_levelset(torch.from_numpy(sc["phi"]), wall=1 if viscous else 0) > 0
+    wall = 1 if viscous else 0
+    Uo = orc.prim_to_cons(c, sc["W"]).astype(np.float32).astype(np.float64)  # what FP32 storage holds
+    Lo, _, _ = orc.rhs(c, Uo, phi=sc["phi"], wall=wall)
+    Ug = torch.from_numpy(Uo).to(device=g.device, dtype=g.dtype).reshape(g.shape).contiguous()
+    assert_fields(to_np(g.rhs(Ug))[0], Lo, 1e-5, f"ibm rhs {prec} viscous={viscous}")
+    dt = 0.4 * orc.cfl_dt(c, Uo, phi=sc["phi"])
+    U1o, _ = orc.rk3_step(c, Uo, dt, phi=sc["phi"], wall=wall)
+    g.step(Ug, dt)
+    errs = assert_fields(to_np(Ug)[0], U1o, 1e-5, f"ibm step {prec} viscous={viscous}")
+    print(f"ibm {prec} viscous={viscous}: step per-field errors {errs}", flush=True)
+
+
 def test_shock_cylinder_ns_trajectory_small(orc):
     """Mach-3 shock on the cylinder, Navier-Stokes, no-slip adiabatic wall, at
     160x80, 40 automatic steps (the shock reaches the cylinder)."""
