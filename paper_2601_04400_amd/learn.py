@@ -421,7 +421,7 @@ def cnn_norm_from(data, centre=None):
     on the snapshots' mean, or on `centre` (conservative rho, m_n, m_t, E)
     if given.  The zero padding of the 3x3 layers at non-periodic edges
     stands for the centre state."""
-    S = data.snaps[:, :, :, :, :]
+    S = data.snaps  # [snapshot][member][4][ny][nx]
     r, E = S[:, :, 0], S[:, :, 3]
     m = torch.cat([S[:, :, 1].flatten(), S[:, :, 2].flatten()])
     mean = (float(r.mean()), float(m.mean()), float(m.mean()), float(E.mean()))
@@ -489,8 +489,9 @@ def main_cylinder(a):
     centre = None
     if a.norm_cyl == "ambient":
         from .infer import PRE
+        gm1 = 1.4 - 1.0  # the set-up runs at the grids' default gamma
         r, u, v, p = PRE
-        centre = (r, r * u, r * v, p / 0.4 + 0.5 * r * (u * u + v * v))
+        centre = (r, r * u, r * v, p / gm1 + 0.5 * r * (u * u + v * v))
     mean, inv = cnn_norm_from(data, centre)
     net = FluxCnn(init_cnn_theta(0, zero_output=True), mean, inv, out_scale=a.out_scale_cyl)
     before = dataset_loss(net, data, m=a.m_cyl)
