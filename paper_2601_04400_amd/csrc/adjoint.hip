@@ -609,9 +609,12 @@ __global__ void __launch_bounds__(256) ibm_entries_rank_kernel(GhostTable gt, in
 // adjoint kernel has already turned the adjoint of every ghost's refilled
 // state into the adjoint gW[k] = (rho, u, v, p)_bar of its image-point
 // primitives (and cleared the ghost's own entry).  Here each source cell
-// (run heads[h] .. heads[h+1] of equal keys in the sorted (source, entry)
-// list) gathers w_m gW[k] over the ghosts k that read it, in entry order,
-// followed by the primitive -> conservative transpose at the source.  The
+// gathers w_m gW[k] over the ghosts k that read it, in entry order, followed
+// by the primitive -> conservative transpose at the source.  The fill table
+// (built when the level set is set) holds a source's cell, entry count,
+// ghost indices and weights at addresses that depend on the source's number
+// only, so a thread's loads wait for one round trip before the ghost
+// adjoints are read, not three (run heads, entries, weights).  The
 // gamma parts are summed in a fixed order into the member's partial; with
 // param_bar set, the member's recorded partials of the whole reverse pass
 // (slots of ps, this launch's own last) are then added to param_bar here
@@ -628,10 +631,13 @@ __device__ __forceinline__ double block_sum_fixed(double v, double* red) {
   return s;
 }
 
+constexpr int FILL_SLOTS = 8;  // entry slots whose loads are issued together
+
 __global__ void __launch_bounds__(FILL_NT) ibm_fill_adjoint_kernel(GridArgs a, GhostTable gt,
-                                                                   const int* __restrict__ keys,
-                                                                   const int* __restrict__ vals,
-                                                                   const int* __restrict__ heads, int nsrc,
+                                                                   const int* __restrict__ fsrc,
+                                                                   const int* __restrict__ fcnt,
+                                                                   const int* __restrict__ fk,
+                                                                   const double* __restrict__ fw, int m, int nsrc,
                                                                    const double* __restrict__ Us, double* __restrict__ X,
                                                                    const double* __restrict__ gW,
                                                                    double* __restrict__ part, PartSlots ps,
@@ -658,23 +664,27 @@ __global__ void __launch_bounds__(FILL_NT) ibm_fill_adjoint_kernel(GridArgs a, G
     for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
   }
   for (int h = threadIdx.x; h < nsrc; h += FILL_NT) {
-    const int i0 = heads[h], i1 = heads[h + 1];
-    const int src = keys[i0];
+    const int src = fsrc[h], cnt = fcnt[h];
     double Wsb[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int j0 = i0; j0 < i1; j0 += 4) {
-      // up to four entries per round with their loads issued together
-      int e[4];
+    for (int t0 = 0; t0 < m; t0 += FILL_SLOTS) {
+      // the slots' ghost indices and weights are loaded without waiting for
+      // the count (m, the most entries of any source, is uniform; unused
+      // slots hold ghost 0 and weight 0 and are skipped)
+      int k[FILL_SLOTS];
+      double wm[FILL_SLOTS];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) e[t] = j0 + t < i1 ? vals[j0 + t] : -1;
+      for (int u = 0; u < FILL_SLOTS; ++u) {
+        const int t = t0 + u;
+        k[u] = t < m ? fk[(long long)t * nsrc + h] : 0;
+        wm[u] = t < m ? fw[(long long)t * nsrc + h] : 0.0;
+      }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (e[t] < 0) continue;
-        const int k = e[t] >> 2;
-        const double wm = gt.w[e[t]];
-        Wsb[0] += wm * gWb[4 * k];
-        Wsb[1] += wm * gWb[4 * k + 1];
-        Wsb[2] += wm * gWb[4 * k + 2];
-        Wsb[3] += wm * gWb[4 * k + 3];
+      for (int u = 0; u < FILL_SLOTS; ++u) {
+        if (t0 + u >= cnt) continue;
+        Wsb[0] += wm[u] * gWb[4 * k[u]];
+        Wsb[1] += wm[u] * gWb[4 * k[u] + 1];
+        Wsb[2] += wm[u] * gWb[4 * k[u] + 2];
+        Wsb[3] += wm[u] * gWb[4 * k[u] + 3];
       }
     }
     const double r = Ub[src];
@@ -773,11 +783,12 @@ hipError_t launch_ibm_entries(const GhostTable& gt, int* keys, int* vals, int* n
   return hipGetLastError();
 }
 
-hipError_t launch_ibm_fill_adjoint(const GridArgs& a, const GhostTable& gt, const int* keys, const int* vals,
-                                   const int* heads, int nsrc, const double* Us, double* X, const double* gW,
-                                   double* part, const PartSlots& prior, double* param_bar, hipStream_t st) {
-  hipLaunchKernelGGL(ibm_fill_adjoint_kernel, dim3(a.nbatch), dim3(FILL_NT), 0, st, a, gt, keys, vals, heads, nsrc, Us,
-                     X, gW, part, prior, param_bar);
+hipError_t launch_ibm_fill_adjoint(const GridArgs& a, const GhostTable& gt, const int* fsrc, const int* fcnt,
+                                   const int* fk, const double* fw, int m, int nsrc, const double* Us, double* X,
+                                   const double* gW, double* part, const PartSlots& prior, double* param_bar,
+                                   hipStream_t st) {
+  hipLaunchKernelGGL(ibm_fill_adjoint_kernel, dim3(a.nbatch), dim3(FILL_NT), 0, st, a, gt, fsrc, fcnt, fk, fw, m, nsrc,
+                     Us, X, gW, part, prior, param_bar);
   return hipGetLastError();
 }
 

@@ -40,6 +40,7 @@ struct shk_grid {
   bool ibm_on;
   int nent = 0;  // valid (ghost, source) entries of the refill transpose
   int nsrc = 0;  // distinct source cells among them
+  int fill_m = 0;  // most entries of one source (the fill table's slots per source)
   NetArgs net{};
   bool net_on = false;
   CnnArgs cnn{};
@@ -372,6 +373,22 @@ shk_status shk_prim_to_cons_vjp(shk_grid* g, const void* W, const void* U_bar, v
                    "prim_to_cons_vjp");
 }
 
+// Byte offsets of the refill-transpose fill table within its workspace
+// region: source cells and entry counts (ns each), then m slots of ghost
+// indices and of weights, slot-major.
+struct FillTable {
+  size_t src, cnt, k, w, end;
+};
+static FillTable fill_table(int ns, int m) {
+  FillTable f;
+  f.src = 0;
+  f.cnt = f.src + al(sizeof(int) * size_t(ns));
+  f.k = f.cnt + al(sizeof(int) * size_t(ns));
+  f.w = f.k + al(sizeof(int) * size_t(m) * ns);
+  f.end = f.w + al(sizeof(double) * size_t(m) * ns);
+  return f;
+}
+
 // Dispatch order of the 2D stage tiles of a grid with a body: workgroup w
 // goes to XCD w % 8 (round robin), so XCD x takes the tiles of queue x in
 // order.  The tiles near the body (their ghost cells chain four dependent
@@ -499,11 +516,43 @@ shk_status shk_set_ib_levelset(shk_grid* g, const double* phi, int wall) {
     for (int i = 0; i < nv; ++i)
       if (i == 0 || hk[i] != hk[i - 1]) heads.push_back(i);
     heads.push_back(nv);
-    int* dh = reinterpret_cast<int*>(g->ws + g->L.entHeads);
-    e = hipMemcpyAsync(dh, heads.data(), sizeof(int) * heads.size(), hipMemcpyHostToDevice, g->st);
+    const int ns = int(heads.size()) - 1;
+    // the fill table, source by source: source cell, entry count, and per
+    // entry slot t the ghost index and weight of its t-th entry (in entry
+    // order), slot-major so that a wave reads consecutive sources; it takes
+    // the place of the sorted entries, which only served to build it
+    std::vector<int> hv(size_t(nv > 0 ? nv : 1));
+    std::vector<double> hw(size_t(4) * gt.n);
+    if (nv > 0) e = hipMemcpyAsync(hv.data(), vals, sizeof(int) * nv, hipMemcpyDeviceToHost, g->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hw.data(), gt.w, sizeof(double) * hw.size(), hipMemcpyDeviceToHost, g->st);
     if (e == hipSuccess) e = hipStreamSynchronize(g->st);
-    if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset (entry heads)");
-    g->nsrc = int(heads.size()) - 1;
+    if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset (entries)");
+    int m = 0;
+    for (int h = 0; h < ns; ++h) m = std::max(m, heads[h + 1] - heads[h]);
+    const FillTable ft = fill_table(ns, m);
+    const size_t cap = g->L.entHeads + al(sizeof(int) * (4 * size_t(g->a.ncell) + 1)) - g->L.entKeys;
+    if (ft.end > cap)
+      return fail(g, SHK_EINVAL, "set_ib_levelset: the refill transpose table (" + std::to_string(ns) +
+                                     " sources, up to " + std::to_string(m) + " entries each) exceeds its workspace");
+    std::vector<char> tab(ft.end, 0);
+    int* fsrc = reinterpret_cast<int*>(tab.data() + ft.src);
+    int* fcnt = reinterpret_cast<int*>(tab.data() + ft.cnt);
+    int* fk = reinterpret_cast<int*>(tab.data() + ft.k);
+    double* fw = reinterpret_cast<double*>(tab.data() + ft.w);
+    for (int h = 0; h < ns; ++h) {
+      fsrc[h] = hk[heads[h]];
+      fcnt[h] = heads[h + 1] - heads[h];
+      for (int t = 0; t < fcnt[h]; ++t) {
+        const int ent = hv[heads[h] + t];
+        fk[size_t(t) * ns + h] = ent >> 2;
+        fw[size_t(t) * ns + h] = hw[ent];
+      }
+    }
+    e = hipMemcpyAsync(g->ws + g->L.entKeys, tab.data(), tab.size(), hipMemcpyHostToDevice, g->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+    if (e != hipSuccess) return hip_check(g, e, "set_ib_levelset (fill table)");
+    g->nsrc = ns;
+    g->fill_m = m;
   }
   return SHK_OK;
 }
@@ -639,12 +688,14 @@ static hipError_t fill64(shk_grid* g, double* X) {
 // filled state Us); with param_bar set it also finalises the pass's partials.
 static hipError_t fillT(shk_grid* g, PartRec& pr, const double* Us, double* X, double* param_bar = nullptr) {
   if (!g->ibm_on || g->nent == 0) return hipSuccess;
-  const int* keys = reinterpret_cast<const int*>(g->ws + g->L.entKeys);
-  const int* vals = reinterpret_cast<const int*>(g->ws + g->L.entVals);
+  const FillTable ft = fill_table(g->nsrc, g->fill_m);
+  const char* base = g->ws + g->L.entKeys;
   const double* gW = reinterpret_cast<const double*>(g->ws + g->L.adjG);
-  const int* heads = reinterpret_cast<const int*>(g->ws + g->L.entHeads);
-  hipError_t e = launch_ibm_fill_adjoint(g->a, g->gt, keys, vals, heads, g->nsrc, Us, X, gW, pr.next(), pr.ps,
-                                         param_bar, g->st);
+  hipError_t e = launch_ibm_fill_adjoint(g->a, g->gt, reinterpret_cast<const int*>(base + ft.src),
+                                         reinterpret_cast<const int*>(base + ft.cnt),
+                                         reinterpret_cast<const int*>(base + ft.k),
+                                         reinterpret_cast<const double*>(base + ft.w), g->fill_m, g->nsrc, Us, X, gW,
+                                         pr.next(), pr.ps, param_bar, g->st);
   if (e == hipSuccess) {
     pr.add(1);
     if (param_bar) pr.finalised = true;

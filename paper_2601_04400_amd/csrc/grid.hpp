@@ -147,11 +147,13 @@ hipError_t launch_ibm_entries(const GhostTable& gt, int* keys, int* vals, int* n
 // kernel.  Its block partial goes to part (1 block per member).  With
 // param_bar set it also finalises: param_bar += the slots of prior (which lie
 // before part, at part - (prior.n - s) * prior.stride for slot s) plus its
-// own partial.  heads[0..nsrc]: start of each source's run in the sorted
-// entry list.
-hipError_t launch_ibm_fill_adjoint(const GridArgs& a, const GhostTable& gt, const int* keys, const int* vals,
-                                   const int* heads, int nsrc, const double* Us, double* X, const double* gW,
-                                   double* part, const PartSlots& prior, double* param_bar, hipStream_t st);
+// own partial.  The fill table: for source h < nsrc its cell fsrc[h], its
+// entry count fcnt[h] <= m, and for entry slot t < fcnt[h] the ghost index
+// fk[t * nsrc + h] and weight fw[t * nsrc + h], in entry order.
+hipError_t launch_ibm_fill_adjoint(const GridArgs& a, const GhostTable& gt, const int* fsrc, const int* fcnt,
+                                   const int* fk, const double* fw, int m, int nsrc, const double* Us, double* X,
+                                   const double* gW, double* part, const PartSlots& prior, double* param_bar,
+                                   hipStream_t st);
 hipError_t launch_axpy(long long n, double alpha, const double* x, double* y, int accumulate, hipStream_t st);
 
 // stage modes
