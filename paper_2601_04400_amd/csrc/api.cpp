@@ -2,6 +2,7 @@
 // workspace carving and kernel sequencing on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
